@@ -1,0 +1,196 @@
+"""Pins of the CPU oracle against things other than itself: brute-force Fock
+space matrices, closed forms, library routines (expm, eigh), invariants and a
+textbook two-level case.  No GPU, no HIP library."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import brute as B
+from oracle import fermion as F
+from oracle import pauli as P
+from vqe_inputs import random_integrals
+
+SMALL = [(4, 2), (5, 2), (5, 3), (6, 3), (6, 2), (7, 4), (8, 4)]
+
+
+def _problem(n, ne, seed=11):
+    h0, h, g = random_integrals(n, seed)
+    return F.Problem(n, ne, h0, h, g), (h0, h, g)
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_brute_hamiltonian_invariants(n):
+    h0, h, g = random_integrals(n, 3)
+    H = B.hamiltonian(n, h0, h, g)
+    N, Sz = B.number_ops(n)
+    assert np.abs(H - H.T).max() < 1e-13
+    assert np.abs(H @ N - N @ H).max() < 1e-12
+    assert np.abs(H @ Sz - Sz @ H).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,ne", SMALL)
+def test_sigma_matches_brute_force(n, ne):
+    prob, (h0, h, g) = _problem(n, ne)
+    Hb = B.hamiltonian(n, h0, h, g)
+    idx = prob.space.bits
+    ref_idx = B.sector_indices(n, prob.space.na, prob.space.nb)
+    assert sorted(idx.tolist()) == ref_idx.tolist()
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=idx.size) + 1j * rng.normal(size=idx.size)
+    assert np.abs(prob.ham.apply(v) - Hb[np.ix_(idx, idx)] @ v).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,ne", SMALL + [(12, 6), (16, 8)])
+def test_energy_at_zero_is_closed_form_hf(n, ne):
+    prob, (h0, h, g) = _problem(n, ne)
+    e0 = prob.energy(np.zeros(prob.n_params))
+    assert abs(e0 - F.hf_energy_closed_form(n, ne, h0, h, g)) < 1e-12
+    if n <= 8:
+        Hb = B.hamiltonian(n, h0, h, g)
+        hf = (1 << ne) - 1
+        assert abs(e0 - Hb[hf, hf]) < 1e-12
+
+
+def test_uccsd_counts():
+    # spin-conserving singles and doubles on the HF reference
+    for n, m in [(4, 3), (12, 117), (16, 360), (20, 875), (24, 1818)]:
+        excs = F.uccsd_excitations(n, n // 2)
+        assert len(excs) == m
+    # 4 qubits: two singles (one per spin) then the one alpha-beta double
+    assert F.uccsd_excitations(4, 2) == [(0, 2), (1, 3), (0, 1, 2, 3)]
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 3), (6, 3), (7, 3)])
+def test_excitation_gate_matches_expm(n, ne):
+    prob, _ = _problem(n, ne)
+    rng = np.random.default_rng(1)
+    for exc in prob.excs:
+        theta = rng.uniform(-1.5, 1.5)
+        psi = rng.normal(size=prob.space.ndet) + 1j * rng.normal(size=prob.space.ndet)
+        got = F.apply_excitation(prob.space, psi, exc, theta)
+        U = B.excitation_unitary(n, exc, theta)
+        full = prob.space.to_statevector(psi)
+        ref = U @ full
+        assert np.abs(ref[prob.space.bits] - got).max() < 1e-12
+        assert np.abs(np.delete(ref, prob.space.bits)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_pauli_jw_matches_brute_force(n):
+    h0, h, g = random_integrals(n, 9)
+    HP = P.jw_hamiltonian(n, 0.7, h, g)
+    assert np.abs(P.matrix(HP, n) - B.hamiltonian(n, 0.7, h, g)).max() < 1e-12
+    # real symmetric Hamiltonian: every folded coefficient is real
+    P.folded_terms(HP)
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 3), (6, 3)])
+def test_rotation_products_match_expm(n, ne):
+    rng = np.random.default_rng(2)
+    for exc in F.uccsd_excitations(n, ne):
+        rots = P.excitation_rotations(n, exc)
+        assert len(rots) == (2 if len(exc) == 2 else 8)
+        assert len({x for x, _, _ in rots}) == 1          # one shared x-mask
+        assert all(abs(abs(s) - (1.0 if len(exc) == 2 else 0.25)) < 1e-15 for *_, s in rots)
+        theta = rng.uniform(-1, 1)
+        psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+        out = psi.copy()
+        for x, z, s in rots:
+            out = P.apply_rotation(out, n, (x, z), s * theta)
+        assert np.abs(out - B.excitation_unitary(n, exc, theta) @ psi).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,ne", [(8, 4), (9, 4), (10, 5)])
+def test_ci_energy_matches_dense_pauli(n, ne):
+    prob, (h0, h, g) = _problem(n, ne, seed=21)
+    HP = P.jw_hamiltonian(n, h0, h, g)
+    theta = np.random.default_rng(3).uniform(-0.3, 0.3, prob.n_params)
+    psi = P.prepare(n, ne, prob.excs, theta)
+    # invariants of the dense evolution: norm, reality, particle number, sector
+    assert abs(np.linalg.norm(psi) - 1) < 1e-13
+    assert np.abs(psi.imag).max() < 1e-14
+    outside = np.delete(psi, prob.space.bits)
+    assert np.abs(outside).max() < 1e-14
+    occ = np.array([bin(b).count("1") for b in range(1 << n)])
+    assert abs(np.sum(np.abs(psi) ** 2 * occ) - ne) < 1e-12
+    assert np.abs(psi[prob.space.bits] - prob.state(theta)).max() < 1e-12
+    assert abs(P.energy(HP, psi, n) - prob.energy(theta)) < 1e-11
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (6, 3), (8, 4), (12, 6)])
+def test_gradient_at_hf_closed_form(n, ne):
+    prob, (h0, h, g) = _problem(n, ne)
+    got = prob.grad_shift(np.zeros(prob.n_params))
+    ref = F.grad_at_hf_closed_form(ne, prob.excs, h, g)
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.abs(ref).max() > 1e-2  # random integrals are not SCF: nonzero
+
+
+@pytest.mark.parametrize("n,ne", [(5, 2), (6, 3), (8, 4)])
+def test_shift_rule_vs_central_difference(n, ne):
+    prob, _ = _problem(n, ne)
+    theta = np.random.default_rng(4).uniform(-0.5, 0.5, prob.n_params)
+    assert np.abs(prob.grad_shift(theta) - prob.grad_fd(theta, h=1e-5)).max() < 1e-8
+
+
+@pytest.mark.parametrize("n,ne", SMALL)
+def test_fci_matches_brute_force_sector(n, ne):
+    prob, (h0, h, g) = _problem(n, ne)
+    Hb = B.hamiltonian(n, h0, h, g)
+    idx = B.sector_indices(n, prob.space.na, prob.space.nb)
+    ref = np.linalg.eigvalsh(Hb[np.ix_(idx, idx)])[0]
+    assert abs(prob.fci() - ref) < 1e-11
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_vqe_4q_reaches_fci(seed):
+    h0, h, g = random_integrals(4, seed)
+    prob = F.Problem(4, 2, h0, h, g)
+    res = prob.vqe(maxiter=50)
+    assert abs(res.fun - prob.fci()) < 1e-9
+
+
+def test_vqe_6q_variational_bound():
+    prob, _ = _problem(6, 3, seed=2)
+    res = prob.vqe(maxiter=200)
+    assert res.fun >= prob.fci() - 1e-10
+    assert res.fun < prob.energy(np.zeros(prob.n_params))
+
+
+def test_two_level_closed_form():
+    """H2-like 4-qubit model (bonding 0 / antibonding 1 orbitals): with h_01 = 0
+    and every (pq|rs) with an odd number of 1-indices zero, the HF determinant
+    couples only to the doubly excited one, so min_theta E(theta) over the
+    double alone is the 2x2 ground state
+      E = (E1 + E2)/2 - sqrt((E1 - E2)^2 / 4 + K^2),
+    E1 = 2 h00 + (00|00), E2 = 2 h11 + (11|11), K = (01|01)."""
+    h = np.diag([-1.25, -0.47])
+    g = np.zeros((2, 2, 2, 2))
+    vals = {(0, 0, 0, 0): 0.67, (1, 1, 1, 1): 0.70, (0, 0, 1, 1): 0.66, (0, 1, 0, 1): 0.18}
+    for (p, q, r, s), v in vals.items():
+        for a, b, c, d in ((p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r),
+                           (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)):
+            g[a, b, c, d] = v
+    prob = F.Problem(4, 2, 0.0, h, g, excs=[(0, 1, 2, 3)])
+    E1 = 2 * h[0, 0] + g[0, 0, 0, 0]
+    E2 = 2 * h[1, 1] + g[1, 1, 1, 1]
+    K = g[0, 1, 0, 1]
+    ref = 0.5 * (E1 + E2) - math.sqrt(0.25 * (E1 - E2) ** 2 + K * K)
+    thetas = np.linspace(-math.pi / 2, math.pi / 2, 2001)
+    es = [prob.energy([t]) for t in thetas]
+    t0 = thetas[int(np.argmin(es))]
+    import scipy.optimize
+    r = scipy.optimize.minimize_scalar(lambda t: prob.energy([t]), bracket=(t0 - 0.01, t0 + 0.01))
+    assert abs(r.fun - ref) < 1e-12
+    assert abs(prob.fci() - ref) < 1e-12
+    # the symmetric model has 15 Pauli terms (the H2 count), generic 4q has 27
+    assert len(P.jw_hamiltonian(4, 0.0, h, g)) == 15
+    assert len(P.jw_hamiltonian(4, *random_integrals(4, 1))) == 27
+
+
+def test_term_and_group_counts_12q():
+    terms = P.folded_terms(P.jw_hamiltonian(12, *random_integrals(12, 2)))
+    xs = {x for x, _ in terms}
+    diag = [k for k in terms if k[0] == 0]
+    assert (len(terms), len(xs), len(diag)) == (1819, 286, 79)
