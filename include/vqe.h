@@ -1,0 +1,234 @@
+/*
+ * vqe.h — C ABI of the MI355X (gfx950) VQE statevector library.
+ *
+ * The library computes the VQE objective of Sec. 2.1.1, Eq. 1,
+ *     E(theta) = <HF| U(theta)^dag H U(theta) |HF>,
+ * for a Jordan-Wigner qubit Hamiltonian H = sum_k c_k P_k (the qubit form of
+ * Eq. 2, Sec. 2.1.1) and a UCCSD ansatz U = exp(T - T^dag) (Sec. 2.1.2),
+ * together with its exact gradient (adjoint reverse sweep) and a BFGS-driven
+ * VQE loop (Sec. 3.1 "Results for parameter optimisation" names BFGS).
+ *
+ * Conventions
+ * -----------
+ * - Qubit q is spin orbital q: spatial orbital q/2, spin q%2 (0 = alpha,
+ *   1 = beta).  Odd qubit counts leave the last spatial orbital alpha-only.
+ *   Bit q of a statevector index is the occupation of spin orbital q.
+ * - A statevector is complex128[2^n], interleaved (re, im), in device memory,
+ *   256-byte aligned.
+ * - Pauli masks are uint32: bit q of x is an X or Y on qubit q, bit q of z a
+ *   Z or Y.  Two different forms are used, and each call says which:
+ *     * Hermitian string P(x, z): Y where x and z are both set,
+ *       P = i^{popcount(x&z)} X^x Z^z;
+ *     * folded form X^x Z^z (Z applied first) with a REAL coefficient
+ *       c' = c * i^{popcount(x&z)}; X^x Z^z |b> = (-1)^{popcount(b&z)} |b^x>.
+ *   Hamiltonians are exchanged in folded form (real coefficients); rotations
+ *   exp(-i phi/2 P) take Hermitian strings.
+ * - Every call returns an int status: VQE_OK (0) or a negative error code;
+ *   vqe_last_error() returns a thread-local message for the last failure.
+ *   The library never aborts or exits.  Arguments are validated on the host
+ *   before any HIP call, so argument errors are reported without a GPU.
+ * - The caller owns every host array passed in; the library copies what it
+ *   keeps.  Handles are not safe for concurrent use from several threads.
+ * - hip_stream arguments are hipStream_t values (NULL = the null stream);
+ *   work is ordered on that stream.  Calls that return host results
+ *   synchronise that stream before returning.
+ */
+#ifndef VQE_H
+#define VQE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VQE_ABI_VERSION 1
+
+enum {
+    VQE_OK = 0,
+    VQE_EINVAL = -1,   /* bad argument: null pointer, NaN, asymmetric integrals, ... */
+    VQE_ERANGE = -2,   /* size out of range: n_qubits, n_electrons, indices */
+    VQE_ENOMEM = -3,   /* host or device allocation failed / would not fit */
+    VQE_EDEVICE = -4,  /* HIP runtime error (message carries hipGetErrorString) */
+    VQE_ENUMERIC = -5  /* non-finite energy or gradient produced */
+};
+
+typedef struct vqe_hamiltonian vqe_hamiltonian;
+typedef struct vqe_ansatz vqe_ansatz;
+typedef struct vqe_state vqe_state;
+typedef struct vqe_batch vqe_batch;
+
+int vqe_abi_version(void);
+const char* vqe_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Hamiltonians (host-only construction; uploaded to a device on first use)
+ * ------------------------------------------------------------------------ */
+
+/* Jordan-Wigner qubit Hamiltonian of Eq. 2 (Sec. 2.1.1) from real spatial
+ * integrals, read as
+ *   H = h0 + sum_{pq,s} h[p][q] a+_{ps} a_{qs}
+ *          + 1/2 sum_{pqrs,s,t} (pq|rs) a+_{ps} a+_{rt} a_{st} a_{qs},
+ * with ns = ceil(n_qubits/2) spatial orbitals; h is row-major [ns][ns] and
+ * g row-major [ns][ns][ns][ns] holding chemist integrals (pq|rs).
+ * Requires 1 <= n_qubits <= 32 (ERANGE), h symmetric and g 8-fold symmetric
+ * within 1e-12 and every value finite (EINVAL).  Terms with |c'| <= 1e-12
+ * after accumulation are dropped.  *out is freed with vqe_hamiltonian_free. */
+int vqe_hamiltonian_from_integrals(int n_qubits, double h0, const double* h,
+                                   const double* g, vqe_hamiltonian** out);
+
+/* Hamiltonian sum_k coef[k] X^{x[k]} Z^{z[k]} in folded form (see above).
+ * Masks must fit n_qubits bits (ERANGE); duplicate (x, z) pairs are summed;
+ * a nonzero term with odd popcount(x&z) makes H non-symmetric and is
+ * rejected (EINVAL); coefficients must be finite (EINVAL). */
+int vqe_hamiltonian_from_paulis(int n_qubits, int64_t n_terms, const uint32_t* x,
+                                const uint32_t* z, const double* coef,
+                                vqe_hamiltonian** out);
+
+/* Sizes: qubits, terms, x-mask groups (any pointer may be NULL). */
+int vqe_hamiltonian_info(const vqe_hamiltonian* H, int* n_qubits, int64_t* n_terms,
+                         int64_t* n_groups);
+
+/* Export the terms in folded form, sorted by (x, z).  *n_terms is the
+ * capacity of x/z/coef on input and the term count on output; with a
+ * capacity smaller than the count nothing is written and ERANGE returned. */
+int vqe_hamiltonian_terms(const vqe_hamiltonian* H, int64_t* n_terms, uint32_t* x,
+                          uint32_t* z, double* coef);
+
+void vqe_hamiltonian_free(vqe_hamiltonian* H);
+
+/* ---------------------------------------------------------------------------
+ * Ansatz programs (host-only construction)
+ * ------------------------------------------------------------------------ */
+
+/* UCCSD (Sec. 2.1.2), one Trotter step, on the HF reference of n_electrons:
+ * singles T = a+_a a_i, doubles T = a+_a a+_b a_j a_i (i < j occupied, a < b
+ * virtual, spin-conserving), U_j = exp(theta_j (T_j - T_j^dag)), applied as
+ * U_M ... U_1 with all singles first (a outer, i inner) and then doubles
+ * ((a, b) outer, (i, j) inner), ascending.  *n_params receives M. */
+int vqe_ansatz_uccsd(int n_qubits, int n_electrons, vqe_ansatz** out, int32_t* n_params);
+
+/* Ansatz of explicit Pauli rotations applied in the given order:
+ * gate k is exp(-i (scale[k] * theta[param_index[k]]) / 2 * P(x[k], z[k]))
+ * with P a Hermitian Pauli string.  0 <= param_index[k] < n_params. */
+int vqe_ansatz_from_rotations(int n_qubits, int32_t n_params, int64_t n_rot,
+                              const uint32_t* x, const uint32_t* z,
+                              const int32_t* param_index, const double* scale,
+                              vqe_ansatz** out);
+
+/* Sizes: qubits, parameters, gates, electrons of the reference (-1 if none). */
+int vqe_ansatz_info(const vqe_ansatz* A, int* n_qubits, int32_t* n_params,
+                    int64_t* n_gates, int* n_electrons);
+
+/* Excitation list of a UCCSD ansatz in application order: orbitals[4*k..]
+ * = (i, a, -1, -1) for a single, (i, j, a, b) for a double.  *n is capacity
+ * in / count out (ERANGE if too small; EINVAL for a rotation ansatz). */
+int vqe_ansatz_excitations(const vqe_ansatz* A, int64_t* n, int32_t* orbitals);
+
+void vqe_ansatz_free(vqe_ansatz* A);
+
+/* ---------------------------------------------------------------------------
+ * Device statevectors
+ * ------------------------------------------------------------------------ */
+
+/* Library-owned statevector of n_qubits (1..32) on the current HIP device,
+ * ordered on hip_stream.  Contents are undefined until prepared. */
+int vqe_state_create(int n_qubits, void* hip_stream, vqe_state** out);
+
+/* Borrow caller memory (complex128[2^n], device, 256-byte aligned); the
+ * library never frees it.  The memory must outlive the handle. */
+int vqe_state_wrap(int n_qubits, void* dev_complex128, void* hip_stream, vqe_state** out);
+
+/* Device pointer of the amplitudes. */
+int vqe_state_data(const vqe_state* s, void** dev_ptr);
+
+void vqe_state_free(vqe_state* s);
+
+/* |HF> = the basis state with the lowest n_electrons spin orbitals occupied
+ * (index 2^n_e - 1), the reference |0> of Eq. 1. */
+int vqe_prepare_hf(vqe_state* s, int n_electrons);
+
+/* psi <- exp(-i theta/2 P(x, z)) psi for a Hermitian Pauli string. */
+int vqe_apply_pauli_rotation(vqe_state* s, uint32_t x, uint32_t z, double theta);
+
+/* psi <- U(theta) psi; theta is a host array of the ansatz's n_params. */
+int vqe_apply_ansatz(vqe_state* s, const vqe_ansatz* A, const double* theta);
+
+/* *energy = Re <psi|H|psi> (Eq. 1's expectation; psi is not renormalised).
+ * Synchronises the state's stream. */
+int vqe_expectation(const vqe_state* s, const vqe_hamiltonian* H, double* energy);
+
+/* Energy and exact gradient at theta (host array, n_params):
+ * prepares |HF> of n_electrons, applies U(theta), evaluates E, and when grad
+ * is non-NULL runs the adjoint reverse sweep for dE/dtheta (n_params
+ * doubles).  Scratch memory is cached per (device, stream) and reused.
+ * NaN/Inf results return ENUMERIC (outputs still written). */
+int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
+                    const double* theta, double* energy, double* grad, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched evaluation of many independent problems
+ * ------------------------------------------------------------------------ */
+
+/* A batch of n_states problems (H[i], A[i], n_electrons[i]); qubit counts
+ * may differ.  Device buffers for every state are allocated here; the
+ * per-evaluation launch sequence is captured once into a HIP graph. */
+int vqe_batch_create(int n_states, const vqe_hamiltonian* const* H,
+                     const vqe_ansatz* const* A, const int* n_electrons,
+                     void* hip_stream, vqe_batch** out);
+
+/* Parameter layout of the batch: offsets[i] is the first entry of state i
+ * in theta_all / g_all, offsets[n_states] the total (n_states + 1 ints). */
+int vqe_batch_offsets(const vqe_batch* b, int64_t* offsets);
+
+/* Energies e_all[n_states] and gradients g_all[total params] (nullable) for
+ * the concatenated host parameters theta_all; one graph launch. */
+int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, double* e_all,
+                          double* g_all);
+
+void vqe_batch_free(vqe_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * BFGS and the VQE loop
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int max_iter;        /* iteration cap (accepted steps) */
+    double gtol;         /* stop when max |g_i| <= gtol */
+    double ftol;         /* stop when |f_k - f_{k+1}| <= ftol * max(1, |f_k|); 0 disables */
+    double max_seconds;  /* wall-clock budget; <= 0 disables */
+    int record_trace;    /* write f after each iteration into trace_out */
+} vqe_options;
+
+typedef struct {
+    double energy;       /* final objective value */
+    int iters;           /* accepted BFGS iterations */
+    int n_evals;         /* objective + gradient evaluations */
+    int converged;       /* 1 if gtol or ftol was met, else 0 */
+} vqe_result;
+
+/* Objective callback: writes f and g (n doubles) at x; returns 0 on success,
+ * nonzero to abort the minimisation (reported as EINVAL). */
+typedef int (*vqe_objective_fn)(void* ctx, int n, const double* x, double* f, double* g);
+
+/* BFGS (inverse-Hessian form, H0 = I rescaled by y's/y'y before the first
+ * update) with a strong-Wolfe line search (c1 = 1e-4, c2 = 0.9; bracketing
+ * and zoom with cubic interpolation).  trace_out (nullable) receives
+ * max_iter + 1 doubles: f after 0, 1, ... iterations (unused entries NaN).
+ * Non-convergence returns VQE_OK with converged = 0; a non-finite f or g
+ * returns ENUMERIC. */
+int vqe_minimize_bfgs(int n, vqe_objective_fn fn, void* ctx, const double* x0,
+                      const vqe_options* opts, double* x_out, double* trace_out,
+                      vqe_result* res);
+
+/* VQE (Sec. 2.1.1, Eq. 1): vqe_minimize_bfgs over vqe_energy_grad from
+ * theta0 (NULL = all zeros, the HF state).  theta_out receives n_params. */
+int vqe_run(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
+            const double* theta0, const vqe_options* opts, double* theta_out,
+            double* trace_out, vqe_result* res, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VQE_H */

@@ -1,0 +1,358 @@
+"""MI355X-native VQE statevector engine (thin Python binding over libvqe.so).
+
+Every step of the hot path runs in the library's HIP kernels; this module
+only marshals arguments.  PyTorch is used, when present, for the HIP stream
+of the caller (``torch.cuda.current_stream()``) and for device tensors that a
+statevector may borrow.
+
+Method (arXiv:2311.01242): VQE objective E(theta) = <HF|U^dag H U|HF>
+(Sec. 2.1.1, Eq. 1) for the Jordan-Wigner form of Eq. 2 and a UCCSD ansatz
+(Sec. 2.1.2); gradients by an adjoint reverse sweep; BFGS (Sec. 3.1).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import Options, Result, lib
+
+VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -2, -3, -4, -5
+
+__all__ = [
+    "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "EnergyGrad",
+    "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream",
+]
+
+
+class VQEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != VQE_OK:
+        raise VQEError(rc, lib().vqe_last_error().decode(errors="replace"))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _u32(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+def current_stream():
+    """hipStream_t of torch's current stream on the current device, or None."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+class Hamiltonian:
+    """Jordan-Wigner qubit Hamiltonian (folded real form c' X^x Z^z)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def from_integrals(cls, n_qubits: int, h0: float, h, g):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        out = C.c_void_p()
+        _check(lib().vqe_hamiltonian_from_integrals(int(n_qubits), float(h0), _dptr(h), _dptr(g),
+                                                    C.byref(out)))
+        return cls(out)
+
+    @classmethod
+    def from_paulis(cls, n_qubits: int, x, z, coef):
+        x = np.ascontiguousarray(x, dtype=np.uint32)
+        z = np.ascontiguousarray(z, dtype=np.uint32)
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        out = C.c_void_p()
+        _check(lib().vqe_hamiltonian_from_paulis(int(n_qubits), x.size, _u32(x), _u32(z),
+                                                 _dptr(coef), C.byref(out)))
+        return cls(out)
+
+    def info(self):
+        n, t, g = C.c_int(), C.c_int64(), C.c_int64()
+        _check(lib().vqe_hamiltonian_info(self._h, C.byref(n), C.byref(t), C.byref(g)))
+        return n.value, t.value, g.value
+
+    def terms(self):
+        _, t, _ = self.info()
+        x = np.empty(t, np.uint32)
+        z = np.empty(t, np.uint32)
+        c = np.empty(t, np.float64)
+        cnt = C.c_int64(t)
+        _check(lib().vqe_hamiltonian_terms(self._h, C.byref(cnt), _u32(x), _u32(z), _dptr(c)))
+        return x, z, c
+
+    def close(self):
+        if self._h:
+            lib().vqe_hamiltonian_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ansatz:
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def uccsd(cls, n_qubits: int, n_electrons: int):
+        out = C.c_void_p()
+        m = C.c_int32()
+        _check(lib().vqe_ansatz_uccsd(int(n_qubits), int(n_electrons), C.byref(out), C.byref(m)))
+        return cls(out)
+
+    @classmethod
+    def from_rotations(cls, n_qubits: int, n_params: int, x, z, param_index, scale):
+        x = np.ascontiguousarray(x, dtype=np.uint32)
+        z = np.ascontiguousarray(z, dtype=np.uint32)
+        pi = np.ascontiguousarray(param_index, dtype=np.int32)
+        sc = np.ascontiguousarray(scale, dtype=np.float64)
+        out = C.c_void_p()
+        _check(lib().vqe_ansatz_from_rotations(int(n_qubits), int(n_params), x.size, _u32(x), _u32(z),
+                                               pi.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(sc),
+                                               C.byref(out)))
+        return cls(out)
+
+    def info(self):
+        n, p, g, e = C.c_int(), C.c_int32(), C.c_int64(), C.c_int()
+        _check(lib().vqe_ansatz_info(self._h, C.byref(n), C.byref(p), C.byref(g), C.byref(e)))
+        return n.value, p.value, g.value, e.value
+
+    @property
+    def n_params(self) -> int:
+        return self.info()[1]
+
+    def excitations(self):
+        _, _, g, _ = self.info()
+        buf = np.empty(4 * g, np.int32)
+        cnt = C.c_int64(g)
+        _check(lib().vqe_ansatz_excitations(self._h, C.byref(cnt),
+                                            buf.ctypes.data_as(C.POINTER(C.c_int32))))
+        return [tuple(int(v) for v in buf[4 * k:4 * k + 4] if v >= 0) for k in range(cnt.value)]
+
+    def close(self):
+        if self._h:
+            lib().vqe_ansatz_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """Device statevector (complex128[2^n]); library-owned or borrowed from a
+    torch tensor (which must stay alive as long as the State)."""
+
+    def __init__(self, handle, n, keep=None):
+        self._h = handle
+        self.n = n
+        self._keep = keep
+
+    @classmethod
+    def create(cls, n_qubits: int, stream=None):
+        out = C.c_void_p()
+        _check(lib().vqe_state_create(int(n_qubits), stream if stream is not None else current_stream(),
+                                      C.byref(out)))
+        return cls(out, n_qubits)
+
+    @classmethod
+    def wrap(cls, tensor, stream=None):
+        import torch
+        if tensor.dtype != torch.complex128 or not tensor.is_cuda or not tensor.is_contiguous():
+            raise ValueError("need a contiguous complex128 device tensor")
+        n = int(tensor.numel()).bit_length() - 1
+        if (1 << n) != tensor.numel():
+            raise ValueError("length must be a power of two")
+        out = C.c_void_p()
+        _check(lib().vqe_state_wrap(n, C.c_void_p(tensor.data_ptr()),
+                                    stream if stream is not None else current_stream(), C.byref(out)))
+        return cls(out, n, keep=tensor)
+
+    def data_ptr(self) -> int:
+        p = C.c_void_p()
+        _check(lib().vqe_state_data(self._h, C.byref(p)))
+        return p.value
+
+    def prepare_hf(self, n_electrons: int):
+        _check(lib().vqe_prepare_hf(self._h, int(n_electrons)))
+
+    def apply_pauli_rotation(self, x: int, z: int, theta: float):
+        _check(lib().vqe_apply_pauli_rotation(self._h, int(x), int(z), float(theta)))
+
+    def apply_ansatz(self, ansatz: Ansatz, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(lib().vqe_apply_ansatz(self._h, ansatz._h, _dptr(theta)))
+
+    def expectation(self, ham: Hamiltonian) -> float:
+        e = C.c_double()
+        _check(lib().vqe_expectation(self._h, ham._h, C.byref(e)))
+        return e.value
+
+    def close(self):
+        if self._h:
+            lib().vqe_state_free(self._h)
+            self._h = None
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def energy_grad(ham: Hamiltonian, ansatz: Ansatz, n_electrons: int, theta, grad: bool = True,
+                stream=None):
+    """(E, dE/dtheta or None) at theta (float64, n_params)."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    e = C.c_double()
+    g = np.empty(max(theta.size, 1), np.float64) if grad else None
+    _check(lib().vqe_energy_grad(ham._h, ansatz._h, int(n_electrons), _dptr(theta), C.byref(e),
+                                 _dptr(g) if grad else None,
+                                 stream if stream is not None else current_stream()))
+    return e.value, (g[:theta.size] if grad else None)
+
+
+def _energy_grad_fn():
+    import torch
+
+    class EnergyGrad(torch.autograd.Function):
+        """E(theta) with the adjoint gradient; theta is a float64 tensor (any
+        device; it is read on the host).  backward returns gE * dE/dtheta."""
+
+        @staticmethod
+        def forward(ctx, theta, ham, ansatz, n_electrons):
+            th = theta.detach().to("cpu", torch.float64).contiguous().numpy()
+            e, g = energy_grad(ham, ansatz, n_electrons, th, grad=True)
+            ctx.save_for_backward(torch.from_numpy(g).to(theta.device))
+            return torch.tensor(e, dtype=torch.float64, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, ge):
+            (g,) = ctx.saved_tensors
+            return ge * g, None, None, None
+
+    return EnergyGrad
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, item):
+        if _Lazy._cls is None:
+            _Lazy._cls = _energy_grad_fn()
+        return getattr(_Lazy._cls, item)
+
+
+EnergyGrad = _Lazy()
+
+
+class Batch:
+    """Many independent (H, ansatz, n_e) problems evaluated by one HIP-graph
+    launch.  The Hamiltonians and ansatzes must outlive the batch."""
+
+    def __init__(self, hams, ansatzes, n_electrons, stream=None):
+        S = len(hams)
+        self._refs = (list(hams), list(ansatzes))
+        Hs = (C.c_void_p * S)(*[h._h.value for h in hams])
+        As = (C.c_void_p * S)(*[a._h.value for a in ansatzes])
+        ne = (C.c_int * S)(*[int(v) for v in n_electrons])
+        out = C.c_void_p()
+        _check(lib().vqe_batch_create(S, Hs, As, ne, stream if stream is not None else current_stream(),
+                                      C.byref(out)))
+        self._h = out
+        self.S = S
+        offs = np.empty(S + 1, np.int64)
+        _check(lib().vqe_batch_offsets(self._h, offs.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.offsets = offs
+
+    def energy_grad(self, theta_all, grad: bool = True):
+        theta_all = np.ascontiguousarray(theta_all, dtype=np.float64)
+        if theta_all.size != self.offsets[-1]:
+            raise ValueError("theta_all has the wrong length")
+        e = np.empty(self.S, np.float64)
+        g = np.empty(max(theta_all.size, 1), np.float64) if grad else None
+        _check(lib().vqe_batch_energy_grad(self._h, _dptr(theta_all), _dptr(e),
+                                           _dptr(g) if grad else None))
+        return e, (g[:theta_all.size] if grad else None)
+
+    def close(self):
+        if self._h:
+            lib().vqe_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _options(max_iter=200, gtol=1e-8, ftol=0.0, max_seconds=0.0, record_trace=True):
+    return Options(int(max_iter), float(gtol), float(ftol), float(max_seconds), int(bool(record_trace)))
+
+
+def minimize_bfgs(fun, x0, **opts):
+    """BFGS of the library on a Python objective fun(x) -> (f, g).
+    Returns (x, Result, trace)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    n = x0.size
+    o = _options(**opts)
+    err = []
+
+    def cb(ctx, nn, xp, fp, gp):
+        try:
+            x = np.ctypeslib.as_array(xp, shape=(nn,)).copy()
+            f, g = fun(x)
+            fp[0] = float(f)
+            np.ctypeslib.as_array(gp, shape=(nn,))[:] = g
+            return 0
+        except Exception as exc:  # reported as an aborted minimisation
+            err.append(exc)
+            return 1
+
+    cfun = _lib.OBJECTIVE(cb)
+    x = np.empty(n, np.float64)
+    trace = np.empty(o.max_iter + 1, np.float64)
+    res = Result()
+    rc = lib().vqe_minimize_bfgs(n, cfun, None, _dptr(x0), C.byref(o), _dptr(x), _dptr(trace),
+                                 C.byref(res))
+    if err:
+        raise err[0]
+    _check(rc)
+    return x, res, trace
+
+
+def run_vqe(ham: Hamiltonian, ansatz: Ansatz, n_electrons: int, theta0=None, stream=None, **opts):
+    """VQE by BFGS over the library's energy + adjoint gradient.
+    Returns (theta, Result, trace)."""
+    m = ansatz.n_params
+    o = _options(**opts)
+    th0 = None if theta0 is None else np.ascontiguousarray(theta0, dtype=np.float64)
+    x = np.empty(m, np.float64)
+    trace = np.empty(o.max_iter + 1, np.float64)
+    res = Result()
+    _check(lib().vqe_run(ham._h, ansatz._h, int(n_electrons), _dptr(th0) if th0 is not None else None,
+                         C.byref(o), _dptr(x), _dptr(trace), C.byref(res),
+                         stream if stream is not None else current_stream()))
+    return x, res, trace

@@ -1,0 +1,687 @@
+// Host side of the VQE library: error reporting, the Jordan-Wigner builder
+// (Sec. 2.1.1, Eq. 2 and the qubit mapping that follows it), x-mask grouping,
+// the UCCSD program (Sec. 2.1.2), the BFGS optimiser (Sec. 3.1) and the
+// host-only C-ABI entry points.  Nothing in this file calls HIP, so every
+// argument check here runs without a GPU.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace vqe {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+bool finite_all(const double* v, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+static inline int popc(uint32_t v) { return __builtin_popcount(v); }
+static inline uint32_t below(int p) { return (p == 0) ? 0u : ((1u << p) - 1u); }
+
+// ------------------------------------------------------------------ JW algebra
+//
+// Operators are sums of folded strings c X^x Z^z with real c.  In this form
+//   a+_P = 1/2 X_P Z_{<P} (1 + Z_P),   a_P = 1/2 X_P Z_{<P} (1 - Z_P),
+// (a+ = |1><0| on qubit P times the Jordan-Wigner parity of the qubits
+// below), and products follow X^x1 Z^z1 X^x2 Z^z2 = (-1)^{|z1 & x2|} X^{x1^x2} Z^{z1^z2}.
+struct XZ {
+    uint32_t x, z;
+    double c;
+};
+
+static void ladder(int P, bool dagger, XZ out[2]) {
+    const uint32_t e = 1u << P;
+    out[0] = {e, below(P), 0.5};
+    out[1] = {e, below(P) | e, dagger ? 0.5 : -0.5};
+}
+
+static inline XZ mul(const XZ& a, const XZ& b) {
+    double s = (popc(a.z & b.x) & 1) ? -1.0 : 1.0;
+    return {a.x ^ b.x, a.z ^ b.z, a.c * b.c * s};
+}
+
+struct KeyHash {
+    size_t operator()(uint64_t k) const { return std::hash<uint64_t>()(k * 0x9E3779B97F4A7C15ull); }
+};
+using TermMap = std::unordered_map<uint64_t, double, KeyHash>;
+
+static inline uint64_t key(uint32_t x, uint32_t z) { return (uint64_t(x) << 32) | z; }
+
+// Builds the grouped device description from sorted terms.
+static void build_groups(vqe_hamiltonian* H) {
+    H->groups.clear();
+    H->subs.clear();
+    H->tabs.clear();
+    H->diag_group = -1;
+    const size_t T = H->x.size();
+    size_t t0 = 0;
+    while (t0 < T) {
+        size_t t1 = t0;
+        const uint32_t x = H->x[t0];
+        while (t1 < T && H->x[t1] == x) ++t1;
+        GroupDesc gd{};
+        gd.x = x;
+        gd.sub_begin = int32_t(H->subs.size());
+        const int k = popc(x);
+        if (x == 0) H->diag_group = int32_t(H->groups.size());
+        if (k <= kMaxTabBits) {
+            int posv[kMaxTabBits];
+            int kk = 0;
+            for (int q = 0; q < 32; ++q)
+                if ((x >> q) & 1u) posv[kk++] = q;
+            uint32_t pos = uint32_t(k);
+            for (int i = 0; i < k; ++i) pos |= uint32_t(posv[i]) << (3 + 5 * i);
+            gd.pos = pos;
+            std::map<uint32_t, int32_t> sub_of;   // w -> subgroup index
+            for (size_t t = t0; t < t1; ++t) {
+                const uint32_t z = H->z[t];
+                const uint32_t w = z & ~x, v = z & x;
+                auto it = sub_of.find(w);
+                if (it == sub_of.end()) {
+                    SubDesc sd{w, int32_t(H->tabs.size())};
+                    H->tabs.resize(H->tabs.size() + (size_t(1) << k), 0.0);
+                    it = sub_of.emplace(w, int32_t(H->subs.size())).first;
+                    H->subs.push_back(sd);
+                }
+                double* tab = &H->tabs[H->subs[it->second].tab];
+                const double sx = (popc(x & z) & 1) ? -1.0 : 1.0;
+                for (uint32_t u = 0; u < (1u << k); ++u) {
+                    uint32_t bits = 0;  // pattern u deposited on the x positions
+                    for (int i = 0; i < k; ++i)
+                        if ((u >> i) & 1u) bits |= 1u << posv[i];
+                    const double sv = (popc(bits & v) & 1) ? -1.0 : 1.0;
+                    tab[u] += H->c[t] * sx * sv;
+                }
+            }
+        } else {
+            gd.pos = 0;
+            for (size_t t = t0; t < t1; ++t) {
+                const uint32_t z = H->z[t];
+                const double sx = (popc(x & z) & 1) ? -1.0 : 1.0;
+                H->subs.push_back(SubDesc{z, int32_t(H->tabs.size())});
+                H->tabs.push_back(H->c[t] * sx);
+            }
+        }
+        gd.sub_end = int32_t(H->subs.size());
+        H->groups.push_back(gd);
+        t0 = t1;
+    }
+}
+
+static void finish_terms(vqe_hamiltonian* H, const TermMap& m, double drop) {
+    std::vector<std::pair<uint64_t, double>> v;
+    v.reserve(m.size());
+    for (auto& kv : m)
+        if (std::fabs(kv.second) > drop) v.push_back(kv);
+    std::sort(v.begin(), v.end());
+    H->x.resize(v.size());
+    H->z.resize(v.size());
+    H->c.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        H->x[i] = uint32_t(v[i].first >> 32);
+        H->z[i] = uint32_t(v[i].first & 0xffffffffu);
+        H->c[i] = v[i].second;
+    }
+    build_groups(H);
+}
+
+// --------------------------------------------------------------- UCCSD program
+
+// Sign of a ladder-operator string applied (right to left) to the bit
+// pattern `state`, Jordan-Wigner ordering; ops are (orbital, +1 create / -1 annihilate).
+static double string_sign(uint32_t state, const int (*ops)[2], int nops) {
+    double s = 1.0;
+    for (int k = nops - 1; k >= 0; --k) {
+        const int p = ops[k][0];
+        if (popc(state & below(p)) & 1) s = -s;
+        state ^= 1u << p;
+    }
+    return s;
+}
+
+// Gate of exp(theta (T - T^dag)) for T given as a ladder string over the
+// orbitals `occ` (annihilated) and `vir` (created).  Every spectator bit
+// contributes to each operator's parity count, so s(D) factors into a
+// constant (the string applied to D0 = occupied pattern alone) times
+// (-1)^{popcount(D & chain)}, chain = XOR of the below-masks outside x.
+static GateDesc excitation_gate(const int (*ops)[2], int nops, uint32_t occ_mask, uint32_t x,
+                                int32_t param) {
+    GateDesc g{};
+    g.type = kExcitation;
+    g.x = x;
+    g.pd = occ_mask;
+    uint32_t chain = 0;
+    for (int k = 0; k < nops; ++k) chain ^= below(ops[k][0]);
+    g.chain = chain & ~x;
+    g.csign = string_sign(occ_mask, ops, nops);
+    g.param = param;
+    g.scale = 1.0;
+    return g;
+}
+
+}  // namespace vqe
+
+using namespace vqe;
+
+// ============================================================== C ABI (host)
+
+extern "C" int vqe_abi_version(void) { return VQE_ABI_VERSION; }
+
+extern "C" const char* vqe_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h, const double* g,
+                                              vqe_hamiltonian** out) {
+    if (!out || !h || !g) return fail(VQE_EINVAL, "null pointer argument");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (!std::isfinite(h0)) return fail(VQE_EINVAL, "h0 is not finite");
+    const int ns = (n + 1) / 2;
+    const int64_t n2 = int64_t(ns) * ns, n4 = n2 * n2;
+    if (!finite_all(h, n2)) return fail(VQE_EINVAL, "h has a non-finite entry");
+    if (!finite_all(g, n4)) return fail(VQE_EINVAL, "g has a non-finite entry");
+    auto H1 = [&](int p, int q) { return h[p * ns + q]; };
+    auto G = [&](int p, int q, int r, int s) { return g[((int64_t(p) * ns + q) * ns + r) * ns + s]; };
+    const double tol = 1e-12;
+    for (int p = 0; p < ns; ++p)
+        for (int q = 0; q < ns; ++q)
+            if (std::fabs(H1(p, q) - H1(q, p)) > tol)
+                return fail(VQE_EINVAL, "h is not symmetric (h[" + std::to_string(p) + "][" +
+                                            std::to_string(q) + "])");
+    for (int p = 0; p < ns; ++p)
+        for (int q = 0; q < ns; ++q)
+            for (int r = 0; r < ns; ++r)
+                for (int s = 0; s < ns; ++s) {
+                    const double v = G(p, q, r, s);
+                    if (std::fabs(v - G(q, p, r, s)) > tol || std::fabs(v - G(p, q, s, r)) > tol ||
+                        std::fabs(v - G(r, s, p, q)) > tol)
+                        return fail(VQE_EINVAL, "g lacks the 8-fold symmetry of real (pq|rs)");
+                }
+
+    TermMap m;
+    m.reserve(size_t(n) * n * n * n);
+    m[key(0, 0)] += h0;
+    XZ cr[32][2], an[32][2];
+    for (int P = 0; P < n; ++P) {
+        ladder(P, true, cr[P]);
+        ladder(P, false, an[P]);
+    }
+    // one-body: sum_PQ h_pq a+_P a_Q over equal spins
+    for (int P = 0; P < n; ++P)
+        for (int Q = 0; Q < n; ++Q) {
+            if ((P & 1) != (Q & 1)) continue;
+            const double v = H1(P / 2, Q / 2);
+            if (v == 0.0) continue;
+            for (auto& a : cr[P])
+                for (auto& b : an[Q]) {
+                    XZ t = mul(a, b);
+                    m[key(t.x, t.z)] += v * t.c;
+                }
+        }
+    // two-body: 1/2 sum (pq|rs) a+_P a+_R a_S a_Q, P~Q and R~S in spin
+    for (int P = 0; P < n; ++P)
+        for (int R = 0; R < n; ++R) {
+            if (P == R) continue;
+            XZ left[4];
+            int li = 0;
+            for (auto& a : cr[P])
+                for (auto& b : cr[R]) left[li++] = mul(a, b);
+            for (int S = 0; S < n; ++S) {
+                if ((S & 1) != (R & 1)) continue;
+                for (int Q = 0; Q < n; ++Q) {
+                    if ((Q & 1) != (P & 1) || Q == S) continue;
+                    const double v = 0.5 * G(P / 2, Q / 2, R / 2, S / 2);
+                    if (v == 0.0) continue;
+                    for (auto& a : left)
+                        for (auto& b : an[S])
+                            for (auto& c : an[Q]) {
+                                XZ t = mul(mul(a, b), c);
+                                m[key(t.x, t.z)] += v * t.c;
+                            }
+                }
+            }
+        }
+    auto* H = new (std::nothrow) vqe_hamiltonian();
+    if (!H) return fail(VQE_ENOMEM, "host allocation failed");
+    H->n = n;
+    finish_terms(H, m, 1e-12);
+    *out = H;
+    return VQE_OK;
+}
+
+extern "C" int vqe_hamiltonian_from_paulis(int n, int64_t n_terms, const uint32_t* x,
+                                           const uint32_t* z, const double* coef,
+                                           vqe_hamiltonian** out) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (n_terms < 0) return fail(VQE_ERANGE, "n_terms < 0");
+    if (n_terms > 0 && (!x || !z || !coef)) return fail(VQE_EINVAL, "null pointer argument");
+    const uint32_t lim = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    TermMap m;
+    for (int64_t k = 0; k < n_terms; ++k) {
+        if ((x[k] & ~lim) || (z[k] & ~lim))
+            return fail(VQE_ERANGE, "Pauli mask has a bit beyond n_qubits (term " + std::to_string(k) + ")");
+        if (!std::isfinite(coef[k])) return fail(VQE_EINVAL, "non-finite coefficient");
+        m[key(x[k], z[k])] += coef[k];
+    }
+    for (auto& kv : m) {
+        const uint32_t xx = uint32_t(kv.first >> 32), zz = uint32_t(kv.first);
+        if ((popc(xx & zz) & 1) && kv.second != 0.0)
+            return fail(VQE_EINVAL, "term with an odd number of Y factors has a nonzero real folded "
+                                    "coefficient: H would not be Hermitian");
+    }
+    auto* H = new (std::nothrow) vqe_hamiltonian();
+    if (!H) return fail(VQE_ENOMEM, "host allocation failed");
+    H->n = n;
+    finish_terms(H, m, 0.0);
+    *out = H;
+    return VQE_OK;
+}
+
+extern "C" int vqe_hamiltonian_info(const vqe_hamiltonian* H, int* n_qubits, int64_t* n_terms,
+                                    int64_t* n_groups) {
+    if (!H) return fail(VQE_EINVAL, "null Hamiltonian");
+    if (n_qubits) *n_qubits = H->n;
+    if (n_terms) *n_terms = int64_t(H->x.size());
+    if (n_groups) *n_groups = int64_t(H->groups.size());
+    return VQE_OK;
+}
+
+extern "C" int vqe_hamiltonian_terms(const vqe_hamiltonian* H, int64_t* n_terms, uint32_t* x,
+                                     uint32_t* z, double* coef) {
+    if (!H || !n_terms) return fail(VQE_EINVAL, "null pointer argument");
+    const int64_t cnt = int64_t(H->x.size());
+    if (*n_terms < cnt) {
+        *n_terms = cnt;
+        return fail(VQE_ERANGE, "capacity smaller than the term count");
+    }
+    if (cnt > 0 && (!x || !z || !coef)) return fail(VQE_EINVAL, "null output array");
+    std::memcpy(x, H->x.data(), cnt * sizeof(uint32_t));
+    std::memcpy(z, H->z.data(), cnt * sizeof(uint32_t));
+    std::memcpy(coef, H->c.data(), cnt * sizeof(double));
+    *n_terms = cnt;
+    return VQE_OK;
+}
+
+extern "C" void vqe_hamiltonian_free(vqe_hamiltonian* H) { delete H; }
+
+extern "C" int vqe_ansatz_uccsd(int n, int ne, vqe_ansatz** out, int32_t* n_params) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (ne < 0 || ne > n) return fail(VQE_ERANGE, "n_electrons must be in [0, n_qubits]");
+    auto* A = new (std::nothrow) vqe_ansatz();
+    if (!A) return fail(VQE_ENOMEM, "host allocation failed");
+    A->n = n;
+    A->n_electrons = ne;
+    A->sector_conserving = true;
+    int32_t p = 0;
+    // singles: a outer, i inner, equal spin
+    for (int a = ne; a < n; ++a)
+        for (int i = 0; i < ne; ++i) {
+            if ((i & 1) != (a & 1)) continue;
+            const int ops[2][2] = {{a, +1}, {i, -1}};
+            A->gates.push_back(excitation_gate(ops, 2, 1u << i, (1u << i) | (1u << a), p++));
+            A->exc.insert(A->exc.end(), {i, a, -1, -1});
+        }
+    // doubles: (a, b) outer, (i, j) inner, spin-conserving
+    for (int a = ne; a < n; ++a)
+        for (int b = a + 1; b < n; ++b)
+            for (int i = 0; i < ne; ++i)
+                for (int j = i + 1; j < ne; ++j) {
+                    if ((i & 1) + (j & 1) != (a & 1) + (b & 1)) continue;
+                    const int ops[4][2] = {{a, +1}, {b, +1}, {j, -1}, {i, -1}};
+                    const uint32_t occ = (1u << i) | (1u << j);
+                    A->gates.push_back(
+                        excitation_gate(ops, 4, occ, occ | (1u << a) | (1u << b), p++));
+                    A->exc.insert(A->exc.end(), {i, j, a, b});
+                }
+    A->n_params = p;
+    if (n_params) *n_params = p;
+    *out = A;
+    return VQE_OK;
+}
+
+extern "C" int vqe_ansatz_from_rotations(int n, int32_t n_params, int64_t n_rot, const uint32_t* x,
+                                         const uint32_t* z, const int32_t* param_index,
+                                         const double* scale, vqe_ansatz** out) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (n_params < 0 || n_rot < 0) return fail(VQE_ERANGE, "negative size");
+    if (n_rot > 0 && (!x || !z || !param_index || !scale))
+        return fail(VQE_EINVAL, "null pointer argument");
+    const uint32_t lim = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    auto* A = new (std::nothrow) vqe_ansatz();
+    if (!A) return fail(VQE_ENOMEM, "host allocation failed");
+    A->n = n;
+    A->n_params = n_params;
+    for (int64_t k = 0; k < n_rot; ++k) {
+        if ((x[k] & ~lim) || (z[k] & ~lim)) {
+            delete A;
+            return fail(VQE_ERANGE, "rotation mask has a bit beyond n_qubits");
+        }
+        if (param_index[k] < 0 || param_index[k] >= n_params) {
+            delete A;
+            return fail(VQE_ERANGE, "param_index out of range");
+        }
+        if (!std::isfinite(scale[k])) {
+            delete A;
+            return fail(VQE_EINVAL, "non-finite scale");
+        }
+        GateDesc g{};
+        g.type = kPauli;
+        g.x = x[k];
+        g.chain = z[k];
+        g.param = param_index[k];
+        g.scale = scale[k];
+        g.csign = 1.0;
+        A->gates.push_back(g);
+    }
+    *out = A;
+    return VQE_OK;
+}
+
+extern "C" int vqe_ansatz_info(const vqe_ansatz* A, int* n_qubits, int32_t* n_params,
+                               int64_t* n_gates, int* n_electrons) {
+    if (!A) return fail(VQE_EINVAL, "null ansatz");
+    if (n_qubits) *n_qubits = A->n;
+    if (n_params) *n_params = A->n_params;
+    if (n_gates) *n_gates = int64_t(A->gates.size());
+    if (n_electrons) *n_electrons = A->n_electrons;
+    return VQE_OK;
+}
+
+extern "C" int vqe_ansatz_excitations(const vqe_ansatz* A, int64_t* n, int32_t* orbitals) {
+    if (!A || !n) return fail(VQE_EINVAL, "null pointer argument");
+    if (A->n_electrons < 0) return fail(VQE_EINVAL, "not an excitation ansatz");
+    const int64_t cnt = int64_t(A->exc.size() / 4);
+    if (*n < cnt) {
+        *n = cnt;
+        return fail(VQE_ERANGE, "capacity smaller than the excitation count");
+    }
+    if (cnt > 0 && !orbitals) return fail(VQE_EINVAL, "null output array");
+    std::memcpy(orbitals, A->exc.data(), A->exc.size() * sizeof(int32_t));
+    *n = cnt;
+    return VQE_OK;
+}
+
+extern "C" void vqe_ansatz_free(vqe_ansatz* A) { delete A; }
+
+// ================================================================== BFGS
+namespace {
+
+struct Objective {
+    vqe_objective_fn fn;
+    void* ctx;
+    int n;
+    int evals = 0;
+    int status = VQE_OK;
+    bool eval(const double* x, double* f, double* g) {
+        ++evals;
+        const int rc = fn(ctx, n, x, f, g);
+        if (rc != 0) {
+            // keep a message set by the callback's own library call, if any
+            status = (rc < 0) ? rc : VQE_EINVAL;
+            if (g_last_error.empty()) g_last_error = "objective callback failed";
+            return false;
+        }
+        if (!std::isfinite(*f) || !finite_all(g, n)) {
+            status = VQE_ENUMERIC;
+            g_last_error = "objective returned a non-finite value";
+            return false;
+        }
+        return true;
+    }
+};
+
+inline double dot(const std::vector<double>& a, const std::vector<double>& b) {
+    double s = 0.0;
+    for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+    return s;
+}
+
+// Minimiser of the cubic through (a, fa, da) and (b, fb, db); NaN if none.
+double cubic_min(double a, double fa, double da, double b, double fb, double db) {
+    const double d1 = da + db - 3.0 * (fa - fb) / (a - b);
+    const double disc = d1 * d1 - da * db;
+    if (!(disc >= 0.0)) return std::numeric_limits<double>::quiet_NaN();
+    const double d2 = std::copysign(std::sqrt(disc), b - a);
+    const double den = db - da + 2.0 * d2;
+    if (den == 0.0) return std::numeric_limits<double>::quiet_NaN();
+    return b - (b - a) * (db + d2 - d1) / den;
+}
+
+struct LinePoint {
+    double a, f, d;
+    std::vector<double> x, g;
+};
+
+// Strong-Wolfe line search: bracketing phase, then zoom with safeguarded
+// cubic interpolation.  Returns false if no acceptable step was found.
+bool line_search(Objective& obj, const std::vector<double>& x0, double f0,
+                 const std::vector<double>& g0, const std::vector<double>& p, double a_init,
+                 LinePoint& out) {
+    const double c1 = 1e-4, c2 = 0.9;
+    const double d0 = dot(g0, p);
+    // Sufficient decrease is tested with a rounding allowance on f: near a
+    // minimum the predicted decrease drops below the resolution of f, and the
+    // (derivative-based) curvature condition then decides.
+    const double epsf = 0x1p-46 * std::max(1.0, std::fabs(f0));
+    const int n = int(x0.size());
+    auto eval_at = [&](double a, LinePoint& pt) -> bool {
+        pt.a = a;
+        pt.x.resize(n);
+        pt.g.resize(n);
+        for (int i = 0; i < n; ++i) pt.x[i] = x0[i] + a * p[i];
+        if (!obj.eval(pt.x.data(), &pt.f, pt.g.data())) return false;
+        pt.d = dot(pt.g, p);
+        return true;
+    };
+    LinePoint prev{0.0, f0, d0, x0, g0};
+    LinePoint cur;
+    double a = a_init;
+    auto zoom = [&](LinePoint lo, LinePoint hi) -> bool {
+        for (int it = 0; it < 30; ++it) {
+            double aj = cubic_min(lo.a, lo.f, lo.d, hi.a, hi.f, hi.d);
+            const double lo_b = std::min(lo.a, hi.a), hi_b = std::max(lo.a, hi.a);
+            const double w = hi_b - lo_b;
+            if (!std::isfinite(aj) || aj < lo_b + 0.1 * w || aj > hi_b - 0.1 * w)
+                aj = 0.5 * (lo.a + hi.a);
+            LinePoint pj;
+            if (!eval_at(aj, pj)) return false;
+            if (pj.f > f0 + c1 * aj * d0 + epsf || pj.f >= lo.f + epsf) {
+                hi = std::move(pj);
+            } else {
+                if (std::fabs(pj.d) <= -c2 * d0) {
+                    out = std::move(pj);
+                    return true;
+                }
+                if (pj.d * (hi.a - lo.a) >= 0.0) hi = lo;
+                lo = std::move(pj);
+            }
+            if (std::fabs(hi.a - lo.a) < 1e-16 * std::max(1.0, std::fabs(lo.a))) break;
+        }
+        // accept the best sufficient-decrease point seen if the bracket collapsed
+        if (lo.a > 0.0 && lo.f <= f0 + epsf && std::fabs(lo.d) < std::fabs(d0)) {
+            out = std::move(lo);
+            return true;
+        }
+        return false;
+    };
+    for (int it = 0; it < 40; ++it) {
+        if (!eval_at(a, cur)) return false;
+        if (cur.f > f0 + c1 * a * d0 + epsf || (it > 0 && cur.f >= prev.f + epsf))
+            return zoom(prev, cur);
+        if (std::fabs(cur.d) <= -c2 * d0) {
+            out = std::move(cur);
+            return true;
+        }
+        if (cur.d >= 0.0) return zoom(cur, prev);
+        prev = cur;
+        a *= 2.0;
+    }
+    return false;
+}
+
+}  // namespace
+
+extern "C" int vqe_minimize_bfgs(int n, vqe_objective_fn fn, void* ctx, const double* x0,
+                                 const vqe_options* opts, double* x_out, double* trace_out,
+                                 vqe_result* res) {
+    if (!fn || !opts || !x_out || !res) return fail(VQE_EINVAL, "null pointer argument");
+    if (n < 1) return fail(VQE_ERANGE, "n must be >= 1");
+    if (opts->max_iter < 0) return fail(VQE_ERANGE, "max_iter < 0");
+    if (!(opts->gtol >= 0.0) || !(opts->ftol >= 0.0))
+        return fail(VQE_EINVAL, "gtol and ftol must be >= 0");
+    std::vector<double> x(n, 0.0);
+    if (x0) {
+        if (!finite_all(x0, n)) return fail(VQE_EINVAL, "theta0 has a non-finite entry");
+        std::copy(x0, x0 + n, x.begin());
+    }
+    clear_error();
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed = [&]() {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    };
+    if (trace_out)
+        for (int i = 0; i <= opts->max_iter; ++i) trace_out[i] = std::numeric_limits<double>::quiet_NaN();
+    Objective obj{fn, ctx, n};
+    std::vector<double> g(n);
+    double f = 0.0;
+    *res = vqe_result{std::numeric_limits<double>::quiet_NaN(), 0, 0, 0};
+    auto finish = [&](int status, int converged) {
+        std::copy(x.begin(), x.end(), x_out);
+        res->energy = f;
+        res->n_evals = obj.evals;
+        res->converged = converged;
+        return status;
+    };
+    if (!obj.eval(x.data(), &f, g.data())) return finish(obj.status, 0);
+    if (trace_out && opts->record_trace) trace_out[0] = f;
+    std::vector<double> Hinv(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Hinv[size_t(i) * n + i] = 1.0;
+    std::vector<double> p(n), s(n), y(n), Hy(n);
+    int k = 0;
+    auto gmax = [&]() {
+        double m = 0.0;
+        for (double v : g) m = std::max(m, std::fabs(v));
+        return m;
+    };
+    while (true) {
+        if (gmax() <= opts->gtol) return finish(VQE_OK, 1);
+        if (k >= opts->max_iter) return finish(VQE_OK, 0);
+        if (opts->max_seconds > 0.0 && elapsed() > opts->max_seconds) return finish(VQE_OK, 0);
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            const double* row = &Hinv[size_t(i) * n];
+            for (int j = 0; j < n; ++j) acc -= row[j] * g[j];
+            p[i] = acc;
+        }
+        if (dot(p, g) >= 0.0) {  // not a descent direction: restart from steepest descent
+            for (int i = 0; i < n; ++i) {
+                std::fill(&Hinv[size_t(i) * n], &Hinv[size_t(i) * n] + n, 0.0);
+                Hinv[size_t(i) * n + i] = 1.0;
+                p[i] = -g[i];
+            }
+        }
+        LinePoint lp;
+        bool found = line_search(obj, x, f, g, p, 1.0, lp);
+        if (!found && obj.status == VQE_OK) {
+            // retry once along steepest descent with a fresh Hessian model
+            bool identity = true;
+            for (int i = 0; i < n && identity; ++i)
+                for (int j = 0; j < n; ++j)
+                    if (Hinv[size_t(i) * n + j] != (i == j ? 1.0 : 0.0)) {
+                        identity = false;
+                        break;
+                    }
+            if (!identity) {
+                for (int i = 0; i < n; ++i) {
+                    std::fill(&Hinv[size_t(i) * n], &Hinv[size_t(i) * n] + n, 0.0);
+                    Hinv[size_t(i) * n + i] = 1.0;
+                    p[i] = -g[i];
+                }
+                found = line_search(obj, x, f, g, p, 1.0, lp);
+            }
+        }
+        if (!found) {
+            if (obj.status != VQE_OK) return finish(obj.status, 0);
+            return finish(VQE_OK, 0);  // no further progress possible
+        }
+        for (int i = 0; i < n; ++i) {
+            s[i] = lp.x[i] - x[i];
+            y[i] = lp.g[i] - g[i];
+        }
+        const double f_old = f;
+        x = lp.x;
+        g = lp.g;
+        f = lp.f;
+        ++k;
+        res->iters = k;
+        if (trace_out && opts->record_trace) trace_out[k] = f;
+        const double ys = dot(y, s);
+        if (ys > 1e-300) {
+            if (k == 1) {  // rescale H0 = (y's / y'y) I before the first update
+                const double sc = ys / dot(y, y);
+                for (auto& v : Hinv) v *= sc;
+            }
+            const double rho = 1.0 / ys;
+            for (int i = 0; i < n; ++i) {
+                double acc = 0.0;
+                const double* row = &Hinv[size_t(i) * n];
+                for (int j = 0; j < n; ++j) acc += row[j] * y[j];
+                Hy[i] = acc;
+            }
+            const double yHy = dot(y, Hy);
+            // H <- (I - rho s y') H (I - rho y s') + rho s s'
+            //    = H - rho (s Hy' + Hy s') + (rho^2 y'Hy + rho) s s'
+            const double c_ss = rho * rho * yHy + rho;
+            for (int i = 0; i < n; ++i) {
+                double* row = &Hinv[size_t(i) * n];
+                for (int j = 0; j < n; ++j)
+                    row[j] += -rho * (s[i] * Hy[j] + Hy[i] * s[j]) + c_ss * s[i] * s[j];
+            }
+        }
+        if (opts->ftol > 0.0 && std::fabs(f_old - f) <= opts->ftol * std::max(1.0, std::fabs(f_old)))
+            return finish(VQE_OK, 1);
+    }
+}
+
+namespace {
+struct RunCtx {
+    const vqe_hamiltonian* H;
+    const vqe_ansatz* A;
+    int ne;
+    void* stream;
+};
+int run_objective(void* ctx, int n, const double* x, double* f, double* g) {
+    auto* c = static_cast<RunCtx*>(ctx);
+    (void)n;
+    return vqe_energy_grad(c->H, c->A, c->ne, x, f, g, c->stream);
+}
+}  // namespace
+
+extern "C" int vqe_run(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
+                       const double* theta0, const vqe_options* opts, double* theta_out,
+                       double* trace_out, vqe_result* res, void* hip_stream) {
+    if (!H || !A || !opts || !theta_out || !res) return fail(VQE_EINVAL, "null pointer argument");
+    if (A->n_params < 1) return fail(VQE_ERANGE, "ansatz has no parameters");
+    RunCtx ctx{H, A, n_electrons, hip_stream};
+    return vqe_minimize_bfgs(A->n_params, run_objective, &ctx, theta0, opts, theta_out, trace_out,
+                             res);
+}

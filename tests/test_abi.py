@@ -1,0 +1,174 @@
+"""Host-side tests of the C ABI (no GPU): symbols, host builders against the
+oracle, argument validation, and the BFGS optimiser."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2311_01242_amd as vq
+from oracle import fermion as F
+from oracle import pauli as P
+from vqe_inputs import random_integrals
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "vqe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(vqe_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = vq.lib()
+    names = _declared_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(vq._lib.SIGNATURES), "binding and header disagree"
+    assert lib.vqe_abi_version() == 1
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (6, 3), (7, 4), (8, 5), (12, 2)])
+def test_exported_terms_match_oracle_jw(n, seed):
+    h0, h, g = random_integrals(n, seed)
+    H = vq.Hamiltonian.from_integrals(n, 0.3, h, g)
+    x, z, c = H.terms()
+    ref = P.folded_terms(P.jw_hamiltonian(n, 0.3, h, g))
+    got = {(int(a), int(b)): float(v) for a, b, v in zip(x, z, c)}
+    assert set(got) == set(ref)
+    assert max(abs(got[k] - ref[k]) for k in ref) < 1e-12
+    keys = list(zip(x.tolist(), z.tolist()))
+    assert keys == sorted(keys)
+    nq, nt, ng = H.info()
+    assert (nq, nt, ng) == (n, len(ref), len({k[0] for k in ref}))
+
+
+def test_term_counts_at_scale():
+    # structural counts of generic spin-adapted integrals (terms, x-groups)
+    for n, terms, groups in [(4, 27, 4), (12, 1819, 286), (16, 5793, 981), (20, 14251, 2536),
+                             (24, 29737, 5479)]:
+        H = vq.Hamiltonian.from_integrals(n, 0.0, *random_integrals(n, 7)[1:])
+        assert H.info()[1:] == (terms, groups)
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 2), (7, 3), (12, 6), (13, 6), (16, 8), (24, 12)])
+def test_uccsd_program_matches_oracle(n, ne):
+    A = vq.Ansatz.uccsd(n, ne)
+    assert A.excitations() == F.uccsd_excitations(n, ne)
+    assert A.info() == (n, len(F.uccsd_excitations(n, ne)), len(F.uccsd_excitations(n, ne)), ne)
+
+
+def test_from_paulis_merges_and_validates():
+    H = vq.Hamiltonian.from_paulis(3, [1, 1, 0], [0, 0, 4], [0.5, 0.25, -1.0])
+    x, z, c = H.terms()
+    assert list(zip(x.tolist(), z.tolist(), c.tolist())) == [(0, 4, -1.0), (1, 0, 0.75)]
+    # odd number of Y factors (x & z = 1 bit) with a nonzero real folded coefficient
+    with pytest.raises(vq.VQEError) as e:
+        vq.Hamiltonian.from_paulis(2, [1], [1], [0.5])
+    assert e.value.code == vq.VQE_EINVAL
+    with pytest.raises(vq.VQEError) as e:
+        vq.Hamiltonian.from_paulis(2, [4], [0], [0.5])   # bit beyond n
+    assert e.value.code == vq.VQE_ERANGE
+    with pytest.raises(vq.VQEError) as e:
+        vq.Hamiltonian.from_paulis(2, [1], [0], [float("nan")])
+    assert e.value.code == vq.VQE_EINVAL
+
+
+def test_host_argument_errors():
+    h0, h, g = random_integrals(4, 1)
+    lib = vq.lib()
+    out = C.c_void_p()
+    for n in (0, 33):
+        rc = lib.vqe_hamiltonian_from_integrals(n, 0.0, vq._dptr(h), vq._dptr(g), C.byref(out))
+        assert rc == vq.VQE_ERANGE
+    assert lib.vqe_hamiltonian_from_integrals(4, 0.0, None, vq._dptr(g), C.byref(out)) == vq.VQE_EINVAL
+    assert "null" in lib.vqe_last_error().decode()
+    bad = h.copy()
+    bad[0, 1] += 1e-6
+    with pytest.raises(vq.VQEError) as e:
+        vq.Hamiltonian.from_integrals(4, 0.0, bad, g)
+    assert e.value.code == vq.VQE_EINVAL and "symmetric" in str(e.value)
+    bad_g = g.copy()
+    bad_g[0, 1, 0, 0] += 1e-6
+    with pytest.raises(vq.VQEError):
+        vq.Hamiltonian.from_integrals(4, 0.0, h, bad_g)
+    nan_h = h.copy()
+    nan_h[1, 1] = np.nan
+    with pytest.raises(vq.VQEError):
+        vq.Hamiltonian.from_integrals(4, 0.0, nan_h, g)
+    with pytest.raises(vq.VQEError) as e:
+        vq.Ansatz.uccsd(4, 5)
+    assert e.value.code == vq.VQE_ERANGE
+    with pytest.raises(vq.VQEError) as e:
+        vq.Ansatz.from_rotations(3, 2, [1], [0], [2], [1.0])
+    assert e.value.code == vq.VQE_ERANGE
+    # energy_grad rejects bad arguments before touching a device
+    H = vq.Hamiltonian.from_integrals(4, 0.0, h, g)
+    A = vq.Ansatz.uccsd(4, 2)
+    with pytest.raises(vq.VQEError) as e:
+        vq.energy_grad(H, A, 2, [0.1, float("nan"), 0.0], stream=C.c_void_p(0))
+    assert e.value.code == vq.VQE_EINVAL
+    with pytest.raises(vq.VQEError) as e:
+        vq.energy_grad(H, A, 3, [0.0, 0.0, 0.0], stream=C.c_void_p(0))
+    assert e.value.code == vq.VQE_EINVAL
+    H6 = vq.Hamiltonian.from_integrals(6, 0.0, *random_integrals(6, 1)[1:])
+    with pytest.raises(vq.VQEError) as e:
+        vq.energy_grad(H6, A, 2, [0.0, 0.0, 0.0], stream=C.c_void_p(0))
+    assert "qubit counts" in str(e.value)
+
+
+def test_bfgs_quadratic_and_rosenbrock():
+    rng = np.random.default_rng(0)
+    Q = rng.normal(size=(8, 8))
+    Q = Q @ Q.T + 8 * np.eye(8)
+    b = rng.normal(size=8)
+    f = lambda x: (0.5 * x @ Q @ x - b @ x, Q @ x - b)
+    x, res, trace = vq.minimize_bfgs(f, np.zeros(8), max_iter=100, gtol=1e-8)
+    assert res.converged == 1
+    # |x - x*| <= |g| / lambda_min(Q) <= 1e-8 * sqrt(8) / 8
+    assert np.abs(x - np.linalg.solve(Q, b)).max() < 1e-8
+    t = trace[: res.iters + 1]
+    assert np.all(np.diff(t) <= 1e-12)                # Armijo decrease every iteration
+    assert np.all(np.isnan(trace[res.iters + 1:]))
+
+    def rosen(x):
+        f = sum(100 * (x[1:] - x[:-1] ** 2) ** 2 + (1 - x[:-1]) ** 2)
+        g = np.zeros_like(x)
+        g[:-1] = -400 * x[:-1] * (x[1:] - x[:-1] ** 2) - 2 * (1 - x[:-1])
+        g[1:] += 200 * (x[1:] - x[:-1] ** 2)
+        return f, g
+    x, res, _ = vq.minimize_bfgs(rosen, np.array([-1.2, 1.0, -0.5, 0.8]), max_iter=500, gtol=1e-7)
+    assert res.converged == 1 and np.abs(x - 1).max() < 1e-6
+
+
+def test_bfgs_budgets_and_errors():
+    f = lambda x: (float(np.sum((x - 3) ** 2)), 2 * (x - 3))
+    x, res, _ = vq.minimize_bfgs(f, np.zeros(3), max_iter=0)
+    assert res.iters == 0 and res.converged == 0 and res.n_evals == 1
+    nanf = lambda x: (float("nan"), np.zeros_like(x))
+    with pytest.raises(vq.VQEError) as e:
+        vq.minimize_bfgs(nanf, np.zeros(3))
+    assert e.value.code == vq.VQE_ENUMERIC
+    calls = []
+
+    def mid_nan(x):
+        calls.append(1)
+        if len(calls) > 1:
+            return float("nan"), np.zeros_like(x)
+        return f(x)
+    with pytest.raises(vq.VQEError) as e:
+        vq.minimize_bfgs(mid_nan, np.zeros(3) + 10)
+    assert e.value.code == vq.VQE_ENUMERIC
+
+    def boom(x):
+        raise ValueError("objective failed")
+    with pytest.raises(ValueError):
+        vq.minimize_bfgs(boom, np.zeros(2))
+    # wall-clock budget of (nearly) zero: stops at once, not converged, not an error
+    x, res, _ = vq.minimize_bfgs(f, np.zeros(3), max_seconds=1e-12)
+    assert res.converged == 0 and res.iters == 0

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Tolerances: energies and gradients 1e-10 Ha absolute
+(FP64 throughout; the only differences are summation order and FMA
+contraction, ~1e-14 here); amplitudes 1e-12."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2311_01242_amd as vq
+from oracle import fermion as F
+from oracle import pauli as P
+from vqe_inputs import random_integrals, scan_integrals, uniform_theta
+
+pytestmark = pytest.mark.gpu
+
+TOL_E = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+
+
+def _pair(n, ne, seed):
+    h0, h, g = random_integrals(n, seed)
+    return (vq.Hamiltonian.from_integrals(n, h0, h, g), vq.Ansatz.uccsd(n, ne),
+            F.Problem(n, ne, h0, h, g))
+
+
+def _new_state(n):
+    """Statevector borrowed from a torch complex128 tensor (the wrap path)."""
+    import torch
+    t = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    return vq.State.wrap(t), t
+
+
+def _read(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 2), (6, 3), (7, 4), (8, 4), (12, 6), (13, 6)])
+def test_energy_at_theta_zero_is_hf(n, ne):
+    H, A, prob = _pair(n, ne, 100 + n)
+    e, g = vq.energy_grad(H, A, ne, np.zeros(A.n_params))
+    assert abs(e - F.hf_energy_closed_form(n, ne, prob.h0, prob.h, prob.g)) < TOL_E
+    assert np.abs(g - F.grad_at_hf_closed_form(ne, prob.excs, prob.h, prob.g)).max() < TOL_E
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 3), (6, 3), (8, 4), (9, 4), (10, 5)])
+def test_energy_and_gradient_vs_oracle(n, ne):
+    H, A, prob = _pair(n, ne, 200 + n)
+    theta = uniform_theta(300 + n, A.n_params, -0.4, 0.4)
+    e, g = vq.energy_grad(H, A, ne, theta)
+    assert abs(e - prob.energy(theta)) < TOL_E
+    assert np.abs(g - prob.grad_shift(theta)).max() < TOL_E
+    e2, none = vq.energy_grad(H, A, ne, theta, grad=False)
+    assert none is None and abs(e2 - e) < 1e-14
+
+
+def test_gradient_12q_sampled_components_and_fd():
+    h0, h, g = scan_integrals(12, 2)(1.3)
+    H = vq.Hamiltonian.from_integrals(12, h0, h, g)
+    A = vq.Ansatz.uccsd(12, 6)
+    prob = F.Problem(12, 6, h0, h, g)
+    theta = uniform_theta(7, A.n_params)
+    e, grad = vq.energy_grad(H, A, 6, theta)
+    assert abs(e - prob.energy(theta)) < TOL_E
+    idx = sorted(np.random.default_rng(1).choice(A.n_params, 24, replace=False).tolist())
+    assert np.abs(grad[idx] - prob.grad_shift(theta, idx)).max() < TOL_E
+    # adjoint vs central finite differences of the GPU energy, h = 1e-5
+    fd = []
+    for j in idx[:8]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += 1e-5
+        tm[j] -= 1e-5
+        fd.append((vq.energy_grad(H, A, 6, tp, grad=False)[0] -
+                   vq.energy_grad(H, A, 6, tm, grad=False)[0]) / 2e-5)
+    assert np.abs(grad[idx[:8]] - np.array(fd)).max() < 1e-6
+
+
+def test_bitwise_reproducible():
+    H, A, _ = _pair(10, 5, 3)
+    theta = uniform_theta(3, A.n_params)
+    r1 = vq.energy_grad(H, A, 5, theta)
+    r2 = vq.energy_grad(H, A, 5, theta)
+    assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1])
+
+
+@pytest.mark.parametrize("n,ne", [(6, 3), (9, 4)])
+def test_statevector_matches_oracle(n, ne):
+    H, A, prob = _pair(n, ne, 400 + n)
+    theta = uniform_theta(5, A.n_params, -0.5, 0.5)
+    st, t = _new_state(n)
+    st.prepare_hf(ne)
+    st.apply_ansatz(A, theta)
+    arr = _read(t)
+    ref = prob.space.to_statevector(prob.state(theta))
+    assert np.abs(arr - ref).max() < 1e-12
+    assert abs(st.expectation(H) - prob.energy(theta)) < TOL_E
+
+
+def test_rotation_ansatz_matches_excitation_ansatz():
+    n, ne = 6, 3
+    H, A, prob = _pair(n, ne, 17)
+    xs, zs, ps, ss = [], [], [], []
+    for p, exc in enumerate(prob.excs):
+        for x, z, s in P.excitation_rotations(n, exc):
+            xs.append(x); zs.append(z); ps.append(p); ss.append(s)
+    R = vq.Ansatz.from_rotations(n, len(prob.excs), xs, zs, ps, ss)
+    theta = uniform_theta(9, A.n_params, -0.5, 0.5)
+    e1, g1 = vq.energy_grad(H, A, ne, theta)
+    e2, g2 = vq.energy_grad(H, R, ne, theta)
+    assert abs(e1 - e2) < TOL_E and np.abs(g1 - g2).max() < TOL_E
+    assert abs(e2 - prob.energy(theta)) < TOL_E
+    st, t = _new_state(n)
+    st.prepare_hf(ne)
+    st.apply_ansatz(R, theta)
+    arr = _read(t)
+    assert np.abs(arr - P.prepare(n, ne, prob.excs, theta)).max() < 1e-12
+
+
+def test_general_pauli_rotations_and_expectation():
+    """Complex states: arbitrary Pauli rotations (incl. diagonal ones and odd
+    numbers of Y) against the dense-Pauli oracle, then <psi|H|psi>."""
+    n = 7
+    h0, h, g = random_integrals(n, 23)
+    H = vq.Hamiltonian.from_integrals(n, h0, h, g)
+    HP = P.jw_hamiltonian(n, h0, h, g)
+    rng = np.random.default_rng(8)
+    st, t = _new_state(n)
+    st.prepare_hf(3)
+    ref = np.zeros(1 << n, np.complex128)
+    ref[7] = 1.0
+    rots = [(0, 0b101, 0.3), (0b11, 0b10, 0.7), (0b1000001, 0b1000000, -1.1), (0b110, 0b110, 0.4)]
+    rots += [(int(rng.integers(0, 1 << n)), int(rng.integers(0, 1 << n)), float(rng.uniform(-2, 2)))
+             for _ in range(12)]
+    for x, z, ang in rots:
+        st.apply_pauli_rotation(x, z, ang)
+        ref = P.apply_rotation(ref, n, (x, z), ang)
+    arr = _read(t)
+    assert np.abs(arr - ref).max() < 1e-12
+    assert np.abs(ref.imag).max() > 1e-3        # genuinely complex
+    assert abs(st.expectation(H) - P.energy(HP, ref, n)) < TOL_E
+
+
+def test_general_rotation_gradient_vs_fd():
+    n, ne = 5, 2
+    h0, h, g = random_integrals(n, 31)
+    H = vq.Hamiltonian.from_integrals(n, h0, h, g)
+    rng = np.random.default_rng(2)
+    k = 10
+    xs = rng.integers(0, 1 << n, k); zs = rng.integers(0, 1 << n, k)
+    ps = rng.integers(0, 4, k); ss = rng.uniform(-1.5, 1.5, k)
+    R = vq.Ansatz.from_rotations(n, 4, xs, zs, ps, ss)
+    theta = rng.uniform(-1, 1, 4)
+    e, grad = vq.energy_grad(H, R, ne, theta)
+    HP = P.jw_hamiltonian(n, h0, h, g)
+
+    def e_or(t):
+        psi = np.zeros(1 << n, np.complex128)
+        psi[(1 << ne) - 1] = 1
+        for x, z, p, s in zip(xs, zs, ps, ss):
+            psi = P.apply_rotation(psi, n, (int(x), int(z)), s * t[p])
+        return P.energy(HP, psi, n)
+    assert abs(e - e_or(theta)) < TOL_E
+    # central differences of the oracle energy (h = 1e-5)
+    shift = np.zeros(4)
+    for j in range(4):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += 1e-5; tm[j] -= 1e-5
+        shift[j] = (e_or(tp) - e_or(tm)) / 2e-5
+    assert np.abs(grad - shift).max() < 1e-7
+
+
+def test_vqe_run_4q_reaches_fci():
+    h0, h, g = random_integrals(4, 1)
+    H = vq.Hamiltonian.from_integrals(4, h0, h, g)
+    A = vq.Ansatz.uccsd(4, 2)
+    theta, res, trace = vq.run_vqe(H, A, 2, max_iter=50, gtol=1e-8)
+    prob = F.Problem(4, 2, h0, h, g)
+    assert res.converged == 1
+    assert abs(res.energy - prob.fci()) < 1e-9
+    assert abs(trace[0] - F.hf_energy_closed_form(4, 2, h0, h, g)) < TOL_E
+    assert abs(prob.energy(theta) - res.energy) < TOL_E
+
+
+def test_batch_matches_single_state_path():
+    specs = [(4, 2, 1), (6, 3, 2), (6, 3, 3), (7, 3, 4), (8, 4, 5), (6, 3, 6), (9, 4, 7)]
+    Hs, As, probs, thetas = [], [], [], []
+    for n, ne, s in specs:
+        H, A, prob = _pair(n, ne, 500 + s)
+        Hs.append(H); As.append(A); probs.append(prob)
+        thetas.append(uniform_theta(600 + s, A.n_params))
+    b = vq.Batch(Hs, As, [ne for _, ne, _ in specs])
+    flat = np.concatenate(thetas)
+    e, g = b.energy_grad(flat)
+    e2, g2 = b.energy_grad(flat)
+    assert np.array_equal(e, e2) and np.array_equal(g, g2)     # graph replays are bitwise stable
+    for i, (n, ne, _) in enumerate(specs):
+        es, gs = vq.energy_grad(Hs[i], As[i], ne, thetas[i])
+        gi = g[b.offsets[i]:b.offsets[i + 1]]
+        assert e[i] == es and np.array_equal(gi, gs)
+        assert abs(e[i] - probs[i].energy(thetas[i])) < TOL_E
+    # a different theta replays through the same graph
+    e3, _ = b.energy_grad(flat * 0.5)
+    for i in range(len(specs)):
+        assert abs(e3[i] - probs[i].energy(thetas[i] * 0.5)) < TOL_E
+
+
+def test_torch_autograd_function():
+    import torch
+    H, A, prob = _pair(6, 3, 41)
+    th = torch.tensor(uniform_theta(2, A.n_params), dtype=torch.float64, requires_grad=True)
+    E = vq.EnergyGrad.apply(th, H, A, 3)
+    (2.0 * E).backward()
+    assert abs(E.item() - prob.energy(th.detach().numpy())) < TOL_E
+    assert np.abs(th.grad.numpy() - 2.0 * prob.grad_shift(th.detach().numpy())).max() < TOL_E
