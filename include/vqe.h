@@ -188,6 +188,26 @@ int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, double* e_all,
 
 void vqe_batch_free(vqe_batch* b);
 
+/* Phase timing of one evaluation, measured with HIP events on the batch
+ * stream over `reps` eager (not graph) launches of the same kernel sequence:
+ * ms[0] forward sweep (angles, |HF>, gate runs), ms[1] H-apply + energy
+ * partials, ms[2] adjoint reverse sweep, ms[3] reductions; averages in ms. */
+int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps, double* ms);
+
+/* Algorithmic work of one evaluation of the whole batch, from the launch
+ * plan: w[0] forward-sweep bytes (each run tile read and written once, plus
+ * the |HF> write), w[1] reserved (0), w[2] reverse-sweep bytes (phi and
+ * lambda tiles read and written once), w[3] bytes of all phi + lambda. */
+int vqe_batch_work(const vqe_batch* b, double* w);
+
+/* Launch-parameter override for states of n_qubits (batched = 1 for batch
+ * members, 0 for single-state calls): LDS bytes of a forward and a reverse
+ * run tile (4 KiB .. 160 KiB) and the low-bit tile of the sector H-apply
+ * (2 .. 14).  All three <= 0 restores the built-in choice.  Applies to plans
+ * made after the call (batches created later, later single-state calls). */
+int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes, int64_t adj_lds_bytes,
+                   int hx_tile_bits);
+
 /* ---------------------------------------------------------------------------
  * BFGS and the VQE loop
  * ------------------------------------------------------------------------ */

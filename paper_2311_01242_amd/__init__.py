@@ -22,8 +22,15 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "EnergyGrad",
-    "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream",
+    "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
 ]
+
+
+def set_tuning(n_qubits: int, batched: bool, fwd_lds_bytes: int = 0, adj_lds_bytes: int = 0,
+               hx_tile_bits: int = 0):
+    """Override the launch parameters for n_qubits (all zeros: built-in choice)."""
+    _check(lib().vqe_set_tuning(int(n_qubits), int(bool(batched)), int(fwd_lds_bytes),
+                                int(adj_lds_bytes), int(hx_tile_bits)))
 
 
 class VQEError(RuntimeError):
@@ -295,6 +302,20 @@ class Batch:
         _check(lib().vqe_batch_energy_grad(self._h, _dptr(theta_all), _dptr(e),
                                            _dptr(g) if grad else None))
         return e, (g[:theta_all.size] if grad else None)
+
+    def profile(self, theta_all, reps: int = 3):
+        """Per-phase milliseconds of one evaluation (forward, H-apply, adjoint,
+        reductions), timed with HIP events on the batch stream."""
+        theta_all = np.ascontiguousarray(theta_all, dtype=np.float64)
+        ms = np.empty(4, np.float64)
+        _check(lib().vqe_batch_profile(self._h, _dptr(theta_all), int(reps), _dptr(ms)))
+        return ms
+
+    def work(self):
+        """Algorithmic bytes of one evaluation: (forward, 0, adjoint, all phi + lambda)."""
+        w = np.empty(4, np.float64)
+        _check(lib().vqe_batch_work(self._h, _dptr(w)))
+        return w
 
     def close(self):
         if self._h:

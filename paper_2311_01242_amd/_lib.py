@@ -51,6 +51,9 @@ SIGNATURES = {
     "vqe_batch_offsets": (c_int, [vp, P(c_int64)]),
     "vqe_batch_energy_grad": (c_int, [vp, P(c_double), P(c_double), P(c_double)]),
     "vqe_batch_free": (None, [vp]),
+    "vqe_batch_profile": (c_int, [vp, P(c_double), c_int, P(c_double)]),
+    "vqe_batch_work": (c_int, [vp, P(c_double)]),
+    "vqe_set_tuning": (c_int, [c_int, c_int, c_int64, c_int64, c_int]),
     "vqe_minimize_bfgs": (c_int, [c_int, OBJECTIVE, vp, P(c_double), P(Options), P(c_double),
                                   P(c_double), P(Result)]),
     "vqe_run": (c_int, [vp, vp, c_int, P(c_double), P(Options), P(c_double), P(c_double),

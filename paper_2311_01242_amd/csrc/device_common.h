@@ -1,0 +1,178 @@
+// Device-side declarations shared by the kernel translation units and the
+// host glue (vqe_device.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace vqe {
+
+constexpr int kBlock = 256;          // threads per block (4 wave64)
+constexpr int kMaxBlocks = 2048;     // grid-stride cap for the per-gate kernels
+constexpr int kHxOuts = 8;           // in-sector outputs per thread in the sector H-apply
+constexpr int kHxMaxL = 14;          // largest low-bit tile of the sector H-apply
+
+// Per-state record; kernels take their state from blockIdx.y.
+struct StateDesc {
+    double2* phi;            // forward state (overwritten by the reverse sweep)
+    double2* lam;            // lambda = H phi
+    const GateDesc* gates;   // [M]
+    double2* cs;             // [M] (cos, sin) of each gate's angle
+    const double* theta;     // [P]
+    const GroupDesc* groups; // [G]
+    const SubDesc* subs;
+    const double* tabs;
+    const int32_t* xbatch;   // sector H-apply: group range starts per x_hi batch [nb + 1]
+    double* part_e;          // energy partials
+    double* part_g;          // gradient partials [M * gstride]
+    double* out_e;           // [1]
+    double* out_g;           // [M] raw per-gate gradient sums
+    int32_t n, G, M, ne;
+    int32_t nb;              // number of x_hi batches
+    int32_t gstride;         // stride of part_g between gates
+};
+
+// A fused tile pass over consecutive excitation gates [g0, g1) that share
+// their created orbitals `key` (so each pair (D, E) has key bits 0 in D and
+// all 1 in E).  A tile holds, for one value of the `outer` bits, every
+// amplitude with key pattern 0 or `key` and any value of the `inner` bits:
+// element e < 2^m has key pattern 0 and inner bits pdep(e, inner); element
+// 2^m + e has key pattern `key`.
+struct RunDesc {
+    int32_t g0, g1;
+    uint32_t inner, key, outer;
+    int32_t m;               // popcount(inner)
+    int32_t contiguous;      // inner == 2^m - 1 (pdep is the identity)
+    int32_t ntiles;          // 2^popcount(outer)
+    int32_t pad;
+};
+
+// One excitation gate of a run, with its masks compressed into the tile's
+// inner coordinates (r-space).  Sign of pair D: csign * (-1)^{popcount(D & chain)}
+// split into the outer part (uniform per tile) and the r-space part.
+struct TileGate {
+    uint32_t xr, pdr, chr, chain_out;
+    double csign;
+};
+
+// Tables of the sector H-apply for a low tile of L bits (alpha = even bits,
+// beta = odd bits).  unA[offA[k] + i] is the i-th L_alpha-bit string of
+// popcount k (ascending) spread onto the even bits; rankA[s] is the rank of
+// compact string s among strings of its popcount.  Same for beta.
+struct HxTables {
+    int32_t L, La, Lb;
+    int32_t offA[9], offB[9];        // popcount offsets (L_alpha, L_beta <= 7)
+    uint16_t unA[128], unB[128];     // spread strings (L <= 14 bits)
+    uint8_t rankA[128], rankB[128];
+};
+
+static_assert(sizeof(HxTables) % 4 == 0, "HxTables is copied as 32-bit words");
+
+struct HxPlan {
+    int32_t L;
+    int32_t ntiles;          // 2^(n - L)
+    int32_t na, nb;          // electrons per spin
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Fixed-order block sum over kBlock threads; result valid in thread 0.
+// Contains __syncthreads(): every thread of the block must call it.
+__device__ __forceinline__ double block_sum(double v, double* sh4) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh4[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) r += sh4[i];
+    }
+    return r;
+}
+
+// Deposit the bits of t into the positions NOT set in x (zeros at x's bits).
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t t, uint32_t x) {
+    while (x) {
+        const int q = __ffs(x) - 1;
+        x &= x - 1;
+        const uint64_t lo = t & ((uint64_t(1) << q) - 1);
+        t = ((t >> q) << (q + 1)) | lo;
+    }
+    return t;
+}
+
+// Scatter the low bits of v onto the set bits of mask (ascending).
+__device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
+    uint32_t out = 0;
+    while (mask) {
+        const uint32_t low = mask & (~mask + 1u);
+        if (v & 1u) out |= low;
+        v >>= 1;
+        mask &= mask - 1;
+    }
+    return out;
+}
+
+__device__ __forceinline__ double parity_sign(uint32_t v) {
+    return (__popc(v) & 1) ? -1.0 : 1.0;
+}
+
+// Table index: the bits of b at the group's (up to 4) x positions.
+__device__ __forceinline__ uint32_t pext_pos(uint32_t b, uint32_t pos) {
+    const int k = pos & 7;
+    uint32_t u = 0;
+    for (int i = 0; i < k; ++i) u |= ((b >> ((pos >> (3 + 5 * i)) & 31)) & 1u) << i;
+    return u;
+}
+
+// D_g(b) = sum over the group's subgroups of (-1)^{|b & w|} tab[pext(b, x)].
+__device__ __forceinline__ double group_coeff(const GroupDesc& gd, const SubDesc* __restrict__ subs,
+                                              const double* __restrict__ tabs, uint32_t b) {
+    const uint32_t u = pext_pos(b, gd.pos);
+    double d = 0.0;
+    for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+        const SubDesc sub = subs[si];
+        const double t = tabs[sub.tab + u];
+        d += (__popc(b & sub.w) & 1) ? -t : t;
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------- launchers
+// (defined next to their kernels; all asynchronous on `st`)
+
+void launch_angles(const StateDesc* sd, int count, int M, hipStream_t st);
+void launch_hf(const StateDesc* sd, int count, uint64_t N, hipStream_t st);
+void launch_exc(const StateDesc* sd, int count, int j, uint64_t npairs, hipStream_t st);
+void launch_pauli(const StateDesc* sd, int count, int j, uint64_t N, hipStream_t st);
+void launch_adj_exc(const StateDesc* sd, int count, int j, uint64_t npairs, int nblk,
+                    hipStream_t st);
+void launch_adj_pauli(const StateDesc* sd, int count, int j, uint64_t N, int nblk,
+                      hipStream_t st);
+void launch_hx_dense(const StateDesc* sd, int count, uint64_t N, int nblk, int write_lam,
+                     hipStream_t st);
+void launch_reduce_e(const StateDesc* sd, int count, int nblk, hipStream_t st);
+void launch_reduce_g(const StateDesc* sd, int count, int M, const int32_t* cnt, int cnt_uniform,
+                     hipStream_t st);
+void launch_run_fwd(const StateDesc* sd, int count, const RunDesc& run, const TileGate* tg,
+                    hipStream_t st);
+void launch_run_adj(const StateDesc* sd, int count, const RunDesc& run, const TileGate* tg,
+                    hipStream_t st);
+void launch_hx_sector(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
+                      hipStream_t st);
+void launch_fill_zero(double2* p, uint64_t n, hipStream_t st);
+
+int blocks_for(uint64_t work);
+
+}  // namespace vqe

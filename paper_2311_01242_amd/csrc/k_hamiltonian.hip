@@ -1,0 +1,173 @@
+// H-apply kernels: lambda = H phi and the expectation Re <phi|lambda>
+// (Sec. 2.1.1, Eq. 1) for H = sum_k c_k P_k grouped by x-mask.
+//
+// For an x-group g the folded terms act as
+//   lambda[b'] += psi[b' ^ x_g] * D_g(b'),
+//   D_g(b')     = sum_{s in sub(g)} (-1)^{popcount(b' & w_s)} tab_s[pext(b', x_g)],
+// so one gather of psi[b' ^ x_g] serves every z-mask of the group.
+//
+//  k_hx_dense   every output index, every group (any state)
+//  k_hx_sector  only outputs in the (N, S_z) sector of the reference (every
+//               number- and spin-conserving circuit stays there, and H maps the
+//               sector to itself).  Outputs are tiled by their low L bits; for
+//               each x_hi = x >> L batch of groups the partner tile's in-sector
+//               amplitudes are staged compressed in LDS, indexed by the
+//               combinatorial rank of their alpha and beta occupation strings.
+#include "device_common.h"
+
+namespace vqe {
+
+__global__ void __launch_bounds__(kBlock) k_hx_dense(const StateDesc* __restrict__ sd, uint64_t N,
+                                                     int write_lam) {
+    __shared__ double red[kBlock / 64];
+    const StateDesc& s = sd[blockIdx.y];
+    const double2* __restrict__ phi = s.phi;
+    const GroupDesc* __restrict__ groups = s.groups;
+    const int G = s.G;
+    double acc = 0.0;
+    for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < N;
+         b += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t b32 = uint32_t(b);
+        double lr = 0.0, li = 0.0;
+        for (int gi = 0; gi < G; ++gi) {
+            const GroupDesc gd = groups[gi];
+            const double2 p = phi[b ^ gd.x];
+            const double d = group_coeff(gd, s.subs, s.tabs, b32);
+            lr += d * p.x;
+            li += d * p.y;
+        }
+        if (write_lam) s.lam[b] = make_double2(lr, li);
+        const double2 q = phi[b];
+        acc += q.x * lr + q.y * li;
+    }
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) s.part_e[blockIdx.x] = r;
+}
+
+// Bits 0, 2, 4, ... of v packed into bits 0, 1, 2, ... (v < 2^14).
+__device__ __forceinline__ uint32_t compact_even(uint32_t v) {
+    v &= 0x5555u;
+    v = (v | (v >> 1)) & 0x3333u;
+    v = (v | (v >> 2)) & 0x0F0Fu;
+    v = (v | (v >> 4)) & 0x00FFu;
+    return v;
+}
+
+constexpr int kMaxStage = 1225;   // C(7,3) * C(7,4): largest class of a 14-bit tile
+
+__global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restrict__ sd,
+                                                      HxPlan plan,
+                                                      const HxTables* __restrict__ tabsrc) {
+    __shared__ double2 stage[kMaxStage];
+    __shared__ HxTables T;
+    __shared__ double red[kBlock / 64];
+    {   // copy the rank/unrank tables into LDS
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
+        for (int i = threadIdx.x; i < int(sizeof(HxTables) / 4); i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+    const StateDesc& s = sd[blockIdx.y];
+    const double2* __restrict__ phi = s.phi;
+    const GroupDesc* __restrict__ groups = s.groups;
+    const SubDesc* __restrict__ subs = s.subs;
+    const double* __restrict__ tabs = s.tabs;
+    const int L = plan.L;
+    const uint32_t lowmask = (1u << L) - 1u;
+    const uint32_t ohi = uint32_t(blockIdx.x) << L;
+    const int kA = plan.na - __popc(ohi & 0x55555555u);
+    const int kB = plan.nb - __popc(ohi & 0xAAAAAAAAu);
+    if (kA < 0 || kA > T.La || kB < 0 || kB > T.Lb) {   // no in-sector output here
+        if (threadIdx.x == 0) s.part_e[blockIdx.x] = 0.0;
+        return;
+    }
+    const int cB = T.offB[kB + 1] - T.offB[kB];
+    const int cnt = (T.offA[kA + 1] - T.offA[kA]) * cB;
+    uint32_t lo[kHxOuts];
+    double lr[kHxOuts], li[kHxOuts];
+#pragma unroll
+    for (int u = 0; u < kHxOuts; ++u) {
+        const int k = threadIdx.x + u * kBlock;
+        lo[u] = (k < cnt) ? uint32_t(T.unA[T.offA[kA] + k / cB] | T.unB[T.offB[kB] + k % cB]) : 0u;
+        lr[u] = li[u] = 0.0;
+    }
+    for (int bi = 0; bi < s.nb; ++bi) {
+        const int g0 = s.xbatch[bi], g1 = s.xbatch[bi + 1];
+        const uint32_t xhi = groups[g0].x >> L;
+        const uint32_t phi_hi = ohi ^ (xhi << L);
+        const int kA2 = plan.na - __popc(phi_hi & 0x55555555u);
+        const int kB2 = plan.nb - __popc(phi_hi & 0xAAAAAAAAu);
+        if (kA2 < 0 || kA2 > T.La || kB2 < 0 || kB2 > T.Lb) continue;   // partner tile empty
+        const int cB2 = T.offB[kB2 + 1] - T.offB[kB2];
+        const int cnt2 = (T.offA[kA2 + 1] - T.offA[kA2]) * cB2;
+        __syncthreads();   // previous batch done reading the stage
+        for (int k = threadIdx.x; k < cnt2; k += kBlock)
+            stage[k] = phi[phi_hi | T.unA[T.offA[kA2] + k / cB2] | T.unB[T.offB[kB2] + k % cB2]];
+        __syncthreads();
+        for (int gi = g0; gi < g1; ++gi) {
+            const GroupDesc gd = groups[gi];
+            const uint32_t xlo = gd.x & lowmask;
+            double2 p[kHxOuts];
+            uint32_t tb[kHxOuts];
+            double d[kHxOuts];
+            bool ok[kHxOuts];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) {
+                const int k = threadIdx.x + u * kBlock;
+                const uint32_t lp = lo[u] ^ xlo;
+                ok[u] = (k < cnt) && __popc(lp & 0x5555u) == kA2 && __popc(lp & 0xAAAAu) == kB2;
+                p[u] = make_double2(0.0, 0.0);
+                if (ok[u]) {
+                    const int idx = int(T.rankA[compact_even(lp)]) * cB2 +
+                                    int(T.rankB[compact_even(lp >> 1)]);
+                    p[u] = stage[idx];
+                    any = true;
+                }
+                tb[u] = pext_pos(ohi | lo[u], gd.pos);
+                d[u] = 0.0;
+            }
+            if (!__ballot(any)) continue;   // wave-uniform skip
+            for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+                const SubDesc sub = subs[si];
+#pragma unroll
+                for (int u = 0; u < kHxOuts; ++u) {
+                    if (ok[u]) {
+                        const double t = tabs[sub.tab + tb[u]];
+                        d[u] += (__popc((ohi | lo[u]) & sub.w) & 1) ? -t : t;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) {
+                lr[u] += d[u] * p[u].x;
+                li[u] += d[u] * p[u].y;
+            }
+        }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < kHxOuts; ++u) {
+        const int k = threadIdx.x + u * kBlock;
+        if (k < cnt) {
+            const uint32_t b = ohi | lo[u];
+            s.lam[b] = make_double2(lr[u], li[u]);
+            const double2 q = phi[b];
+            acc += q.x * lr[u] + q.y * li[u];
+        }
+    }
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) s.part_e[blockIdx.x] = r;
+}
+
+void launch_hx_dense(const StateDesc* sd, int count, uint64_t N, int nblk, int write_lam,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_hx_dense, dim3(nblk, count), dim3(kBlock), 0, st, sd, N, write_lam);
+}
+
+void launch_hx_sector(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_hx_sector, dim3(plan.ntiles, count), dim3(kBlock), 0, st, sd, plan, tabs);
+}
+
+}  // namespace vqe

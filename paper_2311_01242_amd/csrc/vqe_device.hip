@@ -1,24 +1,16 @@
-// Device side of the VQE library for MI355X (gfx950, wave64): statevector
-// kernels and the C-ABI entry points that launch them.
+// Host glue of the device path: device copies of Hamiltonians and ansatz
+// programs, launch plans, workspaces, the batched HIP-graph evaluation and
+// the device-side C-ABI entry points.  Kernels live in k_gates.hip and
+// k_hamiltonian.hip.
 //
-// Every kernel works on a table of StateDesc records and takes its state
-// from blockIdx.y, so one launch serves a single state or a whole batch of
-// structurally identical states.
-//
-// Kernels (all FP64, complex128 amplitudes as double2):
-//   k_angles      (cos, sin) of every gate angle from the device theta vector
-//   k_hf          |HF> = basis state 2^n_e - 1 (Sec. 2.1.1, Eq. 1 reference)
-//   k_exc         UCCSD excitation gate exp(theta (T - T^dag)) (Sec. 2.1.2):
-//                 Givens rotation on index pairs (D, D ^ x) with Jordan-Wigner
-//                 parity sign (-1)^{popcount(D & chain)}
-//   k_pauli       exp(-i phi/2 P) on pairs (b, b ^ x) with popcount phases
-//   k_hx          lambda = H psi by x-mask groups (one gather of psi[b ^ x]
-//                 serves every z-mask of the group) and per-block partials of
-//                 Re <psi|lambda> (Eq. 1's expectation)
-//   k_adj_*       one reverse-sweep step of the adjoint gradient: partial
-//                 sums of <lambda| dU_j |phi> and U_j^dag on phi and lambda
-//   k_reduce      fixed-order sums of the per-block partials (bitwise
-//                 reproducible: no floating-point atomics anywhere)
+// One evaluation of E(theta) and dE/dtheta (Sec. 2.1.1, Eq. 1; UCCSD of
+// Sec. 2.1.2) is the launch sequence
+//   angles -> |HF> -> forward gate steps -> H-apply + energy partials
+//          -> reverse gate steps (adjoint) -> energy and gradient reductions.
+// Forward and reverse gate steps are fused tile passes over runs of
+// excitations (or single per-gate launches for explicit Pauli rotations).
+// The H-apply is restricted to the (N, S_z) sector of the reference whenever
+// every gate conserves both counts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,303 +19,11 @@
 #include <memory>
 #include <tuple>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace vqe {
 
-constexpr int kBlock = 256;          // threads per block (4 wave64)
-constexpr int kMaxBlocks = 2048;     // grid-stride cap (8 blocks per CU)
-
-struct DevHam {
-    GroupDesc* groups = nullptr;
-    SubDesc* subs = nullptr;
-    double* tabs = nullptr;
-};
-
-struct DevAnsatz {
-    GateDesc* gates = nullptr;
-};
-
-struct StateDesc {
-    double2* phi;            // forward state (overwritten by the reverse sweep)
-    double2* lam;            // lambda = H phi (nullable for energy only)
-    const GateDesc* gates;   // [M]
-    double2* cs;             // [M] (cos, sin) of each gate's angle
-    const double* theta;     // [P]
-    const GroupDesc* groups; // [G]
-    const SubDesc* subs;
-    const double* tabs;
-    double* part_e;          // [nblk_e] energy partials
-    double* part_g;          // [M * nblk_g] gradient partials
-    double* out_e;           // [1]
-    double* out_g;           // [M] raw per-gate gradient sums
-    int32_t n, G, M, ne;
-};
-
-// ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Fixed-order block sum; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[kBlock / 64];
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) r += sh[i];
-    }
-    return r;
-}
-
-// Deposit the bits of t into the positions NOT set in x (zeros at x's bits).
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t t, uint32_t x) {
-    while (x) {
-        const int q = __ffs(x) - 1;
-        x &= x - 1;
-        const uint64_t lo = t & ((uint64_t(1) << q) - 1);
-        t = ((t >> q) << (q + 1)) | lo;
-    }
-    return t;
-}
-
-__device__ __forceinline__ double parity_sign(uint32_t v) {
-    return (__popc(v) & 1) ? -1.0 : 1.0;
-}
-
-// Table index: the bits of b at the group's (up to 4) x positions.
-__device__ __forceinline__ uint32_t pext_pos(uint32_t b, uint32_t pos) {
-    const int k = pos & 7;
-    uint32_t u = 0;
-    for (int i = 0; i < k; ++i) u |= ((b >> ((pos >> (3 + 5 * i)) & 31)) & 1u) << i;
-    return u;
-}
-
-// ------------------------------------------------------------------ kernels
-
-__global__ void k_angles(const StateDesc* __restrict__ sd) {
-    const StateDesc& s = sd[blockIdx.y];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= s.M) return;
-    const GateDesc g = s.gates[j];
-    double a = g.scale * s.theta[g.param];
-    if (g.type == kPauli) a *= 0.5;
-    double sn, c;
-    sincos(a, &sn, &c);
-    s.cs[j] = make_double2(c, sn);
-}
-
-__global__ void k_hf(const StateDesc* __restrict__ sd, uint64_t N) {
-    const StateDesc& s = sd[blockIdx.y];
-    const uint64_t hf = (uint64_t(1) << s.ne) - 1;
-    for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < N;
-         b += uint64_t(gridDim.x) * blockDim.x)
-        s.phi[b] = make_double2(b == hf ? 1.0 : 0.0, 0.0);
-}
-
-// Forward excitation gate j on phi.
-__global__ void k_exc(const StateDesc* __restrict__ sd, int j, uint64_t npairs) {
-    const StateDesc& s = sd[blockIdx.y];
-    const GateDesc g = s.gates[j];
-    const double2 cs = s.cs[j];
-    double2* __restrict__ psi = s.phi;
-    for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t < npairs;
-         t += uint64_t(gridDim.x) * blockDim.x) {
-        const uint64_t D = insert_zeros(t, g.x) | g.pd;
-        const uint64_t E = D ^ g.x;
-        const double ss = g.csign * parity_sign(uint32_t(D) & g.chain) * cs.y;
-        const double2 pd = psi[D], pe = psi[E];
-        psi[D] = make_double2(cs.x * pd.x - ss * pe.x, cs.x * pd.y - ss * pe.y);
-        psi[E] = make_double2(cs.x * pe.x + ss * pd.x, cs.x * pe.y + ss * pd.y);
-    }
-}
-
-// i^y for y = popcount(x & z) mod 4, times -i (the rotation's -i sin factor).
-__device__ __forceinline__ double2 minus_i_times_i_pow(int y) {
-    switch (y & 3) {
-        case 0: return make_double2(0.0, -1.0);
-        case 1: return make_double2(1.0, 0.0);
-        case 2: return make_double2(0.0, 1.0);
-        default: return make_double2(-1.0, 0.0);
-    }
-}
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// psi'[b] = c psi[b] + s f (-1)^{|b' & z|} psi[b'],  f = -i * i^{|x & z|},
-// which is exp(-i phi/2 P) with P|b'> = i^y (-1)^{|b' & z|} |b>.
-// s < 0 gives the inverse rotation.
-__device__ __forceinline__ void pauli_pair(double2* psi, uint64_t b, uint32_t x, uint32_t z,
-                                           double c, double s, double2 f) {
-    const uint64_t bp = b ^ x;
-    const double2 a0 = psi[b], a1 = psi[bp];
-    const double s0 = s * parity_sign(uint32_t(bp) & z);   // factor on psi[b'] -> b
-    const double s1 = s * parity_sign(uint32_t(b) & z);    // factor on psi[b] -> b'
-    const double2 t0 = cmul(f, a1), t1 = cmul(f, a0);
-    psi[b] = make_double2(c * a0.x + s0 * t0.x, c * a0.y + s0 * t0.y);
-    psi[bp] = make_double2(c * a1.x + s1 * t1.x, c * a1.y + s1 * t1.y);
-}
-
-__device__ __forceinline__ void pauli_diag(double2* psi, uint64_t b, uint32_t z, double c,
-                                           double s) {
-    // (c - i s sigma) * psi[b], sigma = (-1)^{|b & z|}
-    const double2 a = psi[b];
-    const double ss = s * parity_sign(uint32_t(b) & z);
-    psi[b] = make_double2(c * a.x + ss * a.y, c * a.y - ss * a.x);
-}
-
-__global__ void k_pauli(const StateDesc* __restrict__ sd, int j, uint64_t N, double dir) {
-    const StateDesc& s = sd[blockIdx.y];
-    const GateDesc g = s.gates[j];
-    const double2 cs = s.cs[j];
-    const double sn = dir * cs.y;
-    const uint32_t x = g.x, z = g.chain;
-    if (x == 0) {
-        for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < N;
-             b += uint64_t(gridDim.x) * blockDim.x)
-            pauli_diag(s.phi, b, z, cs.x, sn);
-        return;
-    }
-    const uint32_t low = x & (~x + 1u);
-    const double2 f = minus_i_times_i_pow(__popc(x & z));
-    for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t < (N >> 1);
-         t += uint64_t(gridDim.x) * blockDim.x)
-        pauli_pair(s.phi, insert_zeros(t, low), x, z, cs.x, sn, f);
-}
-
-// lambda = H phi over the x-groups; partials of Re <phi|lambda>.
-__global__ void __launch_bounds__(kBlock) k_hx(const StateDesc* __restrict__ sd, uint64_t N,
-                                               int write_lam) {
-    const StateDesc& s = sd[blockIdx.y];
-    const double2* __restrict__ phi = s.phi;
-    const GroupDesc* __restrict__ groups = s.groups;
-    const SubDesc* __restrict__ subs = s.subs;
-    const double* __restrict__ tabs = s.tabs;
-    const int G = s.G;
-    double acc = 0.0;
-    for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < N;
-         b += uint64_t(gridDim.x) * blockDim.x) {
-        const uint32_t b32 = uint32_t(b);
-        double lr = 0.0, li = 0.0;
-        for (int gi = 0; gi < G; ++gi) {
-            const GroupDesc gd = groups[gi];
-            const double2 p = phi[b ^ gd.x];
-            const uint32_t u = pext_pos(b32, gd.pos);
-            double d = 0.0;
-            for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
-                const SubDesc sub = subs[si];
-                const double t = tabs[sub.tab + u];
-                d += (__popc(b32 & sub.w) & 1) ? -t : t;
-            }
-            lr += d * p.x;
-            li += d * p.y;
-        }
-        if (write_lam) s.lam[b] = make_double2(lr, li);
-        const double2 q = phi[b];
-        acc += q.x * lr + q.y * li;
-    }
-    const double r = block_sum(acc);
-    if (threadIdx.x == 0) s.part_e[blockIdx.x] = r;
-}
-
-// Reverse-sweep step for excitation gate j: partial of Re <lambda| A_j phi>,
-// then phi <- U_j^dag phi and lambda <- U_j^dag lambda.
-__global__ void __launch_bounds__(kBlock) k_adj_exc(const StateDesc* __restrict__ sd, int j,
-                                                    uint64_t npairs) {
-    const StateDesc& s = sd[blockIdx.y];
-    const GateDesc g = s.gates[j];
-    const double2 cs = s.cs[j];
-    double2* __restrict__ phi = s.phi;
-    double2* __restrict__ lam = s.lam;
-    double acc = 0.0;
-    for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t < npairs;
-         t += uint64_t(gridDim.x) * blockDim.x) {
-        const uint64_t D = insert_zeros(t, g.x) | g.pd;
-        const uint64_t E = D ^ g.x;
-        const double sg = g.csign * parity_sign(uint32_t(D) & g.chain);
-        const double2 fD = phi[D], fE = phi[E], lD = lam[D], lE = lam[E];
-        // A|D> = s|E>, A|E> = -s|D>:  <lam|A phi> = s (lam_E^* phi_D - lam_D^* phi_E)
-        acc += sg * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
-        const double ss = sg * cs.y;   // U^dag = rotation by -theta
-        phi[D] = make_double2(cs.x * fD.x + ss * fE.x, cs.x * fD.y + ss * fE.y);
-        phi[E] = make_double2(cs.x * fE.x - ss * fD.x, cs.x * fE.y - ss * fD.y);
-        lam[D] = make_double2(cs.x * lD.x + ss * lE.x, cs.x * lD.y + ss * lE.y);
-        lam[E] = make_double2(cs.x * lE.x - ss * lD.x, cs.x * lE.y - ss * lD.y);
-    }
-    const double r = block_sum(acc);
-    if (threadIdx.x == 0) s.part_g[size_t(j) * gridDim.x + blockIdx.x] = r;
-}
-
-// Reverse-sweep step for Pauli rotation j: partial of Im <lambda|P phi>,
-// then the inverse rotation on phi and lambda.
-__global__ void __launch_bounds__(kBlock) k_adj_pauli(const StateDesc* __restrict__ sd, int j,
-                                                      uint64_t N) {
-    const StateDesc& s = sd[blockIdx.y];
-    const GateDesc g = s.gates[j];
-    const double2 cs = s.cs[j];
-    double2* __restrict__ phi = s.phi;
-    double2* __restrict__ lam = s.lam;
-    const uint32_t x = g.x, z = g.chain;
-    double acc = 0.0;
-    if (x == 0) {
-        for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < N;
-             b += uint64_t(gridDim.x) * blockDim.x) {
-            const double sg = parity_sign(uint32_t(b) & z);
-            const double2 f = phi[b], l = lam[b];
-            acc += sg * (l.x * f.y - l.y * f.x);   // Im(conj(l) f) * sigma
-            pauli_diag(phi, b, z, cs.x, -cs.y);
-            pauli_diag(lam, b, z, cs.x, -cs.y);
-        }
-    } else {
-        const uint32_t low = x & (~x + 1u);
-        const int y = __popc(x & z) & 3;
-        const double2 iy = (y == 0) ? make_double2(1, 0)
-                         : (y == 1) ? make_double2(0, 1)
-                         : (y == 2) ? make_double2(-1, 0) : make_double2(0, -1);
-        const double2 f = minus_i_times_i_pow(y);
-        for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t < (N >> 1);
-             t += uint64_t(gridDim.x) * blockDim.x) {
-            const uint64_t b = insert_zeros(t, low), bp = b ^ x;
-            const double2 f0 = phi[b], f1 = phi[bp], l0 = lam[b], l1 = lam[bp];
-            // (P phi)[b] = i^y sigma(b') phi[b'],  (P phi)[b'] = i^y sigma(b) phi[b]
-            const double2 p0 = cmul(iy, f1), p1 = cmul(iy, f0);
-            const double s0 = parity_sign(uint32_t(bp) & z), s1 = parity_sign(uint32_t(b) & z);
-            acc += s0 * (l0.x * p0.y - l0.y * p0.x) + s1 * (l1.x * p1.y - l1.y * p1.x);
-            pauli_pair(phi, b, x, z, cs.x, -cs.y, f);
-            pauli_pair(lam, b, x, z, cs.x, -cs.y, f);
-        }
-    }
-    const double r = block_sum(acc);
-    if (threadIdx.x == 0) s.part_g[size_t(j) * gridDim.x + blockIdx.x] = r;
-}
-
-// out[i] = sum_b part[i * nblk + b] in a fixed order; grid (count, states).
-__global__ void __launch_bounds__(kBlock) k_reduce(const StateDesc* __restrict__ sd, int which,
-                                                   int nblk) {
-    const StateDesc& s = sd[blockIdx.y];
-    const int i = blockIdx.x;
-    const double* part = which == 0 ? s.part_e : s.part_g + size_t(i) * nblk;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += part[b];
-    const double r = block_sum(acc);
-    if (threadIdx.x == 0) {
-        if (which == 0)
-            s.out_e[0] = r;
-        else
-            s.out_g[i] = r;
-    }
-}
-
-// ---------------------------------------------------------------- host glue
+int enable_large_lds(size_t bytes);   // k_gates.hip
 
 #define HIPCHK(expr)                                                                        \
     do {                                                                                    \
@@ -333,22 +33,79 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const StateDesc* __restrict__
                                          hipGetErrorString(e_));                            \
     } while (0)
 
-static int blocks_for(uint64_t work) {
-    const uint64_t b = (work + kBlock - 1) / kBlock;
-    return int(std::max<uint64_t>(1, std::min<uint64_t>(b, kMaxBlocks)));
+// ------------------------------------------------------------------ tuning
+
+// Launch parameters of one (qubit count, batched or single) configuration.
+struct Tuning {
+    int64_t fwd_budget;   // LDS bytes of a forward run tile
+    int64_t adj_budget;   // LDS bytes of a reverse run tile (phi + lambda)
+    int L;                // low-bit tile of the sector H-apply
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, Tuning> g_tune;   // (n, batched) -> override
+
+static Tuning default_tuning(int n, bool batched) {
+    Tuning t;
+    t.fwd_budget = (n >= 22) ? (128 << 10) : (64 << 10);
+    t.adj_budget = (n >= 21) ? (128 << 10) : (64 << 10);
+    int L = std::min(n, kHxMaxL);
+    if (!batched) {
+        // a single state should still spread over the CUs: >= 256 output tiles if possible
+        while (L > 10 && (n - L) < 8) --L;
+    }
+    t.L = L;
+    return t;
 }
 
-template <class T>
-static int upload(T** dst, const std::vector<T>& src) {
-    *dst = nullptr;
-    if (src.empty()) return VQE_OK;
-    HIPCHK(hipMalloc(dst, src.size() * sizeof(T)));
-    HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-    return VQE_OK;
+static Tuning tuning_for(int n, bool batched) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({n, batched ? 1 : 0});
+    if (it != g_tune.end()) return it->second;
+    return default_tuning(n, batched);
 }
+
+// ------------------------------------------------------------ device copies
+
+struct AnsatzPlan {
+    int64_t fwd_budget = 0, adj_budget = 0;
+    // step: kind 0 = fused run (index into runs), kind 1 = single gate (gate index)
+    std::vector<std::pair<int, int>> fwd_steps, adj_steps;
+    std::vector<RunDesc> fwd_runs, adj_runs;
+    std::vector<int> fwd_off, adj_off;   // TileGate offset per run
+    TileGate* d_fwd_tg = nullptr;
+    TileGate* d_adj_tg = nullptr;
+    std::vector<int32_t> gcnt;           // gradient partials per gate
+    int32_t* d_gcnt = nullptr;
+    int32_t gstride = 1;
+    size_t max_lds = 0;
+    // algorithmic traffic of one evaluation (bytes) from the tile geometry
+    double fwd_bytes = 0.0, adj_bytes = 0.0;
+};
+
+struct DevHam {
+    GroupDesc* groups = nullptr;
+    SubDesc* subs = nullptr;
+    double* tabs = nullptr;
+    std::map<int, std::pair<int32_t*, int>> xbatch;   // L -> (device starts, count)
+};
+
+struct DevAnsatz {
+    GateDesc* gates = nullptr;
+    std::map<std::pair<int64_t, int64_t>, AnsatzPlan*> plans;
+};
 
 static int current_device(int* dev) {
     HIPCHK(hipGetDevice(dev));
+    return VQE_OK;
+}
+
+template <class T>
+static int upload(T** dst, const T* src, size_t count) {
+    *dst = nullptr;
+    if (count == 0) return VQE_OK;
+    HIPCHK(hipMalloc(dst, count * sizeof(T)));
+    HIPCHK(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
     return VQE_OK;
 }
 
@@ -362,9 +119,9 @@ static int dev_ham(const vqe_hamiltonian* H, DevHam** out) {
         return VQE_OK;
     }
     auto* d = new DevHam();
-    int rc = upload(&d->groups, H->groups);
-    if (!rc) rc = upload(&d->subs, H->subs);
-    if (!rc) rc = upload(&d->tabs, H->tabs);
+    int rc = upload(&d->groups, H->groups.data(), H->groups.size());
+    if (!rc) rc = upload(&d->subs, H->subs.data(), H->subs.size());
+    if (!rc) rc = upload(&d->tabs, H->tabs.data(), H->tabs.size());
     if (rc) {
         (void)hipFree(d->groups);
         (void)hipFree(d->subs);
@@ -374,6 +131,150 @@ static int dev_ham(const vqe_hamiltonian* H, DevHam** out) {
     }
     H->dev[dev] = d;
     *out = d;
+    return VQE_OK;
+}
+
+// Group ranges with equal x >> L (groups are sorted by x).
+static int ham_xbatch(const vqe_hamiltonian* H, DevHam* d, int L, int32_t** out, int* nb) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    auto it = d->xbatch.find(L);
+    if (it != d->xbatch.end()) {
+        *out = it->second.first;
+        *nb = it->second.second;
+        return VQE_OK;
+    }
+    std::vector<int32_t> starts;
+    for (size_t g = 0; g < H->groups.size(); ++g)
+        if (g == 0 || (H->groups[g].x >> L) != (H->groups[g - 1].x >> L)) starts.push_back(int32_t(g));
+    const int cnt = int(starts.size());
+    starts.push_back(int32_t(H->groups.size()));
+    int32_t* p = nullptr;
+    if (int rc = upload(&p, starts.data(), starts.size())) return rc;
+    d->xbatch[L] = {p, cnt};
+    *out = p;
+    *nb = cnt;
+    return VQE_OK;
+}
+
+static uint32_t pext_host(uint32_t v, uint32_t mask) {
+    uint32_t out = 0;
+    int k = 0;
+    for (int q = 0; q < 32; ++q)
+        if ((mask >> q) & 1u) out |= ((v >> q) & 1u) << k++;
+    return out;
+}
+
+// Greedy split of the gate list into fused runs: consecutive excitations with
+// the same created orbitals (key) whose tile of `vectors` statevectors fits
+// `budget` LDS bytes.  The tile's inner bits always include the lowest three
+// qubits (minus key bits) so that loads and stores move whole 128-byte lines.
+static void plan_direction(const vqe_ansatz* A, int64_t budget, int vectors,
+                           std::vector<std::pair<int, int>>& steps, std::vector<RunDesc>& runs,
+                           std::vector<int>& offs, std::vector<TileGate>& tgs, double& bytes) {
+    const int n = A->n;
+    const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
+    const int64_t M = int64_t(A->gates.size());
+    bytes = 0.0;
+    auto tile_bytes = [&](uint32_t inner) {
+        return (int64_t(2) << __builtin_popcount(inner)) * int64_t(sizeof(double2)) * vectors;
+    };
+    int64_t j = 0;
+    while (j < M) {
+        const GateDesc& g = A->gates[j];
+        if (g.type != kExcitation) {
+            steps.push_back({1, int(j)});
+            bytes += 2.0 * vectors * double(sizeof(double2)) * double(uint64_t(1) << n);
+            ++j;
+            continue;
+        }
+        const uint32_t key = g.x & ~g.pd;
+        const uint32_t low = std::min<uint32_t>(7u, full) & ~key;
+        uint32_t inner = (g.pd | low) & ~key;
+        int64_t j2 = j + 1;
+        while (j2 < M) {
+            const GateDesc& h = A->gates[j2];
+            if (h.type != kExcitation || (h.x & ~h.pd) != key) break;
+            const uint32_t cand = inner | h.pd;
+            if (tile_bytes(cand) > budget) break;
+            inner = cand;
+            ++j2;
+        }
+        RunDesc r{};
+        r.g0 = int32_t(j);
+        r.g1 = int32_t(j2);
+        r.inner = inner;
+        r.key = key;
+        r.outer = full & ~inner & ~key;
+        r.m = __builtin_popcount(inner);
+        r.contiguous = (inner == ((1u << r.m) - 1u)) ? 1 : 0;
+        r.ntiles = int32_t(1u << __builtin_popcount(r.outer));
+        offs.push_back(int(tgs.size()));
+        for (int64_t k = j; k < j2; ++k) {
+            const GateDesc& h = A->gates[k];
+            TileGate t{};
+            t.xr = pext_host(h.pd, inner);
+            t.pdr = t.xr;
+            t.chr = pext_host(h.chain & inner, inner);
+            t.chain_out = h.chain & r.outer;
+            t.csign = h.csign;
+            tgs.push_back(t);
+        }
+        steps.push_back({0, int(runs.size())});
+        runs.push_back(r);
+        bytes += 2.0 * double(tile_bytes(inner)) * double(r.ntiles);   // read + write every tile
+        j = j2;
+    }
+}
+
+static int get_plan(const vqe_ansatz* A, DevAnsatz* da, const Tuning& tn, AnsatzPlan** out) {
+    std::lock_guard<std::mutex> lk(A->mu);
+    auto key = std::make_pair(tn.fwd_budget, tn.adj_budget);
+    auto it = da->plans.find(key);
+    if (it != da->plans.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    auto* p = new AnsatzPlan();
+    p->fwd_budget = tn.fwd_budget;
+    p->adj_budget = tn.adj_budget;
+    std::vector<TileGate> tf, ta;
+    plan_direction(A, tn.fwd_budget, 1, p->fwd_steps, p->fwd_runs, p->fwd_off, tf, p->fwd_bytes);
+    plan_direction(A, tn.adj_budget, 2, p->adj_steps, p->adj_runs, p->adj_off, ta, p->adj_bytes);
+    const int n = A->n;
+    const uint64_t N = uint64_t(1) << n;
+    p->fwd_bytes += double(sizeof(double2)) * double(N);   // |HF> write
+    p->gcnt.assign(A->gates.size(), 1);
+    int32_t gstride = 1;
+    for (auto& st : p->adj_steps) {
+        if (st.first == 0) {
+            const RunDesc& r = p->adj_runs[st.second];
+            for (int k = r.g0; k < r.g1; ++k) p->gcnt[k] = r.ntiles;
+            gstride = std::max(gstride, r.ntiles);
+        } else {
+            const int nb = blocks_for(N >> 1);
+            p->gcnt[st.second] = nb;
+            gstride = std::max(gstride, nb);
+        }
+    }
+    p->gstride = gstride;
+    for (auto& r : p->fwd_runs)
+        p->max_lds = std::max(p->max_lds, (size_t(2) << r.m) * sizeof(double2));
+    for (auto& r : p->adj_runs)
+        p->max_lds = std::max(p->max_lds, (size_t(2) << r.m) * sizeof(double2) * 2);
+    int rc = upload(&p->d_fwd_tg, tf.data(), tf.size());
+    if (!rc) rc = upload(&p->d_adj_tg, ta.data(), ta.size());
+    if (!rc) rc = upload(&p->d_gcnt, p->gcnt.data(), p->gcnt.size());
+    if (!rc && p->max_lds > (64u << 10) && enable_large_lds(p->max_lds) != 0)
+        rc = fail(VQE_EDEVICE, "could not enable " + std::to_string(p->max_lds) + " bytes of LDS");
+    if (rc) {
+        (void)hipFree(p->d_fwd_tg);
+        (void)hipFree(p->d_adj_tg);
+        (void)hipFree(p->d_gcnt);
+        delete p;
+        return rc;
+    }
+    da->plans[key] = p;
+    *out = p;
     return VQE_OK;
 }
 
@@ -387,7 +288,7 @@ static int dev_ansatz(const vqe_ansatz* A, DevAnsatz** out) {
         return VQE_OK;
     }
     auto* d = new DevAnsatz();
-    if (int rc = upload(&d->gates, A->gates)) {
+    if (int rc = upload(&d->gates, A->gates.data(), A->gates.size())) {
         delete d;
         return rc;
     }
@@ -396,12 +297,61 @@ static int dev_ansatz(const vqe_ansatz* A, DevAnsatz** out) {
     return VQE_OK;
 }
 
-// Reusable device scratch for single-state evaluations, one per
-// (device, stream); grows, never shrinks.
+// Rank/unrank tables of the sector H-apply, one per (device, L).
+static std::mutex g_hxt_mu;
+static std::map<std::pair<int, int>, HxTables*> g_hxt;
+
+static void fill_tables(int L, HxTables& T) {
+    std::memset(&T, 0, sizeof(T));
+    T.L = L;
+    T.La = (L + 1) / 2;
+    T.Lb = L / 2;
+    auto build = [](int bits, int shift, int32_t* off, uint16_t* un, uint8_t* rank) {
+        int pos = 0;
+        for (int k = 0; k <= bits; ++k) {
+            off[k] = pos;
+            int r = 0;
+            for (uint32_t s = 0; s < (1u << bits); ++s) {
+                if (__builtin_popcount(s) != k) continue;
+                uint32_t spread = 0;
+                for (int i = 0; i < bits; ++i)
+                    if ((s >> i) & 1u) spread |= 1u << (2 * i + shift);
+                un[pos++] = uint16_t(spread);
+                rank[s] = uint8_t(r++);
+            }
+        }
+        for (int k = bits + 1; k <= 8; ++k) off[k] = pos;
+    };
+    build(T.La, 0, T.offA, T.unA, T.rankA);
+    build(T.Lb, 1, T.offB, T.unB, T.rankB);
+}
+
+static int hx_tables(int L, HxTables** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_hxt_mu);
+    auto it = g_hxt.find({dev, L});
+    if (it != g_hxt.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    HxTables T;
+    fill_tables(L, T);
+    HxTables* d = nullptr;
+    if (int rc = upload(&d, &T, 1)) return rc;
+    g_hxt[{dev, L}] = d;
+    *out = d;
+    return VQE_OK;
+}
+
+// ------------------------------------------------------------- workspaces
+
+// Reusable device memory of the single-state path, one per (device, stream).
 struct Workspace {
     size_t state_bytes = 0;
     double2* phi = nullptr;
     double2* lam = nullptr;
+    int64_t lam_zero_key = -1;   // sector for which lambda is zero outside it
     size_t scratch_bytes = 0;
     char* scratch = nullptr;     // theta, cs, partials, outputs, descriptor
 };
@@ -418,21 +368,20 @@ static int fits_device(size_t bytes) {
     return VQE_OK;
 }
 
-static int workspace(void* stream, size_t state_bytes, bool two, size_t scratch_bytes,
-                     Workspace** out) {
+static int workspace(void* stream, size_t state_bytes, size_t scratch_bytes, Workspace** out) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace*& ws = g_ws[{dev, stream}];
     if (!ws) ws = new Workspace();
-    if (ws->state_bytes < state_bytes || (two && !ws->lam)) {
+    if (ws->state_bytes < state_bytes) {
         HIPCHK(hipStreamSynchronize((hipStream_t)stream));
         (void)hipFree(ws->phi);
         (void)hipFree(ws->lam);
         ws->phi = ws->lam = nullptr;
         ws->state_bytes = 0;
-        const size_t need = state_bytes * 2;   // always keep room for lambda
-        if (int rc = fits_device(need)) return rc;
+        ws->lam_zero_key = -1;
+        if (int rc = fits_device(state_bytes * 2)) return rc;
         HIPCHK(hipMalloc(&ws->phi, state_bytes));
         HIPCHK(hipMalloc(&ws->lam, state_bytes));
         ws->state_bytes = state_bytes;
@@ -457,78 +406,100 @@ struct Carver {
     T* take(size_t count) {
         off = (off + 255) & ~size_t(255);
         T* p = reinterpret_cast<T*>(base + off);
-        off += count * sizeof(T);
+        off += std::max<size_t>(count, 1) * sizeof(T);
         return p;
     }
 };
 
-static size_t carve_size(int64_t M, int64_t P, int nblk_e, int nblk_g) {
-    size_t s = 0;
-    auto add = [&](size_t bytes) { s = ((s + 255) & ~size_t(255)) + bytes; };
-    add(sizeof(double) * std::max<int64_t>(P, 1));          // theta
-    add(sizeof(double2) * std::max<int64_t>(M, 1));         // cs
-    add(sizeof(double) * nblk_e);                           // part_e
-    add(sizeof(double) * size_t(std::max<int64_t>(M, 1)) * nblk_g);  // part_g
-    add(sizeof(double));                                    // out_e
-    add(sizeof(double) * std::max<int64_t>(M, 1));          // out_g
-    add(sizeof(StateDesc));
-    return s + 256;
-}
-
-// Launch geometry shared by the single-state and batched paths.
-struct Geometry {
-    uint64_t N;
-    int nblk_e, nblk_g;
+struct ScratchSize {
+    size_t s = 256;
+    template <class T>
+    void add(size_t count) {
+        s = ((s + 255) & ~size_t(255)) + std::max<size_t>(count, 1) * sizeof(T);
+    }
 };
 
-static Geometry geometry(int n) {
-    Geometry g;
-    g.N = uint64_t(1) << n;
-    g.nblk_e = blocks_for(g.N);
-    g.nblk_g = blocks_for(g.N >> 2);
-    return g;
+// -------------------------------------------------------------- evaluation
+
+// What one evaluation of a group of identical-program states needs.
+struct EvalPlan {
+    int n = 0, ne = 0, M = 0;
+    const vqe_ansatz* A = nullptr;
+    AnsatzPlan* ap = nullptr;
+    bool sector = false;
+    HxPlan hx{};
+    HxTables* hxt = nullptr;
+    int nblk_e = 1;          // energy partials per state
+};
+
+static bool sector_path(const vqe_ansatz* A, int ne) {
+    return A->sector_conserving && A->n_electrons == ne;
 }
 
+static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* ep) {
+    const int n = A->n;
+    ep->n = n;
+    ep->ne = ne;
+    ep->M = int(A->gates.size());
+    ep->A = A;
+    const Tuning tn = tuning_for(n, batched);
+    DevAnsatz* da;
+    if (int rc = dev_ansatz(A, &da)) return rc;
+    if (int rc = get_plan(A, da, tn, &ep->ap)) return rc;
+    ep->sector = sector_path(A, ne);
+    if (ep->sector) {
+        ep->hx.L = std::min(n, tn.L);
+        ep->hx.ntiles = 1 << (n - ep->hx.L);
+        ep->hx.na = (ne + 1) / 2;
+        ep->hx.nb = ne / 2;
+        if (int rc = hx_tables(ep->hx.L, &ep->hxt)) return rc;
+        ep->nblk_e = ep->hx.ntiles;
+    } else {
+        ep->nblk_e = blocks_for(uint64_t(1) << n);
+    }
+    return VQE_OK;
+}
 
-// Enqueue one energy (+ gradient) evaluation for `count` consecutive
-// StateDesc records at sd_dev, all with n qubits and the gate program of A.
-static int enqueue_eval(const StateDesc* sd_dev, int count, int n, const vqe_ansatz* A,
-                        bool grad, hipStream_t st) {
-    const Geometry geo = geometry(n);
-    const int64_t M = int64_t(A->gates.size());
-    if (M > 0)
-        hipLaunchKernelGGL(k_angles, dim3(unsigned((M + kBlock - 1) / kBlock), count),
-                           dim3(kBlock), 0, st, sd_dev);
-    hipLaunchKernelGGL(k_hf, dim3(blocks_for(geo.N), count), dim3(kBlock), 0, st, sd_dev, geo.N);
-    for (int64_t j = 0; j < M; ++j) {
-        const GateDesc& g = A->gates[j];
-        if (g.type == kExcitation) {
-            const uint64_t np = geo.N >> __builtin_popcount(g.x);
-            hipLaunchKernelGGL(k_exc, dim3(blocks_for(np), count), dim3(kBlock), 0, st, sd_dev,
-                               int(j), np);
-        } else {
-            hipLaunchKernelGGL(k_pauli, dim3(blocks_for(geo.N >> 1), count), dim3(kBlock), 0, st,
-                               sd_dev, int(j), geo.N, 1.0);
+enum Phase { kPhaseFwd = 0, kPhaseHx = 1, kPhaseAdj = 2, kPhaseReduce = 3 };
+
+// Enqueue one phase of an evaluation for `count` states at sd.
+static void enqueue_phase(const EvalPlan& ep, const StateDesc* sd, int count, int phase, bool grad,
+                          hipStream_t st) {
+    const uint64_t N = uint64_t(1) << ep.n;
+    const AnsatzPlan& ap = *ep.ap;
+    if (phase == kPhaseFwd) {
+        launch_angles(sd, count, ep.M, st);
+        launch_hf(sd, count, N, st);
+        for (auto& s : ap.fwd_steps) {
+            if (s.first == 0)
+                launch_run_fwd(sd, count, ap.fwd_runs[s.second], ap.d_fwd_tg + ap.fwd_off[s.second],
+                               st);
+            else
+                launch_pauli(sd, count, s.second, N, st);
         }
-    }
-    hipLaunchKernelGGL(k_hx, dim3(geo.nblk_e, count), dim3(kBlock), 0, st, sd_dev, geo.N,
-                       grad ? 1 : 0);
-    hipLaunchKernelGGL(k_reduce, dim3(1, count), dim3(kBlock), 0, st, sd_dev, 0, geo.nblk_e);
-    if (grad && M > 0) {
-        for (int64_t j = M - 1; j >= 0; --j) {
-            const GateDesc& g = A->gates[j];
-            if (g.type == kExcitation) {
-                const uint64_t np = geo.N >> __builtin_popcount(g.x);
-                hipLaunchKernelGGL(k_adj_exc, dim3(geo.nblk_g, count), dim3(kBlock), 0, st,
-                                   sd_dev, int(j), np);
-            } else {
-                hipLaunchKernelGGL(k_adj_pauli, dim3(geo.nblk_g, count), dim3(kBlock), 0, st,
-                                   sd_dev, int(j), geo.N);
-            }
+    } else if (phase == kPhaseHx) {
+        if (ep.sector)
+            launch_hx_sector(sd, count, ep.hx, ep.hxt, st);
+        else
+            launch_hx_dense(sd, count, N, ep.nblk_e, grad ? 1 : 0, st);
+    } else if (phase == kPhaseAdj) {
+        if (!grad) return;
+        for (auto it = ap.adj_steps.rbegin(); it != ap.adj_steps.rend(); ++it) {
+            if (it->first == 0)
+                launch_run_adj(sd, count, ap.adj_runs[it->second],
+                               ap.d_adj_tg + ap.adj_off[it->second], st);
+            else
+                launch_adj_pauli(sd, count, it->second, N, ap.gcnt[it->second], st);
         }
-        hipLaunchKernelGGL(k_reduce, dim3(unsigned(M), count), dim3(kBlock), 0, st, sd_dev, 1,
-                           geo.nblk_g);
+    } else {
+        launch_reduce_e(sd, count, ep.nblk_e, st);
+        if (grad) launch_reduce_g(sd, count, ep.M, ap.d_gcnt, 0, st);
     }
+}
+
+static int enqueue_eval(const EvalPlan& ep, const StateDesc* sd, int count, bool grad,
+                        hipStream_t st) {
+    for (int ph = kPhaseFwd; ph <= kPhaseReduce; ++ph) enqueue_phase(ep, sd, count, ph, grad, st);
     HIPCHK(hipGetLastError());
     return VQE_OK;
 }
@@ -552,6 +523,8 @@ static int check_pair(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne) {
     return VQE_OK;
 }
 
+static int64_t sector_key(int n, int ne) { return (int64_t(n) << 16) | ne; }
+
 }  // namespace vqe
 
 using namespace vqe;
@@ -574,6 +547,7 @@ vqe_hamiltonian::~vqe_hamiltonian() {
         (void)hipFree(kv.second->groups);
         (void)hipFree(kv.second->subs);
         (void)hipFree(kv.second->tabs);
+        for (auto& xb : kv.second->xbatch) (void)hipFree(xb.second.first);
         delete kv.second;
     }
     (void)hipSetDevice(cur);
@@ -585,6 +559,12 @@ vqe_ansatz::~vqe_ansatz() {
     for (auto& kv : dev) {
         (void)hipSetDevice(kv.first);
         (void)hipFree(kv.second->gates);
+        for (auto& pl : kv.second->plans) {
+            (void)hipFree(pl.second->d_fwd_tg);
+            (void)hipFree(pl.second->d_adj_tg);
+            (void)hipFree(pl.second->d_gcnt);
+            delete pl.second;
+        }
         delete kv.second;
     }
     (void)hipSetDevice(cur);
@@ -642,23 +622,31 @@ extern "C" void vqe_state_free(vqe_state* s) {
     delete s;
 }
 
-// Small scratch carve for state-level calls: descriptor + a few buffers.
 namespace {
+// Scratch of a state-level call: descriptor plus small buffers.
 struct StateCall {
-    Workspace* ws;
-    Carver cv;
+    Workspace* ws = nullptr;
+    Carver cv{nullptr};
     StateDesc sd{};
-    StateDesc* sd_dev;
+    StateDesc* sd_dev = nullptr;
 };
 
 int begin_state_call(const vqe_state* s, int64_t M, int64_t P, int nblk_e, StateCall* c) {
-    if (int rc = workspace(s->st, 0, false, carve_size(M, P, nblk_e, 1), &c->ws)) return rc;
+    ScratchSize sz;
+    sz.add<double>(P);
+    sz.add<double2>(M);
+    sz.add<GateDesc>(M);
+    sz.add<double>(nblk_e);
+    sz.add<double>(1);
+    sz.add<StateDesc>(1);
+    if (int rc = workspace(s->st, 0, sz.s, &c->ws)) return rc;
     c->cv = Carver{c->ws->scratch};
     std::memset(&c->sd, 0, sizeof(StateDesc));
     c->sd.phi = s->ptr;
     c->sd.n = s->n;
-    c->sd.theta = c->cv.take<double>(std::max<int64_t>(P, 1));
-    c->sd.cs = c->cv.take<double2>(std::max<int64_t>(M, 1));
+    c->sd.gstride = 1;
+    c->sd.theta = c->cv.take<double>(P);
+    c->sd.cs = c->cv.take<double2>(M);
     c->sd.part_e = c->cv.take<double>(nblk_e);
     c->sd.out_e = c->cv.take<double>(1);
     c->sd_dev = c->cv.take<StateDesc>(1);
@@ -673,8 +661,7 @@ extern "C" int vqe_prepare_hf(vqe_state* s, int ne) {
     if (int rc = begin_state_call(s, 0, 0, 1, &c)) return rc;
     c.sd.ne = ne;
     HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
-    const uint64_t N = uint64_t(1) << s->n;
-    hipLaunchKernelGGL(k_hf, dim3(blocks_for(N), 1), dim3(kBlock), 0, s->st, c.sd_dev, N);
+    launch_hf(c.sd_dev, 1, uint64_t(1) << s->n, s->st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->st));
     return VQE_OK;
@@ -700,10 +687,8 @@ extern "C" int vqe_apply_pauli_rotation(vqe_state* s, uint32_t x, uint32_t z, do
     HIPCHK(hipMemcpyAsync(const_cast<double*>(c.sd.theta), &theta, sizeof(double),
                           hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
-    const uint64_t N = uint64_t(1) << s->n;
-    hipLaunchKernelGGL(k_angles, dim3(1, 1), dim3(kBlock), 0, s->st, c.sd_dev);
-    hipLaunchKernelGGL(k_pauli, dim3(blocks_for(N >> 1), 1), dim3(kBlock), 0, s->st, c.sd_dev, 0,
-                       N, 1.0);
+    launch_angles(c.sd_dev, 1, 1, s->st);
+    launch_pauli(c.sd_dev, 1, 0, uint64_t(1) << s->n, s->st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->st));
     return VQE_OK;
@@ -716,6 +701,8 @@ extern "C" int vqe_apply_ansatz(vqe_state* s, const vqe_ansatz* A, const double*
     if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
     DevAnsatz* da;
     if (int rc = dev_ansatz(A, &da)) return rc;
+    AnsatzPlan* ap;
+    if (int rc = get_plan(A, da, tuning_for(A->n, false), &ap)) return rc;
     const int64_t M = int64_t(A->gates.size());
     StateCall c;
     if (int rc = begin_state_call(s, M, A->n_params, 1, &c)) return rc;
@@ -726,19 +713,13 @@ extern "C" int vqe_apply_ansatz(vqe_state* s, const vqe_ansatz* A, const double*
                               hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
     const uint64_t N = uint64_t(1) << s->n;
-    if (M > 0)
-        hipLaunchKernelGGL(k_angles, dim3(unsigned((M + kBlock - 1) / kBlock), 1), dim3(kBlock), 0,
-                           s->st, c.sd_dev);
-    for (int64_t j = 0; j < M; ++j) {
-        const GateDesc& g = A->gates[j];
-        if (g.type == kExcitation) {
-            const uint64_t np = N >> __builtin_popcount(g.x);
-            hipLaunchKernelGGL(k_exc, dim3(blocks_for(np), 1), dim3(kBlock), 0, s->st, c.sd_dev,
-                               int(j), np);
-        } else {
-            hipLaunchKernelGGL(k_pauli, dim3(blocks_for(N >> 1), 1), dim3(kBlock), 0, s->st,
-                               c.sd_dev, int(j), N, 1.0);
-        }
+    launch_angles(c.sd_dev, 1, int(M), s->st);
+    for (auto& st : ap->fwd_steps) {
+        if (st.first == 0)
+            launch_run_fwd(c.sd_dev, 1, ap->fwd_runs[st.second], ap->d_fwd_tg + ap->fwd_off[st.second],
+                           s->st);
+        else
+            launch_pauli(c.sd_dev, 1, st.second, N, s->st);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->st));
@@ -750,16 +731,17 @@ extern "C" int vqe_expectation(const vqe_state* s, const vqe_hamiltonian* H, dou
     if (H->n != s->n) return fail(VQE_EINVAL, "Hamiltonian and state qubit counts differ");
     DevHam* dh;
     if (int rc = dev_ham(H, &dh)) return rc;
-    const Geometry geo = geometry(s->n);
+    const uint64_t N = uint64_t(1) << s->n;
+    const int nblk = blocks_for(N);
     StateCall c;
-    if (int rc = begin_state_call(s, 0, 0, geo.nblk_e, &c)) return rc;
+    if (int rc = begin_state_call(s, 0, 0, nblk, &c)) return rc;
     c.sd.groups = dh->groups;
     c.sd.subs = dh->subs;
     c.sd.tabs = dh->tabs;
     c.sd.G = int32_t(H->groups.size());
     HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
-    hipLaunchKernelGGL(k_hx, dim3(geo.nblk_e, 1), dim3(kBlock), 0, s->st, c.sd_dev, geo.N, 0);
-    hipLaunchKernelGGL(k_reduce, dim3(1, 1), dim3(kBlock), 0, s->st, c.sd_dev, 0, geo.nblk_e);
+    launch_hx_dense(c.sd_dev, 1, N, nblk, 0, s->st);
+    launch_reduce_e(c.sd_dev, 1, nblk, s->st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(energy, c.sd.out_e, sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
@@ -775,40 +757,61 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
     hipStream_t st = (hipStream_t)stream;
     const int n = H->n;
-    const Geometry geo = geometry(n);
     const int64_t M = int64_t(A->gates.size()), P = A->n_params;
     DevHam* dh;
-    DevAnsatz* da;
     if (int rc = dev_ham(H, &dh)) return rc;
+    EvalPlan ep;
+    if (int rc = make_eval_plan(A, ne, false, &ep)) return rc;
+    DevAnsatz* da;
     if (int rc = dev_ansatz(A, &da)) return rc;
+    int32_t* xb = nullptr;
+    int nb = 0;
+    if (ep.sector)
+        if (int rc = ham_xbatch(H, dh, ep.hx.L, &xb, &nb)) return rc;
+    ScratchSize sz;
+    sz.add<double>(P);
+    sz.add<double2>(M);
+    sz.add<double>(ep.nblk_e);
+    sz.add<double>(size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride);
+    sz.add<double>(1);
+    sz.add<double>(M);
+    sz.add<StateDesc>(1);
     Workspace* ws;
-    if (int rc = workspace(stream, sizeof(double2) << n, grad != nullptr,
-                           carve_size(M, P, geo.nblk_e, geo.nblk_g), &ws))
-        return rc;
+    if (int rc = workspace(stream, sizeof(double2) << n, sz.s, &ws)) return rc;
+    // the sector H-apply writes only in-sector entries: lambda must be zero elsewhere
+    if (ep.sector && ws->lam_zero_key != sector_key(n, ne)) {
+        launch_fill_zero(ws->lam, ws->state_bytes / sizeof(double2), st);
+        ws->lam_zero_key = sector_key(n, ne);
+    } else if (!ep.sector) {
+        ws->lam_zero_key = -1;
+    }
     Carver cv{ws->scratch};
     StateDesc sd{};
     sd.phi = ws->phi;
     sd.lam = ws->lam;
     sd.gates = da->gates;
-    sd.theta = cv.take<double>(std::max<int64_t>(P, 1));
-    sd.cs = cv.take<double2>(std::max<int64_t>(M, 1));
+    sd.theta = cv.take<double>(P);
+    sd.cs = cv.take<double2>(M);
     sd.groups = dh->groups;
     sd.subs = dh->subs;
     sd.tabs = dh->tabs;
-    sd.part_e = cv.take<double>(geo.nblk_e);
-    sd.part_g = cv.take<double>(size_t(std::max<int64_t>(M, 1)) * geo.nblk_g);
+    sd.xbatch = xb;
+    sd.part_e = cv.take<double>(ep.nblk_e);
+    sd.part_g = cv.take<double>(size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride);
     sd.out_e = cv.take<double>(1);
-    sd.out_g = cv.take<double>(std::max<int64_t>(M, 1));
+    sd.out_g = cv.take<double>(M);
     sd.n = n;
     sd.G = int32_t(H->groups.size());
     sd.M = int32_t(M);
     sd.ne = ne;
+    sd.nb = nb;
+    sd.gstride = ep.ap->gstride;
     StateDesc* sd_dev = cv.take<StateDesc>(1);
     if (P > 0)
         HIPCHK(hipMemcpyAsync(const_cast<double*>(sd.theta), theta, sizeof(double) * P,
                               hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(sd_dev, &sd, sizeof(StateDesc), hipMemcpyHostToDevice, st));
-    if (int rc = enqueue_eval(sd_dev, 1, n, A, grad != nullptr, st)) return rc;
+    if (int rc = enqueue_eval(ep, sd_dev, 1, grad != nullptr, st)) return rc;
     std::vector<double> raw(std::max<int64_t>(M, 1));
     HIPCHK(hipMemcpyAsync(energy, sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
     if (grad && M > 0)
@@ -828,11 +831,21 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
 struct vqe_batch {
     int S = 0;
     int dev = 0;
-    hipStream_t st = nullptr;
+    hipStream_t user = nullptr;     // caller's stream: evaluations are ordered after its work
+    hipStream_t st = nullptr;       // the batch's own stream (graph capture and launches)
+    hipEvent_t user_ev = nullptr;
     std::vector<const vqe_ansatz*> A;
     std::vector<int64_t> poff;      // parameter offsets [S+1]
     std::vector<int64_t> goff;      // gate offsets [S+1]
-    std::vector<char*> allocs;      // every device allocation
+    std::vector<char*> allocs;      // every device allocation of the batch
+    std::vector<hipStream_t> side;  // fork streams of the graph capture
+    std::vector<hipEvent_t> events;
+    struct Class {
+        EvalPlan ep;
+        int k0 = 0, count = 0;      // slice of the ordered descriptor table
+    };
+    std::vector<Class> classes;
+    StateDesc* sd_dev = nullptr;
     double* theta_dev = nullptr;
     double* e_dev = nullptr;
     double* g_dev = nullptr;        // raw per-gate sums, concatenated
@@ -841,12 +854,17 @@ struct vqe_batch {
     double* g_h = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    double work[4] = {0, 0, 0, 0};  // algorithmic work of one evaluation
     ~vqe_batch() {
         int cur = 0;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(dev);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t s : side) (void)hipStreamDestroy(s);
+        if (user_ev) (void)hipEventDestroy(user_ev);
+        if (st) (void)hipStreamDestroy(st);
         for (char* p : allocs) (void)hipFree(p);
         (void)hipHostFree(theta_h);
         (void)hipHostFree(e_h);
@@ -857,7 +875,8 @@ struct vqe_batch {
 
 namespace {
 bool same_program(const vqe_ansatz* a, const vqe_ansatz* b) {
-    return a->n == b->n && a->n_params == b->n_params && a->gates.size() == b->gates.size() &&
+    return a->n == b->n && a->n_params == b->n_params && a->n_electrons == b->n_electrons &&
+           a->sector_conserving == b->sector_conserving && a->gates.size() == b->gates.size() &&
            std::memcmp(a->gates.data(), b->gates.data(), a->gates.size() * sizeof(GateDesc)) == 0;
 }
 
@@ -870,6 +889,23 @@ int dalloc(vqe_batch* b, T** p, size_t count) {
                     std::string("batch allocation: ") + hipGetErrorString(e));
     b->allocs.push_back(static_cast<char*>(q));
     *p = static_cast<T*>(q);
+    return VQE_OK;
+}
+
+// One full evaluation of every class; classes run on forked streams.
+int enqueue_batch(vqe_batch* b) {
+    const size_t C = b->classes.size();
+    const size_t ns = b->side.size();
+    HIPCHK(hipEventRecord(b->events[0], b->st));
+    for (size_t i = 0; i < ns; ++i) HIPCHK(hipStreamWaitEvent(b->side[i], b->events[0], 0));
+    for (size_t i = 0; i < C; ++i) {
+        auto& c = b->classes[i];
+        if (int rc = enqueue_eval(c.ep, b->sd_dev + c.k0, c.count, true, b->side[i % ns])) return rc;
+    }
+    for (size_t i = 0; i < ns; ++i) {
+        HIPCHK(hipEventRecord(b->events[1 + i], b->side[i]));
+        HIPCHK(hipStreamWaitEvent(b->st, b->events[1 + i], 0));
+    }
     return VQE_OK;
 }
 }  // namespace
@@ -889,8 +925,11 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     auto* b = new vqe_batch();
     std::unique_ptr<vqe_batch> guard(b);
     b->S = S;
-    b->st = (hipStream_t)stream;
+    b->user = (hipStream_t)stream;
     HIPCHK(hipGetDevice(&b->dev));
+    HIPCHK(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->user_ev, hipEventDisableTiming));
+    HIPCHK(hipStreamSynchronize(b->user));
     b->A.assign(A, A + S);
     b->poff.assign(S + 1, 0);
     b->goff.assign(S + 1, 0);
@@ -898,12 +937,11 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         b->poff[i + 1] = b->poff[i] + A[i]->n_params;
         b->goff[i + 1] = b->goff[i] + int64_t(A[i]->gates.size());
     }
-    // classes: states with equal qubit count and identical gate programs
+    // classes: states with identical gate programs and references
     std::vector<int> cls(S, -1), rep;
     for (int i = 0; i < S; ++i) {
         for (size_t c = 0; c < rep.size(); ++c)
-            if (same_program(A[rep[c]], A[i]) && A[rep[c]]->n_electrons == A[i]->n_electrons &&
-                ne[rep[c]] == ne[i]) {
+            if (same_program(A[rep[c]], A[i]) && ne[rep[c]] == ne[i]) {
                 cls[i] = int(c);
                 break;
             }
@@ -912,21 +950,26 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             rep.push_back(i);
         }
     }
+    std::vector<int> order(S);
+    for (int i = 0; i < S; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cls[a] < cls[c]; });
+    b->classes.resize(rep.size());
+    for (size_t c = 0; c < rep.size(); ++c)
+        if (int rc = make_eval_plan(A[rep[c]], ne[rep[c]], true, &b->classes[c].ep)) return rc;
     if (int rc = dalloc(b, &b->theta_dev, b->poff[S])) return rc;
     if (int rc = dalloc(b, &b->e_dev, S)) return rc;
     if (int rc = dalloc(b, &b->g_dev, b->goff[S])) return rc;
     HIPCHK(hipHostMalloc(&b->theta_h, sizeof(double) * std::max<int64_t>(b->poff[S], 1)));
     HIPCHK(hipHostMalloc(&b->e_h, sizeof(double) * S));
     HIPCHK(hipHostMalloc(&b->g_h, sizeof(double) * std::max<int64_t>(b->goff[S], 1)));
-    // descriptors, ordered by class so each class is one contiguous slice
-    std::vector<int> order(S);
-    for (int i = 0; i < S; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cls[a] < cls[c]; });
     std::vector<StateDesc> sds(S);
     for (int k = 0; k < S; ++k) {
         const int i = order[k];
+        auto& cl = b->classes[cls[i]];
+        if (cl.count == 0) cl.k0 = k;
+        ++cl.count;
+        const EvalPlan& ep = cl.ep;
         const int n = H[i]->n;
-        const Geometry geo = geometry(n);
         const int64_t M = int64_t(A[i]->gates.size());
         DevHam* dh;
         DevAnsatz* da;
@@ -934,11 +977,18 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         if (int rc = dev_ansatz(A[i], &da)) return rc;
         StateDesc& sd = sds[k];
         std::memset(&sd, 0, sizeof(sd));
+        if (ep.sector) {
+            int32_t* xb = nullptr;
+            if (int rc = ham_xbatch(H[i], dh, ep.hx.L, &xb, &sd.nb)) return rc;
+            sd.xbatch = xb;
+        }
         if (int rc = dalloc(b, &sd.phi, size_t(1) << n)) return rc;
         if (int rc = dalloc(b, &sd.lam, size_t(1) << n)) return rc;
-        if (int rc = dalloc(b, &sd.cs, std::max<int64_t>(M, 1))) return rc;
-        if (int rc = dalloc(b, &sd.part_e, geo.nblk_e)) return rc;
-        if (int rc = dalloc(b, &sd.part_g, size_t(std::max<int64_t>(M, 1)) * geo.nblk_g)) return rc;
+        launch_fill_zero(sd.lam, uint64_t(1) << n, b->st);
+        if (int rc = dalloc(b, &sd.cs, M)) return rc;
+        if (int rc = dalloc(b, &sd.part_e, ep.nblk_e)) return rc;
+        if (int rc = dalloc(b, &sd.part_g, size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride))
+            return rc;
         sd.gates = da->gates;
         sd.theta = b->theta_dev + b->poff[i];
         sd.groups = dh->groups;
@@ -950,22 +1000,31 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         sd.G = int32_t(H[i]->groups.size());
         sd.M = int32_t(M);
         sd.ne = ne[i];
+        sd.gstride = ep.ap->gstride;
+        b->work[0] += ep.ap->fwd_bytes;
+        b->work[2] += ep.ap->adj_bytes;
+        b->work[3] += 2.0 * double(sizeof(double2)) * double(uint64_t(1) << n);
     }
-    StateDesc* sd_dev;
-    if (int rc = dalloc(b, &sd_dev, S)) return rc;
-    HIPCHK(hipMemcpy(sd_dev, sds.data(), sizeof(StateDesc) * S, hipMemcpyHostToDevice));
-    // capture one evaluation of every class into a graph
+    HIPCHK(hipGetLastError());
+    if (int rc = dalloc(b, &b->sd_dev, S)) return rc;
+    HIPCHK(hipMemcpy(b->sd_dev, sds.data(), sizeof(StateDesc) * S, hipMemcpyHostToDevice));
+    HIPCHK(hipStreamSynchronize(b->st));
+    const int nside = int(std::min<size_t>(b->classes.size(), 4));
+    for (int i = 0; i < nside; ++i) {
+        hipStream_t s;
+        HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->side.push_back(s);
+    }
+    for (int i = 0; i < nside + 1; ++i) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->events.push_back(e);
+    }
     HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-    int k0 = 0;
-    int cap_rc = VQE_OK;
-    while (k0 < S && cap_rc == VQE_OK) {
-        int k1 = k0;
-        while (k1 < S && cls[order[k1]] == cls[order[k0]]) ++k1;
-        const vqe_ansatz* a = A[order[k0]];
-        cap_rc = enqueue_eval(sd_dev + k0, k1 - k0, a->n, a, true, b->st);
-        k0 = k1;
-    }
-    hipError_t ce = hipStreamEndCapture(b->st, &b->graph);
+    const int cap_rc = enqueue_batch(b);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->st, &graph);
+    b->graph = graph;
     if (cap_rc) return cap_rc;
     HIPCHK(ce);
     HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -979,18 +1038,28 @@ extern "C" int vqe_batch_offsets(const vqe_batch* b, int64_t* offsets) {
     return VQE_OK;
 }
 
-extern "C" int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, double* e_all,
-                                     double* g_all) {
-    if (!b || !e_all) return fail(VQE_EINVAL, "null pointer argument");
+static int batch_upload_theta(vqe_batch* b, const double* theta_all) {
     const int64_t P = b->poff[b->S];
     if (P > 0 && !theta_all) return fail(VQE_EINVAL, "null theta_all");
     if (!finite_all(theta_all, P)) return fail(VQE_EINVAL, "theta_all has a non-finite entry");
     int cur = 0;
     HIPCHK(hipGetDevice(&cur));
     if (cur != b->dev) return fail(VQE_EINVAL, "batch belongs to another device");
+    // order after the caller's pending work, and do not overwrite the pinned
+    // staging buffer while a previous upload could still read it
+    HIPCHK(hipEventRecord(b->user_ev, b->user));
+    HIPCHK(hipStreamWaitEvent(b->st, b->user_ev, 0));
+    HIPCHK(hipStreamSynchronize(b->st));
     std::memcpy(b->theta_h, theta_all, sizeof(double) * P);
     HIPCHK(hipMemcpyAsync(b->theta_dev, b->theta_h, sizeof(double) * P, hipMemcpyHostToDevice,
                           b->st));
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, double* e_all,
+                                     double* g_all) {
+    if (!b || !e_all) return fail(VQE_EINVAL, "null pointer argument");
+    if (int rc = batch_upload_theta(b, theta_all)) return rc;
     HIPCHK(hipGraphLaunch(b->exec, b->st));
     HIPCHK(hipMemcpyAsync(b->e_h, b->e_dev, sizeof(double) * b->S, hipMemcpyDeviceToHost, b->st));
     if (g_all)
@@ -1000,10 +1069,67 @@ extern "C" int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, doub
     std::memcpy(e_all, b->e_h, sizeof(double) * b->S);
     bool ok = finite_all(e_all, b->S);
     if (g_all) {
-        for (int i = 0; i < b->S; ++i) accumulate_grad(b->A[i], b->g_h + b->goff[i], g_all + b->poff[i]);
-        ok = ok && finite_all(g_all, P);
+        for (int i = 0; i < b->S; ++i)
+            accumulate_grad(b->A[i], b->g_h + b->goff[i], g_all + b->poff[i]);
+        ok = ok && finite_all(g_all, b->poff[b->S]);
     }
     if (!ok) return fail(VQE_ENUMERIC, "non-finite energy or gradient");
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps, double* ms) {
+    if (!b || !ms) return fail(VQE_EINVAL, "null pointer argument");
+    if (reps < 1) return fail(VQE_ERANGE, "reps must be >= 1");
+    if (int rc = batch_upload_theta(b, theta_all)) return rc;
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    double acc[4] = {0, 0, 0, 0};
+    int rc = VQE_OK;
+    for (int r = 0; r < reps && rc == VQE_OK; ++r) {
+        (void)hipEventRecord(ev[0], b->st);
+        for (int ph = kPhaseFwd; ph <= kPhaseReduce; ++ph) {
+            for (auto& c : b->classes) enqueue_phase(c.ep, b->sd_dev + c.k0, c.count, ph, true, b->st);
+            (void)hipEventRecord(ev[ph + 1], b->st);
+        }
+        hipError_t e = hipEventSynchronize(ev[4]);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) {
+            rc = fail(VQE_EDEVICE, std::string("profile: ") + hipGetErrorString(e));
+            break;
+        }
+        for (int ph = 0; ph < 4; ++ph) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev[ph], ev[ph + 1]);
+            acc[ph] += t;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    for (int ph = 0; ph < 4; ++ph) ms[ph] = acc[ph] / reps;
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_work(const vqe_batch* b, double* work) {
+    if (!b || !work) return fail(VQE_EINVAL, "null pointer argument");
+    std::copy(b->work, b->work + 4, work);
+    return VQE_OK;
+}
+
+extern "C" int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes,
+                              int64_t adj_lds_bytes, int hx_tile_bits) {
+    if (n_qubits < 1 || n_qubits > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto key = std::make_pair(n_qubits, batched ? 1 : 0);
+    if (fwd_lds_bytes <= 0 && adj_lds_bytes <= 0 && hx_tile_bits <= 0) {
+        g_tune.erase(key);   // back to the built-in heuristic
+        return VQE_OK;
+    }
+    if (fwd_lds_bytes < 4096 || fwd_lds_bytes > (160 << 10) || adj_lds_bytes < 4096 ||
+        adj_lds_bytes > (160 << 10))
+        return fail(VQE_ERANGE, "LDS budgets must be in [4 KiB, 160 KiB]");
+    if (hx_tile_bits < 2 || hx_tile_bits > kHxMaxL)
+        return fail(VQE_ERANGE, "hx_tile_bits must be in [2, 14]");
+    g_tune[key] = Tuning{fwd_lds_bytes, adj_lds_bytes, hx_tile_bits};
     return VQE_OK;
 }
 
