@@ -39,6 +39,9 @@ def _parse():
     ap.add_argument("--states", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 2 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -104,10 +107,21 @@ def cpu_baseline_batch(spec, budget_s=20.0):
             "sample": sample}
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_2311_01242_amd", "tuning_cache.json")
+
+
 def run_batch(args):
     import torch
     import paper_2311_01242_amd as vq
+    from paper_2311_01242_amd import autotune
     spec, Hs, As, nes, theta = build_batch(args.states)
+    if not args.no_autotune:
+        offs = np.cumsum([0] + [a.n_params for a in As])
+        t0 = time.perf_counter()
+        tuned = autotune.autotune_batch(Hs, As, nes, theta, offs, cache=TUNE_CACHE)
+        print(f"# autotune {time.perf_counter() - t0:.1f}s: "
+              + " ".join(f"n{n}=({f >> 10}K,{a >> 10}K,L{L})" for n, (f, a, L) in sorted(tuned.items())),
+              file=sys.stderr, flush=True)
     b = vq.Batch(Hs, As, nes)
     for _ in range(args.warmup):
         b.energy_grad(theta)
@@ -224,6 +238,15 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.init()
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.complex128, device="cuda")   # 2 GiB
+        b = torch.empty_like(a)
+        a.zero_()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_per_launch": a.numel() * 16, "launches": 3}))
+        return
     fn = {"batch512": run_batch, "single24": run_single24, "scan12": run_scan12}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 

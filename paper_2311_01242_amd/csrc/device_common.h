@@ -12,8 +12,9 @@ namespace vqe {
 
 constexpr int kBlock = 256;          // threads per block (4 wave64)
 constexpr int kMaxBlocks = 2048;     // grid-stride cap for the per-gate kernels
-constexpr int kHxOuts = 8;           // in-sector outputs per thread in the sector H-apply
+constexpr int kHxOuts = 5;           // in-sector outputs per thread in the sector H-apply
 constexpr int kHxMaxL = 14;          // largest low-bit tile of the sector H-apply
+constexpr int kMaxRunGates = 128;    // gates per fused run (per-gate partials live in LDS)
 
 // Per-state record; kernels take their state from blockIdx.y.
 struct StateDesc {
@@ -25,13 +26,15 @@ struct StateDesc {
     const GroupDesc* groups; // [G]
     const SubDesc* subs;
     const double* tabs;
-    const int32_t* xbatch;   // sector H-apply: group range starts per x_hi batch [nb + 1]
+    const struct HxChunk* chunks;   // sector H-apply work list [nb]
+    const GroupDesc* cgroups;       // chunk-local group descriptors
+    const SubDesc* csubs;           // chunk-local subgroup descriptors
     double* part_e;          // energy partials
     double* part_g;          // gradient partials [M * gstride]
     double* out_e;           // [1]
     double* out_g;           // [M] raw per-gate gradient sums
     int32_t n, G, M, ne;
-    int32_t nb;              // number of x_hi batches
+    int32_t nb;              // number of H-apply chunks
     int32_t gstride;         // stride of part_g between gates
 };
 
@@ -70,6 +73,21 @@ struct HxTables {
 };
 
 static_assert(sizeof(HxTables) % 4 == 0, "HxTables is copied as 32-bit words");
+
+// The sector H-apply walks the groups in chunks small enough to stage in
+// LDS: chunk c covers chunk-local groups [cg0, cg1) (their sub ranges are
+// relative to cs0), subgroups [cs0, cs1) (table offsets relative to t0) and
+// table entries [t0, t1) of the state's tables.  All groups of a chunk share
+// x >> L; a group with many subgroups may continue in the next chunk.
+constexpr int kChunkGroups = 128;
+constexpr int kChunkSubs = 256;
+constexpr int kChunkTabs = 1024;
+
+struct HxChunk {
+    int32_t cg0, cg1, cs0, cs1, t0, t1;
+    uint32_t xhi;
+    int32_t pad;
+};
 
 struct HxPlan {
     int32_t L;
@@ -122,6 +140,16 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
         mask &= mask - 1;
     }
     return out;
+}
+
+// Streaming (non-temporal) accesses for data with no reuse in L2.
+__device__ __forceinline__ double2 nt_load(const double2* p) {
+    return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+
+__device__ __forceinline__ void nt_store(double2* p, double2 v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
 }
 
 __device__ __forceinline__ double parity_sign(uint32_t v) {

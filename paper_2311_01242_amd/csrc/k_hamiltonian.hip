@@ -54,11 +54,15 @@ __device__ __forceinline__ uint32_t compact_even(uint32_t v) {
 }
 
 constexpr int kMaxStage = 1225;   // C(7,3) * C(7,4): largest class of a 14-bit tile
+constexpr int kStagePer = (kMaxStage + kBlock - 1) / kBlock;
 
 __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restrict__ sd,
                                                       HxPlan plan,
                                                       const HxTables* __restrict__ tabsrc) {
-    __shared__ double2 stage[kMaxStage];
+    __shared__ double2 stage[kMaxStage];      // partner tile, in-sector amplitudes by rank
+    __shared__ double tch[kChunkTabs];        // the chunk's coefficient tables
+    __shared__ GroupDesc gch[kChunkGroups];   // the chunk's groups (chunk-local sub ranges)
+    __shared__ SubDesc sch[kChunkSubs];       // the chunk's subgroups (chunk-local tables)
     __shared__ HxTables T;
     __shared__ double red[kBlock / 64];
     {   // copy the rank/unrank tables into LDS
@@ -69,8 +73,6 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
     __syncthreads();
     const StateDesc& s = sd[blockIdx.y];
     const double2* __restrict__ phi = s.phi;
-    const GroupDesc* __restrict__ groups = s.groups;
-    const SubDesc* __restrict__ subs = s.subs;
     const double* __restrict__ tabs = s.tabs;
     const int L = plan.L;
     const uint32_t lowmask = (1u << L) - 1u;
@@ -91,25 +93,50 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
         lo[u] = (k < cnt) ? uint32_t(T.unA[T.offA[kA] + k / cB] | T.unB[T.offB[kB] + k % cB]) : 0u;
         lr[u] = li[u] = 0.0;
     }
-    for (int bi = 0; bi < s.nb; ++bi) {
-        const int g0 = s.xbatch[bi], g1 = s.xbatch[bi + 1];
-        const uint32_t xhi = groups[g0].x >> L;
-        const uint32_t phi_hi = ohi ^ (xhi << L);
-        const int kA2 = plan.na - __popc(phi_hi & 0x55555555u);
-        const int kB2 = plan.nb - __popc(phi_hi & 0xAAAAAAAAu);
-        if (kA2 < 0 || kA2 > T.La || kB2 < 0 || kB2 > T.Lb) continue;   // partner tile empty
-        const int cB2 = T.offB[kB2 + 1] - T.offB[kB2];
-        const int cnt2 = (T.offA[kA2 + 1] - T.offA[kA2]) * cB2;
-        __syncthreads();   // previous batch done reading the stage
-        for (int k = threadIdx.x; k < cnt2; k += kBlock)
-            stage[k] = phi[phi_hi | T.unA[T.offA[kA2] + k / cB2] | T.unB[T.offB[kB2] + k % cB2]];
+    uint32_t staged = 0xffffffffu;   // x_hi whose partner tile is in `stage`
+    int kA2 = 0, kB2 = 0, cB2 = 1;
+    for (int c = 0; c < s.nb; ++c) {
+        const HxChunk ck = s.chunks[c];
+        if (ck.xhi != staged) {
+            const uint32_t phi_hi = ohi ^ (ck.xhi << L);
+            const int a2 = plan.na - __popc(phi_hi & 0x55555555u);
+            const int b2 = plan.nb - __popc(phi_hi & 0xAAAAAAAAu);
+            if (a2 < 0 || a2 > T.La || b2 < 0 || b2 > T.Lb) {   // partner tile empty: skip batch
+                while (c + 1 < s.nb && s.chunks[c + 1].xhi == ck.xhi) ++c;
+                continue;
+            }
+            kA2 = a2;
+            kB2 = b2;
+            cB2 = T.offB[kB2 + 1] - T.offB[kB2];
+            const int cnt2 = (T.offA[kA2 + 1] - T.offA[kA2]) * cB2;
+            double2 v[kStagePer];
+#pragma unroll
+            for (int k = 0; k < kStagePer; ++k) {
+                const int i = threadIdx.x + k * kBlock;
+                if (i < cnt2)
+                    v[k] = phi[phi_hi | T.unA[T.offA[kA2] + i / cB2] | T.unB[T.offB[kB2] + i % cB2]];
+            }
+            __syncthreads();   // everyone done with the previous stage
+#pragma unroll
+            for (int k = 0; k < kStagePer; ++k) {
+                const int i = threadIdx.x + k * kBlock;
+                if (i < cnt2) stage[i] = v[k];
+            }
+            staged = ck.xhi;
+        } else {
+            __syncthreads();   // everyone done with the previous chunk
+        }
+        // stage the chunk's descriptors and tables
+        const int ng = ck.cg1 - ck.cg0, ns = ck.cs1 - ck.cs0, nt = ck.t1 - ck.t0;
+        for (int i = threadIdx.x; i < ng; i += kBlock) gch[i] = s.cgroups[ck.cg0 + i];
+        for (int i = threadIdx.x; i < ns; i += kBlock) sch[i] = s.csubs[ck.cs0 + i];
+        for (int i = threadIdx.x; i < nt; i += kBlock) tch[i] = tabs[ck.t0 + i];
         __syncthreads();
-        for (int gi = g0; gi < g1; ++gi) {
-            const GroupDesc gd = groups[gi];
+        for (int gi = 0; gi < ng; ++gi) {
+            const GroupDesc gd = gch[gi];
             const uint32_t xlo = gd.x & lowmask;
             double2 p[kHxOuts];
             uint32_t tb[kHxOuts];
-            double d[kHxOuts];
             bool ok[kHxOuts];
             bool any = false;
 #pragma unroll
@@ -118,30 +145,33 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
                 const uint32_t lp = lo[u] ^ xlo;
                 ok[u] = (k < cnt) && __popc(lp & 0x5555u) == kA2 && __popc(lp & 0xAAAAu) == kB2;
                 p[u] = make_double2(0.0, 0.0);
+                tb[u] = 0;
                 if (ok[u]) {
                     const int idx = int(T.rankA[compact_even(lp)]) * cB2 +
                                     int(T.rankB[compact_even(lp >> 1)]);
                     p[u] = stage[idx];
+                    tb[u] = pext_pos(ohi | lo[u], gd.pos);
                     any = true;
                 }
-                tb[u] = pext_pos(ohi | lo[u], gd.pos);
-                d[u] = 0.0;
             }
             if (!__ballot(any)) continue;   // wave-uniform skip
+            double d[kHxOuts];
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) d[u] = 0.0;
             for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
-                const SubDesc sub = subs[si];
+                const SubDesc sub = sch[si];
 #pragma unroll
                 for (int u = 0; u < kHxOuts; ++u) {
-                    if (ok[u]) {
-                        const double t = tabs[sub.tab + tb[u]];
-                        d[u] += (__popc((ohi | lo[u]) & sub.w) & 1) ? -t : t;
-                    }
+                    const double t = tch[sub.tab + tb[u]];
+                    d[u] += (__popc((ohi | lo[u]) & sub.w) & 1) ? -t : t;
                 }
             }
 #pragma unroll
             for (int u = 0; u < kHxOuts; ++u) {
-                lr[u] += d[u] * p[u].x;
-                li[u] += d[u] * p[u].y;
+                if (ok[u]) {
+                    lr[u] += d[u] * p[u].x;
+                    li[u] += d[u] * p[u].y;
+                }
             }
         }
     }

@@ -87,7 +87,7 @@ struct DevHam {
     GroupDesc* groups = nullptr;
     SubDesc* subs = nullptr;
     double* tabs = nullptr;
-    std::map<int, std::pair<int32_t*, int>> xbatch;   // L -> (device starts, count)
+    std::map<int, struct HxWork*> work;   // L -> sector H-apply work list
 };
 
 struct DevAnsatz {
@@ -134,25 +134,83 @@ static int dev_ham(const vqe_hamiltonian* H, DevHam** out) {
     return VQE_OK;
 }
 
-// Group ranges with equal x >> L (groups are sorted by x).
-static int ham_xbatch(const vqe_hamiltonian* H, DevHam* d, int L, int32_t** out, int* nb) {
+// Work list of the sector H-apply for tile bits L: the groups (sorted by x,
+// hence by x >> L) cut into chunks that fit the kernel's LDS buffers.
+struct HxWork {
+    HxChunk* chunks = nullptr;
+    GroupDesc* cgroups = nullptr;
+    SubDesc* csubs = nullptr;
+    int count = 0;
+};
+
+static int ham_chunks(const vqe_hamiltonian* H, DevHam* d, int L, HxWork** out) {
     std::lock_guard<std::mutex> lk(H->mu);
-    auto it = d->xbatch.find(L);
-    if (it != d->xbatch.end()) {
-        *out = it->second.first;
-        *nb = it->second.second;
+    auto it = d->work.find(L);
+    if (it != d->work.end()) {
+        *out = it->second;
         return VQE_OK;
     }
-    std::vector<int32_t> starts;
-    for (size_t g = 0; g < H->groups.size(); ++g)
-        if (g == 0 || (H->groups[g].x >> L) != (H->groups[g - 1].x >> L)) starts.push_back(int32_t(g));
-    const int cnt = int(starts.size());
-    starts.push_back(int32_t(H->groups.size()));
-    int32_t* p = nullptr;
-    if (int rc = upload(&p, starts.data(), starts.size())) return rc;
-    d->xbatch[L] = {p, cnt};
-    *out = p;
-    *nb = cnt;
+    std::vector<HxChunk> ch;
+    std::vector<GroupDesc> cg;
+    std::vector<SubDesc> cs;
+    HxChunk cur{};
+    bool open = false;
+    auto close = [&]() {
+        if (open) {
+            cur.cg1 = int32_t(cg.size());
+            cur.cs1 = int32_t(cs.size());
+            ch.push_back(cur);
+        }
+        open = false;
+    };
+    for (size_t gi = 0; gi < H->groups.size(); ++gi) {
+        const GroupDesc& g = H->groups[gi];
+        const uint32_t xhi = g.x >> L;
+        const int ts = 1 << (g.pos & 7);
+        int si = g.sub_begin;
+        while (si < g.sub_end) {
+            if (open && (cur.xhi != xhi || int(cg.size()) - cur.cg0 >= kChunkGroups ||
+                         int(cs.size()) - cur.cs0 >= kChunkSubs ||
+                         H->subs[si].tab + ts - cur.t0 > kChunkTabs))
+                close();
+            if (!open) {
+                cur = HxChunk{};
+                cur.cg0 = int32_t(cg.size());
+                cur.cs0 = int32_t(cs.size());
+                cur.t0 = H->subs[si].tab;
+                cur.t1 = cur.t0;
+                cur.xhi = xhi;
+                open = true;
+            }
+            GroupDesc lg = g;
+            lg.sub_begin = int32_t(cs.size()) - cur.cs0;
+            // as many of this group's subgroups as fit the open chunk
+            while (si < g.sub_end && int(cs.size()) - cur.cs0 < kChunkSubs &&
+                   H->subs[si].tab + ts - cur.t0 <= kChunkTabs) {
+                cs.push_back(SubDesc{H->subs[si].w, H->subs[si].tab - cur.t0});
+                cur.t1 = H->subs[si].tab + ts;
+                ++si;
+            }
+            lg.sub_end = int32_t(cs.size()) - cur.cs0;
+            if (lg.sub_end > lg.sub_begin) cg.push_back(lg);
+            if (si < g.sub_end) close();   // continue this group in a new chunk
+        }
+    }
+    close();
+    auto* w = new HxWork();
+    w->count = int(ch.size());
+    int rc = upload(&w->chunks, ch.data(), ch.size());
+    if (!rc) rc = upload(&w->cgroups, cg.data(), cg.size());
+    if (!rc) rc = upload(&w->csubs, cs.data(), cs.size());
+    if (rc) {
+        (void)hipFree(w->chunks);
+        (void)hipFree(w->cgroups);
+        (void)hipFree(w->csubs);
+        delete w;
+        return rc;
+    }
+    d->work[L] = w;
+    *out = w;
     return VQE_OK;
 }
 
@@ -193,11 +251,19 @@ static void plan_direction(const vqe_ansatz* A, int64_t budget, int vectors,
         int64_t j2 = j + 1;
         while (j2 < M) {
             const GateDesc& h = A->gates[j2];
-            if (h.type != kExcitation || (h.x & ~h.pd) != key) break;
+            if (h.type != kExcitation || (h.x & ~h.pd) != key || j2 - j >= kMaxRunGates) break;
             const uint32_t cand = inner | h.pd;
             if (tile_bytes(cand) > budget) break;
             inner = cand;
             ++j2;
+        }
+        // grow the tile with the lowest free qubits up to the budget: the same
+        // total traffic in fewer, larger tiles with longer contiguous chunks
+        for (int q = 0; q < n; ++q) {
+            const uint32_t bit = 1u << q;
+            if ((inner | key) & bit) continue;
+            if (tile_bytes(inner | bit) > budget) break;
+            inner |= bit;
         }
         RunDesc r{};
         r.g0 = int32_t(j);
@@ -547,7 +613,12 @@ vqe_hamiltonian::~vqe_hamiltonian() {
         (void)hipFree(kv.second->groups);
         (void)hipFree(kv.second->subs);
         (void)hipFree(kv.second->tabs);
-        for (auto& xb : kv.second->xbatch) (void)hipFree(xb.second.first);
+        for (auto& w : kv.second->work) {
+            (void)hipFree(w.second->chunks);
+            (void)hipFree(w.second->cgroups);
+            (void)hipFree(w.second->csubs);
+            delete w.second;
+        }
         delete kv.second;
     }
     (void)hipSetDevice(cur);
@@ -764,10 +835,9 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     if (int rc = make_eval_plan(A, ne, false, &ep)) return rc;
     DevAnsatz* da;
     if (int rc = dev_ansatz(A, &da)) return rc;
-    int32_t* xb = nullptr;
-    int nb = 0;
+    HxWork* hw = nullptr;
     if (ep.sector)
-        if (int rc = ham_xbatch(H, dh, ep.hx.L, &xb, &nb)) return rc;
+        if (int rc = ham_chunks(H, dh, ep.hx.L, &hw)) return rc;
     ScratchSize sz;
     sz.add<double>(P);
     sz.add<double2>(M);
@@ -795,7 +865,12 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     sd.groups = dh->groups;
     sd.subs = dh->subs;
     sd.tabs = dh->tabs;
-    sd.xbatch = xb;
+    if (hw) {
+        sd.chunks = hw->chunks;
+        sd.cgroups = hw->cgroups;
+        sd.csubs = hw->csubs;
+        sd.nb = hw->count;
+    }
     sd.part_e = cv.take<double>(ep.nblk_e);
     sd.part_g = cv.take<double>(size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride);
     sd.out_e = cv.take<double>(1);
@@ -804,7 +879,6 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     sd.G = int32_t(H->groups.size());
     sd.M = int32_t(M);
     sd.ne = ne;
-    sd.nb = nb;
     sd.gstride = ep.ap->gstride;
     StateDesc* sd_dev = cv.take<StateDesc>(1);
     if (P > 0)
@@ -978,9 +1052,12 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         StateDesc& sd = sds[k];
         std::memset(&sd, 0, sizeof(sd));
         if (ep.sector) {
-            int32_t* xb = nullptr;
-            if (int rc = ham_xbatch(H[i], dh, ep.hx.L, &xb, &sd.nb)) return rc;
-            sd.xbatch = xb;
+            HxWork* hw = nullptr;
+            if (int rc = ham_chunks(H[i], dh, ep.hx.L, &hw)) return rc;
+            sd.chunks = hw->chunks;
+            sd.cgroups = hw->cgroups;
+            sd.csubs = hw->csubs;
+            sd.nb = hw->count;
         }
         if (int rc = dalloc(b, &sd.phi, size_t(1) << n)) return rc;
         if (int rc = dalloc(b, &sd.lam, size_t(1) << n)) return rc;
