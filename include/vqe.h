@@ -247,6 +247,41 @@ int vqe_run(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
             const double* theta0, const vqe_options* opts, double* theta_out,
             double* trace_out, vqe_result* res, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Warm-start MLP (a project addition beside the method: it predicts UCCSD
+ * amplitudes for a new bond-stretch geometry from the converged amplitudes
+ * of neighbouring geometries, Sec. 3.1 "Results for bond stretching")
+ *
+ * Layers z_l = a_{l-1} W_l^T + b_l, GELU (exact erf form) after every layer
+ * but the last; loss = mean squared error; Adam.  Products take bfloat16
+ * operands (round to nearest even) on the matrix cores with FP32
+ * accumulation; biases, activations' pre-images, loss, master weights and
+ * Adam moments are FP32.  Parameters are packed per layer as W_l
+ * [out][in] row-major followed by b_l [out].  All arrays are host arrays.
+ * ------------------------------------------------------------------------ */
+typedef struct vqe_mlp vqe_mlp;
+
+/* widths[0..n_layers]: input, hidden..., output (1 <= n_layers <= 8, each
+ * width in [1, 8192]).  Parameters start at zero; hip_stream is unused (the
+ * network orders its work on a private stream). */
+int vqe_mlp_create(int n_layers, const int32_t* widths, void* hip_stream, vqe_mlp** out);
+int vqe_mlp_n_params(const vqe_mlp* n, int64_t* count);
+/* Load the FP32 master parameters (finite) and reset the Adam state. */
+int vqe_mlp_set_params(vqe_mlp* n, const float* params);
+int vqe_mlp_get_params(const vqe_mlp* n, float* params);
+/* y[batch][out] = network(x[batch][in]); 1 <= batch <= 65536. */
+int vqe_mlp_forward(vqe_mlp* n, int batch, const float* x, float* y);
+/* Loss and its gradient with respect to the packed parameters (grad
+ * nullable), without an update. */
+int vqe_mlp_loss_grad(vqe_mlp* n, int batch, const float* x, const float* y, float* loss,
+                      float* grad);
+/* `steps` full-batch Adam steps (one HIP-graph launch per step); the Adam
+ * step count continues across calls.  loss_trace (nullable, `steps` floats)
+ * receives the loss before each step. */
+int vqe_mlp_train(vqe_mlp* n, int batch, const float* x, const float* y, int steps, float lr,
+                  float beta1, float beta2, float eps, float* loss_trace);
+void vqe_mlp_free(vqe_mlp* n);
+
 #ifdef __cplusplus
 }
 #endif

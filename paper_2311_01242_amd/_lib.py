@@ -54,6 +54,15 @@ SIGNATURES = {
     "vqe_batch_profile": (c_int, [vp, P(c_double), c_int, P(c_double)]),
     "vqe_batch_work": (c_int, [vp, P(c_double)]),
     "vqe_set_tuning": (c_int, [c_int, c_int, c_int64, c_int64, c_int]),
+    "vqe_mlp_create": (c_int, [c_int, P(c_int32), vp, P(vp)]),
+    "vqe_mlp_n_params": (c_int, [vp, P(c_int64)]),
+    "vqe_mlp_set_params": (c_int, [vp, P(C.c_float)]),
+    "vqe_mlp_get_params": (c_int, [vp, P(C.c_float)]),
+    "vqe_mlp_forward": (c_int, [vp, c_int, P(C.c_float), P(C.c_float)]),
+    "vqe_mlp_loss_grad": (c_int, [vp, c_int, P(C.c_float), P(C.c_float), P(C.c_float), P(C.c_float)]),
+    "vqe_mlp_train": (c_int, [vp, c_int, P(C.c_float), P(C.c_float), c_int, C.c_float, C.c_float,
+                              C.c_float, C.c_float, P(C.c_float)]),
+    "vqe_mlp_free": (None, [vp]),
     "vqe_minimize_bfgs": (c_int, [c_int, OBJECTIVE, vp, P(c_double), P(Options), P(c_double),
                                   P(c_double), P(Result)]),
     "vqe_run": (c_int, [vp, vp, c_int, P(c_double), P(Options), P(c_double), P(c_double),

@@ -194,3 +194,55 @@ def test_term_and_group_counts_12q():
     xs = {x for x, _ in terms}
     diag = [k for k in terms if k[0] == 0]
     assert (len(terms), len(xs), len(diag)) == (1819, 286, 79)
+
+
+# ----------------------------------------------------------------- MLP oracle
+from oracle import mlp as NN  # noqa: E402
+
+
+def test_bf16_rounding_known_values():
+    # 1 + 2^-8 is halfway between bf16 neighbours 1 and 1 + 2^-7: ties to even -> 1
+    assert NN.bf16(1.0 + 2.0 ** -8) == 1.0
+    # 1 + 3 * 2^-8 is halfway between 1 + 2^-7 and 1 + 2^-6: ties to even -> 1 + 2^-6
+    assert NN.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    assert NN.bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7   # above the tie
+    assert NN.bf16(-3.14159265) == -3.140625
+    assert NN.bf16(65504.0) == 65536.0
+    assert np.isnan(NN.bf16(np.nan))
+    x = np.random.default_rng(0).normal(size=1000).astype(np.float32).astype(np.float64)
+    rel = np.abs(NN.bf16(x) - x) / np.abs(x)
+    assert rel.max() <= 2.0 ** -8 + 1e-12
+
+
+def test_gelu_closed_forms():
+    assert NN.gelu(0.0) == 0.0
+    assert abs(NN.gelu(1.0) - 0.8413447460685429) < 1e-15      # Phi(1)
+    z = np.linspace(-4, 4, 41)
+    h = 1e-6
+    fd = (NN.gelu(z + h) - NN.gelu(z - h)) / (2 * h)
+    assert np.abs(fd - NN.gelu_grad(z)).max() < 1e-8
+
+
+def test_mlp_gradient_vs_central_differences():
+    widths = [5, 7, 6, 4]
+    rng = np.random.default_rng(3)
+    p = NN.init_params(widths, 1) + rng.normal(0, 0.1, NN.n_params(widths))
+    x = rng.normal(size=(9, 5))
+    y = rng.normal(size=(9, 4))
+    _, g = NN.loss_and_grad(p, widths, x, y, rounding=False)
+    fd = np.empty_like(p)
+    for k in range(p.size):
+        e = np.zeros_like(p)
+        e[k] = 1e-6
+        fd[k] = (NN.loss_and_grad(p + e, widths, x, y, False)[0] -
+                 NN.loss_and_grad(p - e, widths, x, y, False)[0]) / 2e-6
+    assert np.abs(fd - g).max() < 1e-8
+    assert NN.n_params([37, 256, 256, 360]) == 168040
+
+
+def test_adam_first_step_closed_form():
+    # t = 1: m_hat = g, v_hat = g^2, so the step is lr * g / (|g| + eps)
+    p = np.array([0.5, -1.0, 2.0])
+    g = np.array([0.1, -3.0, 0.0])
+    p1, m, v = NN.adam_step(p, g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-8)
+    assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
