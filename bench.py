@@ -35,11 +35,16 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch512", choices=["batch512", "single24", "scan12"])
+    ap.add_argument("--workload", default="batch512",
+                    choices=["batch512", "single24", "scan12", "warmstart16"])
+    ap.add_argument("--scan-points", type=int, default=200)
+    ap.add_argument("--mlp-steps", type=int, default=4000)
     ap.add_argument("--states", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="batch512: only the eager HIP-event phase profile (for rocprof runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -108,6 +113,43 @@ def cpu_baseline_batch(spec, budget_s=20.0):
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2311_01242_amd", "tuning_cache.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "batch512_hbm_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc", "k_gates.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def roofline(b, theta, reps):
+    """Roofline of the dominant kernel, the reverse-sweep run kernel
+    k_run_adj: the batch's plan gives its algorithmic bytes and launch count
+    per evaluation; its duration comes from HIP events on the batch stream
+    around the same launches issued eagerly (the graph replays interleave the
+    size classes on forked streams, so single kernels cannot be timed there).
+    `traffic` is the rocprof FETCH+WRITE measurement of the same kernel,
+    reported only while the kernel source still matches the measured one."""
+    phase_ms = b.profile(theta, reps=reps)
+    w = b.work()
+    launches = w[6]
+    avg_us = 1e3 * phase_ms[2] / launches
+    bytes_per_launch = w[2] / launches
+    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+        if t.get("kernel_source_sha256") == kernel_source_hash():
+            traffic = t["k_run_adj_bytes_per_launch"]
+    return {"bound": "hbm", "kernel": "k_run_adj (reverse-sweep gate runs)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
+            "avg_launch_us": round(avg_us, 2), "launches_per_eval": int(launches),
+            "phase_ms": {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
+                         "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}}
 
 
 def run_batch(args):
@@ -123,6 +165,10 @@ def run_batch(args):
               + " ".join(f"n{n}=({f >> 10}K,{a >> 10}K,L{L})" for n, (f, a, L) in sorted(tuned.items())),
               file=sys.stderr, flush=True)
     b = vq.Batch(Hs, As, nes)
+    if args.profile_only:
+        phase_ms = b.profile(theta, reps=args.profile_reps)
+        return {"profile_only": True, "phase_ms": [round(x, 3) for x in phase_ms],
+                "work": b.work().tolist()}
     for _ in range(args.warmup):
         b.energy_grad(theta)
     torch.cuda.synchronize()
@@ -133,17 +179,7 @@ def run_batch(args):
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
-    phase_ms = b.profile(theta, reps=args.profile_reps)
-    work = b.work()
-    phases = {"forward": (phase_ms[0], work[0]), "adjoint": (phase_ms[2], work[2])}
-    name, (ms, byts) = max(phases.items(), key=lambda kv: kv[1][0])
-    achieved = byts / (ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": f"{name} gate runs (k_run_{'fwd' if name == 'forward' else 'adj'})",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "phase_ms": {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
-                         "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)},
-            "algorithmic_bytes": {"forward": work[0], "adjoint": work[2]}}
+    roof = roofline(b, theta, args.profile_reps)
     out = {
         "metric": "energy+adjoint-grad evals/s",
         "value": round(args.states * args.steps / dt, 2),
@@ -181,20 +217,15 @@ def run_single24(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     b = vq.Batch([H], [A], [ne])
-    phase_ms = b.profile(th, reps=args.profile_reps)
-    work = b.work()
-    phases = {"forward": (phase_ms[0], work[0]), "adjoint": (phase_ms[2], work[2])}
-    name, (ms, byts) = max(phases.items(), key=lambda kv: kv[1][0])
-    achieved = byts / (ms * 1e-3) / 1e9
+    roof = roofline(b, th, args.profile_reps)
+    roof["traffic"] = None
     return {
         "metric": "energy+adjoint-grad evals/s", "value": round(args.steps / dt, 3), "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "complex128",
         "data": "synthetic",
         "config": {"workload": "single 24-qubit UCCSD energy+adjoint gradient (12 e-, 1818 params)"},
-        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "phase_ms": [round(x, 3) for x in phase_ms]},
+        "roofline": roof,
     }
 
 
@@ -226,6 +257,40 @@ def run_scan12(args):
     }
 
 
+def run_warmstart16(args):
+    """Config of the learned warm start: 16 qubits, 8 electrons, 200 scan
+    points of h, g = A + B e^-lam + C e^-2lam on lam in [0.7, 3.0]; plain VQE
+    at every point, MLP (37 -> 256 -> 256 -> 360) trained on 160 points,
+    warm-started VQE at the 40 held-out points."""
+    from paper_2311_01242_amd import warmstart as W
+    from vqe_inputs import WARM_LAMBDAS, warmstart_integrals
+    n, ne = 16, 8
+    fam = warmstart_integrals(n, 5)
+    lams = WARM_LAMBDAS[: args.scan_points]
+    t0 = time.perf_counter()
+    A, scan = W.run_scan(fam, n, ne, lams,
+                         log=lambda s: print("#", s, file=sys.stderr, flush=True))
+    t_scan = time.perf_counter() - t0
+    train, held = W.split(len(lams))
+    t1 = time.perf_counter()
+    net, norm, loss = W.train_warmstart(scan, train, steps=args.mlp_steps)
+    t_train = time.perf_counter() - t1
+    rows = W.evaluate(scan, held, net, norm, A, n, ne, fam)
+    s = W.summarize(rows)
+    return {
+        "metric": "VQE iterations to 1 mHa, warm start vs plain", "value": s["warm_iters_to_1mHa"]["mean"],
+        "unit": "BFGS iterations (mean over held-out points)", "higher_is_better": False,
+        "n_gpus": 1, "dtype": "complex128 (VQE) / bf16+fp32 (MLP)", "data": "synthetic",
+        "vs_baseline": None,
+        "config": {"workload": f"16-qubit warm-start scan, {len(lams)} points, {len(train)} train / "
+                               f"{len(held)} held out", "mlp": [37, 256, 256, 360],
+                   "mlp_steps": args.mlp_steps},
+        "summary": s, "plain_scan_seconds": round(t_scan, 2), "mlp_train_seconds": round(t_train, 3),
+        "mlp_loss_first_last": [float(loss[0]), float(loss[-1])],
+        "per_point": [{k: (round(v, 9) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
+    }
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -247,7 +312,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_per_launch": a.numel() * 16, "launches": 3}))
         return
-    fn = {"batch512": run_batch, "single24": run_single24, "scan12": run_scan12}[args.workload]
+    fn = {"batch512": run_batch, "single24": run_single24, "scan12": run_scan12,
+          "warmstart16": run_warmstart16}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

@@ -195,9 +195,11 @@ void vqe_batch_free(vqe_batch* b);
 int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps, double* ms);
 
 /* Algorithmic work of one evaluation of the whole batch, from the launch
- * plan: w[0] forward-sweep bytes (each run tile read and written once, plus
- * the |HF> write), w[1] reserved (0), w[2] reverse-sweep bytes (phi and
- * lambda tiles read and written once), w[3] bytes of all phi + lambda. */
+ * plan (8 doubles): w[0] forward-sweep bytes (each run tile read and written
+ * once, plus the |HF> write), w[1] 0, w[2] reverse-sweep bytes (phi and
+ * lambda tiles read and written once), w[3] bytes of all phi + lambda,
+ * w[4] gate-step launches of the forward sweep, w[5] H-apply launches,
+ * w[6] gate-step launches of the reverse sweep, w[7] 0. */
 int vqe_batch_work(const vqe_batch* b, double* w);
 
 /* Launch-parameter override for states of n_qubits (batched = 1 for batch

@@ -312,8 +312,9 @@ class Batch:
         return ms
 
     def work(self):
-        """Algorithmic bytes of one evaluation: (forward, 0, adjoint, all phi + lambda)."""
-        w = np.empty(4, np.float64)
+        """Work of one evaluation: (forward bytes, 0, adjoint bytes, all phi + lambda
+        bytes, forward launches, H-apply launches, adjoint launches, 0)."""
+        w = np.empty(8, np.float64)
         _check(lib().vqe_batch_work(self._h, _dptr(w)))
         return w
 

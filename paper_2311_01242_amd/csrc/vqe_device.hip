@@ -928,7 +928,7 @@ struct vqe_batch {
     double* g_h = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    double work[4] = {0, 0, 0, 0};  // algorithmic work of one evaluation
+    double work[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // algorithmic work of one evaluation
     ~vqe_batch() {
         int cur = 0;
         (void)hipGetDevice(&cur);
@@ -1083,6 +1083,11 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         b->work[3] += 2.0 * double(sizeof(double2)) * double(uint64_t(1) << n);
     }
     HIPCHK(hipGetLastError());
+    for (auto& c : b->classes) {   // launches per evaluation (one per class and step)
+        b->work[4] += double(c.ep.ap->fwd_steps.size());
+        b->work[5] += 1.0;
+        b->work[6] += double(c.ep.ap->adj_steps.size());
+    }
     if (int rc = dalloc(b, &b->sd_dev, S)) return rc;
     HIPCHK(hipMemcpy(b->sd_dev, sds.data(), sizeof(StateDesc) * S, hipMemcpyHostToDevice));
     HIPCHK(hipStreamSynchronize(b->st));
@@ -1188,7 +1193,7 @@ extern "C" int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps
 
 extern "C" int vqe_batch_work(const vqe_batch* b, double* work) {
     if (!b || !work) return fail(VQE_EINVAL, "null pointer argument");
-    std::copy(b->work, b->work + 4, work);
+    std::copy(b->work, b->work + 8, work);
     return VQE_OK;
 }
 
