@@ -210,6 +210,16 @@ int vqe_batch_work(const vqe_batch* b, double* w);
 int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes, int64_t adj_lds_bytes,
                    int hx_tile_bits);
 
+/* Evaluation layout switch (process-wide, default 1).  With 1, energy and
+ * gradient evaluations of programs made only of number- and spin-conserving
+ * excitations (UCCSD, Sec. 2.1.2) run on the packed sector layout: only the
+ * amplitudes of the reference's (N, S_z) sector are stored, C(ceil(n/2),
+ * N_alpha) C(floor(n/2), N_beta) per vector instead of 2^n; the hx tile bits
+ * are raised to the number of electrons if smaller.  With 0 they use full
+ * 2^n vectors.  Results agree to rounding; applies to plans made after the
+ * call.  Never fails. */
+int vqe_set_packed(int enable);
+
 /* ---------------------------------------------------------------------------
  * BFGS and the VQE loop
  * ------------------------------------------------------------------------ */

@@ -89,6 +89,26 @@ struct HxChunk {
     int32_t pad;
 };
 
+// A run on the packed sector layout: gates [g0, g1) whose created orbitals
+// have the same high part khi (bits of the block index h = b >> L).  Tile o
+// is the block pair (h, h | khi) with h = pdep(o, free_hi), or the single
+// block h when khi = 0.  shape selects the launch shape; max_entries bounds
+// the entries of one tile (LDS per vector).
+struct PackedRun {
+    int32_t g0, g1;
+    uint32_t khi, free_hi;
+    int32_t ntiles, L, na, nb;
+    int32_t shape, max_entries;
+};
+
+// One excitation of a packed run: annihilated orbitals pd and created
+// orbitals klo in the low bits, chain parity split into low (chlo) and high
+// (chhi, global bit positions) parts; pair sign csign (-1)^{|D & chain|}.
+struct PackedGate {
+    uint32_t pd, klo, chlo, chhi;
+    double csign;
+};
+
 struct HxPlan {
     int32_t L;
     int32_t ntiles;          // 2^(n - L)
@@ -152,6 +172,13 @@ __device__ __forceinline__ void nt_store(double2* p, double2 v) {
     __builtin_nontemporal_store(v.y, &p->y);
 }
 
+// Pair update of an excitation: D' = c D - ss E, E' = c E + ss D (ss = s * sin).
+__device__ __forceinline__ void givens(double2& d, double2& e, double c, double ss) {
+    const double2 pd = d, pe = e;
+    d = make_double2(c * pd.x - ss * pe.x, c * pd.y - ss * pe.y);
+    e = make_double2(c * pe.x + ss * pd.x, c * pe.y + ss * pd.y);
+}
+
 __device__ __forceinline__ double parity_sign(uint32_t v) {
     return (__popc(v) & 1) ? -1.0 : 1.0;
 }
@@ -199,7 +226,15 @@ void launch_run_adj(const StateDesc* sd, int count, const RunDesc& run, const Ti
                     hipStream_t st);
 void launch_hx_sector(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
                       hipStream_t st);
+void launch_hx_packed(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
+                      const int32_t* base, hipStream_t st);
 void launch_fill_zero(double2* p, uint64_t n, hipStream_t st);
+void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st);
+void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
+                       const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st);
+int packed_shape(int max_block);      // launch shape index covering blocks of that size, or -1
+int packed_shape_threads(int shape);
+int packed_enable_lds(size_t bytes);  // 0 on success
 
 int blocks_for(uint64_t work);
 

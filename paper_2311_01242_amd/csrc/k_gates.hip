@@ -50,13 +50,6 @@ __global__ void k_fill_zero(double2* __restrict__ p, uint64_t n) {
         p[i] = make_double2(0.0, 0.0);
 }
 
-// Pair update of an excitation: D' = c D - ss E, E' = c E + ss D (ss = s * sin).
-__device__ __forceinline__ void givens(double2& d, double2& e, double c, double ss) {
-    const double2 pd = d, pe = e;
-    d = make_double2(c * pd.x - ss * pe.x, c * pd.y - ss * pe.y);
-    e = make_double2(c * pe.x + ss * pd.x, c * pe.y + ss * pd.y);
-}
-
 __global__ void k_exc(const StateDesc* __restrict__ sd, int j, uint64_t npairs) {
     const StateDesc& s = sd[blockIdx.y];
     const GateDesc g = s.gates[j];

@@ -56,9 +56,14 @@ __device__ __forceinline__ uint32_t compact_even(uint32_t v) {
 constexpr int kMaxStage = 1225;   // C(7,3) * C(7,4): largest class of a 14-bit tile
 constexpr int kStagePer = (kMaxStage + kBlock - 1) / kBlock;
 
+// PACKED: phi and lambda hold only the sector, block h = b >> L from base[h]
+// in the same (alpha rank, beta rank) order as the tile here; otherwise they
+// are full 2^n vectors.
+template <bool PACKED>
 __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restrict__ sd,
                                                       HxPlan plan,
-                                                      const HxTables* __restrict__ tabsrc) {
+                                                      const HxTables* __restrict__ tabsrc,
+                                                      const int32_t* __restrict__ base) {
     __shared__ double2 stage[kMaxStage];      // partner tile, in-sector amplitudes by rank
     __shared__ double tch[kChunkTabs];        // the chunk's coefficient tables
     __shared__ GroupDesc gch[kChunkGroups];   // the chunk's groups (chunk-local sub ranges)
@@ -113,8 +118,12 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
 #pragma unroll
             for (int k = 0; k < kStagePer; ++k) {
                 const int i = threadIdx.x + k * kBlock;
-                if (i < cnt2)
-                    v[k] = phi[phi_hi | T.unA[T.offA[kA2] + i / cB2] | T.unB[T.offB[kB2] + i % cB2]];
+                if (i < cnt2) {
+                    if (PACKED)
+                        v[k] = phi[int64_t(base[phi_hi >> L]) + i];
+                    else
+                        v[k] = phi[phi_hi | T.unA[T.offA[kA2] + i / cB2] | T.unB[T.offB[kB2] + i % cB2]];
+                }
             }
             __syncthreads();   // everyone done with the previous stage
 #pragma unroll
@@ -176,11 +185,12 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
         }
     }
     double acc = 0.0;
+    const int64_t obase = PACKED ? int64_t(base[blockIdx.x]) : 0;
 #pragma unroll
     for (int u = 0; u < kHxOuts; ++u) {
         const int k = threadIdx.x + u * kBlock;
         if (k < cnt) {
-            const uint32_t b = ohi | lo[u];
+            const int64_t b = PACKED ? obase + k : int64_t(ohi | lo[u]);
             s.lam[b] = make_double2(lr[u], li[u]);
             const double2 q = phi[b];
             acc += q.x * lr[u] + q.y * li[u];
@@ -197,7 +207,14 @@ void launch_hx_dense(const StateDesc* sd, int count, uint64_t N, int nblk, int w
 
 void launch_hx_sector(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
                       hipStream_t st) {
-    hipLaunchKernelGGL(k_hx_sector, dim3(plan.ntiles, count), dim3(kBlock), 0, st, sd, plan, tabs);
+    hipLaunchKernelGGL(k_hx_sector<false>, dim3(plan.ntiles, count), dim3(kBlock), 0, st, sd, plan,
+                       tabs, nullptr);
+}
+
+void launch_hx_packed(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
+                      const int32_t* base, hipStream_t st) {
+    hipLaunchKernelGGL(k_hx_sector<true>, dim3(plan.ntiles, count), dim3(kBlock), 0, st, sd, plan,
+                       tabs, base);
 }
 
 }  // namespace vqe

@@ -1,0 +1,244 @@
+// Ansatz kernels on the packed sector layout (Sec. 2.1.2, Eq. 1; gradient of
+// Eq. 3 by the reverse sweep).
+//
+// Every UCCSD gate conserves the alpha and beta electron counts, so a state
+// prepared from the reference |HF> has nonzero amplitudes only in the
+// reference's (N, S_z) sector.  The packed layout stores exactly those
+// amplitudes: strings b are grouped in blocks by their high bits h = b >> L,
+// block h holds the in-sector strings with that high part ordered by
+// (rank of the low alpha string, rank of the low beta string) among strings
+// of their popcounts, and blocks follow each other in increasing h from
+// base[h].  Empty blocks take no space.  The reference is entry 0.
+//
+// With L no smaller than the number of electrons, the annihilated orbitals
+// of every UCCSD excitation lie in the low bits.  A gate then pairs D in
+// block h (created orbitals empty, annihilated ones occupied) with
+// E = D ^ x in block h | khi, khi being the high part of the created
+// orbitals.  Consecutive gates with the same khi form a run, applied tile by
+// tile: a tile is the block pair (h, h | khi) (one block when khi = 0),
+// staged in LDS, all the run's gates applied, written back.
+#include "device_common.h"
+
+namespace vqe {
+
+__device__ __forceinline__ uint32_t even_bits7(uint32_t v) {   // bits 0,2,..,12 -> 0..6
+    v &= 0x5555u;
+    v = (v | (v >> 1)) & 0x3333u;
+    v = (v | (v >> 2)) & 0x0F0Fu;
+    v = (v | (v >> 4)) & 0x00FFu;
+    return v;
+}
+
+struct BlockShape {
+    int kA, kB, cB, cnt;
+};
+
+// Alpha/beta electrons left to the low bits of block h, and its size (0 when
+// the high part alone has too many or too few electrons).
+__device__ __forceinline__ BlockShape block_shape(const HxTables& T, uint32_t hb, int na, int nb) {
+    BlockShape b;
+    b.kA = na - __popc(hb & 0x55555555u);
+    b.kB = nb - __popc(hb & 0xAAAAAAAAu);
+    if (b.kA < 0 || b.kA > T.La || b.kB < 0 || b.kB > T.Lb) {
+        b.cB = 1;
+        b.cnt = 0;
+        return b;
+    }
+    b.cB = T.offB[b.kB + 1] - T.offB[b.kB];
+    b.cnt = (T.offA[b.kA + 1] - T.offA[b.kA]) * b.cB;
+    return b;
+}
+
+__global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
+    const StateDesc& s = sd[blockIdx.y];
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
+         k += int64_t(gridDim.x) * blockDim.x)
+        nt_store(&s.phi[k], make_double2(k == 0 ? 1.0 : 0.0, 0.0));
+}
+
+// VEC = 1: forward pass on phi.  VEC = 2: reverse sweep on phi and lambda
+// with per-gate, per-tile partials of Re <lambda|A_j phi> (A_j = T_j - T_j^dag).
+// Entry k of the tile (k < c0: block h, else block h | khi) is held by
+// thread k % BS; EPT * BS covers the largest block of the run.
+template <int VEC, int BS, int EPT>
+__global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, PackedRun run,
+                                             const PackedGate* __restrict__ pg,
+                                             const HxTables* __restrict__ tabsrc,
+                                             const int32_t* __restrict__ base) {
+    extern __shared__ double2 sh[];
+    __shared__ HxTables T;
+    __shared__ double red[VEC == 2 ? kMaxRunGates : 1][BS / 64];
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
+        for (int i = threadIdx.x; i < int(sizeof(HxTables) / 4); i += BS) dst[i] = src[i];
+    }
+    __syncthreads();
+    const StateDesc& s = sd[blockIdx.y];
+    const int o = blockIdx.x;
+    const int tid = threadIdx.x;
+    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi);
+    const uint32_t h1 = h0 | run.khi;
+    const uint32_t hb0 = h0 << run.L;
+    const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
+    const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
+    if (B0.cnt == 0 || B1.cnt == 0) {   // no pair of the run has both ends in the sector
+        if (VEC == 2)
+            for (int jl = tid; jl < run.g1 - run.g0; jl += BS)
+                s.part_g[size_t(run.g0 + jl) * s.gstride + o] = 0.0;
+        return;
+    }
+    const int c0 = B0.cnt;
+    const int c1 = run.khi ? B1.cnt : 0;
+    const int nE = c0 + c1;
+    const int eoff = run.khi ? c0 : 0;   // E entries: block h | khi, or block h itself
+    const int cBE = B1.cB;
+    const int64_t g0 = base[h0], g1 = base[h1];
+    double2* shp = sh;
+    double2* shl = sh + nE;
+#pragma unroll
+    for (int u = 0; u < 2 * EPT; ++u) {
+        const int k = tid + BS * u;
+        if (k < nE) {
+            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            shp[k] = nt_load(&s.phi[gi]);
+            if (VEC == 2) shl[k] = nt_load(&s.lam[gi]);
+        }
+    }
+    uint32_t r[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int k = tid + BS * u;
+        r[u] = (k < c0) ? uint32_t(T.unA[T.offA[B0.kA] + k / B0.cB] | T.unB[T.offB[B0.kB] + k % B0.cB])
+                        : 0u;
+    }
+    __syncthreads();
+    const bool fwd = (VEC == 1);
+    const int ng = run.g1 - run.g0;
+    for (int t = 0; t < ng; ++t) {
+        const int jl = fwd ? t : ng - 1 - t;
+        const PackedGate g = pg[jl];
+        const double2 cs = s.cs[run.g0 + jl];
+        const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const uint32_t rd = r[u];
+            const int k = tid + BS * u;
+            if (k < c0 && (rd & (g.pd | g.klo)) == g.pd) {
+                const uint32_t re = rd ^ g.pd ^ g.klo;
+                const int ie = eoff + int(T.rankA[even_bits7(re)]) * cBE + int(T.rankB[even_bits7(re >> 1)]);
+                const double sg = sgn_hi * parity_sign(rd & g.chlo);
+                if (fwd) {
+                    double2 d = shp[k], e = shp[ie];
+                    givens(d, e, cs.x, sg * cs.y);
+                    shp[k] = d;
+                    shp[ie] = e;
+                } else {
+                    double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
+                    // <lam| A phi> with A|D> = s|E>, A|E> = -s|D>
+                    acc += sg * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
+                    const double ss = -sg * cs.y;   // U^dag: rotation by -theta
+                    givens(fD, fE, cs.x, ss);
+                    givens(lD, lE, cs.x, ss);
+                    shp[k] = fD;
+                    shp[ie] = fE;
+                    shl[k] = lD;
+                    shl[ie] = lE;
+                }
+            }
+        }
+        if (!fwd) {
+            acc = wave_sum(acc);
+            if ((tid & 63) == 0) red[jl][tid >> 6] = acc;
+        }
+        __syncthreads();
+    }
+    if (!fwd) {
+        for (int jl = tid; jl < ng; jl += BS) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < BS / 64; ++w) v += red[jl][w];
+            s.part_g[size_t(run.g0 + jl) * s.gstride + o] = v;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * EPT; ++u) {
+        const int k = tid + BS * u;
+        if (k < nE) {
+            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            nt_store(&s.phi[gi], shp[k]);
+            if (VEC == 2) nt_store(&s.lam[gi], shl[k]);
+        }
+    }
+}
+
+// Launch shapes (threads per tile, entries per thread) by block capacity.
+struct PShape {
+    int bs, ept;
+};
+constexpr PShape kPShapes[] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {256, 3}, {256, 5}};
+constexpr int kNumPShapes = int(sizeof(kPShapes) / sizeof(kPShapes[0]));
+
+int packed_shape(int max_block) {
+    for (int i = 0; i < kNumPShapes; ++i)
+        if (kPShapes[i].bs * kPShapes[i].ept >= max_block) return i;
+    return -1;
+}
+
+int packed_shape_threads(int shape) { return kPShapes[shape].bs; }
+
+template <int VEC, int BS, int EPT>
+static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
+                       const HxTables* tabs, const int32_t* base, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(run.ntiles, count), dim3(BS), lds, st, sd, run,
+                       pg, tabs, base);
+}
+
+template <int VEC>
+static void launch_vec(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
+                       const HxTables* tabs, const int32_t* base, hipStream_t st) {
+    const size_t lds = size_t(run.max_entries) * sizeof(double2) * VEC;
+    switch (run.shape) {
+        case 0: launch_one<VEC, 64, 1>(sd, count, run, pg, tabs, base, lds, st); break;
+        case 1: launch_one<VEC, 64, 2>(sd, count, run, pg, tabs, base, lds, st); break;
+        case 2: launch_one<VEC, 64, 4>(sd, count, run, pg, tabs, base, lds, st); break;
+        case 3: launch_one<VEC, 64, 8>(sd, count, run, pg, tabs, base, lds, st); break;
+        case 4: launch_one<VEC, 256, 3>(sd, count, run, pg, tabs, base, lds, st); break;
+        default: launch_one<VEC, 256, 5>(sd, count, run, pg, tabs, base, lds, st); break;
+    }
+}
+
+void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
+                       const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st) {
+    if (adjoint)
+        launch_vec<2>(sd, count, run, pg, tabs, base, st);
+    else
+        launch_vec<1>(sd, count, run, pg, tabs, base, st);
+}
+
+void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st) {
+    const int nblk = blocks_for(uint64_t(size));
+    hipLaunchKernelGGL(k_packed_hf, dim3(nblk, count), dim3(kBlock), 0, st, sd, size);
+}
+
+int packed_enable_lds(size_t bytes) {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+        if (r != hipSuccess) e = r;
+    };
+#define VQE_PSET(V)                                                    \
+    set(reinterpret_cast<const void*>(&k_prun<V, 64, 1>));             \
+    set(reinterpret_cast<const void*>(&k_prun<V, 64, 2>));             \
+    set(reinterpret_cast<const void*>(&k_prun<V, 64, 4>));             \
+    set(reinterpret_cast<const void*>(&k_prun<V, 64, 8>));             \
+    set(reinterpret_cast<const void*>(&k_prun<V, 256, 3>));            \
+    set(reinterpret_cast<const void*>(&k_prun<V, 256, 5>));
+    VQE_PSET(1)
+    VQE_PSET(2)
+#undef VQE_PSET
+    return e == hipSuccess ? 0 : 1;
+}
+
+}  // namespace vqe

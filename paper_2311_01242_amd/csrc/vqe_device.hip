@@ -10,10 +10,13 @@
 // Forward and reverse gate steps are fused tile passes over runs of
 // excitations (or single per-gate launches for explicit Pauli rotations).
 // The H-apply is restricted to the (N, S_z) sector of the reference whenever
-// every gate conserves both counts.
+// every gate conserves both counts; for UCCSD programs the whole evaluation
+// then runs on the packed sector layout (k_packed.hip), which stores only the
+// in-sector amplitudes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -90,9 +93,23 @@ struct DevHam {
     std::map<int, struct HxWork*> work;   // L -> sector H-apply work list
 };
 
+// Launch plan of an ansatz on the packed sector layout with block bits L.
+struct PackedPlan {
+    int L = 0;
+    std::vector<PackedRun> runs;
+    std::vector<int> off;             // PackedGate offset per run
+    PackedGate* d_gates = nullptr;
+    std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
+    int32_t* d_gcnt = nullptr;
+    int32_t gstride = 1;
+    size_t max_lds = 0;
+    double fwd_bytes = 0.0, adj_bytes = 0.0;   // algorithmic traffic of one evaluation
+};
+
 struct DevAnsatz {
     GateDesc* gates = nullptr;
     std::map<std::pair<int64_t, int64_t>, AnsatzPlan*> plans;
+    std::map<int, PackedPlan*> packed;   // by L
 };
 
 static int current_device(int* dev) {
@@ -410,6 +427,178 @@ static int hx_tables(int L, HxTables** out) {
     return VQE_OK;
 }
 
+// ---------------------------------------------------------- packed layout
+
+// Block sizes and offsets of the packed sector layout of (n, ne) with block
+// bits L: block h holds C(La, kA) C(Lb, kB) amplitudes, kA and kB being the
+// electrons the reference leaves to the low bits after h's own.
+struct PackedLayout {
+    int n = 0, na = 0, nb = 0, L = 0;
+    int64_t size = 0;                    // in-sector amplitudes
+    std::vector<int32_t> base, bsize;    // per block h < 2^(n - L)
+    int32_t* d_base = nullptr;
+};
+
+static std::mutex g_lay_mu;
+static std::map<std::tuple<int, int, int, int>, PackedLayout*> g_lay;   // (dev, n, ne, L)
+
+static int64_t binom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+static int packed_layout(int n, int ne, int L, PackedLayout** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_lay_mu);
+    const auto key = std::make_tuple(dev, n, ne, L);
+    auto it = g_lay.find(key);
+    if (it != g_lay.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    auto* lay = new PackedLayout();
+    lay->n = n;
+    lay->na = (ne + 1) / 2;
+    lay->nb = ne / 2;
+    lay->L = L;
+    const int La = (L + 1) / 2, Lb = L / 2;
+    const uint32_t nblocks = 1u << (n - L);
+    lay->base.resize(nblocks);
+    lay->bsize.resize(nblocks);
+    int64_t pos = 0;
+    for (uint32_t h = 0; h < nblocks; ++h) {
+        const uint32_t hb = h << L;
+        const int kA = lay->na - __builtin_popcount(hb & 0x55555555u);
+        const int kB = lay->nb - __builtin_popcount(hb & 0xAAAAAAAAu);
+        const int64_t c = binom(La, kA) * binom(Lb, kB);
+        lay->base[h] = int32_t(pos);
+        lay->bsize[h] = int32_t(c);
+        pos += c;
+    }
+    lay->size = pos;
+    if (pos != binom((n + 1) / 2, lay->na) * binom(n / 2, lay->nb) || pos > INT32_MAX) {
+        delete lay;
+        return fail(VQE_EINVAL, "packed layout: sector size mismatch");
+    }
+    if (int rc = upload(&lay->d_base, lay->base.data(), lay->base.size())) {
+        delete lay;
+        return rc;
+    }
+    g_lay[key] = lay;
+    *out = lay;
+    return VQE_OK;
+}
+
+// Smallest block-bit count for which every gate of A can run on the packed
+// layout (all excitations, annihilated orbitals in the low bits) and the
+// reference of ne electrons is entry 0 (block 0), or -1.
+static int packed_min_L(const vqe_ansatz* A, int ne) {
+    int need = std::max(1, ne);
+    for (const GateDesc& g : A->gates) {
+        if (g.type != kExcitation || g.pd == 0) return -1;
+        const uint32_t key = g.x & ~g.pd;
+        if (__builtin_popcount(g.pd & 0x55555555u) != __builtin_popcount(key & 0x55555555u) ||
+            __builtin_popcount(g.pd & 0xAAAAAAAAu) != __builtin_popcount(key & 0xAAAAAAAAu))
+            return -1;
+        need = std::max(need, 32 - __builtin_clz(g.pd));
+    }
+    return need;
+}
+
+static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& lay,
+                       PackedPlan** out) {
+    std::lock_guard<std::mutex> lk(A->mu);
+    auto it = da->packed.find(lay.L);
+    if (it != da->packed.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    const int n = A->n, L = lay.L;
+    const uint32_t hmask = (1u << (n - L)) - 1u, lowmask = (1u << L) - 1u;
+    const int64_t M = int64_t(A->gates.size());
+    auto* p = new PackedPlan();
+    p->L = L;
+    p->gcnt.assign(size_t(M), 1);
+    std::vector<PackedGate> pg;
+    int64_t j = 0;
+    while (j < M) {
+        const GateDesc& g = A->gates[j];
+        const uint32_t khi = (g.x & ~g.pd) >> L;
+        int64_t j2 = j + 1;
+        while (j2 < M && j2 - j < kMaxRunGates &&
+               ((A->gates[j2].x & ~A->gates[j2].pd) >> L) == khi)
+            ++j2;
+        PackedRun r{};
+        r.g0 = int32_t(j);
+        r.g1 = int32_t(j2);
+        r.khi = khi;
+        r.free_hi = hmask & ~khi;
+        r.ntiles = int32_t(1u << __builtin_popcount(r.free_hi));
+        r.L = L;
+        r.na = lay.na;
+        r.nb = lay.nb;
+        int maxb = 1, maxe = 1;
+        int64_t moved = 0;
+        for (int32_t o = 0; o < r.ntiles; ++o) {
+            uint32_t h0 = 0, bits = r.free_hi, v = uint32_t(o);
+            while (bits) {
+                const uint32_t low = bits & (~bits + 1u);
+                if (v & 1u) h0 |= low;
+                v >>= 1;
+                bits &= bits - 1;
+            }
+            const int c0 = lay.bsize[h0], c1 = khi ? lay.bsize[h0 | khi] : 0;
+            if (c0 == 0 || (khi && c1 == 0)) continue;
+            maxb = std::max(maxb, std::max(c0, c1));
+            maxe = std::max(maxe, c0 + c1);
+            moved += c0 + c1;
+        }
+        r.shape = packed_shape(maxb);
+        r.max_entries = maxe;
+        if (r.shape < 0) {
+            delete p;
+            return fail(VQE_EINVAL, "packed layout: block too large for the run kernels");
+        }
+        p->off.push_back(int(pg.size()));
+        for (int64_t k = j; k < j2; ++k) {
+            const GateDesc& h = A->gates[k];
+            PackedGate q{};
+            q.pd = h.pd;
+            q.klo = (h.x & ~h.pd) & lowmask;
+            q.chlo = h.chain & lowmask;
+            q.chhi = h.chain & ~lowmask;
+            q.csign = h.csign;
+            pg.push_back(q);
+            p->gcnt[k] = r.ntiles;
+        }
+        p->gstride = std::max(p->gstride, r.ntiles);
+        p->max_lds = std::max(p->max_lds, size_t(maxe) * sizeof(double2) * 2);
+        p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved);
+        p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved);
+        p->runs.push_back(r);
+        j = j2;
+    }
+    p->fwd_bytes += double(sizeof(double2)) * double(lay.size);   // |HF> write
+    int rc = upload(&p->d_gates, pg.data(), pg.size());
+    if (!rc) rc = upload(&p->d_gcnt, p->gcnt.data(), p->gcnt.size());
+    if (!rc && p->max_lds > (64u << 10) && packed_enable_lds(p->max_lds) != 0)
+        rc = fail(VQE_EDEVICE, "could not enable " + std::to_string(p->max_lds) + " bytes of LDS");
+    if (rc) {
+        (void)hipFree(p->d_gates);
+        (void)hipFree(p->d_gcnt);
+        delete p;
+        return rc;
+    }
+    da->packed[L] = p;
+    *out = p;
+    return VQE_OK;
+}
+
+static std::atomic<int> g_packed_enabled{1};
+
 // ------------------------------------------------------------- workspaces
 
 // Reusable device memory of the single-state path, one per (device, stream).
@@ -493,9 +682,17 @@ struct EvalPlan {
     const vqe_ansatz* A = nullptr;
     AnsatzPlan* ap = nullptr;
     bool sector = false;
+    bool packed = false;     // the whole evaluation on the packed sector layout
+    PackedLayout* lay = nullptr;
+    PackedPlan* pp = nullptr;
     HxPlan hx{};
     HxTables* hxt = nullptr;
     int nblk_e = 1;          // energy partials per state
+    int32_t gstride = 1;     // gradient partials per gate (stride)
+    const int32_t* d_gcnt = nullptr;
+    int64_t elems = 0;       // amplitudes per state vector
+    double fwd_bytes = 0.0, adj_bytes = 0.0;
+    size_t fwd_steps = 0, adj_steps = 0;
 };
 
 static bool sector_path(const vqe_ansatz* A, int ne) {
@@ -513,13 +710,35 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
     if (int rc = dev_ansatz(A, &da)) return rc;
     if (int rc = get_plan(A, da, tn, &ep->ap)) return rc;
     ep->sector = sector_path(A, ne);
+    ep->gstride = ep->ap->gstride;
+    ep->d_gcnt = ep->ap->d_gcnt;
+    ep->elems = int64_t(1) << n;
+    ep->fwd_bytes = ep->ap->fwd_bytes;
+    ep->adj_bytes = ep->ap->adj_bytes;
+    ep->fwd_steps = ep->ap->fwd_steps.size();
+    ep->adj_steps = ep->ap->adj_steps.size();
     if (ep->sector) {
         ep->hx.L = std::min(n, tn.L);
+        const int need = g_packed_enabled.load() ? packed_min_L(A, ne) : -1;
+        if (need > 0 && need <= std::min(n, kHxMaxL)) {
+            ep->packed = true;
+            ep->hx.L = std::max(ep->hx.L, need);
+        }
         ep->hx.ntiles = 1 << (n - ep->hx.L);
         ep->hx.na = (ne + 1) / 2;
         ep->hx.nb = ne / 2;
         if (int rc = hx_tables(ep->hx.L, &ep->hxt)) return rc;
         ep->nblk_e = ep->hx.ntiles;
+        if (ep->packed) {
+            if (int rc = packed_layout(n, ne, ep->hx.L, &ep->lay)) return rc;
+            if (int rc = packed_plan(A, da, *ep->lay, &ep->pp)) return rc;
+            ep->gstride = ep->pp->gstride;
+            ep->d_gcnt = ep->pp->d_gcnt;
+            ep->elems = ep->lay->size;
+            ep->fwd_bytes = ep->pp->fwd_bytes;
+            ep->adj_bytes = ep->pp->adj_bytes;
+            ep->fwd_steps = ep->adj_steps = ep->pp->runs.size();
+        }
     } else {
         ep->nblk_e = blocks_for(uint64_t(1) << n);
     }
@@ -529,8 +748,34 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
 enum Phase { kPhaseFwd = 0, kPhaseHx = 1, kPhaseAdj = 2, kPhaseReduce = 3 };
 
 // Enqueue one phase of an evaluation for `count` states at sd.
+static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, int phase,
+                           bool grad, hipStream_t st) {
+    const PackedPlan& pp = *ep.pp;
+    if (phase == kPhaseFwd) {
+        launch_angles(sd, count, ep.M, st);
+        launch_packed_hf(sd, count, ep.lay->size, st);
+        for (size_t r = 0; r < pp.runs.size(); ++r)
+            launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
+                              ep.lay->d_base, false, st);
+    } else if (phase == kPhaseHx) {
+        launch_hx_packed(sd, count, ep.hx, ep.hxt, ep.lay->d_base, st);
+    } else if (phase == kPhaseAdj) {
+        if (!grad) return;
+        for (size_t r = pp.runs.size(); r-- > 0;)
+            launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
+                              ep.lay->d_base, true, st);
+    } else {
+        launch_reduce_e(sd, count, ep.nblk_e, st);
+        if (grad) launch_reduce_g(sd, count, ep.M, pp.d_gcnt, 0, st);
+    }
+}
+
 static void enqueue_phase(const EvalPlan& ep, const StateDesc* sd, int count, int phase, bool grad,
                           hipStream_t st) {
+    if (ep.packed) {
+        enqueue_packed(ep, sd, count, phase, grad, st);
+        return;
+    }
     const uint64_t N = uint64_t(1) << ep.n;
     const AnsatzPlan& ap = *ep.ap;
     if (phase == kPhaseFwd) {
@@ -633,6 +878,11 @@ vqe_ansatz::~vqe_ansatz() {
         for (auto& pl : kv.second->plans) {
             (void)hipFree(pl.second->d_fwd_tg);
             (void)hipFree(pl.second->d_adj_tg);
+            (void)hipFree(pl.second->d_gcnt);
+            delete pl.second;
+        }
+        for (auto& pl : kv.second->packed) {
+            (void)hipFree(pl.second->d_gates);
             (void)hipFree(pl.second->d_gcnt);
             delete pl.second;
         }
@@ -842,14 +1092,17 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     sz.add<double>(P);
     sz.add<double2>(M);
     sz.add<double>(ep.nblk_e);
-    sz.add<double>(size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride);
+    sz.add<double>(size_t(std::max<int64_t>(M, 1)) * ep.gstride);
     sz.add<double>(1);
     sz.add<double>(M);
     sz.add<StateDesc>(1);
     Workspace* ws;
-    if (int rc = workspace(stream, sizeof(double2) << n, sz.s, &ws)) return rc;
-    // the sector H-apply writes only in-sector entries: lambda must be zero elsewhere
-    if (ep.sector && ws->lam_zero_key != sector_key(n, ne)) {
+    if (int rc = workspace(stream, sizeof(double2) * size_t(ep.elems), sz.s, &ws)) return rc;
+    // the full-layout sector H-apply writes only in-sector entries: lambda
+    // must be zero elsewhere (the packed layout holds nothing else)
+    if (ep.packed) {
+        ws->lam_zero_key = -1;
+    } else if (ep.sector && ws->lam_zero_key != sector_key(n, ne)) {
         launch_fill_zero(ws->lam, ws->state_bytes / sizeof(double2), st);
         ws->lam_zero_key = sector_key(n, ne);
     } else if (!ep.sector) {
@@ -872,14 +1125,14 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
         sd.nb = hw->count;
     }
     sd.part_e = cv.take<double>(ep.nblk_e);
-    sd.part_g = cv.take<double>(size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride);
+    sd.part_g = cv.take<double>(size_t(std::max<int64_t>(M, 1)) * ep.gstride);
     sd.out_e = cv.take<double>(1);
     sd.out_g = cv.take<double>(M);
     sd.n = n;
     sd.G = int32_t(H->groups.size());
     sd.M = int32_t(M);
     sd.ne = ne;
-    sd.gstride = ep.ap->gstride;
+    sd.gstride = ep.gstride;
     StateDesc* sd_dev = cv.take<StateDesc>(1);
     if (P > 0)
         HIPCHK(hipMemcpyAsync(const_cast<double*>(sd.theta), theta, sizeof(double) * P,
@@ -989,13 +1242,9 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     if (!out || !H || !A || !ne) return fail(VQE_EINVAL, "null pointer argument");
     *out = nullptr;
     if (S < 1) return fail(VQE_ERANGE, "n_states must be >= 1");
-    size_t need = 0;
-    for (int i = 0; i < S; ++i) {
+    for (int i = 0; i < S; ++i)
         if (int rc = check_pair(H[i], A[i], ne[i]))
             return fail(rc, "state " + std::to_string(i) + ": " + vqe_last_error());
-        need += 2 * (sizeof(double2) << H[i]->n);
-    }
-    if (int rc = fits_device(need)) return rc;
     auto* b = new vqe_batch();
     std::unique_ptr<vqe_batch> guard(b);
     b->S = S;
@@ -1030,6 +1279,9 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     b->classes.resize(rep.size());
     for (size_t c = 0; c < rep.size(); ++c)
         if (int rc = make_eval_plan(A[rep[c]], ne[rep[c]], true, &b->classes[c].ep)) return rc;
+    size_t need = 0;
+    for (int i = 0; i < S; ++i) need += 2 * sizeof(double2) * size_t(b->classes[cls[i]].ep.elems);
+    if (int rc = fits_device(need)) return rc;
     if (int rc = dalloc(b, &b->theta_dev, b->poff[S])) return rc;
     if (int rc = dalloc(b, &b->e_dev, S)) return rc;
     if (int rc = dalloc(b, &b->g_dev, b->goff[S])) return rc;
@@ -1059,12 +1311,12 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.csubs = hw->csubs;
             sd.nb = hw->count;
         }
-        if (int rc = dalloc(b, &sd.phi, size_t(1) << n)) return rc;
-        if (int rc = dalloc(b, &sd.lam, size_t(1) << n)) return rc;
-        launch_fill_zero(sd.lam, uint64_t(1) << n, b->st);
+        if (int rc = dalloc(b, &sd.phi, size_t(ep.elems))) return rc;
+        if (int rc = dalloc(b, &sd.lam, size_t(ep.elems))) return rc;
+        launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
         if (int rc = dalloc(b, &sd.part_e, ep.nblk_e)) return rc;
-        if (int rc = dalloc(b, &sd.part_g, size_t(std::max<int64_t>(M, 1)) * ep.ap->gstride))
+        if (int rc = dalloc(b, &sd.part_g, size_t(std::max<int64_t>(M, 1)) * ep.gstride))
             return rc;
         sd.gates = da->gates;
         sd.theta = b->theta_dev + b->poff[i];
@@ -1077,16 +1329,16 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         sd.G = int32_t(H[i]->groups.size());
         sd.M = int32_t(M);
         sd.ne = ne[i];
-        sd.gstride = ep.ap->gstride;
-        b->work[0] += ep.ap->fwd_bytes;
-        b->work[2] += ep.ap->adj_bytes;
-        b->work[3] += 2.0 * double(sizeof(double2)) * double(uint64_t(1) << n);
+        sd.gstride = ep.gstride;
+        b->work[0] += ep.fwd_bytes;
+        b->work[2] += ep.adj_bytes;
+        b->work[3] += 2.0 * double(sizeof(double2)) * double(ep.elems);
     }
     HIPCHK(hipGetLastError());
     for (auto& c : b->classes) {   // launches per evaluation (one per class and step)
-        b->work[4] += double(c.ep.ap->fwd_steps.size());
+        b->work[4] += double(c.ep.fwd_steps);
         b->work[5] += 1.0;
-        b->work[6] += double(c.ep.ap->adj_steps.size());
+        b->work[6] += double(c.ep.adj_steps);
     }
     if (int rc = dalloc(b, &b->sd_dev, S)) return rc;
     HIPCHK(hipMemcpy(b->sd_dev, sds.data(), sizeof(StateDesc) * S, hipMemcpyHostToDevice));
@@ -1216,3 +1468,8 @@ extern "C" int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes,
 }
 
 extern "C" void vqe_batch_free(vqe_batch* b) { delete b; }
+
+extern "C" int vqe_set_packed(int enable) {
+    g_packed_enabled.store(enable ? 1 : 0);
+    return VQE_OK;
+}

@@ -274,3 +274,83 @@ def test_workspace_switches_between_dense_and_sector_paths():
     e, g = vq.energy_grad(H, A, ne, theta)
     assert abs(e - prob.energy(theta)) < TOL_E
     assert np.abs(g - prob.grad_shift(theta)).max() < TOL_E
+
+
+# ------------------------------------------------------ packed sector layout
+
+def _eval_layout(H, n, ne, theta, packed):
+    """energy_grad with the packed layout on or off (fresh ansatz handle, so
+    the plan is made under the requested setting)."""
+    vq.set_packed(packed)
+    try:
+        return vq.energy_grad(H, vq.Ansatz.uccsd(n, ne), ne, theta)
+    finally:
+        vq.set_packed(True)
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 2), (6, 3), (7, 3), (8, 4), (9, 5), (10, 5),
+                                  (11, 4), (12, 6), (13, 7), (14, 7), (16, 8)])
+def test_packed_layout_matches_full_layout_and_oracle(n, ne):
+    """The packed sector layout (only in-sector amplitudes stored) against
+    full 2^n vectors and the oracle, odd and even n, open shells."""
+    H, A, prob = _pair(n, ne, 1100 + n)
+    theta = uniform_theta(1200 + n, A.n_params)
+    ep, gp = _eval_layout(H, n, ne, theta, True)
+    ef, gf = _eval_layout(H, n, ne, theta, False)
+    assert abs(ep - ef) < 1e-12 and np.abs(gp - gf).max() < 1e-12
+    assert abs(ep - prob.energy(theta)) < TOL_E
+    idx = sorted(np.random.default_rng(n).choice(A.n_params, min(4, A.n_params),
+                                                 replace=False).tolist())
+    assert np.abs(gp[idx] - prob.grad_shift(theta, idx)).max() < TOL_E
+
+
+@pytest.mark.parametrize("L", [6, 7, 9, 11, 12])
+def test_packed_block_bits_agree(L):
+    """Every block-bit count from the electron count up gives the same result
+    (different block pairs, run splits and H-apply tiles)."""
+    n, ne = 12, 6
+    H, A, prob = _pair(n, ne, 1301)
+    theta = uniform_theta(1302, A.n_params)
+    lib = vq.lib()
+    try:
+        assert lib.vqe_set_tuning(n, 0, 65536, 65536, L) == 0
+        e, g = vq.energy_grad(H, vq.Ansatz.uccsd(n, ne), ne, theta)
+    finally:
+        lib.vqe_set_tuning(n, 0, 0, 0, 0)
+    ef, gf = _eval_layout(H, n, ne, theta, False)
+    assert abs(e - prob.energy(theta)) < TOL_E
+    assert abs(e - ef) < 1e-12 and np.abs(g - gf).max() < 1e-12
+
+
+def test_packed_reference_only_programs():
+    """Programs without excitations (closed shells ne = 0 and ne = n): the
+    packed state is the reference alone."""
+    for n, ne in [(6, 0), (6, 6), (5, 5)]:
+        h0, h, g = random_integrals(n, 1400 + n)
+        H = vq.Hamiltonian.from_integrals(n, h0, h, g)
+        A = vq.Ansatz.uccsd(n, ne)
+        assert A.n_params == 0
+        e, grad = vq.energy_grad(H, A, ne, np.zeros(0))
+        assert grad.size == 0
+        assert abs(e - F.Problem(n, ne, h0, h, g).energy(np.zeros(0))) < TOL_E
+
+
+def test_batch_packed_matches_full_layout():
+    specs = [(8, 4, 1), (10, 5, 2), (11, 5, 3), (12, 6, 4), (12, 6, 5), (14, 7, 6)]
+    Hs, thetas = [], []
+    for n, ne, s in specs:
+        h0, h, g = random_integrals(n, 1500 + s)
+        Hs.append(vq.Hamiltonian.from_integrals(n, h0, h, g))
+        thetas.append(uniform_theta(1600 + s, vq.Ansatz.uccsd(n, ne).n_params))
+    flat = np.concatenate(thetas)
+    out = []
+    for packed in (True, False):
+        vq.set_packed(packed)
+        try:
+            b = vq.Batch(Hs, [vq.Ansatz.uccsd(n, ne) for n, ne, _ in specs],
+                         [ne for _, ne, _ in specs])
+        finally:
+            vq.set_packed(True)
+        out.append(b.energy_grad(flat))
+    (e1, g1), (e2, g2) = out
+    assert np.abs(e1 - e2).max() < 1e-12 and np.abs(g1 - g2).max() < 1e-12
