@@ -31,7 +31,8 @@ constexpr int kMaxTabBits = 4;
 
 struct GroupDesc {
     uint32_t x;        // flip mask
-    uint32_t pos;      // bits 0..2: k (table bits); then k 5-bit positions
+    uint32_t pos;      // bits 0..2: k (table bits); then four 5-bit positions, the
+                       // k table bits in ascending order, unused slots = 31
     int32_t sub_begin; // subgroup range [sub_begin, sub_end)
     int32_t sub_end;
 };

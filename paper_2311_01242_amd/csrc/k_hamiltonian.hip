@@ -200,6 +200,163 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
     if (threadIdx.x == 0) s.part_e[blockIdx.x] = r;
 }
 
+// Sector H-apply on the packed layout.  Same tiling as k_hx_sector (output
+// tile = block h, partner block h ^ x_hi staged in LDS), with each output's
+// low alpha and beta bits kept as compact 7-bit strings, so that the
+// partner's position is two rank-table reads, and with every group and
+// subgroup field read into scalar registers (they are the same for all
+// lanes).  A group can pair sector states only when its flip mask has an
+// even number of alpha and of beta bits, half of them occupied in the output.
+__global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restrict__ sd, HxPlan plan,
+                                                      const HxTables* __restrict__ tabsrc,
+                                                      const int32_t* __restrict__ base) {
+    __shared__ double2 stage[kMaxStage];
+    __shared__ double tch[kChunkTabs];
+    __shared__ GroupDesc gch[kChunkGroups];
+    __shared__ SubDesc sch[kChunkSubs];
+    __shared__ HxTables T;
+    __shared__ double red[kBlock / 64];
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
+        for (int i = threadIdx.x; i < int(sizeof(HxTables) / 4); i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+    const StateDesc& s = sd[blockIdx.y];
+    const double2* __restrict__ phi = s.phi;
+    const double* __restrict__ tabs = s.tabs;
+    const int L = plan.L;
+    const uint32_t ohi = uint32_t(blockIdx.x) << L;
+    const int kA = plan.na - __popc(ohi & 0x55555555u);
+    const int kB = plan.nb - __popc(ohi & 0xAAAAAAAAu);
+    if (kA < 0 || kA > T.La || kB < 0 || kB > T.Lb) {   // empty block
+        if (threadIdx.x == 0) s.part_e[blockIdx.x] = 0.0;
+        return;
+    }
+    const int cB = T.offB[kB + 1] - T.offB[kB];
+    const int cnt = (T.offA[kA + 1] - T.offA[kA]) * cB;
+    uint32_t sv[kHxOuts], ca[kHxOuts], cb[kHxOuts];
+    bool live[kHxOuts];
+    double lr[kHxOuts], li[kHxOuts];
+    // a slot past the block's end works on a copy of entry 0 and is not written
+#pragma unroll
+    for (int u = 0; u < kHxOuts; ++u) {
+        const int k = threadIdx.x + u * kBlock;
+        live[u] = k < cnt;
+        const int kc = live[u] ? k : 0;
+        const uint32_t lo = uint32_t(T.unA[T.offA[kA] + kc / cB] | T.unB[T.offB[kB] + kc % cB]);
+        sv[u] = ohi | lo;
+        ca[u] = compact_even(lo);
+        cb[u] = compact_even(lo >> 1);
+        lr[u] = li[u] = 0.0;
+    }
+    uint32_t staged = 0xffffffffu;   // x_hi whose partner block is in `stage`
+    int cB2 = 1, cnt2 = 1;
+    for (int c = 0; c < s.nb; ++c) {
+        const HxChunk ck = s.chunks[c];
+        if (ck.xhi != staged) {
+            const uint32_t hp = uint32_t(blockIdx.x) ^ ck.xhi;
+            const uint32_t phi_hi = hp << L;
+            const int a2 = plan.na - __popc(phi_hi & 0x55555555u);
+            const int b2 = plan.nb - __popc(phi_hi & 0xAAAAAAAAu);
+            if (a2 < 0 || a2 > T.La || b2 < 0 || b2 > T.Lb) {   // partner block empty: skip batch
+                while (c + 1 < s.nb && s.chunks[c + 1].xhi == ck.xhi) ++c;
+                continue;
+            }
+            cB2 = T.offB[b2 + 1] - T.offB[b2];
+            cnt2 = (T.offA[a2 + 1] - T.offA[a2]) * cB2;
+            const double* src = reinterpret_cast<const double*>(phi + base[hp]);
+            double vr[kStagePer], vi[kStagePer];
+#pragma unroll
+            for (int k = 0; k < kStagePer; ++k) {   // clamped: every load is in the block
+                const int i = min(int(threadIdx.x) + k * kBlock, cnt2 - 1);
+                vr[k] = src[2 * i];
+                vi[k] = src[2 * i + 1];
+            }
+            __syncthreads();   // everyone done with the previous stage
+#pragma unroll
+            for (int k = 0; k < kStagePer; ++k) {
+                const int i = threadIdx.x + k * kBlock;
+                if (i < cnt2) stage[i] = make_double2(vr[k], vi[k]);
+            }
+            staged = ck.xhi;
+        } else {
+            __syncthreads();   // everyone done with the previous chunk
+        }
+        const int ng = ck.cg1 - ck.cg0, ns = ck.cs1 - ck.cs0, nt = ck.t1 - ck.t0;
+        for (int i = threadIdx.x; i < ng; i += kBlock) gch[i] = s.cgroups[ck.cg0 + i];
+        for (int i = threadIdx.x; i < ns; i += kBlock) sch[i] = s.csubs[ck.cs0 + i];
+        for (int i = threadIdx.x; i < nt; i += kBlock) tch[i] = tabs[ck.t0 + i];
+        __syncthreads();
+        for (int gi = 0; gi < ng; ++gi) {
+            const uint32_t x = __builtin_amdgcn_readfirstlane(gch[gi].x);
+            const uint32_t pos = __builtin_amdgcn_readfirstlane(gch[gi].pos);
+            const int sb = __builtin_amdgcn_readfirstlane(gch[gi].sub_begin);
+            const int se = __builtin_amdgcn_readfirstlane(gch[gi].sub_end);
+            const int nxa = __popc(x & 0x55555555u), nxb = __popc(x & 0xAAAAAAAAu);
+            if ((nxa | nxb) & 1) continue;   // changes N_alpha or N_beta: no in-sector pair
+            const uint32_t xl = x & ((1u << L) - 1u);
+            const uint32_t xa = compact_even(xl), xb = compact_even(xl >> 1);
+            const int ta = (nxa >> 1) - __popc(ohi & x & 0x55555555u);
+            const int tb = (nxb >> 1) - __popc(ohi & x & 0xAAAAAAAAu);
+            bool ok[kHxOuts];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) {
+                ok[u] = (__popc(ca[u] & xa) == ta) & (__popc(cb[u] & xb) == tb);
+                any |= ok[u];
+            }
+            if (!__ballot(any)) continue;   // wave-uniform skip
+            // table positions (bit 31 of an output string is 0: n < 32)
+            const uint32_t q0 = (pos >> 3) & 31, q1 = (pos >> 8) & 31, q2 = (pos >> 13) & 31,
+                           q3 = (pos >> 18) & 31;
+            double2 p[kHxOuts];
+            uint32_t ti[kHxOuts];
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) {
+                ti[u] = ((sv[u] >> q0) & 1u) | (((sv[u] >> q1) & 1u) << 1) |
+                        (((sv[u] >> q2) & 1u) << 2) | (((sv[u] >> q3) & 1u) << 3);
+                const int idx = int(T.rankA[ca[u] ^ xa]) * cB2 + int(T.rankB[cb[u] ^ xb]);
+                const double2 v = stage[min(idx, cnt2 - 1)];
+                p[u] = ok[u] ? v : make_double2(0.0, 0.0);
+            }
+            double d[kHxOuts];
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) d[u] = 0.0;
+            for (int si = sb; si < se; ++si) {
+                const uint32_t w = __builtin_amdgcn_readfirstlane(sch[si].w);
+                const int toff = __builtin_amdgcn_readfirstlane(sch[si].tab);
+#pragma unroll
+                for (int u = 0; u < kHxOuts; ++u) {
+                    // (-1)^{|b & w|} applied as a flip of the sign bit
+                    const double t = tch[toff + ti[u]];
+                    const uint32_t flip = uint32_t(__popc(sv[u] & w)) << 31;
+                    d[u] += __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kHxOuts; ++u) {
+                lr[u] += d[u] * p[u].x;   // p = 0 where the pair is not in the sector
+                li[u] += d[u] * p[u].y;
+            }
+        }
+    }
+    double acc = 0.0;
+    double2* out = s.lam + base[blockIdx.x];
+    const double2* own = phi + base[blockIdx.x];
+#pragma unroll
+    for (int u = 0; u < kHxOuts; ++u) {
+        const int k = threadIdx.x + u * kBlock;
+        if (live[u]) {
+            out[k] = make_double2(lr[u], li[u]);
+            const double2 q = own[k];
+            acc += q.x * lr[u] + q.y * li[u];
+        }
+    }
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) s.part_e[blockIdx.x] = r;
+}
+
 void launch_hx_dense(const StateDesc* sd, int count, uint64_t N, int nblk, int write_lam,
                      hipStream_t st) {
     hipLaunchKernelGGL(k_hx_dense, dim3(nblk, count), dim3(kBlock), 0, st, sd, N, write_lam);
@@ -213,8 +370,8 @@ void launch_hx_sector(const StateDesc* sd, int count, const HxPlan& plan, const 
 
 void launch_hx_packed(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
                       const int32_t* base, hipStream_t st) {
-    hipLaunchKernelGGL(k_hx_sector<true>, dim3(plan.ntiles, count), dim3(kBlock), 0, st, sd, plan,
-                       tabs, base);
+    hipLaunchKernelGGL(k_hx_packed, dim3(plan.ntiles, count), dim3(kBlock), 0, st, sd, plan, tabs,
+                       base);
 }
 
 }  // namespace vqe

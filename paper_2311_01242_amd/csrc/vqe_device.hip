@@ -496,6 +496,7 @@ static int packed_layout(int n, int ne, int L, PackedLayout** out) {
 // layout (all excitations, annihilated orbitals in the low bits) and the
 // reference of ne electrons is entry 0 (block 0), or -1.
 static int packed_min_L(const vqe_ansatz* A, int ne) {
+    if (A->n > 31) return -1;   // the packed H-apply relies on bit 31 of a string being 0
     int need = std::max(1, ne);
     for (const GateDesc& g : A->gates) {
         if (g.type != kExcitation || g.pd == 0) return -1;

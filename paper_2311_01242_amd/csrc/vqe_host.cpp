@@ -84,7 +84,8 @@ static void build_groups(vqe_hamiltonian* H) {
             for (int q = 0; q < 32; ++q)
                 if ((x >> q) & 1u) posv[kk++] = q;
             uint32_t pos = uint32_t(k);
-            for (int i = 0; i < k; ++i) pos |= uint32_t(posv[i]) << (3 + 5 * i);
+            for (int i = 0; i < kMaxTabBits; ++i)   // unused slots name bit 31 (zero when n < 32)
+                pos |= uint32_t(i < k ? posv[i] : 31) << (3 + 5 * i);
             gd.pos = pos;
             std::map<uint32_t, int32_t> sub_of;   // w -> subgroup index
             for (size_t t = t0; t < t1; ++t) {
@@ -109,6 +110,7 @@ static void build_groups(vqe_hamiltonian* H) {
             }
         } else {
             gd.pos = 0;
+            for (int i = 0; i < kMaxTabBits; ++i) gd.pos |= 31u << (3 + 5 * i);
             for (size_t t = t0; t < t1; ++t) {
                 const uint32_t z = H->z[t];
                 const double sx = (popc(x & z) & 1) ? -1.0 : 1.0;
