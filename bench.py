@@ -160,7 +160,9 @@ def run_batch(args):
     if not args.no_autotune:
         offs = np.cumsum([0] + [a.n_params for a in As])
         t0 = time.perf_counter()
-        tuned = autotune.autotune_batch(Hs, As, nes, theta, offs, cache=TUNE_CACHE)
+        tuned = autotune.autotune_batch(
+            Hs, As, nes, theta, offs, cache=TUNE_CACHE,
+            log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         print(f"# autotune {time.perf_counter() - t0:.1f}s: "
               + " ".join(f"n{n}=({f >> 10}K,{a >> 10}K,L{L})" for n, (f, a, L) in sorted(tuned.items())),
               file=sys.stderr, flush=True)

@@ -9,9 +9,12 @@ candidate parameters and keeps the fastest:
 * low-bit tile L of the sector H-apply.
 
 The three phases are timed separately, so the search is per phase rather
-than over the product of the candidate sets.  Only tiling changes: the gate
-order, and therefore the result up to summation order, never does.  Results
-are cached in a JSON file keyed by (device name, qubits, electrons, states).
+than over the product of the candidate sets.  On the packed sector layout
+(UCCSD programs, the default) L is also the layout's block size and the run
+budgets play no part, so only L is searched, by the time of the whole
+evaluation.  Only tiling changes: the gate order, and therefore the result
+up to summation order, never does.  Results are cached in a JSON file keyed
+by (device name, layout, qubits, electrons, states).
 """
 from __future__ import annotations
 
@@ -41,7 +44,7 @@ def _device_name():
         return "unknown"
 
 
-def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None):
+def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None, packed=True):
     """Best (fwd_budget, adj_budget, L) for one size class (batched launches)."""
     def measure(fwd, adj, L):
         set_tuning(n, True, fwd, adj, L)
@@ -50,6 +53,17 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None):
         ms = b.profile(theta, reps=reps)
         b.close()
         return ms
+    if packed:
+        best, best_t, best_ms = None, None, None
+        for L in sorted({min(n, max(L, ne)) for L in (8, 9, 10, 11, 12, 13, 14)}):
+            m = measure(64 << 10, 64 << 10, L)
+            t = m[0] + m[1] + m[2]
+            if log:
+                log(f"n={n} packed L={L}: {m[0]:.3f} + {m[1]:.3f} + {m[2]:.3f} ms")
+            if best_t is None or t < best_t:
+                best, best_t, best_ms = (64 << 10, 64 << 10, L), t, m
+        set_tuning(n, True, *best)
+        return best, best_ms
     base = (64 << 10, 64 << 10, min(n, 14))
     best = list(base)
     ms = measure(*base)
@@ -83,7 +97,7 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None):
 
 
 def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, max_per_class=64,
-                   log=None):
+                   log=None, packed=True):
     """Tune every size class of a batch and install the results (set_tuning).
     Returns {n: (fwd, adj, L)}."""
     cache_data = {}
@@ -97,7 +111,7 @@ def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, 
         classes.setdefault((n, ne), []).append(i)
     out = {}
     for (n, ne), idx in sorted(classes.items()):
-        key = f"{dev}|n={n}|ne={ne}|states={len(idx)}"
+        key = f"{dev}|{'packed' if packed else 'full'}|n={n}|ne={ne}|states={len(idx)}"
         if key in cache_data:
             fwd, adj, L = cache_data[key]
             set_tuning(n, True, fwd, adj, L)
@@ -105,7 +119,8 @@ def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, 
             continue
         sub = idx[:max_per_class]
         th = np.concatenate([theta_all[offsets[i]:offsets[i + 1]] for i in sub])
-        best, _ = tune_class([hams[i] for i in sub], ansatzes[sub[0]], n, ne, th, log=log)
+        best, _ = tune_class([hams[i] for i in sub], ansatzes[sub[0]], n, ne, th, log=log,
+                             packed=packed)
         out[n] = best
         cache_data[key] = list(best)
     if cache:

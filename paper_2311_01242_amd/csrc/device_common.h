@@ -74,6 +74,16 @@ struct HxTables {
 
 static_assert(sizeof(HxTables) % 4 == 0, "HxTables is copied as 32-bit words");
 
+// Rank of a compact 7-bit string within a popcount class, or -4096 when the
+// string's popcount differs: a[k][s] for alpha strings with k electrons,
+// b[k][s] for beta.  Stored right after HxTables (kRankKOffset bytes in).
+struct RankK {
+    int16_t a[8][128];
+    int16_t b[8][128];
+};
+constexpr size_t kRankKOffset = (sizeof(HxTables) + 255) & ~size_t(255);
+constexpr int kRankMiss = -4096;
+
 // The sector H-apply walks the groups in chunks small enough to stage in
 // LDS: chunk c covers chunk-local groups [cg0, cg1) (their sub ranges are
 // relative to cs0), subgroups [cs0, cs1) (table offsets relative to t0) and

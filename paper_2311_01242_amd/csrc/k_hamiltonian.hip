@@ -201,12 +201,13 @@ __global__ void __launch_bounds__(kBlock) k_hx_sector(const StateDesc* __restric
 }
 
 // Sector H-apply on the packed layout.  Same tiling as k_hx_sector (output
-// tile = block h, partner block h ^ x_hi staged in LDS), with each output's
-// low alpha and beta bits kept as compact 7-bit strings, so that the
-// partner's position is two rank-table reads, and with every group and
-// subgroup field read into scalar registers (they are the same for all
-// lanes).  A group can pair sector states only when its flip mask has an
-// even number of alpha and of beta bits, half of them occupied in the output.
+// tile = block h, partner block h ^ x_hi staged in LDS).  Thread t owns the
+// outputs k = t * kHxOuts + u; each output's low alpha and beta bits are
+// kept as compact 7-bit strings, and the partner's position within the
+// staged block comes from two class rank tables that also flag a partner of
+// the wrong electron count (negative index), so no separate sector test is
+// needed.  Group and subgroup fields are read into scalar registers (they
+// are the same for all lanes).
 __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restrict__ sd, HxPlan plan,
                                                       const HxTables* __restrict__ tabsrc,
                                                       const int32_t* __restrict__ base) {
@@ -215,11 +216,16 @@ __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restric
     __shared__ GroupDesc gch[kChunkGroups];
     __shared__ SubDesc sch[kChunkSubs];
     __shared__ HxTables T;
+    __shared__ RankK R;
     __shared__ double red[kBlock / 64];
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
         for (int i = threadIdx.x; i < int(sizeof(HxTables) / 4); i += kBlock) dst[i] = src[i];
+        const uint32_t* srk = reinterpret_cast<const uint32_t*>(
+            reinterpret_cast<const char*>(tabsrc) + kRankKOffset);
+        uint32_t* drk = reinterpret_cast<uint32_t*>(&R);
+        for (int i = threadIdx.x; i < int(sizeof(RankK) / 4); i += kBlock) drk[i] = srk[i];
     }
     __syncthreads();
     const StateDesc& s = sd[blockIdx.y];
@@ -236,22 +242,22 @@ __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restric
     const int cB = T.offB[kB + 1] - T.offB[kB];
     const int cnt = (T.offA[kA + 1] - T.offA[kA]) * cB;
     uint32_t sv[kHxOuts], ca[kHxOuts], cb[kHxOuts];
-    bool live[kHxOuts];
     double lr[kHxOuts], li[kHxOuts];
     // a slot past the block's end works on a copy of entry 0 and is not written
 #pragma unroll
     for (int u = 0; u < kHxOuts; ++u) {
-        const int k = threadIdx.x + u * kBlock;
-        live[u] = k < cnt;
-        const int kc = live[u] ? k : 0;
+        const int k = threadIdx.x * kHxOuts + u;
+        const int kc = (k < cnt) ? k : 0;
         const uint32_t lo = uint32_t(T.unA[T.offA[kA] + kc / cB] | T.unB[T.offB[kB] + kc % cB]);
         sv[u] = ohi | lo;
         ca[u] = compact_even(lo);
         cb[u] = compact_even(lo >> 1);
         lr[u] = li[u] = 0.0;
     }
+    // waves whose outputs all lie past the block's end only help with staging
+    const bool wave_live = __ballot(int(threadIdx.x) * kHxOuts < cnt) != 0;
     uint32_t staged = 0xffffffffu;   // x_hi whose partner block is in `stage`
-    int cB2 = 1, cnt2 = 1;
+    int cB2 = 1, kA2 = 0, kB2 = 0;
     for (int c = 0; c < s.nb; ++c) {
         const HxChunk ck = s.chunks[c];
         if (ck.xhi != staged) {
@@ -263,8 +269,10 @@ __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restric
                 while (c + 1 < s.nb && s.chunks[c + 1].xhi == ck.xhi) ++c;
                 continue;
             }
+            kA2 = a2;
+            kB2 = b2;
             cB2 = T.offB[b2 + 1] - T.offB[b2];
-            cnt2 = (T.offA[a2 + 1] - T.offA[a2]) * cB2;
+            const int cnt2 = (T.offA[a2 + 1] - T.offA[a2]) * cB2;
             const double* src = reinterpret_cast<const double*>(phi + base[hp]);
             double vr[kStagePer], vi[kStagePer];
 #pragma unroll
@@ -288,23 +296,24 @@ __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restric
         for (int i = threadIdx.x; i < ns; i += kBlock) sch[i] = s.csubs[ck.cs0 + i];
         for (int i = threadIdx.x; i < nt; i += kBlock) tch[i] = tabs[ck.t0 + i];
         __syncthreads();
+        if (!wave_live) continue;
+        const int16_t* ra = R.a[kA2];
+        const int16_t* rb = R.b[kB2];
         for (int gi = 0; gi < ng; ++gi) {
             const uint32_t x = __builtin_amdgcn_readfirstlane(gch[gi].x);
+            if ((__popc(x & 0x55555555u) | __popc(x & 0xAAAAAAAAu)) & 1)
+                continue;   // changes N_alpha or N_beta: no in-sector pair
             const uint32_t pos = __builtin_amdgcn_readfirstlane(gch[gi].pos);
             const int sb = __builtin_amdgcn_readfirstlane(gch[gi].sub_begin);
             const int se = __builtin_amdgcn_readfirstlane(gch[gi].sub_end);
-            const int nxa = __popc(x & 0x55555555u), nxb = __popc(x & 0xAAAAAAAAu);
-            if ((nxa | nxb) & 1) continue;   // changes N_alpha or N_beta: no in-sector pair
             const uint32_t xl = x & ((1u << L) - 1u);
             const uint32_t xa = compact_even(xl), xb = compact_even(xl >> 1);
-            const int ta = (nxa >> 1) - __popc(ohi & x & 0x55555555u);
-            const int tb = (nxb >> 1) - __popc(ohi & x & 0xAAAAAAAAu);
-            bool ok[kHxOuts];
+            int idx[kHxOuts];
             bool any = false;
 #pragma unroll
             for (int u = 0; u < kHxOuts; ++u) {
-                ok[u] = (__popc(ca[u] & xa) == ta) & (__popc(cb[u] & xb) == tb);
-                any |= ok[u];
+                idx[u] = int(ra[ca[u] ^ xa]) * cB2 + int(rb[cb[u] ^ xb]);
+                any |= idx[u] >= 0;
             }
             if (!__ballot(any)) continue;   // wave-uniform skip
             // table positions (bit 31 of an output string is 0: n < 32)
@@ -314,11 +323,10 @@ __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restric
             uint32_t ti[kHxOuts];
 #pragma unroll
             for (int u = 0; u < kHxOuts; ++u) {
-                ti[u] = ((sv[u] >> q0) & 1u) | (((sv[u] >> q1) & 1u) << 1) |
-                        (((sv[u] >> q2) & 1u) << 2) | (((sv[u] >> q3) & 1u) << 3);
-                const int idx = int(T.rankA[ca[u] ^ xa]) * cB2 + int(T.rankB[cb[u] ^ xb]);
-                const double2 v = stage[min(idx, cnt2 - 1)];
-                p[u] = ok[u] ? v : make_double2(0.0, 0.0);
+                ti[u] = __builtin_amdgcn_ubfe(sv[u], q0, 1) | (__builtin_amdgcn_ubfe(sv[u], q1, 1) << 1) |
+                        (__builtin_amdgcn_ubfe(sv[u], q2, 1) << 2) |
+                        (__builtin_amdgcn_ubfe(sv[u], q3, 1) << 3);
+                p[u] = (idx[u] >= 0) ? stage[idx[u]] : make_double2(0.0, 0.0);
             }
             double d[kHxOuts];
 #pragma unroll
@@ -346,8 +354,8 @@ __global__ void __launch_bounds__(kBlock) k_hx_packed(const StateDesc* __restric
     const double2* own = phi + base[blockIdx.x];
 #pragma unroll
     for (int u = 0; u < kHxOuts; ++u) {
-        const int k = threadIdx.x + u * kBlock;
-        if (live[u]) {
+        const int k = threadIdx.x * kHxOuts + u;
+        if (k < cnt) {
             out[k] = make_double2(lr[u], li[u]);
             const double2 q = own[k];
             acc += q.x * lr[u] + q.y * li[u];

@@ -418,10 +418,20 @@ static int hx_tables(int L, HxTables** out) {
         *out = it->second;
         return VQE_OK;
     }
-    HxTables T;
+    // HxTables followed by the class rank tables (RankK) at kRankKOffset
+    std::vector<char> buf(kRankKOffset + sizeof(RankK), 0);
+    HxTables& T = *reinterpret_cast<HxTables*>(buf.data());
     fill_tables(L, T);
-    HxTables* d = nullptr;
-    if (int rc = upload(&d, &T, 1)) return rc;
+    RankK& R = *reinterpret_cast<RankK*>(buf.data() + kRankKOffset);
+    for (int k = 0; k < 8; ++k)
+        for (uint32_t v = 0; v < 128; ++v) {
+            const bool inA = v < (1u << T.La), inB = v < (1u << T.Lb);
+            R.a[k][v] = int16_t((inA && __builtin_popcount(v) == k) ? T.rankA[v] : kRankMiss);
+            R.b[k][v] = int16_t((inB && __builtin_popcount(v) == k) ? T.rankB[v] : kRankMiss);
+        }
+    char* dptr = nullptr;
+    if (int rc = upload(&dptr, buf.data(), buf.size())) return rc;
+    HxTables* d = reinterpret_cast<HxTables*>(dptr);
     g_hxt[{dev, L}] = d;
     *out = d;
     return VQE_OK;
