@@ -164,7 +164,7 @@ def run_batch(args):
             Hs, As, nes, theta, offs, cache=TUNE_CACHE,
             log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         print(f"# autotune {time.perf_counter() - t0:.1f}s: "
-              + " ".join(f"n{n}=({f >> 10}K,{a >> 10}K,L{L})" for n, (f, a, L) in sorted(tuned.items())),
+              + " ".join(f"n{n}=" + ",".join(str(v) for v in vals) for n, vals in sorted(tuned.items())),
               file=sys.stderr, flush=True)
     b = vq.Batch(Hs, As, nes)
     if args.profile_only:

@@ -210,6 +210,14 @@ int vqe_batch_work(const vqe_batch* b, double* w);
 int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes, int64_t adj_lds_bytes,
                    int hx_tile_bits);
 
+/* Launch-shape override of the packed-layout gate runs for states of
+ * n_qubits (batched as in vqe_set_tuning): the least number of threads per
+ * run tile (64, 256, 512 or 1024) of the forward and of the reverse pass;
+ * a tile too large for that count with the available shapes uses fewer
+ * threads with more entries each.  Both <= 0 restores the built-in choice
+ * (64).  Applies to plans made after the call.  Errors: ERANGE. */
+int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_threads);
+
 /* Evaluation layout switch (process-wide, default 1).  With 1, energy and
  * gradient evaluations of programs made only of number- and spin-conserving
  * excitations (UCCSD, Sec. 2.1.2) run on the packed sector layout: only the

@@ -23,7 +23,7 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
-    "set_packed",
+    "set_packed", "set_run_threads",
 ]
 
 
@@ -32,6 +32,12 @@ def set_tuning(n_qubits: int, batched: bool, fwd_lds_bytes: int = 0, adj_lds_byt
     """Override the launch parameters for n_qubits (all zeros: built-in choice)."""
     _check(lib().vqe_set_tuning(int(n_qubits), int(bool(batched)), int(fwd_lds_bytes),
                                 int(adj_lds_bytes), int(hx_tile_bits)))
+
+
+def set_run_threads(n_qubits: int, batched: bool, fwd_threads: int = 0, adj_threads: int = 0):
+    """Least threads per packed run tile (64/256/512/1024; zeros: built-in)."""
+    _check(lib().vqe_set_run_threads(int(n_qubits), int(bool(batched)), int(fwd_threads),
+                                     int(adj_threads)))
 
 
 def set_packed(enable: bool):

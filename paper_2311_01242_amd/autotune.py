@@ -23,7 +23,9 @@ import os
 
 import numpy as np
 
-from . import Batch, set_tuning
+from . import Batch, set_run_threads, set_tuning
+
+RUN_THREADS = (64, 256, 512, 1024)
 
 FWD_CANDIDATES = (16 << 10, 32 << 10, 64 << 10, 128 << 10)
 ADJ_CANDIDATES = (32 << 10, 64 << 10, 128 << 10)
@@ -54,16 +56,29 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None, packed=True):
         b.close()
         return ms
     if packed:
+        # L first (all three phases), then the run threads of each pass at that L
         best, best_t, best_ms = None, None, None
+        set_run_threads(n, True, 0, 0)
         for L in sorted({min(n, max(L, ne)) for L in (8, 9, 10, 11, 12, 13, 14)}):
             m = measure(64 << 10, 64 << 10, L)
             t = m[0] + m[1] + m[2]
             if log:
                 log(f"n={n} packed L={L}: {m[0]:.3f} + {m[1]:.3f} + {m[2]:.3f} ms")
             if best_t is None or t < best_t:
-                best, best_t, best_ms = (64 << 10, 64 << 10, L), t, m
+                best, best_t, best_ms = (64 << 10, 64 << 10, L), t, list(m)
+        tf, ta = 64, 64
+        for th in RUN_THREADS[1:]:
+            set_run_threads(n, True, th, th)
+            m = measure(*best)
+            if log:
+                log(f"n={n} packed L={best[2]} threads={th}: fwd {m[0]:.3f} adj {m[2]:.3f} ms")
+            if m[0] < best_ms[0]:
+                tf, best_ms[0] = th, m[0]
+            if m[2] < best_ms[2]:
+                ta, best_ms[2] = th, m[2]
         set_tuning(n, True, *best)
-        return best, best_ms
+        set_run_threads(n, True, tf, ta)
+        return (*best, tf, ta), best_ms
     base = (64 << 10, 64 << 10, min(n, 14))
     best = list(base)
     ms = measure(*base)
@@ -113,9 +128,11 @@ def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, 
     for (n, ne), idx in sorted(classes.items()):
         key = f"{dev}|{'packed' if packed else 'full'}|n={n}|ne={ne}|states={len(idx)}"
         if key in cache_data:
-            fwd, adj, L = cache_data[key]
-            set_tuning(n, True, fwd, adj, L)
-            out[n] = (fwd, adj, L)
+            vals = tuple(cache_data[key])
+            set_tuning(n, True, *vals[:3])
+            if len(vals) == 5:
+                set_run_threads(n, True, *vals[3:])
+            out[n] = vals
             continue
         sub = idx[:max_per_class]
         th = np.concatenate([theta_all[offsets[i]:offsets[i + 1]] for i in sub])

@@ -108,7 +108,9 @@ struct PackedRun {
     int32_t g0, g1;
     uint32_t khi, free_hi;
     int32_t ntiles, L, na, nb;
-    int32_t shape, max_entries;
+    int32_t shape, shape_adj;   // launch shapes of the forward and reverse passes
+    int32_t max_entries;
+    int32_t pad;
 };
 
 // One excitation of a packed run: annihilated orbitals pd and created
@@ -131,6 +133,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Wave total of v in a fixed order, returned to every lane: inclusive scans
+// within each 16-lane row by DPP row shifts (VALU only, no LDS round trips),
+// then the four row totals read from lanes 15, 31, 47, 63.
+template <int CTRL>
+__device__ __forceinline__ double dpp_from(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_from<0x111>(v);   // row_shr:1
+    v += dpp_from<0x112>(v);   // row_shr:2
+    v += dpp_from<0x114>(v);   // row_shr:4
+    v += dpp_from<0x118>(v);   // row_shr:8
+    auto lane = [&](int l) {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                                __builtin_amdgcn_readlane(__double2loint(v), l));
+    };
+    return (lane(15) + lane(31)) + (lane(47) + lane(63));
 }
 
 // Fixed-order block sum over kBlock threads; result valid in thread 0.
@@ -242,7 +266,9 @@ void launch_fill_zero(double2* p, uint64_t n, hipStream_t st);
 void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st);
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st);
-int packed_shape(int max_block);      // launch shape index covering blocks of that size, or -1
+// Launch shape covering blocks of max_block entries with at least min_threads
+// threads per tile if there is one (else any), or -1.
+int packed_shape(int max_block, int min_threads);
 int packed_shape_threads(int shape);
 int packed_enable_lds(size_t bytes);  // 0 on success
 

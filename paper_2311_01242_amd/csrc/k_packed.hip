@@ -67,7 +67,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                                              const int32_t* __restrict__ base) {
     extern __shared__ double2 sh[];
     __shared__ HxTables T;
-    __shared__ double red[VEC == 2 ? kMaxRunGates : 1][BS / 64];
+    __shared__ double red[2][BS / 64];                      // wave totals of the last two gates
+    __shared__ double gsum[VEC == 2 ? kMaxRunGates : 1];   // per-gate tile totals
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
@@ -149,18 +150,26 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             }
         }
         if (!fwd) {
-            acc = wave_sum(acc);
-            if ((tid & 63) == 0) red[jl][tid >> 6] = acc;
+            acc = wave_total(acc);
+            if ((tid & 63) == 0) red[t & 1][tid >> 6] = acc;
+            if (tid == 0 && t > 0) {   // previous gate's wave totals, fixed order
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < BS / 64; ++w) v += red[(t - 1) & 1][w];
+                gsum[jl + 1] = v;
+            }
         }
         __syncthreads();
     }
     if (!fwd) {
-        for (int jl = tid; jl < ng; jl += BS) {
+        if (tid == 0) {
             double v = 0.0;
 #pragma unroll
-            for (int w = 0; w < BS / 64; ++w) v += red[jl][w];
-            s.part_g[size_t(run.g0 + jl) * s.gstride + o] = v;
+            for (int w = 0; w < BS / 64; ++w) v += red[(ng - 1) & 1][w];
+            gsum[0] = v;
         }
+        __syncthreads();
+        for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + o] = gsum[jl];
     }
 #pragma unroll
     for (int u = 0; u < 2 * EPT; ++u) {
@@ -173,48 +182,56 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     }
 }
 
-// Launch shapes (threads per tile, entries per thread) by block capacity.
+// Launch shapes (threads per tile, entries per thread).
+#define VQE_PACKED_SHAPES(X)                                                                  \
+    X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(256, 1) X(256, 2) X(256, 3) X(256, 5) X(512, 1)     \
+    X(512, 2) X(512, 3) X(1024, 1) X(1024, 2)
+
 struct PShape {
     int bs, ept;
 };
-constexpr PShape kPShapes[] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {256, 3}, {256, 5}};
+#define VQE_SHAPE_ENTRY(B, E) {B, E},
+constexpr PShape kPShapes[] = {VQE_PACKED_SHAPES(VQE_SHAPE_ENTRY)};
+#undef VQE_SHAPE_ENTRY
 constexpr int kNumPShapes = int(sizeof(kPShapes) / sizeof(kPShapes[0]));
 
-int packed_shape(int max_block) {
-    for (int i = 0; i < kNumPShapes; ++i)
-        if (kPShapes[i].bs * kPShapes[i].ept >= max_block) return i;
-    return -1;
+int packed_shape(int max_block, int min_threads) {
+    int best = -1;
+    for (int pass = 0; pass < 2 && best < 0; ++pass)   // second pass: any thread count
+        for (int i = 0; i < kNumPShapes; ++i) {
+            const PShape& p = kPShapes[i];
+            if ((pass == 0 && p.bs < min_threads) || p.bs * p.ept < max_block) continue;
+            if (best < 0 || p.bs * p.ept < kPShapes[best].bs * kPShapes[best].ept) best = i;
+        }
+    return best;
 }
 
 int packed_shape_threads(int shape) { return kPShapes[shape].bs; }
 
+using PackedLauncher = void (*)(const StateDesc*, int, const PackedRun&, const PackedGate*,
+                                const HxTables*, const int32_t*, hipStream_t);
+
 template <int VEC, int BS, int EPT>
 static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, size_t lds, hipStream_t st) {
+                       const HxTables* tabs, const int32_t* base, hipStream_t st) {
+    const size_t lds = size_t(run.max_entries) * sizeof(double2) * VEC;
     hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(run.ntiles, count), dim3(BS), lds, st, sd, run,
                        pg, tabs, base);
 }
 
-template <int VEC>
-static void launch_vec(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, hipStream_t st) {
-    const size_t lds = size_t(run.max_entries) * sizeof(double2) * VEC;
-    switch (run.shape) {
-        case 0: launch_one<VEC, 64, 1>(sd, count, run, pg, tabs, base, lds, st); break;
-        case 1: launch_one<VEC, 64, 2>(sd, count, run, pg, tabs, base, lds, st); break;
-        case 2: launch_one<VEC, 64, 4>(sd, count, run, pg, tabs, base, lds, st); break;
-        case 3: launch_one<VEC, 64, 8>(sd, count, run, pg, tabs, base, lds, st); break;
-        case 4: launch_one<VEC, 256, 3>(sd, count, run, pg, tabs, base, lds, st); break;
-        default: launch_one<VEC, 256, 5>(sd, count, run, pg, tabs, base, lds, st); break;
-    }
-}
+#define VQE_FWD_ENTRY(B, E) &launch_one<1, B, E>,
+#define VQE_ADJ_ENTRY(B, E) &launch_one<2, B, E>,
+static const PackedLauncher kFwdLaunch[] = {VQE_PACKED_SHAPES(VQE_FWD_ENTRY)};
+static const PackedLauncher kAdjLaunch[] = {VQE_PACKED_SHAPES(VQE_ADJ_ENTRY)};
+#undef VQE_FWD_ENTRY
+#undef VQE_ADJ_ENTRY
 
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st) {
     if (adjoint)
-        launch_vec<2>(sd, count, run, pg, tabs, base, st);
+        kAdjLaunch[run.shape_adj](sd, count, run, pg, tabs, base, st);
     else
-        launch_vec<1>(sd, count, run, pg, tabs, base, st);
+        kFwdLaunch[run.shape](sd, count, run, pg, tabs, base, st);
 }
 
 void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st) {
@@ -228,16 +245,11 @@ int packed_enable_lds(size_t bytes) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
         if (r != hipSuccess) e = r;
     };
-#define VQE_PSET(V)                                                    \
-    set(reinterpret_cast<const void*>(&k_prun<V, 64, 1>));             \
-    set(reinterpret_cast<const void*>(&k_prun<V, 64, 2>));             \
-    set(reinterpret_cast<const void*>(&k_prun<V, 64, 4>));             \
-    set(reinterpret_cast<const void*>(&k_prun<V, 64, 8>));             \
-    set(reinterpret_cast<const void*>(&k_prun<V, 256, 3>));            \
-    set(reinterpret_cast<const void*>(&k_prun<V, 256, 5>));
-    VQE_PSET(1)
-    VQE_PSET(2)
-#undef VQE_PSET
+#define VQE_SET_ENTRY(B, E)                                          \
+    set(reinterpret_cast<const void*>(&k_prun<1, B, E>));            \
+    set(reinterpret_cast<const void*>(&k_prun<2, B, E>));
+    VQE_PACKED_SHAPES(VQE_SET_ENTRY)
+#undef VQE_SET_ENTRY
     return e == hipSuccess ? 0 : 1;
 }
 

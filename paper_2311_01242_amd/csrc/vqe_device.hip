@@ -43,10 +43,13 @@ struct Tuning {
     int64_t fwd_budget;   // LDS bytes of a forward run tile
     int64_t adj_budget;   // LDS bytes of a reverse run tile (phi + lambda)
     int L;                // low-bit tile of the sector H-apply
+    int fwd_threads = 64; // packed layout: least threads per forward run tile
+    int adj_threads = 64; // packed layout: least threads per reverse run tile
 };
 
 static std::mutex g_tune_mu;
 static std::map<std::pair<int, int>, Tuning> g_tune;   // (n, batched) -> override
+static std::map<std::pair<int, int>, std::pair<int, int>> g_threads;   // -> run threads
 
 static Tuning default_tuning(int n, bool batched) {
     Tuning t;
@@ -64,8 +67,13 @@ static Tuning default_tuning(int n, bool batched) {
 static Tuning tuning_for(int n, bool batched) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find({n, batched ? 1 : 0});
-    if (it != g_tune.end()) return it->second;
-    return default_tuning(n, batched);
+    Tuning t = (it != g_tune.end()) ? it->second : default_tuning(n, batched);
+    auto th = g_threads.find({n, batched ? 1 : 0});
+    if (th != g_threads.end()) {
+        t.fwd_threads = th->second.first;
+        t.adj_threads = th->second.second;
+    }
+    return t;
 }
 
 // ------------------------------------------------------------ device copies
@@ -109,7 +117,7 @@ struct PackedPlan {
 struct DevAnsatz {
     GateDesc* gates = nullptr;
     std::map<std::pair<int64_t, int64_t>, AnsatzPlan*> plans;
-    std::map<int, PackedPlan*> packed;   // by L
+    std::map<std::tuple<int, int, int>, PackedPlan*> packed;   // by (L, fwd, adj threads)
 };
 
 static int current_device(int* dev) {
@@ -520,9 +528,10 @@ static int packed_min_L(const vqe_ansatz* A, int ne) {
 }
 
 static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& lay,
-                       PackedPlan** out) {
+                       const Tuning& tn, PackedPlan** out) {
     std::lock_guard<std::mutex> lk(A->mu);
-    auto it = da->packed.find(lay.L);
+    const auto pkey = std::make_tuple(lay.L, tn.fwd_threads, tn.adj_threads);
+    auto it = da->packed.find(pkey);
     if (it != da->packed.end()) {
         *out = it->second;
         return VQE_OK;
@@ -567,9 +576,10 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             maxe = std::max(maxe, c0 + c1);
             moved += c0 + c1;
         }
-        r.shape = packed_shape(maxb);
+        r.shape = packed_shape(maxb, tn.fwd_threads);
+        r.shape_adj = packed_shape(maxb, tn.adj_threads);
         r.max_entries = maxe;
-        if (r.shape < 0) {
+        if (r.shape < 0 || r.shape_adj < 0) {
             delete p;
             return fail(VQE_EINVAL, "packed layout: block too large for the run kernels");
         }
@@ -603,7 +613,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         delete p;
         return rc;
     }
-    da->packed[L] = p;
+    da->packed[pkey] = p;
     *out = p;
     return VQE_OK;
 }
@@ -742,7 +752,7 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
         ep->nblk_e = ep->hx.ntiles;
         if (ep->packed) {
             if (int rc = packed_layout(n, ne, ep->hx.L, &ep->lay)) return rc;
-            if (int rc = packed_plan(A, da, *ep->lay, &ep->pp)) return rc;
+            if (int rc = packed_plan(A, da, *ep->lay, tn, &ep->pp)) return rc;
             ep->gstride = ep->pp->gstride;
             ep->d_gcnt = ep->pp->d_gcnt;
             ep->elems = ep->lay->size;
@@ -1479,6 +1489,21 @@ extern "C" int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes,
 }
 
 extern "C" void vqe_batch_free(vqe_batch* b) { delete b; }
+
+extern "C" int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_threads) {
+    if (n_qubits < 1 || n_qubits > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto key = std::make_pair(n_qubits, batched ? 1 : 0);
+    if (fwd_threads <= 0 && adj_threads <= 0) {
+        g_threads.erase(key);
+        return VQE_OK;
+    }
+    auto ok = [](int t) { return t == 64 || t == 256 || t == 512 || t == 1024; };
+    if (!ok(fwd_threads) || !ok(adj_threads))
+        return fail(VQE_ERANGE, "run threads must be 64, 256, 512 or 1024");
+    g_threads[key] = {fwd_threads, adj_threads};
+    return VQE_OK;
+}
 
 extern "C" int vqe_set_packed(int enable) {
     g_packed_enabled.store(enable ? 1 : 0);

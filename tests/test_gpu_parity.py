@@ -354,3 +354,20 @@ def test_batch_packed_matches_full_layout():
         out.append(b.energy_grad(flat))
     (e1, g1), (e2, g2) = out
     assert np.abs(e1 - e2).max() < 1e-12 and np.abs(g1 - g2).max() < 1e-12
+
+
+@pytest.mark.parametrize("threads", [64, 256, 512, 1024])
+def test_packed_run_thread_counts_agree(threads):
+    """Every launch shape of the packed gate runs (threads per tile, entries
+    per thread) gives the same energy and gradient."""
+    n, ne = 14, 7
+    H, A, prob = _pair(n, ne, 1701)
+    theta = uniform_theta(1702, A.n_params)
+    e0, g0 = vq.energy_grad(H, A, ne, theta)
+    try:
+        vq.set_run_threads(n, False, threads, threads)
+        e, g = vq.energy_grad(H, vq.Ansatz.uccsd(n, ne), ne, theta)
+    finally:
+        vq.set_run_threads(n, False, 0, 0)
+    assert abs(e - prob.energy(theta)) < TOL_E
+    assert abs(e - e0) < 1e-12 and np.abs(g - g0).max() < 1e-12
