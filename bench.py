@@ -114,42 +114,90 @@ def cpu_baseline_batch(spec, budget_s=20.0):
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2311_01242_amd", "tuning_cache.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "batch512_hbm_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc", "k_gates.hip")
+CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
+# lane-operations per second of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+OPS_PER_PAIR = 4   # sign parity (AND + BCNT) and a real-by-complex multiply-add (2 FMA)
+
+# phase -> (kernel, source file, bound)
+PHASE_KERNELS = {
+    "forward": ("k_prun<1,*,*> (packed forward gate runs)", "k_packed.hip", "hbm"),
+    "h_apply": ("k_hx_packed (packed sector H-apply)", "k_hamiltonian.hip", "alu"),
+    "adjoint": ("k_prun<2,*,*> (packed reverse-sweep gate runs)", "k_packed.hip", "hbm"),
+}
 
 
-def kernel_source_hash():
+def source_hash(name):
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
+    with open(os.path.join(CSRC, name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def roofline(b, theta, reps):
-    """Roofline of the dominant kernel, the reverse-sweep run kernel
-    k_run_adj: the batch's plan gives its algorithmic bytes and launch count
-    per evaluation; its duration comes from HIP events on the batch stream
-    around the same launches issued eagerly (the graph replays interleave the
-    size classes on forked streams, so single kernels cannot be timed there).
-    `traffic` is the rocprof FETCH+WRITE measurement of the same kernel,
-    reported only while the kernel source still matches the measured one."""
+def _binom(n, k):
+    from scipy.special import comb
+    return comb(n, k, exact=False)
+
+
+def sector_pairs(H, n, ne):
+    """(output, term) pairs of the H-apply whose output and partner both lie in
+    the (N, S_z) sector of the reference: for a term X^x Z^z, the outputs that
+    have half of x's alpha bits and half of its beta bits occupied."""
+    x, _, _ = H.terms()
+    x = x.astype(np.uint64)
+    pa = np.array([bin(int(v) & 0x55555555).count("1") for v in x])
+    pb = np.array([bin(int(v) & 0xAAAAAAAA).count("1") for v in x])
+    na, nb = (ne + 1) // 2, ne // 2
+    oa, ob = (n + 1) // 2, n // 2
+    ok = (pa % 2 == 0) & (pb % 2 == 0)
+    cnt = (_binom(pa, pa // 2) * _binom(oa - pa, na - pa // 2) *
+           _binom(pb, pb // 2) * _binom(ob - pb, nb - pb // 2))
+    return float(np.sum(np.where(ok, cnt, 0.0)))
+
+
+def roofline(b, theta, reps, Hs, nes):
+    """Rooflines of the three phases from one eager, HIP-event-timed
+    evaluation of the batch (the graph replays interleave the size classes on
+    forked streams, so phases cannot be timed there); the dominant phase's
+    kernel is reported as `roofline`.  Gate runs: algorithmic bytes from the
+    launch plan (each live tile read and written once) against HBM peak.
+    H-apply: 4 lane-operations per in-sector (output, term) pair against the
+    vector-ALU lane rate.  `traffic` is the rocprof FETCH+WRITE measurement of
+    the kernel, reported only while its source still matches the measured one."""
     phase_ms = b.profile(theta, reps=reps)
     w = b.work()
-    launches = w[6]
-    avg_us = 1e3 * phase_ms[2] / launches
-    bytes_per_launch = w[2] / launches
-    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
-    traffic = None
+    pairs = sum(sector_pairs(H, H.info()[0], ne) for H, ne in zip(Hs, nes))
+    traffic = {}
     if os.path.exists(TRAFFIC):
         with open(TRAFFIC) as f:
-            t = json.load(f)
-        if t.get("kernel_source_sha256") == kernel_source_hash():
-            traffic = t["k_run_adj_bytes_per_launch"]
-    return {"bound": "hbm", "kernel": "k_run_adj (reverse-sweep gate runs)",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
-            "avg_launch_us": round(avg_us, 2), "launches_per_eval": int(launches),
-            "phase_ms": {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
-                         "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}}
+            traffic = json.load(f).get("kernels", {})
+    recs = {}
+    for i, (phase, work, launches) in enumerate(
+            [("forward", w[0], w[4]), ("h_apply", OPS_PER_PAIR * pairs, w[5]),
+             ("adjoint", w[2], w[6])]):
+        kernel, src, bound = PHASE_KERNELS[phase]
+        t_s = phase_ms[i] * 1e-3
+        if bound == "hbm":
+            achieved, peak, unit = work / t_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            achieved, peak, unit = work / t_s / 1e12, VALU_PEAK_TOPS, "Top/s"
+        t = traffic.get(phase)
+        measured = t["bytes_per_launch"] if t and t.get("source_sha256") == source_hash(src) else None
+        recs[phase] = {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3 if bound == "alu" else 1),
+                       "peak": round(peak, 2), "unit": unit, "frac": round(achieved / peak, 4),
+                       "traffic": measured,
+                       ("algorithmic_bytes_per_launch" if bound == "hbm" else "algorithmic_ops_per_launch"):
+                           round(work / launches, 1),
+                       "avg_launch_us": round(1e3 * phase_ms[i] / launches, 2),
+                       "launches_per_eval": int(launches), "phase_ms": round(phase_ms[i], 3)}
+    dom = max(recs, key=lambda k: recs[k]["phase_ms"])
+    out = dict(recs[dom])
+    out["dominant_phase"] = dom
+    out["phases"] = {k: {kk: v[kk] for kk in ("kernel", "bound", "achieved", "unit", "frac", "phase_ms")}
+                     for k, v in recs.items()}
+    out["phase_ms"] = {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
+                       "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}
+    out["in_sector_term_pairs_per_eval"] = pairs
+    return out
 
 
 def run_batch(args):
@@ -181,7 +229,7 @@ def run_batch(args):
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
-    roof = roofline(b, theta, args.profile_reps)
+    roof = roofline(b, theta, args.profile_reps, Hs, nes)
     out = {
         "metric": "energy+adjoint-grad evals/s",
         "value": round(args.states * args.steps / dt, 2),
@@ -219,7 +267,7 @@ def run_single24(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     b = vq.Batch([H], [A], [ne])
-    roof = roofline(b, th, args.profile_reps)
+    roof = roofline(b, th, args.profile_reps, [H], [ne])
     roof["traffic"] = None
     return {
         "metric": "energy+adjoint-grad evals/s", "value": round(args.steps / dt, 3), "unit": "evals/s",

@@ -102,8 +102,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         const int k = tid + BS * u;
         if (k < nE) {
             const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
-            shp[k] = nt_load(&s.phi[gi]);
-            if (VEC == 2) shl[k] = nt_load(&s.lam[gi]);
+            shp[k] = s.phi[gi];
+            if (VEC == 2) shl[k] = s.lam[gi];
         }
     }
     uint32_t r[EPT];
@@ -176,8 +176,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         const int k = tid + BS * u;
         if (k < nE) {
             const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
-            nt_store(&s.phi[gi], shp[k]);
-            if (VEC == 2) nt_store(&s.lam[gi], shl[k]);
+            s.phi[gi] = shp[k];
+            if (VEC == 2) s.lam[gi] = shl[k];
         }
     }
 }
