@@ -122,7 +122,8 @@ OPS_PER_PAIR = 4   # sign parity (AND + BCNT) and a real-by-complex multiply-add
 # phase -> (kernel, source file, bound)
 PHASE_KERNELS = {
     "forward": ("k_prun<1,*,*> (packed forward gate runs)", "k_packed.hip", "hbm"),
-    "h_apply": ("k_hx_packed (packed sector H-apply)", "k_hamiltonian.hip", "alu"),
+    "h_apply": ("k_hx_ci<*,*> (string-product sector H-apply, with the two order conversions)",
+                "k_hx_ci.hip", "alu"),
     "adjoint": ("k_prun<2,*,*> (packed reverse-sweep gate runs)", "k_packed.hip", "hbm"),
 }
 

@@ -218,15 +218,18 @@ int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes, int64_t adj
  * (64).  Applies to plans made after the call.  Errors: ERANGE. */
 int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_threads);
 
-/* Evaluation layout switch (process-wide, default 1).  With 1, energy and
- * gradient evaluations of programs made only of number- and spin-conserving
- * excitations (UCCSD, Sec. 2.1.2) run on the packed sector layout: only the
- * amplitudes of the reference's (N, S_z) sector are stored, C(ceil(n/2),
- * N_alpha) C(floor(n/2), N_beta) per vector instead of 2^n; the hx tile bits
- * are raised to the number of electrons if smaller.  With 0 they use full
- * 2^n vectors.  Results agree to rounding; applies to plans made after the
- * call.  Never fails. */
-int vqe_set_packed(int enable);
+/* Evaluation layout switch (process-wide, default 2).  With 1 or 2, energy
+ * and gradient evaluations of programs made only of number- and
+ * spin-conserving excitations (UCCSD, Sec. 2.1.2) run on the packed sector
+ * layout: only the amplitudes of the reference's (N, S_z) sector are stored,
+ * C(ceil(n/2), N_alpha) C(floor(n/2), N_beta) per vector instead of 2^n, and
+ * the hx tile bits are raised to the number of electrons if smaller.  Mode 2
+ * also applies H in string-product order (alpha string x beta string) when
+ * both spins have at most 13 orbitals and at most 1024 beta strings; mode 1
+ * applies it in the packed block order.  With 0 evaluations use full 2^n
+ * vectors.  Results agree to rounding; applies to plans made after the call.
+ * Errors: ERANGE for other modes. */
+int vqe_set_packed(int mode);
 
 /* ---------------------------------------------------------------------------
  * BFGS and the VQE loop

@@ -40,10 +40,13 @@ def set_run_threads(n_qubits: int, batched: bool, fwd_threads: int = 0, adj_thre
                                      int(adj_threads)))
 
 
-def set_packed(enable: bool):
-    """Packed sector layout for UCCSD evaluations (default on); off: full 2^n
-    vectors.  Applies to plans made afterwards."""
-    _check(lib().vqe_set_packed(int(bool(enable))))
+def set_packed(mode=True):
+    """Evaluation layout of UCCSD programs (applies to plans made afterwards):
+    True or 2 = packed sector layout with the string-product H-apply (the
+    default), 1 = packed layout with the block-order H-apply, False or 0 =
+    full 2^n vectors."""
+    m = 2 if mode is True else (0 if mode is False else int(mode))
+    _check(lib().vqe_set_packed(m))
 
 
 class VQEError(RuntimeError):

@@ -33,9 +33,65 @@ struct StateDesc {
     double* part_g;          // gradient partials [M * gstride]
     double* out_e;           // [1]
     double* out_g;           // [M] raw per-gate gradient sums
+    const struct CiChunk* ci_chunks;    // string-product H-apply plan (packed path)
+    const struct CiGroup* ci_groups;
+    const struct CiSub* ci_subs;
+    const double* ci_tabs;
+    double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
     int32_t nb;              // number of H-apply chunks
     int32_t gstride;         // stride of part_g between gates
+    int32_t ci_nchunks;
+    int32_t pad;
+};
+
+// String-product ("CI") order of the sector: the amplitude of alpha string a
+// and beta string b sits at rank(a) * NB + rank(b), ranks counted among the
+// strings with the reference's alpha / beta electron counts (ascending).
+// Strings are compact: bit i of an alpha string is qubit 2i, of a beta
+// string qubit 2i + 1.  The H-apply in this order takes one alpha string
+// (a row) per wave and the beta strings across the lanes; the groups are
+// sorted into classes by the alpha part of their flip mask, so whether a
+// group can pair the row with an in-sector partner row is the same for all
+// lanes.
+struct CiGroup {
+    uint32_t xa;             // compact alpha flip mask (the group's class)
+    uint32_t xb;             // compact beta flip mask
+    uint32_t tbb;            // compact beta table positions, 4 x 5 bits (31 = none)
+    uint32_t tba;            // compact alpha table positions (mask)
+    int32_t meta;            // |xa| / 2 | ka << 8 | col_only << 16
+    int32_t s0, s1;          // subgroup range, local to the chunk
+    uint32_t wa, wb;         // the first subgroup (s0), repeated here
+    int32_t tab;
+    int32_t pad[2];
+};
+
+// Table index: (alpha pattern) | (beta pattern << ka), patterns in ascending
+// position order; sign (-1)^{|a & wa| + |b & wb|}.
+struct CiSub {
+    uint32_t wa, wb;
+    int32_t tab;             // local to the chunk
+    int32_t pad;
+};
+
+// The groups, sorted by (xa, xb), cut into chunks that fit the kernel's LDS
+// buffers; a group with many subgroups may continue in the next chunk.
+constexpr int kCiChunkGroups = 128;
+constexpr int kCiChunkSubs = 256;
+constexpr int kCiChunkTabs = 1024;
+
+struct CiChunk {
+    int32_t g0, g1, s0, s1, t0, t1;
+    int32_t pad[2];
+};
+
+struct CiArgs {
+    const uint32_t* sa;      // alpha strings [na_str]
+    const uint32_t* sb;      // beta strings [nb_str]
+    const int32_t* rank_a;   // [2^oa], -1 for other popcounts
+    const int16_t* rank_b;   // [2^ob], -1 for other popcounts
+    int32_t na_str, nb_str, ob;
+    int32_t pad;
 };
 
 // A fused tile pass over consecutive excitation gates [g0, g1) that share
@@ -263,6 +319,15 @@ void launch_hx_sector(const StateDesc* sd, int count, const HxPlan& plan, const 
 void launch_hx_packed(const StateDesc* sd, int count, const HxPlan& plan, const HxTables* tabs,
                       const int32_t* base, hipStream_t st);
 void launch_fill_zero(double2* p, uint64_t n, hipStream_t st);
+// Packed block order <-> string-product order: lam[perm[k]] = phi[k], and
+// lam[k] = aux[perm[k]].
+void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
+                       hipStream_t st);
+void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
+                      hipStream_t st);
+// lambda (aux) = H phi (lam) in string-product order, energy partial per row.
+void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st);
+int ci_prepare(const CiArgs& ci);   // 0 when the kernel can launch for these sizes
 void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st);
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st);

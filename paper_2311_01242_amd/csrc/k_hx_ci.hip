@@ -1,0 +1,293 @@
+// H-apply in string-product order (Sec. 2.1.1, Eq. 1): lambda = H phi and
+// Re <phi|lambda> restricted to the reference's (N, S_z) sector.
+//
+// With alpha strings along rows and beta strings along columns, a group with
+// flip mask x = xa (alpha part) + xb (beta part) maps row a to row a ^ xa and
+// column b to column b ^ xb.  A row has an in-sector partner row iff half of
+// xa is occupied in it, which is the same for every column of the row, so a
+// wave (one row, beta strings across the lanes) skips such a group as a
+// whole; only the beta half of the test remains per lane.  Groups come
+// sorted by (xa, xb): the partner row changes only between classes of equal
+// xa and is staged once per class in the wave's slice of LDS, from which the
+// lanes gather column b ^ xb.  Groups of classes whose members all have
+// xb = 0 read the partner in the same column straight from memory.  The
+// workgroup's rows share the group, subgroup and table data, staged chunk by
+// chunk in LDS with the next chunk's loads in flight during the current one.
+#include "device_common.h"
+
+namespace vqe {
+
+// Group and subgroup descriptors are the same for every lane: they are read
+// through the scalar data cache (constant address space) one group ahead.
+// The tables, gathered per lane, are staged chunk by chunk in LDS with the
+// next chunk's loads in flight during the current one.
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+    using W = const __attribute__((address_space(4))) uint32_t;
+    W* w = reinterpret_cast<W*>(reinterpret_cast<uintptr_t>(p));
+    T out;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i) o[i] = w[i];
+    return out;
+}
+
+__device__ __forceinline__ uint32_t pext_mask(uint32_t v, uint32_t mask) {
+    uint32_t out = 0;
+    int k = 0;
+    while (mask) {
+        const int q = __ffs(mask) - 1;
+        mask &= mask - 1;
+        out |= ((v >> q) & 1u) << k++;
+    }
+    return out;
+}
+
+// R rows (waves) per workgroup, COLS beta strings per lane.
+template <int COLS, int R>
+__global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci) {
+    constexpr int kT = R * 64;
+    constexpr int kTPer = (kCiChunkTabs + kT - 1) / kT;
+    extern __shared__ double2 lds_ci[];
+    __shared__ double tstage[2][kCiChunkTabs];
+    const int nrank = 1 << ci.ob;
+    int16_t* RB = reinterpret_cast<int16_t*>(lds_ci);
+    double2* rows = lds_ci + ((nrank * 2 + 15) >> 4);
+    for (int i = threadIdx.x; i < nrank; i += kT) RB[i] = ci.rank_b[i];
+    const StateDesc& s = sd[blockIdx.y];
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int ia = blockIdx.x * R + wave;
+    const bool row_live = ia < ci.na_str;   // waves past the last row only help with staging
+    const int NB = ci.nb_str;
+    double2* row = rows + size_t(wave) * NB;
+    const double2* __restrict__ phi = s.lam;   // phi in string-product order
+    const uint32_t sA = uint32_t(__builtin_amdgcn_readfirstlane(int(ci.sa[row_live ? ia : 0])));
+    uint32_t sB[COLS];
+    double lr[COLS], li[COLS];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        const int ib = lane + 64 * c;
+        sB[c] = ci.sb[ib < NB ? ib : 0];   // a column past the end repeats column 0, unwritten
+        lr[c] = li[c] = 0.0;
+    }
+    const int nch = s.ci_nchunks;
+    double treg[kTPer];
+    auto tload = [&](int c) {
+        const CiChunk ck = ldc(s.ci_chunks + c);
+#pragma unroll
+        for (int k = 0; k < kTPer; ++k) {
+            const int i = threadIdx.x + k * kT;
+            treg[k] = (i < ck.t1 - ck.t0) ? s.ci_tabs[ck.t0 + i] : 0.0;
+        }
+    };
+    auto tstore = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < kTPer; ++k) tstage[buf][threadIdx.x + k * kT] = treg[k];
+    };
+    tload(0);
+    tstore(0);
+    __syncthreads();
+    uint32_t cur_xa = 0xffffffffu;   // class whose partner row is staged
+    bool valid = false, col_only = false;
+    const double2* prow = phi;
+    for (int ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) tload(ch + 1);   // in flight during this chunk
+        const double* tab = tstage[ch & 1];
+        const CiChunk ck = ldc(s.ci_chunks + ch);
+        const CiGroup* gp = s.ci_groups + ck.g0;
+        const CiSub* sp = s.ci_subs + ck.s0;
+        const int ng = ck.g1 - ck.g0;
+        CiGroup G = ldc(gp);
+        for (int g = 0; row_live && g < ng; ++g) {
+            const CiGroup Gn = ldc(gp + (g + 1 < ng ? g + 1 : g));   // next group, ahead
+            if (G.xa != cur_xa) {   // a new class: its partner row
+                cur_xa = G.xa;
+                valid = __popc(sA & G.xa) == (G.meta & 0xff);
+                col_only = (G.meta >> 16) & 1;
+                if (valid) {
+                    prow = phi + size_t(ci.rank_a[sA ^ G.xa]) * NB;
+                    if (!col_only) {
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int c = 0; c < COLS; ++c) {
+                            const int ib = lane + 64 * c;
+                            if (ib < NB) row[ib] = prow[ib];
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                }
+            }
+            if (valid) {
+                const uint32_t xb = G.xb;
+                const uint32_t ta = pext_mask(sA, G.tba);
+                const int ka = (G.meta >> 8) & 0xff;
+                const uint32_t q0 = G.tbb & 31, q1 = (G.tbb >> 5) & 31, q2 = (G.tbb >> 10) & 31,
+                               q3 = (G.tbb >> 15) & 31;
+                double2 p[COLS];
+                uint32_t tix[COLS];
+                if (col_only) {
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c) {
+                        const int ib = lane + 64 * c;
+                        p[c] = prow[ib < NB ? ib : 0];
+                    }
+                } else {   // all loads first, then the selects
+                    int rp[COLS];
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c) rp[c] = RB[sB[c] ^ xb];
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c) p[c] = row[rp[c] >= 0 ? rp[c] : 0];
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c)
+                        if (rp[c] < 0) p[c] = make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    // beta table pattern (bit 31 of a beta string is 0)
+                    const uint32_t tb = __builtin_amdgcn_ubfe(sB[c], q0, 1) |
+                                        (__builtin_amdgcn_ubfe(sB[c], q1, 1) << 1) |
+                                        (__builtin_amdgcn_ubfe(sB[c], q2, 1) << 2) |
+                                        (__builtin_amdgcn_ubfe(sB[c], q3, 1) << 3);
+                    tix[c] = ta | (tb << ka);
+                }
+                double d[COLS];
+                {   // the first subgroup comes with the group record
+                    const uint32_t par = uint32_t(__popc(sA & G.wa));
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c) {
+                        const double t = tab[G.tab + tix[c]];
+                        const uint32_t flip = (uint32_t(__popc(sB[c] & G.wb)) + par) << 31;
+                        d[c] = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+                    }
+                }
+                for (int si = G.s0 + 1; si < G.s1; ++si) {
+                    const CiSub S = ldc(sp + si);
+                    const uint32_t par = uint32_t(__popc(sA & S.wa));
+#pragma unroll
+                    for (int c = 0; c < COLS; ++c) {
+                        const double t = tab[S.tab + tix[c]];
+                        const uint32_t flip = (uint32_t(__popc(sB[c] & S.wb)) + par) << 31;
+                        d[c] += __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    lr[c] += d[c] * p[c].x;
+                    li[c] += d[c] * p[c].y;
+                }
+            }
+            G = Gn;
+        }
+        if (ch + 1 < nch) tstore((ch + 1) & 1);   // the buffer read two chunks ago
+        __syncthreads();
+    }
+    if (!row_live) return;
+    double acc = 0.0;
+    const double2* mine = phi + size_t(ia) * NB;
+    double2* out = s.aux + size_t(ia) * NB;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        const int ib = lane + 64 * c;
+        if (ib < NB) {
+            out[ib] = make_double2(lr[c], li[c]);
+            const double2 q = mine[ib];
+            acc += q.x * lr[c] + q.y * li[c];
+        }
+    }
+    acc = wave_total(acc);
+    if (lane == 0) s.part_e[ia] = acc;
+}
+
+__global__ void k_ci_scatter(const StateDesc* __restrict__ sd, const int32_t* __restrict__ perm,
+                             int64_t size) {
+    const StateDesc& s = sd[blockIdx.y];
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
+         k += int64_t(gridDim.x) * blockDim.x)
+        s.lam[perm[k]] = s.phi[k];
+}
+
+__global__ void k_ci_gather(const StateDesc* __restrict__ sd, const int32_t* __restrict__ perm,
+                            int64_t size) {
+    const StateDesc& s = sd[blockIdx.y];
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
+         k += int64_t(gridDim.x) * blockDim.x)
+        s.lam[k] = s.aux[perm[k]];
+}
+
+void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_ci_scatter, dim3(blocks_for(uint64_t(size)), count), dim3(kBlock), 0, st,
+                       sd, perm, size);
+}
+
+void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_ci_gather, dim3(blocks_for(uint64_t(size)), count), dim3(kBlock), 0, st,
+                       sd, perm, size);
+}
+
+// Rows per workgroup for a row length: as many as fit 64 KiB of row buffers, at most 8.
+static int ci_rows(int nb) {
+    int r = 8;
+    while (r > 1 && size_t(r) * nb * sizeof(double2) > (64u << 10)) r >>= 1;
+    return r;
+}
+
+static size_t ci_lds(const CiArgs& ci) {
+    const size_t rank_bytes = ((size_t(2) << ci.ob) + 15) & ~size_t(15);
+    return rank_bytes + size_t(ci_rows(ci.nb_str)) * ci.nb_str * sizeof(double2);
+}
+
+template <int COLS, int R>
+static void launch_cr(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
+    const dim3 grid((ci.na_str + R - 1) / R, count);
+    hipLaunchKernelGGL((k_hx_ci<COLS, R>), grid, dim3(R * 64), ci_lds(ci), st, sd, ci);
+}
+
+template <int COLS>
+static void launch_c(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
+    switch (ci_rows(ci.nb_str)) {
+        case 8: launch_cr<COLS, 8>(sd, count, ci, st); break;
+        case 4: launch_cr<COLS, 4>(sd, count, ci, st); break;
+        case 2: launch_cr<COLS, 2>(sd, count, ci, st); break;
+        default: launch_cr<COLS, 1>(sd, count, ci, st); break;
+    }
+}
+
+void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
+    const int cols = (ci.nb_str + 63) / 64;
+    if (cols <= 1) launch_c<1>(sd, count, ci, st);
+    else if (cols <= 2) launch_c<2>(sd, count, ci, st);
+    else if (cols <= 4) launch_c<4>(sd, count, ci, st);
+    else if (cols <= 8) launch_c<8>(sd, count, ci, st);
+    else launch_c<16>(sd, count, ci, st);
+}
+
+int ci_prepare(const CiArgs& ci) {
+    const size_t lds = ci_lds(ci);
+    const size_t fixed = sizeof(double) * 2 * kCiChunkTabs;
+    if ((ci.nb_str + 63) / 64 > 16 || lds + fixed > (160u << 10)) return 1;
+    if (lds + fixed <= (64u << 10)) return 0;
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (r != hipSuccess) e = r;
+    };
+#define VQE_CI_SET(C)                                                   \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 8>));                 \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 4>));                 \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 2>));                 \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 1>));
+    VQE_CI_SET(1)
+    VQE_CI_SET(2)
+    VQE_CI_SET(4)
+    VQE_CI_SET(8)
+    VQE_CI_SET(16)
+#undef VQE_CI_SET
+    return e == hipSuccess ? 0 : 1;
+}
+
+}  // namespace vqe

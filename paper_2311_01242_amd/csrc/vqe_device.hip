@@ -94,11 +94,22 @@ struct AnsatzPlan {
     double fwd_bytes = 0.0, adj_bytes = 0.0;
 };
 
+// String-product H-apply plan of a Hamiltonian (groups sorted into classes
+// by the alpha part of their flip mask; see k_hx_ci.hip).
+struct CiHam {
+    CiChunk* chunks = nullptr;
+    CiGroup* groups = nullptr;
+    CiSub* subs = nullptr;
+    double* tabs = nullptr;
+    int nchunks = 0;
+};
+
 struct DevHam {
     GroupDesc* groups = nullptr;
     SubDesc* subs = nullptr;
     double* tabs = nullptr;
     std::map<int, struct HxWork*> work;   // L -> sector H-apply work list
+    CiHam* ci = nullptr;
 };
 
 // Launch plan of an ansatz on the packed sector layout with block bits L.
@@ -417,6 +428,19 @@ static void fill_tables(int L, HxTables& T) {
     build(T.Lb, 1, T.offB, T.unB, T.rankB);
 }
 
+static const HxTables* host_tables(int L) {
+    static std::mutex mu;
+    static std::map<int, HxTables> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(L);
+    if (it == cache.end()) {
+        HxTables T;
+        fill_tables(L, T);
+        it = cache.emplace(L, T).first;
+    }
+    return &it->second;
+}
+
 static int hx_tables(int L, HxTables** out) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
@@ -455,6 +479,7 @@ struct PackedLayout {
     int64_t size = 0;                    // in-sector amplitudes
     std::vector<int32_t> base, bsize;    // per block h < 2^(n - L)
     int32_t* d_base = nullptr;
+    int32_t* d_perm = nullptr;           // block order -> string-product order (or null)
 };
 
 static std::mutex g_lay_mu;
@@ -507,6 +532,242 @@ static int packed_layout(int n, int ne, int L, PackedLayout** out) {
     }
     g_lay[key] = lay;
     *out = lay;
+    return VQE_OK;
+}
+
+// ------------------------------------------------------ string-product order
+
+static uint32_t compact_even_host(uint32_t v) {   // bits 0, 2, 4, ... -> 0, 1, 2, ...
+    uint32_t out = 0;
+    for (int i = 0; i < 16; ++i) out |= ((v >> (2 * i)) & 1u) << i;
+    return out;
+}
+
+// Alpha and beta strings of (n, ne) with their rank tables.
+struct CiSpace {
+    int oa = 0, ob = 0, NA = 0, NB = 0;
+    std::vector<uint32_t> sa, sb;
+    std::vector<int32_t> rank_a;
+    std::vector<int16_t> rank_b;
+    uint32_t* d_sa = nullptr;
+    uint32_t* d_sb = nullptr;
+    int32_t* d_rank_a = nullptr;
+    int16_t* d_rank_b = nullptr;
+    CiArgs args() const {
+        CiArgs a{};
+        a.sa = d_sa;
+        a.sb = d_sb;
+        a.rank_a = d_rank_a;
+        a.rank_b = d_rank_b;
+        a.na_str = NA;
+        a.nb_str = NB;
+        a.ob = ob;
+        return a;
+    }
+};
+
+constexpr int kCiMaxBits = 13;    // alpha / beta orbitals of the string-product path
+constexpr int kCiMaxCols = 1024;  // beta strings per row (16 per lane)
+
+static std::mutex g_cis_mu;
+static std::map<std::tuple<int, int, int>, CiSpace*> g_cis;   // (dev, n, ne)
+
+static int ci_space(int n, int ne, CiSpace** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_cis_mu);
+    const auto key = std::make_tuple(dev, n, ne);
+    auto it = g_cis.find(key);
+    if (it != g_cis.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    auto* c = new CiSpace();
+    c->oa = (n + 1) / 2;
+    c->ob = n / 2;
+    const int na = (ne + 1) / 2, nb = ne / 2;
+    c->rank_a.assign(size_t(1) << c->oa, -1);
+    c->rank_b.assign(size_t(1) << c->ob, int16_t(-1));
+    for (uint32_t v = 0; v < (1u << c->oa); ++v)
+        if (__builtin_popcount(v) == na) {
+            c->rank_a[v] = int32_t(c->sa.size());
+            c->sa.push_back(v);
+        }
+    for (uint32_t v = 0; v < (1u << c->ob); ++v)
+        if (__builtin_popcount(v) == nb) {
+            c->rank_b[v] = int16_t(c->sb.size());
+            c->sb.push_back(v);
+        }
+    c->NA = int(c->sa.size());
+    c->NB = int(c->sb.size());
+    int rc = upload(&c->d_sa, c->sa.data(), c->sa.size());
+    if (!rc) rc = upload(&c->d_sb, c->sb.data(), c->sb.size());
+    if (!rc) rc = upload(&c->d_rank_a, c->rank_a.data(), c->rank_a.size());
+    if (!rc) rc = upload(&c->d_rank_b, c->rank_b.data(), c->rank_b.size());
+    if (rc) {
+        (void)hipFree(c->d_sa);
+        (void)hipFree(c->d_sb);
+        (void)hipFree(c->d_rank_a);
+        (void)hipFree(c->d_rank_b);
+        delete c;
+        return rc;
+    }
+    g_cis[key] = c;
+    *out = c;
+    return VQE_OK;
+}
+
+// Block order -> string-product order of a packed layout.
+static int layout_perm(PackedLayout* lay, const CiSpace& cs, const HxTables& T) {
+    if (lay->d_perm) return VQE_OK;
+    std::vector<int32_t> perm(size_t(lay->size));
+    const uint32_t nblocks = uint32_t(lay->base.size());
+    for (uint32_t h = 0; h < nblocks; ++h) {
+        if (lay->bsize[h] == 0) continue;
+        const uint32_t hb = h << lay->L;
+        const int kA = lay->na - __builtin_popcount(hb & 0x55555555u);
+        const int kB = lay->nb - __builtin_popcount(hb & 0xAAAAAAAAu);
+        const int cB = T.offB[kB + 1] - T.offB[kB];
+        for (int k = 0; k < lay->bsize[h]; ++k) {
+            const uint32_t b = hb | T.unA[T.offA[kA] + k / cB] | T.unB[T.offB[kB] + k % cB];
+            const int32_t ra = cs.rank_a[compact_even_host(b)];
+            const int32_t rb = cs.rank_b[compact_even_host(b >> 1)];
+            if (ra < 0 || rb < 0) return fail(VQE_EINVAL, "string-product order: string outside the sector");
+            perm[size_t(lay->base[h]) + k] = ra * cs.NB + rb;
+        }
+    }
+    return upload(&lay->d_perm, perm.data(), perm.size());
+}
+
+// Groups, subgroups and re-indexed tables of the string-product H-apply,
+// from the folded group structure, cut into LDS-sized chunks.  Groups that
+// change N_alpha or N_beta are left out (they pair no two sector states).
+static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    if (d->ci) {
+        *out = d->ci;
+        return VQE_OK;
+    }
+    struct G {
+        uint32_t xa, xb;
+        size_t gi;
+    };
+    std::vector<G> order;
+    for (size_t gi = 0; gi < H->groups.size(); ++gi) {
+        const uint32_t x = H->groups[gi].x;
+        if ((__builtin_popcount(x & 0x55555555u) | __builtin_popcount(x & 0xAAAAAAAAu)) & 1) continue;
+        order.push_back(G{compact_even_host(x), compact_even_host(x >> 1), gi});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const G& a, const G& b) {
+        return a.xa != b.xa ? a.xa < b.xa : a.xb < b.xb;
+    });
+    std::map<uint32_t, int> col_only;   // xa -> every group of the class has xb = 0
+    for (const G& o : order) {
+        auto it = col_only.find(o.xa);
+        if (it == col_only.end()) it = col_only.emplace(o.xa, 1).first;
+        if (o.xb != 0) it->second = 0;
+    }
+    std::vector<CiChunk> chunks;
+    std::vector<CiGroup> grp;
+    std::vector<CiSub> sub;
+    std::vector<double> tab;
+    CiChunk cur{};
+    bool open = false;
+    auto close = [&]() {
+        if (open) {
+            cur.g1 = int32_t(grp.size());
+            cur.s1 = int32_t(sub.size());
+            cur.t1 = int32_t(tab.size());
+            chunks.push_back(cur);
+        }
+        open = false;
+    };
+    for (const G& o : order) {
+        const GroupDesc& gd = H->groups[o.gi];
+        const int k = int(gd.pos & 7);
+        const int nt = 1 << k;
+        int pa[4], pb[4], ka = 0, kb = 0, slot_a[4], slot_b[4];
+        for (int i = 0; i < k; ++i) {
+            const int q = int((gd.pos >> (3 + 5 * i)) & 31);
+            if (q % 2 == 0) {
+                pa[ka] = q / 2;
+                slot_a[ka++] = i;
+            } else {
+                pb[kb] = q / 2;
+                slot_b[kb++] = i;
+            }
+        }
+        CiGroup g{};
+        g.xa = o.xa;
+        g.xb = o.xb;
+        for (int i = 0; i < ka; ++i) g.tba |= 1u << pa[i];
+        for (int i = 0; i < 4; ++i) g.tbb |= uint32_t(i < kb ? pb[i] : 31) << (5 * i);
+        g.meta = (__builtin_popcount(o.xa) / 2) | (ka << 8) | (col_only[o.xa] << 16);
+        int si = gd.sub_begin;
+        while (si < gd.sub_end) {
+            if (open && (int(grp.size()) - cur.g0 >= kCiChunkGroups ||
+                         int(sub.size()) - cur.s0 >= kCiChunkSubs ||
+                         int(tab.size()) - cur.t0 + nt > kCiChunkTabs))
+                close();
+            if (!open) {
+                cur = CiChunk{};
+                cur.g0 = int32_t(grp.size());
+                cur.s0 = int32_t(sub.size());
+                cur.t0 = int32_t(tab.size());
+                open = true;
+            }
+            CiGroup lg = g;
+            lg.s0 = int32_t(sub.size()) - cur.s0;
+            // as many of this group's subgroups as fit the open chunk
+            while (si < gd.sub_end && int(sub.size()) - cur.s0 < kCiChunkSubs &&
+                   int(tab.size()) - cur.t0 + nt <= kCiChunkTabs) {
+                const SubDesc& sd = H->subs[si];
+                CiSub cs{};
+                cs.wa = compact_even_host(sd.w);
+                cs.wb = compact_even_host(sd.w >> 1);
+                cs.tab = int32_t(tab.size()) - cur.t0;
+                for (int t = 0; t < nt; ++t) {   // new index t = alpha pattern | beta pattern << ka
+                    uint32_t old = 0;
+                    for (int i = 0; i < ka; ++i)
+                        if ((t >> i) & 1) old |= 1u << slot_a[i];
+                    for (int i = 0; i < kb; ++i)
+                        if ((t >> (ka + i)) & 1) old |= 1u << slot_b[i];
+                    tab.push_back(H->tabs[size_t(sd.tab) + old]);
+                }
+                sub.push_back(cs);
+                ++si;
+            }
+            lg.s1 = int32_t(sub.size()) - cur.s0;
+            if (lg.s1 > lg.s0) {
+                const CiSub& first = sub[size_t(cur.s0 + lg.s0)];
+                lg.wa = first.wa;
+                lg.wb = first.wb;
+                lg.tab = first.tab;
+                grp.push_back(lg);
+            }
+            if (si < gd.sub_end) close();   // continue this group in a new chunk
+        }
+    }
+    close();
+    if (chunks.empty()) {   // no in-sector pair at all: one empty chunk
+        chunks.push_back(CiChunk{});
+    }
+    auto* c = new CiHam();
+    c->nchunks = int(chunks.size());
+    int rc = upload(&c->chunks, chunks.data(), chunks.size());
+    if (!rc) rc = upload(&c->groups, grp.data(), grp.size());
+    if (!rc) rc = upload(&c->subs, sub.data(), sub.size());
+    if (!rc) rc = upload(&c->tabs, tab.data(), tab.size());
+    if (rc) {
+        (void)hipFree(c->chunks);
+        (void)hipFree(c->groups);
+        (void)hipFree(c->subs);
+        (void)hipFree(c->tabs);
+        delete c;
+        return rc;
+    }
+    d->ci = c;
+    *out = c;
     return VQE_OK;
 }
 
@@ -618,7 +879,9 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     return VQE_OK;
 }
 
-static std::atomic<int> g_packed_enabled{1};
+// 0: full 2^n vectors; 1: packed layout with the block-order H-apply;
+// 2: packed layout with the string-product H-apply where it applies.
+static std::atomic<int> g_packed_enabled{2};
 
 // ------------------------------------------------------------- workspaces
 
@@ -627,6 +890,7 @@ struct Workspace {
     size_t state_bytes = 0;
     double2* phi = nullptr;
     double2* lam = nullptr;
+    double2* aux = nullptr;      // lambda in string-product order (packed path)
     int64_t lam_zero_key = -1;   // sector for which lambda is zero outside it
     size_t scratch_bytes = 0;
     char* scratch = nullptr;     // theta, cs, partials, outputs, descriptor
@@ -654,12 +918,14 @@ static int workspace(void* stream, size_t state_bytes, size_t scratch_bytes, Wor
         HIPCHK(hipStreamSynchronize((hipStream_t)stream));
         (void)hipFree(ws->phi);
         (void)hipFree(ws->lam);
-        ws->phi = ws->lam = nullptr;
+        (void)hipFree(ws->aux);
+        ws->phi = ws->lam = ws->aux = nullptr;
         ws->state_bytes = 0;
         ws->lam_zero_key = -1;
-        if (int rc = fits_device(state_bytes * 2)) return rc;
+        if (int rc = fits_device(state_bytes * 3)) return rc;
         HIPCHK(hipMalloc(&ws->phi, state_bytes));
         HIPCHK(hipMalloc(&ws->lam, state_bytes));
+        HIPCHK(hipMalloc(&ws->aux, state_bytes));
         ws->state_bytes = state_bytes;
     }
     if (ws->scratch_bytes < scratch_bytes) {
@@ -714,6 +980,9 @@ struct EvalPlan {
     int64_t elems = 0;       // amplitudes per state vector
     double fwd_bytes = 0.0, adj_bytes = 0.0;
     size_t fwd_steps = 0, adj_steps = 0;
+    bool ci = false;         // packed path with the string-product H-apply
+    CiArgs ciargs{};
+    const int32_t* perm = nullptr;
 };
 
 static bool sector_path(const vqe_ansatz* A, int ne) {
@@ -759,6 +1028,19 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
             ep->fwd_bytes = ep->pp->fwd_bytes;
             ep->adj_bytes = ep->pp->adj_bytes;
             ep->fwd_steps = ep->adj_steps = ep->pp->runs.size();
+            if (g_packed_enabled.load() >= 2 && (n + 1) / 2 <= kCiMaxBits) {
+                CiSpace* cs;
+                if (int rc = ci_space(n, ne, &cs)) return rc;
+                if (cs->NB <= kCiMaxCols) {
+                    if (int rc = layout_perm(ep->lay, *cs, *host_tables(ep->hx.L))) return rc;
+                    ep->ci = true;
+                    ep->ciargs = cs->args();
+                    ep->perm = ep->lay->d_perm;
+                    ep->nblk_e = cs->NA;
+                    if (ci_prepare(ep->ciargs) != 0)
+                        return fail(VQE_EDEVICE, "could not enable the string-product LDS size");
+                }
+            }
         }
     } else {
         ep->nblk_e = blocks_for(uint64_t(1) << n);
@@ -779,7 +1061,13 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
             launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
                               ep.lay->d_base, false, st);
     } else if (phase == kPhaseHx) {
-        launch_hx_packed(sd, count, ep.hx, ep.hxt, ep.lay->d_base, st);
+        if (ep.ci) {
+            launch_ci_scatter(sd, count, ep.perm, ep.lay->size, st);
+            launch_hx_ci(sd, count, ep.ciargs, st);
+            launch_ci_gather(sd, count, ep.perm, ep.lay->size, st);
+        } else {
+            launch_hx_packed(sd, count, ep.hx, ep.hxt, ep.lay->d_base, st);
+        }
     } else if (phase == kPhaseAdj) {
         if (!grad) return;
         for (size_t r = pp.runs.size(); r-- > 0;)
@@ -884,6 +1172,13 @@ vqe_hamiltonian::~vqe_hamiltonian() {
             (void)hipFree(w.second->cgroups);
             (void)hipFree(w.second->csubs);
             delete w.second;
+        }
+        if (CiHam* c = kv.second->ci) {
+            (void)hipFree(c->chunks);
+            (void)hipFree(c->groups);
+            (void)hipFree(c->subs);
+            (void)hipFree(c->tabs);
+            delete c;
         }
         delete kv.second;
     }
@@ -1133,6 +1428,16 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     StateDesc sd{};
     sd.phi = ws->phi;
     sd.lam = ws->lam;
+    sd.aux = ws->aux;
+    if (ep.ci) {
+        CiHam* ch;
+        if (int rc = ci_ham(H, dh, &ch)) return rc;
+        sd.ci_chunks = ch->chunks;
+        sd.ci_groups = ch->groups;
+        sd.ci_subs = ch->subs;
+        sd.ci_tabs = ch->tabs;
+        sd.ci_nchunks = ch->nchunks;
+    }
     sd.gates = da->gates;
     sd.theta = cv.take<double>(P);
     sd.cs = cv.take<double2>(M);
@@ -1301,7 +1606,8 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     for (size_t c = 0; c < rep.size(); ++c)
         if (int rc = make_eval_plan(A[rep[c]], ne[rep[c]], true, &b->classes[c].ep)) return rc;
     size_t need = 0;
-    for (int i = 0; i < S; ++i) need += 2 * sizeof(double2) * size_t(b->classes[cls[i]].ep.elems);
+    for (int i = 0; i < S; ++i)
+        need += (b->classes[cls[i]].ep.ci ? 3 : 2) * sizeof(double2) * size_t(b->classes[cls[i]].ep.elems);
     if (int rc = fits_device(need)) return rc;
     if (int rc = dalloc(b, &b->theta_dev, b->poff[S])) return rc;
     if (int rc = dalloc(b, &b->e_dev, S)) return rc;
@@ -1334,6 +1640,16 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         }
         if (int rc = dalloc(b, &sd.phi, size_t(ep.elems))) return rc;
         if (int rc = dalloc(b, &sd.lam, size_t(ep.elems))) return rc;
+        if (ep.ci) {
+            if (int rc = dalloc(b, &sd.aux, size_t(ep.elems))) return rc;
+            CiHam* ch;
+            if (int rc = ci_ham(H[i], dh, &ch)) return rc;
+            sd.ci_chunks = ch->chunks;
+            sd.ci_groups = ch->groups;
+            sd.ci_subs = ch->subs;
+            sd.ci_tabs = ch->tabs;
+            sd.ci_nchunks = ch->nchunks;
+        }
         launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
         if (int rc = dalloc(b, &sd.part_e, ep.nblk_e)) return rc;
@@ -1505,7 +1821,8 @@ extern "C" int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, i
     return VQE_OK;
 }
 
-extern "C" int vqe_set_packed(int enable) {
-    g_packed_enabled.store(enable ? 1 : 0);
+extern "C" int vqe_set_packed(int mode) {
+    if (mode < 0 || mode > 2) return fail(VQE_ERANGE, "packed mode must be 0, 1 or 2");
+    g_packed_enabled.store(mode);
     return VQE_OK;
 }

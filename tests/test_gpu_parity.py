@@ -291,13 +291,16 @@ def _eval_layout(H, n, ne, theta, packed):
 @pytest.mark.parametrize("n,ne", [(4, 2), (5, 2), (6, 3), (7, 3), (8, 4), (9, 5), (10, 5),
                                   (11, 4), (12, 6), (13, 7), (14, 7), (16, 8)])
 def test_packed_layout_matches_full_layout_and_oracle(n, ne):
-    """The packed sector layout (only in-sector amplitudes stored) against
-    full 2^n vectors and the oracle, odd and even n, open shells."""
+    """The packed sector layout (only in-sector amplitudes stored), with the
+    string-product and the block-order H-apply, against full 2^n vectors and
+    the oracle, odd and even n, open shells."""
     H, A, prob = _pair(n, ne, 1100 + n)
     theta = uniform_theta(1200 + n, A.n_params)
-    ep, gp = _eval_layout(H, n, ne, theta, True)
-    ef, gf = _eval_layout(H, n, ne, theta, False)
+    ep, gp = _eval_layout(H, n, ne, theta, 2)
+    eb, gb = _eval_layout(H, n, ne, theta, 1)
+    ef, gf = _eval_layout(H, n, ne, theta, 0)
     assert abs(ep - ef) < 1e-12 and np.abs(gp - gf).max() < 1e-12
+    assert abs(eb - ef) < 1e-12 and np.abs(gb - gf).max() < 1e-12
     assert abs(ep - prob.energy(theta)) < TOL_E
     idx = sorted(np.random.default_rng(n).choice(A.n_params, min(4, A.n_params),
                                                  replace=False).tolist())
@@ -344,7 +347,7 @@ def test_batch_packed_matches_full_layout():
         thetas.append(uniform_theta(1600 + s, vq.Ansatz.uccsd(n, ne).n_params))
     flat = np.concatenate(thetas)
     out = []
-    for packed in (True, False):
+    for packed in (2, 0):
         vq.set_packed(packed)
         try:
             b = vq.Batch(Hs, [vq.Ansatz.uccsd(n, ne) for n, ne, _ in specs],
