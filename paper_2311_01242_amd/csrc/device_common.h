@@ -37,12 +37,17 @@ struct StateDesc {
     const struct CiGroup* ci_groups;
     const struct CiSub* ci_subs;
     const double* ci_tabs;
+    const struct CiPairClass* ci_pcls;   // beta-pair classes
+    const struct CiPairRec* ci_precs;
+    const struct CiGroup* ci_rgroups;    // their other groups
+    const struct CiSub* ci_rsubs;
+    const double* ci_ptabs;              // tables of the pair classes (global offsets)
     double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
     int32_t nb;              // number of H-apply chunks
     int32_t gstride;         // stride of part_g between gates
     int32_t ci_nchunks;
-    int32_t pad;
+    int32_t ci_npcls;
 };
 
 // String-product ("CI") order of the sector: the amplitude of alpha string a
@@ -85,13 +90,36 @@ struct CiChunk {
     int32_t pad[2];
 };
 
+// Beta-pair classes.  The groups of a class (xa) that flip exactly two beta
+// orbitals and have one subgroup are applied by walking, per column, the
+// beta pairs that column can flip (one orbital occupied, one empty; the
+// same count for every column) from a precomputed list, instead of testing
+// every group in every lane.  Pair p of the class has record rec0 + p.
+struct CiPairClass {
+    uint32_t xa;
+    int32_t half;
+    int32_t rec0;
+    int32_t rest0, rest1;    // the class's other groups (CiGroup with global subgroups)
+    int32_t pad[3];
+};
+
+struct CiPairRec {
+    int32_t tab;             // table offset (-1: the class has no group for this pair)
+    uint32_t wa, wb;
+    int32_t ka;              // alpha table bits: entry (alpha pattern) | (beta pattern << ka)
+};
+
 struct CiArgs {
     const uint32_t* sa;      // alpha strings [na_str]
     const uint32_t* sb;      // beta strings [nb_str]
     const int32_t* rank_a;   // [2^oa], -1 for other popcounts
     const int16_t* rank_b;   // [2^ob], -1 for other popcounts
+    // beta-pair lists, entry-major [e1][nb_str]: partner column (bits 0-15),
+    // pair index (bits 16-23), 1 if the pair's higher orbital is the occupied one (bit 24)
+    const uint32_t* plist;
     int32_t na_str, nb_str, ob;
-    int32_t pad;
+    int32_t npairs, e1;      // beta pairs C(ob, 2); list entries per column
+    int32_t pad[3];
 };
 
 // A fused tile pass over consecutive excitation gates [g0, g1) that share

@@ -44,6 +44,87 @@ __device__ __forceinline__ uint32_t pext_mask(uint32_t v, uint32_t mask) {
     return out;
 }
 
+// Words of a wave's LDS slice: its staged row, then the beta-pair
+// coefficient records of the current pair class.
+__host__ __device__ inline int ci_wave_words(int nb, int npairs) {
+    return nb + npairs + (npairs * 4 + 15) / 16;   // in double2 (16-byte) units
+}
+
+// lambda += D_G(b) phi(partner) for one group over the wave's columns.
+// tab: the group's table base (LDS chunk or global); sp: its subgroups.
+template <int COLS>
+__device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, const double* tab,
+                                         uint32_t sA, const uint32_t (&sB)[COLS], bool col_only,
+                                         const double2* prow, const double2* row,
+                                         const int16_t* RB, int NB, int lane, double (&lr)[COLS],
+                                         double (&li)[COLS]) {
+    const uint32_t ta = pext_mask(sA, G.tba);
+    const int ka = (G.meta >> 8) & 0xff;
+    const uint32_t q0 = G.tbb & 31, q1 = (G.tbb >> 5) & 31, q2 = (G.tbb >> 10) & 31,
+                   q3 = (G.tbb >> 15) & 31;
+    double2 p[COLS];
+    bool ok[COLS];
+    if (col_only) {
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            const int ib = lane + 64 * c;
+            p[c] = prow[ib < NB ? ib : 0];
+            ok[c] = true;
+        }
+    } else {   // all loads first, then the selects
+        int rp[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) rp[c] = RB[sB[c] ^ G.xb];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            ok[c] = rp[c] >= 0;
+            p[c] = row[ok[c] ? rp[c] : 0];
+        }
+    }
+    uint32_t tix[COLS];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        // beta table pattern (bit 31 of a beta string is 0)
+        const uint32_t tb = __builtin_amdgcn_ubfe(sB[c], q0, 1) |
+                            (__builtin_amdgcn_ubfe(sB[c], q1, 1) << 1) |
+                            (__builtin_amdgcn_ubfe(sB[c], q2, 1) << 2) |
+                            (__builtin_amdgcn_ubfe(sB[c], q3, 1) << 3);
+        tix[c] = ta | (tb << ka);
+    }
+    double d[COLS];
+    {   // the first subgroup comes with the group record
+        const uint32_t par = uint32_t(__popc(sA & G.wa));
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            const double t = tab[G.tab + tix[c]];
+            const uint32_t flip = (uint32_t(__popc(sB[c] & G.wb)) + par) << 31;
+            d[c] = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+        }
+    }
+    for (int si = G.s0 + 1; si < G.s1; ++si) {
+        const CiSub S = ldc(sp + si);
+        const uint32_t par = uint32_t(__popc(sA & S.wa));
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            const double t = tab[S.tab + tix[c]];
+            const uint32_t flip = (uint32_t(__popc(sB[c] & S.wb)) + par) << 31;
+            d[c] += __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        const double dd = ok[c] ? d[c] : 0.0;
+        lr[c] += dd * p[c].x;
+        li[c] += dd * p[c].y;
+    }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // R rows (waves) per workgroup, COLS beta strings per lane.
 template <int COLS, int R>
 __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci) {
@@ -53,24 +134,78 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
     __shared__ double tstage[2][kCiChunkTabs];
     const int nrank = 1 << ci.ob;
     int16_t* RB = reinterpret_cast<int16_t*>(lds_ci);
-    double2* rows = lds_ci + ((nrank * 2 + 15) >> 4);
     for (int i = threadIdx.x; i < nrank; i += kT) RB[i] = ci.rank_b[i];
     const StateDesc& s = sd[blockIdx.y];
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int ia = blockIdx.x * R + wave;
     const bool row_live = ia < ci.na_str;   // waves past the last row only help with staging
     const int NB = ci.nb_str;
-    double2* row = rows + size_t(wave) * NB;
+    double2* row = lds_ci + ((nrank * 2 + 15) >> 4) + size_t(wave) * ci_wave_words(NB, ci.npairs);
+    double2* wc = row + NB;                                   // pair coefficients (tb = 1, tb = 2)
+    uint32_t* ww = reinterpret_cast<uint32_t*>(wc + ci.npairs);   // pair beta sign masks
     const double2* __restrict__ phi = s.lam;   // phi in string-product order
     const uint32_t sA = uint32_t(__builtin_amdgcn_readfirstlane(int(ci.sa[row_live ? ia : 0])));
     uint32_t sB[COLS];
+    int ibc[COLS];
     double lr[COLS], li[COLS];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const int ib = lane + 64 * c;
-        sB[c] = ci.sb[ib < NB ? ib : 0];   // a column past the end repeats column 0, unwritten
+        ibc[c] = ib < NB ? ib : 0;   // a column past the end repeats column 0, unwritten
+        sB[c] = ci.sb[ibc[c]];
         lr[c] = li[c] = 0.0;
     }
+    auto stage_row = [&](const double2* prow) {
+        __builtin_amdgcn_wave_barrier();   // the wave's reads of the previous row are done
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            const int ib = lane + 64 * c;
+            if (ib < NB) row[ib] = prow[ib];
+        }
+        wave_lds_sync();
+    };
+    // ---- beta-pair classes
+    for (int pc = 0; row_live && pc < s.ci_npcls; ++pc) {
+        const CiPairClass P = ldc(s.ci_pcls + pc);
+        if (__popc(sA & P.xa) != P.half) continue;   // no in-sector partner row
+        stage_row(phi + size_t(ci.rank_a[sA ^ P.xa]) * NB);
+        const uint32_t ta = pext_mask(sA, P.xa);
+        for (int j = lane; j < ci.npairs; j += 64) {   // this row's coefficient of each pair
+            const CiPairRec r = s.ci_precs[P.rec0 + j];
+            double c1 = 0.0, c2 = 0.0;
+            uint32_t wb = 0;
+            if (r.tab >= 0) {
+                const double sg = (__popc(sA & r.wa) & 1) ? -1.0 : 1.0;
+                c1 = sg * s.ci_ptabs[r.tab + int(ta | (1u << r.ka))];
+                c2 = sg * s.ci_ptabs[r.tab + int(ta | (2u << r.ka))];
+                wb = r.wb;
+            }
+            wc[j] = make_double2(c1, c2);
+            ww[j] = wb;
+        }
+        wave_lds_sync();
+        const uint32_t* lst = ci.plist;
+        for (int e = 0; e < ci.e1; ++e, lst += NB) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const uint32_t ent = lst[ibc[c]];
+                const int pid = (ent >> 16) & 0xff;
+                const double2 cc = wc[pid];
+                const double2 p = row[ent & 0xffff];
+                const double t = ((ent >> 24) & 1) ? cc.y : cc.x;
+                const uint32_t flip = uint32_t(__popc(sB[c] & ww[pid])) << 31;
+                const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+                lr[c] += coef * p.x;
+                li[c] += coef * p.y;
+            }
+        }
+        for (int g = P.rest0; g < P.rest1; ++g) {   // the class's other groups
+            const CiGroup G = ldc(s.ci_rgroups + g);
+            ci_group<COLS>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, false, nullptr, row, RB, NB, lane, lr,
+                           li);
+        }
+    }
+    // ---- generic groups, chunk by chunk
     const int nch = s.ci_nchunks;
     double treg[kTPer];
     auto tload = [&](int c) {
@@ -107,78 +242,10 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
                 col_only = (G.meta >> 16) & 1;
                 if (valid) {
                     prow = phi + size_t(ci.rank_a[sA ^ G.xa]) * NB;
-                    if (!col_only) {
-                        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                        for (int c = 0; c < COLS; ++c) {
-                            const int ib = lane + 64 * c;
-                            if (ib < NB) row[ib] = prow[ib];
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    }
+                    if (!col_only) stage_row(prow);
                 }
             }
-            if (valid) {
-                const uint32_t xb = G.xb;
-                const uint32_t ta = pext_mask(sA, G.tba);
-                const int ka = (G.meta >> 8) & 0xff;
-                const uint32_t q0 = G.tbb & 31, q1 = (G.tbb >> 5) & 31, q2 = (G.tbb >> 10) & 31,
-                               q3 = (G.tbb >> 15) & 31;
-                double2 p[COLS];
-                uint32_t tix[COLS];
-                if (col_only) {
-#pragma unroll
-                    for (int c = 0; c < COLS; ++c) {
-                        const int ib = lane + 64 * c;
-                        p[c] = prow[ib < NB ? ib : 0];
-                    }
-                } else {   // all loads first, then the selects
-                    int rp[COLS];
-#pragma unroll
-                    for (int c = 0; c < COLS; ++c) rp[c] = RB[sB[c] ^ xb];
-#pragma unroll
-                    for (int c = 0; c < COLS; ++c) p[c] = row[rp[c] >= 0 ? rp[c] : 0];
-#pragma unroll
-                    for (int c = 0; c < COLS; ++c)
-                        if (rp[c] < 0) p[c] = make_double2(0.0, 0.0);
-                }
-#pragma unroll
-                for (int c = 0; c < COLS; ++c) {
-                    // beta table pattern (bit 31 of a beta string is 0)
-                    const uint32_t tb = __builtin_amdgcn_ubfe(sB[c], q0, 1) |
-                                        (__builtin_amdgcn_ubfe(sB[c], q1, 1) << 1) |
-                                        (__builtin_amdgcn_ubfe(sB[c], q2, 1) << 2) |
-                                        (__builtin_amdgcn_ubfe(sB[c], q3, 1) << 3);
-                    tix[c] = ta | (tb << ka);
-                }
-                double d[COLS];
-                {   // the first subgroup comes with the group record
-                    const uint32_t par = uint32_t(__popc(sA & G.wa));
-#pragma unroll
-                    for (int c = 0; c < COLS; ++c) {
-                        const double t = tab[G.tab + tix[c]];
-                        const uint32_t flip = (uint32_t(__popc(sB[c] & G.wb)) + par) << 31;
-                        d[c] = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
-                    }
-                }
-                for (int si = G.s0 + 1; si < G.s1; ++si) {
-                    const CiSub S = ldc(sp + si);
-                    const uint32_t par = uint32_t(__popc(sA & S.wa));
-#pragma unroll
-                    for (int c = 0; c < COLS; ++c) {
-                        const double t = tab[S.tab + tix[c]];
-                        const uint32_t flip = (uint32_t(__popc(sB[c] & S.wb)) + par) << 31;
-                        d[c] += __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < COLS; ++c) {
-                    lr[c] += d[c] * p[c].x;
-                    li[c] += d[c] * p[c].y;
-                }
-            }
+            if (valid) ci_group<COLS>(G, sp, tab, sA, sB, col_only, prow, row, RB, NB, lane, lr, li);
             G = Gn;
         }
         if (ch + 1 < nch) tstore((ch + 1) & 1);   // the buffer read two chunks ago
@@ -229,16 +296,17 @@ void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64
                        sd, perm, size);
 }
 
-// Rows per workgroup for a row length: as many as fit 64 KiB of row buffers, at most 8.
-static int ci_rows(int nb) {
+// Rows per workgroup: as many as fit 64 KiB of wave slices, at most 8.
+static int ci_rows(const CiArgs& ci) {
+    const size_t w = size_t(ci_wave_words(ci.nb_str, ci.npairs)) * sizeof(double2);
     int r = 8;
-    while (r > 1 && size_t(r) * nb * sizeof(double2) > (64u << 10)) r >>= 1;
+    while (r > 1 && size_t(r) * w > (64u << 10)) r >>= 1;
     return r;
 }
 
 static size_t ci_lds(const CiArgs& ci) {
     const size_t rank_bytes = ((size_t(2) << ci.ob) + 15) & ~size_t(15);
-    return rank_bytes + size_t(ci_rows(ci.nb_str)) * ci.nb_str * sizeof(double2);
+    return rank_bytes + size_t(ci_rows(ci)) * ci_wave_words(ci.nb_str, ci.npairs) * sizeof(double2);
 }
 
 template <int COLS, int R>
@@ -249,7 +317,7 @@ static void launch_cr(const StateDesc* sd, int count, const CiArgs& ci, hipStrea
 
 template <int COLS>
 static void launch_c(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    switch (ci_rows(ci.nb_str)) {
+    switch (ci_rows(ci)) {
         case 8: launch_cr<COLS, 8>(sd, count, ci, st); break;
         case 4: launch_cr<COLS, 4>(sd, count, ci, st); break;
         case 2: launch_cr<COLS, 2>(sd, count, ci, st); break;

@@ -102,6 +102,13 @@ struct CiHam {
     CiSub* subs = nullptr;
     double* tabs = nullptr;
     int nchunks = 0;
+    int ob = 0;   // beta orbitals the pair records are laid out for
+    CiPairClass* pcls = nullptr;
+    CiPairRec* precs = nullptr;
+    CiGroup* rgroups = nullptr;
+    CiSub* rsubs = nullptr;
+    double* ptabs = nullptr;
+    int npcls = 0;
 };
 
 struct DevHam {
@@ -553,18 +560,26 @@ struct CiSpace {
     uint32_t* d_sb = nullptr;
     int32_t* d_rank_a = nullptr;
     int16_t* d_rank_b = nullptr;
+    int npairs = 0, e1 = 0;
+    uint32_t* d_plist = nullptr;
     CiArgs args() const {
         CiArgs a{};
         a.sa = d_sa;
         a.sb = d_sb;
         a.rank_a = d_rank_a;
         a.rank_b = d_rank_b;
+        a.plist = d_plist;
         a.na_str = NA;
         a.nb_str = NB;
         a.ob = ob;
+        a.npairs = npairs;
+        a.e1 = e1;
         return a;
     }
 };
+
+// Index of the beta pair (p < q) among the pairs of ob orbitals, lexicographic.
+static int pair_index(int p, int q, int ob) { return p * ob - p * (p + 1) / 2 + (q - p - 1); }
 
 constexpr int kCiMaxBits = 13;    // alpha / beta orbitals of the string-product path
 constexpr int kCiMaxCols = 1024;  // beta strings per row (16 per lane)
@@ -600,7 +615,25 @@ static int ci_space(int n, int ne, CiSpace** out) {
         }
     c->NA = int(c->sa.size());
     c->NB = int(c->sb.size());
+    // beta-pair lists: for each column, the pairs with one orbital occupied
+    c->npairs = c->ob * (c->ob - 1) / 2;
+    c->e1 = nb * (c->ob - nb);
+    std::vector<uint32_t> plist(size_t(c->e1) * size_t(c->NB));
+    for (int ib = 0; ib < c->NB; ++ib) {
+        const uint32_t b = c->sb[ib];
+        int e = 0;
+        for (int p = 0; p < c->ob; ++p)
+            for (int q = p + 1; q < c->ob; ++q) {
+                const int bp = (b >> p) & 1, bq = (b >> q) & 1;
+                if (bp == bq) continue;
+                const int16_t r = c->rank_b[b ^ (1u << p) ^ (1u << q)];
+                plist[size_t(e) * c->NB + ib] = uint32_t(r) | (uint32_t(pair_index(p, q, c->ob)) << 16) |
+                                                (uint32_t(bq) << 24);
+                ++e;
+            }
+    }
     int rc = upload(&c->d_sa, c->sa.data(), c->sa.size());
+    if (!rc && !plist.empty()) rc = upload(&c->d_plist, plist.data(), plist.size());
     if (!rc) rc = upload(&c->d_sb, c->sb.data(), c->sb.size());
     if (!rc) rc = upload(&c->d_rank_a, c->rank_a.data(), c->rank_a.size());
     if (!rc) rc = upload(&c->d_rank_b, c->rank_b.data(), c->rank_b.size());
@@ -609,6 +642,7 @@ static int ci_space(int n, int ne, CiSpace** out) {
         (void)hipFree(c->d_sb);
         (void)hipFree(c->d_rank_a);
         (void)hipFree(c->d_rank_b);
+        (void)hipFree(c->d_plist);
         delete c;
         return rc;
     }
@@ -640,14 +674,19 @@ static int layout_perm(PackedLayout* lay, const CiSpace& cs, const HxTables& T) 
 }
 
 // Groups, subgroups and re-indexed tables of the string-product H-apply,
-// from the folded group structure, cut into LDS-sized chunks.  Groups that
-// change N_alpha or N_beta are left out (they pair no two sector states).
+// from the folded group structure.  Groups that change N_alpha or N_beta are
+// left out (they pair no two sector states).  Classes (equal alpha flip
+// mask xa) with groups that flip two beta orbitals and have one subgroup
+// become beta-pair classes; every other group goes to the generic list, cut
+// into LDS-sized chunks.
 static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     std::lock_guard<std::mutex> lk(H->mu);
     if (d->ci) {
         *out = d->ci;
         return VQE_OK;
     }
+    const int ob = H->n / 2;
+    const int npairs = ob * (ob - 1) / 2;
     struct G {
         uint32_t xa, xb;
         size_t gi;
@@ -661,8 +700,110 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     std::stable_sort(order.begin(), order.end(), [](const G& a, const G& b) {
         return a.xa != b.xa ? a.xa < b.xa : a.xb < b.xb;
     });
+    // table layout of a group: alpha and beta positions and their original table bits
+    struct Layout {
+        int k, ka, kb, pa[4], pb[4], slot_a[4], slot_b[4];
+    };
+    auto layout = [](const GroupDesc& gd) {
+        Layout l{};
+        l.k = int(gd.pos & 7);
+        for (int i = 0; i < l.k; ++i) {
+            const int q = int((gd.pos >> (3 + 5 * i)) & 31);
+            if (q % 2 == 0) {
+                l.pa[l.ka] = q / 2;
+                l.slot_a[l.ka++] = i;
+            } else {
+                l.pb[l.kb] = q / 2;
+                l.slot_b[l.kb++] = i;
+            }
+        }
+        return l;
+    };
+    auto push_table = [&](const Layout& l, const SubDesc& sd, std::vector<double>& t) {
+        for (int e = 0; e < (1 << l.k); ++e) {   // new index e = alpha pattern | beta pattern << ka
+            uint32_t old = 0;
+            for (int i = 0; i < l.ka; ++i)
+                if ((e >> i) & 1) old |= 1u << l.slot_a[i];
+            for (int i = 0; i < l.kb; ++i)
+                if ((e >> (l.ka + i)) & 1) old |= 1u << l.slot_b[i];
+            t.push_back(H->tabs[size_t(sd.tab) + old]);
+        }
+    };
+    auto pair_eligible = [&](const G& o) {
+        const GroupDesc& gd = H->groups[o.gi];
+        const Layout l = layout(gd);
+        return __builtin_popcount(o.xb) == 2 && gd.sub_end - gd.sub_begin == 1 &&
+               l.k == __builtin_popcount(H->groups[o.gi].x) && ob >= 2;
+    };
+    auto make_group = [&](const G& o, const Layout& l, int col_only) {
+        CiGroup g{};
+        g.xa = o.xa;
+        g.xb = o.xb;
+        for (int i = 0; i < l.ka; ++i) g.tba |= 1u << l.pa[i];
+        for (int i = 0; i < 4; ++i) g.tbb |= uint32_t(i < l.kb ? l.pb[i] : 31) << (5 * i);
+        g.meta = (__builtin_popcount(o.xa) / 2) | (l.ka << 8) | (col_only << 16);
+        return g;
+    };
+    std::map<uint32_t, int> is_pair;   // xa -> the class has a beta-pair group
+    for (const G& o : order)
+        if (pair_eligible(o)) is_pair[o.xa] = 1;
+    // ---- beta-pair classes
+    std::vector<CiPairClass> pcls;
+    std::vector<CiPairRec> precs;
+    std::vector<CiGroup> rgrp;
+    std::vector<CiSub> rsub;
+    std::vector<double> ptab;
+    for (size_t i = 0; i < order.size();) {
+        size_t j = i;
+        while (j < order.size() && order[j].xa == order[i].xa) ++j;
+        if (is_pair.count(order[i].xa)) {
+            CiPairClass pc{};
+            pc.xa = order[i].xa;
+            pc.half = __builtin_popcount(pc.xa) / 2;
+            pc.rec0 = int32_t(precs.size());
+            precs.resize(precs.size() + size_t(npairs), CiPairRec{-1, 0u, 0u, 0});
+            pc.rest0 = int32_t(rgrp.size());
+            for (size_t t = i; t < j; ++t) {
+                const G& o = order[t];
+                const GroupDesc& gd = H->groups[o.gi];
+                const Layout l = layout(gd);
+                if (pair_eligible(o)) {
+                    const int p = __builtin_ctz(o.xb), q = 31 - __builtin_clz(o.xb);
+                    CiPairRec& r = precs[size_t(pc.rec0 + pair_index(p, q, ob))];
+                    const SubDesc& sd = H->subs[gd.sub_begin];
+                    r.tab = int32_t(ptab.size());
+                    r.wa = compact_even_host(sd.w);
+                    r.wb = compact_even_host(sd.w >> 1);
+                    r.ka = l.ka;
+                    push_table(l, sd, ptab);
+                } else {
+                    CiGroup g = make_group(o, l, 0);
+                    g.s0 = int32_t(rsub.size());
+                    for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+                        const SubDesc& sd = H->subs[si];
+                        CiSub cs{};
+                        cs.wa = compact_even_host(sd.w);
+                        cs.wb = compact_even_host(sd.w >> 1);
+                        cs.tab = int32_t(ptab.size());
+                        push_table(l, sd, ptab);
+                        rsub.push_back(cs);
+                    }
+                    g.s1 = int32_t(rsub.size());
+                    g.wa = rsub[size_t(g.s0)].wa;
+                    g.wb = rsub[size_t(g.s0)].wb;
+                    g.tab = rsub[size_t(g.s0)].tab;
+                    rgrp.push_back(g);
+                }
+            }
+            pc.rest1 = int32_t(rgrp.size());
+            pcls.push_back(pc);
+        }
+        i = j;
+    }
+    // ---- generic groups (the other classes), chunked
     std::map<uint32_t, int> col_only;   // xa -> every group of the class has xb = 0
     for (const G& o : order) {
+        if (is_pair.count(o.xa)) continue;
         auto it = col_only.find(o.xa);
         if (it == col_only.end()) it = col_only.emplace(o.xa, 1).first;
         if (o.xb != 0) it->second = 0;
@@ -683,26 +824,11 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         open = false;
     };
     for (const G& o : order) {
+        if (is_pair.count(o.xa)) continue;
         const GroupDesc& gd = H->groups[o.gi];
-        const int k = int(gd.pos & 7);
-        const int nt = 1 << k;
-        int pa[4], pb[4], ka = 0, kb = 0, slot_a[4], slot_b[4];
-        for (int i = 0; i < k; ++i) {
-            const int q = int((gd.pos >> (3 + 5 * i)) & 31);
-            if (q % 2 == 0) {
-                pa[ka] = q / 2;
-                slot_a[ka++] = i;
-            } else {
-                pb[kb] = q / 2;
-                slot_b[kb++] = i;
-            }
-        }
-        CiGroup g{};
-        g.xa = o.xa;
-        g.xb = o.xb;
-        for (int i = 0; i < ka; ++i) g.tba |= 1u << pa[i];
-        for (int i = 0; i < 4; ++i) g.tbb |= uint32_t(i < kb ? pb[i] : 31) << (5 * i);
-        g.meta = (__builtin_popcount(o.xa) / 2) | (ka << 8) | (col_only[o.xa] << 16);
+        const Layout l = layout(gd);
+        const int nt = 1 << l.k;
+        const CiGroup g = make_group(o, l, col_only[o.xa]);
         int si = gd.sub_begin;
         while (si < gd.sub_end) {
             if (open && (int(grp.size()) - cur.g0 >= kCiChunkGroups ||
@@ -726,14 +852,9 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
                 cs.wa = compact_even_host(sd.w);
                 cs.wb = compact_even_host(sd.w >> 1);
                 cs.tab = int32_t(tab.size()) - cur.t0;
-                for (int t = 0; t < nt; ++t) {   // new index t = alpha pattern | beta pattern << ka
-                    uint32_t old = 0;
-                    for (int i = 0; i < ka; ++i)
-                        if ((t >> i) & 1) old |= 1u << slot_a[i];
-                    for (int i = 0; i < kb; ++i)
-                        if ((t >> (ka + i)) & 1) old |= 1u << slot_b[i];
-                    tab.push_back(H->tabs[size_t(sd.tab) + old]);
-                }
+                std::vector<double> t1;
+                push_table(l, sd, t1);
+                tab.insert(tab.end(), t1.begin(), t1.end());
                 sub.push_back(cs);
                 ++si;
             }
@@ -749,20 +870,30 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         }
     }
     close();
-    if (chunks.empty()) {   // no in-sector pair at all: one empty chunk
-        chunks.push_back(CiChunk{});
-    }
+    if (chunks.empty()) chunks.push_back(CiChunk{});   // nothing generic: one empty chunk
     auto* c = new CiHam();
     c->nchunks = int(chunks.size());
+    c->ob = ob;
+    c->npcls = int(pcls.size());
     int rc = upload(&c->chunks, chunks.data(), chunks.size());
     if (!rc) rc = upload(&c->groups, grp.data(), grp.size());
     if (!rc) rc = upload(&c->subs, sub.data(), sub.size());
     if (!rc) rc = upload(&c->tabs, tab.data(), tab.size());
+    if (!rc) rc = upload(&c->pcls, pcls.data(), pcls.size());
+    if (!rc) rc = upload(&c->precs, precs.data(), precs.size());
+    if (!rc) rc = upload(&c->rgroups, rgrp.data(), rgrp.size());
+    if (!rc) rc = upload(&c->rsubs, rsub.data(), rsub.size());
+    if (!rc) rc = upload(&c->ptabs, ptab.data(), ptab.size());
     if (rc) {
         (void)hipFree(c->chunks);
         (void)hipFree(c->groups);
         (void)hipFree(c->subs);
         (void)hipFree(c->tabs);
+        (void)hipFree(c->pcls);
+        (void)hipFree(c->precs);
+        (void)hipFree(c->rgroups);
+        (void)hipFree(c->rsubs);
+        (void)hipFree(c->ptabs);
         delete c;
         return rc;
     }
@@ -1178,6 +1309,11 @@ vqe_hamiltonian::~vqe_hamiltonian() {
             (void)hipFree(c->groups);
             (void)hipFree(c->subs);
             (void)hipFree(c->tabs);
+            (void)hipFree(c->pcls);
+            (void)hipFree(c->precs);
+            (void)hipFree(c->rgroups);
+            (void)hipFree(c->rsubs);
+            (void)hipFree(c->ptabs);
             delete c;
         }
         delete kv.second;
@@ -1437,6 +1573,12 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
         sd.ci_subs = ch->subs;
         sd.ci_tabs = ch->tabs;
         sd.ci_nchunks = ch->nchunks;
+        sd.ci_pcls = ch->pcls;
+        sd.ci_precs = ch->precs;
+        sd.ci_rgroups = ch->rgroups;
+        sd.ci_rsubs = ch->rsubs;
+        sd.ci_ptabs = ch->ptabs;
+        sd.ci_npcls = ch->npcls;
     }
     sd.gates = da->gates;
     sd.theta = cv.take<double>(P);
@@ -1649,6 +1791,12 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.ci_subs = ch->subs;
             sd.ci_tabs = ch->tabs;
             sd.ci_nchunks = ch->nchunks;
+            sd.ci_pcls = ch->pcls;
+            sd.ci_precs = ch->precs;
+            sd.ci_rgroups = ch->rgroups;
+            sd.ci_rsubs = ch->rsubs;
+            sd.ci_ptabs = ch->ptabs;
+            sd.ci_npcls = ch->npcls;
         }
         launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
