@@ -188,13 +188,19 @@ struct HxChunk {
 // is the block pair (h, h | khi) with h = pdep(o, free_hi), or the single
 // block h when khi = 0.  shape selects the launch shape; max_entries bounds
 // the entries of one tile (LDS per vector).
+// Gate j of a run pairs, in a tile whose first block has electron class
+// cls = kA * (Lb + 1) + kB, the entries listed in ent[off, off + cnt) with
+// {off, cnt} = info[(j - g0) * ncls + cls]: D index (bits 0-10), E index in
+// the tile (bits 11-22), parity of the D string's low chain bits (bit 23).
 struct PackedRun {
     int32_t g0, g1;
     uint32_t khi, free_hi;
     int32_t ntiles, L, na, nb;
     int32_t shape, shape_adj;   // launch shapes of the forward and reverse passes
     int32_t max_entries;
-    int32_t pad;
+    int32_t ncls;
+    const int2* info;
+    const uint32_t* ent;
 };
 
 // One excitation of a packed run: annihilated orbitals pd and created
@@ -277,6 +283,21 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
         v >>= 1;
         mask &= mask - 1;
     }
+    return out;
+}
+
+// Read-only load of a descriptor that is the same for every lane, through
+// the scalar data cache (constant address space: the compiler emits scalar
+// loads when the address is uniform).
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
+    using W = const __attribute__((address_space(4))) uint32_t;
+    W* w = reinterpret_cast<W*>(reinterpret_cast<uintptr_t>(p));
+    T out;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i) o[i] = w[i];
     return out;
 }
 

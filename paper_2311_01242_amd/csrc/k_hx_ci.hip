@@ -18,21 +18,9 @@
 namespace vqe {
 
 // Group and subgroup descriptors are the same for every lane: they are read
-// through the scalar data cache (constant address space) one group ahead.
+// through the scalar data cache (ldc) one group ahead.
 // The tables, gathered per lane, are staged chunk by chunk in LDS with the
 // next chunk's loads in flight during the current one.
-template <class T>
-__device__ __forceinline__ T ldc(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "descriptor of whole words");
-    using W = const __attribute__((address_space(4))) uint32_t;
-    W* w = reinterpret_cast<W*>(reinterpret_cast<uintptr_t>(p));
-    T out;
-    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
-#pragma unroll
-    for (int i = 0; i < int(sizeof(T) / 4); ++i) o[i] = w[i];
-    return out;
-}
-
 __device__ __forceinline__ uint32_t pext_mask(uint32_t v, uint32_t mask) {
     uint32_t out = 0;
     int k = 0;

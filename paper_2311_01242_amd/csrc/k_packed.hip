@@ -21,14 +21,6 @@
 
 namespace vqe {
 
-__device__ __forceinline__ uint32_t even_bits7(uint32_t v) {   // bits 0,2,..,12 -> 0..6
-    v &= 0x5555u;
-    v = (v | (v >> 1)) & 0x3333u;
-    v = (v | (v >> 2)) & 0x0F0Fu;
-    v = (v | (v >> 4)) & 0x00FFu;
-    return v;
-}
-
 struct BlockShape {
     int kA, kB, cB, cnt;
 };
@@ -58,8 +50,10 @@ __global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
 
 // VEC = 1: forward pass on phi.  VEC = 2: reverse sweep on phi and lambda
 // with per-gate, per-tile partials of Re <lambda|A_j phi> (A_j = T_j - T_j^dag).
-// Entry k of the tile (k < c0: block h, else block h | khi) is held by
-// thread k % BS; EPT * BS covers the largest block of the run.
+// Tile entry k (k < c0: block h, else block h | khi) is staged by thread
+// k % BS (EPT * BS covers the largest block of the run); a gate's pairs come
+// from the run's precomputed list for the tile's electron class, one pair
+// per thread per pass.
 template <int VEC, int BS, int EPT>
 __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, PackedRun run,
                                              const PackedGate* __restrict__ pg,
@@ -106,47 +100,43 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             if (VEC == 2) shl[k] = s.lam[gi];
         }
     }
-    uint32_t r[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int k = tid + BS * u;
-        r[u] = (k < c0) ? uint32_t(T.unA[T.offA[B0.kA] + k / B0.cB] | T.unB[T.offB[B0.kB] + k % B0.cB])
-                        : 0u;
-    }
     __syncthreads();
     const bool fwd = (VEC == 1);
     const int ng = run.g1 - run.g0;
+    const int cls = B0.kA * (T.Lb + 1) + B0.kB;
+    // the first list entry of each thread is loaded one gate ahead
+    int2 li = ldc(run.info + size_t(fwd ? 0 : ng - 1) * run.ncls + cls);
+    uint32_t ecur = (tid < li.y) ? run.ent[li.x + tid] : 0u;
     for (int t = 0; t < ng; ++t) {
         const int jl = fwd ? t : ng - 1 - t;
-        const PackedGate g = pg[jl];
+        int2 ln = make_int2(0, 0);
+        if (t + 1 < ng) ln = ldc(run.info + size_t(fwd ? jl + 1 : jl - 1) * run.ncls + cls);
+        const uint32_t enext = (tid < ln.y) ? run.ent[ln.x + tid] : 0u;
+        const PackedGate g = ldc(pg + jl);
         const double2 cs = s.cs[run.g0 + jl];
-        const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);
+        const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);   // the tile's part of the sign
+        const double ssin = sgn_hi * cs.y;
         double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const uint32_t rd = r[u];
-            const int k = tid + BS * u;
-            if (k < c0 && (rd & (g.pd | g.klo)) == g.pd) {
-                const uint32_t re = rd ^ g.pd ^ g.klo;
-                const int ie = eoff + int(T.rankA[even_bits7(re)]) * cBE + int(T.rankB[even_bits7(re >> 1)]);
-                const double sg = sgn_hi * parity_sign(rd & g.chlo);
-                if (fwd) {
-                    double2 d = shp[k], e = shp[ie];
-                    givens(d, e, cs.x, sg * cs.y);
-                    shp[k] = d;
-                    shp[ie] = e;
-                } else {
-                    double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
-                    // <lam| A phi> with A|D> = s|E>, A|E> = -s|D>
-                    acc += sg * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
-                    const double ss = -sg * cs.y;   // U^dag: rotation by -theta
-                    givens(fD, fE, cs.x, ss);
-                    givens(lD, lE, cs.x, ss);
-                    shp[k] = fD;
-                    shp[ie] = fE;
-                    shl[k] = lD;
-                    shl[ie] = lE;
-                }
+        for (int i = tid; i < li.y; i += BS) {
+            const uint32_t e = (i == tid) ? ecur : run.ent[li.x + i];
+            const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
+            const double ss = ((e >> 23) & 1u) ? -ssin : ssin;
+            if (fwd) {
+                double2 d = shp[k], f = shp[ie];
+                givens(d, f, cs.x, ss);
+                shp[k] = d;
+                shp[ie] = f;
+            } else {
+                double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
+                // <lam| A phi> with A|D> = s|E>, A|E> = -s|D> (s = ss / sin)
+                const double sg_t = ((e >> 23) & 1u) ? -sgn_hi : sgn_hi;
+                acc += sg_t * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
+                givens(fD, fE, cs.x, -ss);   // U^dag: rotation by -theta
+                givens(lD, lE, cs.x, -ss);
+                shp[k] = fD;
+                shp[ie] = fE;
+                shl[k] = lD;
+                shl[ie] = lE;
             }
         }
         if (!fwd) {
@@ -160,6 +150,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             }
         }
         __syncthreads();
+        li = ln;
+        ecur = enext;
     }
     if (!fwd) {
         if (tid == 0) {

@@ -125,6 +125,8 @@ struct PackedPlan {
     std::vector<PackedRun> runs;
     std::vector<int> off;             // PackedGate offset per run
     PackedGate* d_gates = nullptr;
+    int2* d_info = nullptr;           // pair-list index: {offset, count} per run, gate, class
+    uint32_t* d_ent = nullptr;        // pair lists
     std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
     int32_t* d_gcnt = nullptr;
     int32_t gstride = 1;
@@ -931,10 +933,15 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     const int n = A->n, L = lay.L;
     const uint32_t hmask = (1u << (n - L)) - 1u, lowmask = (1u << L) - 1u;
     const int64_t M = int64_t(A->gates.size());
+    const HxTables& T = *host_tables(L);
+    const int ncls = (T.La + 1) * (T.Lb + 1);
     auto* p = new PackedPlan();
     p->L = L;
     p->gcnt.assign(size_t(M), 1);
     std::vector<PackedGate> pg;
+    std::vector<int2> info;       // per run, gate and first-block class: {offset, count}
+    std::vector<uint32_t> ent;    // pair lists
+    std::vector<size_t> info0;    // offset of each run's info table
     int64_t j = 0;
     while (j < M) {
         const GateDesc& g = A->gates[j];
@@ -954,6 +961,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         r.nb = lay.nb;
         int maxb = 1, maxe = 1;
         int64_t moved = 0;
+        std::vector<char> used(size_t(ncls), 0);   // first-block classes of live tiles
         for (int32_t o = 0; o < r.ntiles; ++o) {
             uint32_t h0 = 0, bits = r.free_hi, v = uint32_t(o);
             while (bits) {
@@ -967,6 +975,44 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             maxb = std::max(maxb, std::max(c0, c1));
             maxe = std::max(maxe, c0 + c1);
             moved += c0 + c1;
+            const uint32_t hb = h0 << L;
+            const int kA = lay.na - __builtin_popcount(hb & 0x55555555u);
+            const int kB = lay.nb - __builtin_popcount(hb & 0xAAAAAAAAu);
+            used[size_t(kA * (T.Lb + 1) + kB)] = 1;
+        }
+        r.ncls = ncls;
+        info0.push_back(info.size());
+        const uint32_t khb = khi << L;
+        const int dA = __builtin_popcount(khb & 0x55555555u), dB = __builtin_popcount(khb & 0xAAAAAAAAu);
+        for (int64_t k = j; k < j2; ++k) {
+            const GateDesc& h = A->gates[k];
+            const uint32_t pd = h.pd, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
+            for (int cls = 0; cls < ncls; ++cls) {
+                int2 rec = make_int2(int(ent.size()), 0);
+                if (used[size_t(cls)]) {
+                    const int kA0 = cls / (T.Lb + 1), kB0 = cls % (T.Lb + 1);
+                    const int kA1 = kA0 - dA, kB1 = kB0 - dB;
+                    const int cB0 = T.offB[kB0 + 1] - T.offB[kB0];
+                    const int c0 = (T.offA[kA0 + 1] - T.offA[kA0]) * cB0;
+                    const int cB1 = T.offB[kB1 + 1] - T.offB[kB1];
+                    const int eoff = khi ? c0 : 0;
+                    for (int e = 0; e < c0; ++e) {   // D entries of the first block, rank order
+                        const uint32_t rd = uint32_t(T.unA[T.offA[kA0] + e / cB0] | T.unB[T.offB[kB0] + e % cB0]);
+                        if ((rd & (pd | klo)) != pd) continue;
+                        const uint32_t re = rd ^ pd ^ klo;
+                        const int ie = eoff + int(T.rankA[compact_even_host(re)]) * cB1 +
+                                       int(T.rankB[compact_even_host(re >> 1)]);
+                        const uint32_t par = uint32_t(__builtin_popcount(rd & chlo) & 1);
+                        if (e >= 2048 || ie >= 4096) {
+                            delete p;
+                            return fail(VQE_EINVAL, "packed layout: tile too large for the pair lists");
+                        }
+                        ent.push_back(uint32_t(e) | (uint32_t(ie) << 11) | (par << 23));
+                    }
+                    rec.y = int(ent.size()) - rec.x;
+                }
+                info.push_back(rec);
+            }
         }
         r.shape = packed_shape(maxb, tn.fwd_threads);
         r.shape_adj = packed_shape(maxb, tn.adj_threads);
@@ -997,11 +1043,20 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     p->fwd_bytes += double(sizeof(double2)) * double(lay.size);   // |HF> write
     int rc = upload(&p->d_gates, pg.data(), pg.size());
     if (!rc) rc = upload(&p->d_gcnt, p->gcnt.data(), p->gcnt.size());
+    if (!rc) rc = upload(&p->d_info, info.data(), info.size());
+    if (!rc) rc = upload(&p->d_ent, ent.data(), ent.size());
+    if (!rc)
+        for (size_t r = 0; r < p->runs.size(); ++r) {
+            p->runs[r].info = p->d_info + info0[r];
+            p->runs[r].ent = p->d_ent;
+        }
     if (!rc && p->max_lds > (64u << 10) && packed_enable_lds(p->max_lds) != 0)
         rc = fail(VQE_EDEVICE, "could not enable " + std::to_string(p->max_lds) + " bytes of LDS");
     if (rc) {
         (void)hipFree(p->d_gates);
         (void)hipFree(p->d_gcnt);
+        (void)hipFree(p->d_info);
+        (void)hipFree(p->d_ent);
         delete p;
         return rc;
     }
@@ -1336,6 +1391,8 @@ vqe_ansatz::~vqe_ansatz() {
         for (auto& pl : kv.second->packed) {
             (void)hipFree(pl.second->d_gates);
             (void)hipFree(pl.second->d_gcnt);
+            (void)hipFree(pl.second->d_info);
+            (void)hipFree(pl.second->d_ent);
             delete pl.second;
         }
         delete kv.second;
