@@ -56,29 +56,25 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None, packed=True):
         b.close()
         return ms
     if packed:
-        # L first (all three phases), then the run threads of each pass at that L
+        # every (L, threads) pair: the run threads of each pass are chosen per L,
+        # then L by the time of the whole evaluation
         best, best_t, best_ms = None, None, None
-        set_run_threads(n, True, 0, 0)
         for L in sorted({min(n, max(L, ne)) for L in (8, 9, 10, 11, 12, 13, 14)}):
-            m = measure(64 << 10, 64 << 10, L)
-            t = m[0] + m[1] + m[2]
+            rec = {}
+            for th in RUN_THREADS[:3]:
+                set_run_threads(n, True, th, th)
+                rec[th] = measure(64 << 10, 64 << 10, L)
+            tf = min(rec, key=lambda t: rec[t][0])
+            ta = min(rec, key=lambda t: rec[t][2])
+            m = [rec[tf][0], min(r[1] for r in rec.values()), rec[ta][2]]
+            t = sum(m)
             if log:
-                log(f"n={n} packed L={L}: {m[0]:.3f} + {m[1]:.3f} + {m[2]:.3f} ms")
+                log(f"n={n} packed L={L}: fwd {m[0]:.3f} ({tf}) + H {m[1]:.3f} + adj {m[2]:.3f} ({ta}) ms")
             if best_t is None or t < best_t:
-                best, best_t, best_ms = (64 << 10, 64 << 10, L), t, list(m)
-        tf, ta = 64, 64
-        for th in RUN_THREADS[1:]:
-            set_run_threads(n, True, th, th)
-            m = measure(*best)
-            if log:
-                log(f"n={n} packed L={best[2]} threads={th}: fwd {m[0]:.3f} adj {m[2]:.3f} ms")
-            if m[0] < best_ms[0]:
-                tf, best_ms[0] = th, m[0]
-            if m[2] < best_ms[2]:
-                ta, best_ms[2] = th, m[2]
-        set_tuning(n, True, *best)
-        set_run_threads(n, True, tf, ta)
-        return (*best, tf, ta), best_ms
+                best, best_t, best_ms = (64 << 10, 64 << 10, L, tf, ta), t, m
+        set_tuning(n, True, *best[:3])
+        set_run_threads(n, True, *best[3:])
+        return best, best_ms
     base = (64 << 10, 64 << 10, min(n, 14))
     best = list(base)
     ms = measure(*base)
