@@ -1,0 +1,134 @@
+"""Summaries of rocprofv3 output for the benchmark's roofline accounting.
+
+Two sub-commands, both reading the CSV files rocprofv3 writes with
+``--output-format csv``:
+
+``stats``   kernel-trace statistics (``*_kernel_stats.csv``) grouped into the
+            evaluation's phases, as a markdown table (stdout).
+
+``traffic`` HBM bytes per launch of each phase's kernels from two ``--pmc``
+            runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by
+            what the same counters read for a plain device copy of known size
+            (``bench.py --calibrate-copy``: 3 copies of 2 GiB).  Writes the
+            JSON that ``bench.py`` reads for ``roofline.traffic`` (keyed by
+            phase, with the sha256 of the kernel source it was measured on)
+            and prints a markdown table.
+
+Phase of a kernel: k_prun<1,...> forward, k_prun<2,...> adjoint,
+k_hx_ci / k_ci_scatter / k_ci_gather / k_hx_packed / k_hx_sector H-apply.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
+PHASE_SOURCE = {"forward": "k_packed.hip", "adjoint": "k_packed.hip", "h_apply": "k_hx_ci.hip"}
+COPY_BYTES = 2 ** 31
+
+
+def phase_of(name: str):
+    if "k_prun<1" in name:
+        return "forward"
+    if "k_prun<2" in name:
+        return "adjoint"
+    if any(k in name for k in ("k_hx_ci", "k_ci_scatter", "k_ci_gather", "k_hx_packed",
+                               "k_hx_sector")):
+        return "h_apply"
+    return None
+
+
+def short(name: str) -> str:
+    name = name.replace("void ", "").replace("vqe::", "")
+    return name.split("(")[0]
+
+
+def cmd_stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    by_phase = collections.defaultdict(lambda: [0, 0.0])
+    print("| kernel | calls | total ms | avg us | % |")
+    print("|---|---:|---:|---:|---:|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        calls, ns = int(r["Calls"]), float(r["TotalDurationNs"])
+        print(f"| {short(r['Name'])} | {calls} | {ns / 1e6:.2f} | {ns / calls / 1e3:.2f} | "
+              f"{100 * ns / total:.1f} |")
+        ph = phase_of(r["Name"])
+        if ph:
+            by_phase[ph][0] += calls
+            by_phase[ph][1] += ns
+    print()
+    print("| phase | calls | total ms | avg us per launch |")
+    print("|---|---:|---:|---:|")
+    for ph, (calls, ns) in sorted(by_phase.items()):
+        print(f"| {ph} | {calls} | {ns / 1e6:.2f} | {ns / calls / 1e3:.2f} |")
+
+
+def _sum_counter(path):
+    tot = collections.defaultdict(float)
+    cnt = collections.Counter()
+    for r in csv.DictReader(open(path)):
+        ph = phase_of(r["Kernel_Name"]) or short(r["Kernel_Name"])
+        tot[ph] += float(r["Counter_Value"])
+        cnt[ph] += 1
+    return tot, cnt
+
+
+def _sha(name):
+    with open(os.path.join(CSRC, name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def cmd_traffic(args):
+    f, fc = _sum_counter(args.fetch)
+    w, _ = _sum_counter(args.write)
+    cf, _ = _sum_counter(args.copy_fetch)
+    cw, _ = _sum_counter(args.copy_write)
+    copy_key = next(k for k in cf if "copyBuffer" in k)
+    kf = 3 * COPY_BYTES / (cf[copy_key] * 1024)
+    kw = 3 * COPY_BYTES / (cw[copy_key] * 1024)
+    out = {"calibration": {"fetch_factor": kf, "write_factor": kw,
+                           "copy_bytes": COPY_BYTES, "copies": 3},
+           "evaluations": args.evals, "kernels": {}}
+    print(f"calibration: FETCH_SIZE factor {kf:.3f}, WRITE_SIZE factor {kw:.3f}")
+    print()
+    print("| phase | launches / eval | fetch GB / eval | write GB / eval | bytes per launch |")
+    print("|---|---:|---:|---:|---:|")
+    for ph in ("forward", "h_apply", "adjoint"):
+        if ph not in f:
+            continue
+        fetch = f[ph] * 1024 * kf / args.evals
+        write = w.get(ph, 0.0) * 1024 * kw / args.evals
+        launches = fc[ph] / args.evals
+        per = (fetch + write) / launches
+        out["kernels"][ph] = {"source_sha256": _sha(PHASE_SOURCE[ph]), "source": PHASE_SOURCE[ph],
+                              "fetch_bytes_per_eval": fetch, "write_bytes_per_eval": write,
+                              "launches_per_eval": launches, "bytes_per_launch": per}
+        print(f"| {ph} | {launches:.0f} | {fetch / 1e9:.2f} | {write / 1e9:.2f} | {per / 1e6:.2f} MB |")
+    with open(args.out, "w") as fo:
+        json.dump(out, fo, indent=1, sort_keys=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(prog="python -m paper_2311_01242_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-fetch", required=True)
+    t.add_argument("--copy-write", required=True)
+    t.add_argument("--evals", type=float, required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
+
+
+if __name__ == "__main__":
+    main()
