@@ -40,11 +40,12 @@ __host__ __device__ inline int ci_wave_words(int nb, int npairs) {
 
 // lambda += D_G(b) phi(partner) for one group over the wave's columns.
 // tab: the group's table base (LDS chunk or global); sp: its subgroups.
-template <int COLS>
+template <int COLS, int W>
 __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, const double* tab,
-                                         uint32_t sA, const uint32_t (&sB)[COLS], bool col_only,
+                                         uint32_t sA, const uint32_t (&sB)[COLS],
+                                         const int (&ibc)[COLS], bool col_only,
                                          const double2* prow, const double2* row,
-                                         const int16_t* RB, int NB, int lane, double (&lr)[COLS],
+                                         const int16_t* RB, double (&lr)[COLS],
                                          double (&li)[COLS]) {
     const uint32_t ta = pext_mask(sA, G.tba);
     const int ka = (G.meta >> 8) & 0xff;
@@ -55,8 +56,7 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
     if (col_only) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            const int ib = lane + 64 * c;
-            p[c] = prow[ib < NB ? ib : 0];
+            p[c] = prow[ibc[c]];
             ok[c] = true;
         }
     } else {   // all loads first, then the selects
@@ -113,22 +113,28 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// R rows (waves) per workgroup, COLS beta strings per lane.
-template <int COLS, int R>
-__global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci) {
-    constexpr int kT = R * 64;
+// R rows per workgroup, W waves per row (R = 1 when W > 1), COLS beta
+// strings per lane: lane l of the row's wave w holds columns
+// (64 w + l) + 64 W c.  The waves of a row share its LDS slice.
+template <int COLS, int R, int W>
+__global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci) {
+    static_assert(R == 1 || W == 1, "several rows of one wave each, or one row of several waves");
+    constexpr int kT = R * W * 64;
     constexpr int kTPer = (kCiChunkTabs + kT - 1) / kT;
     extern __shared__ double2 lds_ci[];
     __shared__ double tstage[2][kCiChunkTabs];
+    __shared__ double ered[W];
     const int nrank = 1 << ci.ob;
     int16_t* RB = reinterpret_cast<int16_t*>(lds_ci);
     for (int i = threadIdx.x; i < nrank; i += kT) RB[i] = ci.rank_b[i];
     const StateDesc& s = sd[blockIdx.y];
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int ia = blockIdx.x * R + wave;
+    const int rslot = wave / W, wr = wave % W;   // row slot in the block, wave within the row
+    const int rt = wr * 64 + lane;               // thread within the row
+    const int ia = blockIdx.x * R + rslot;
     const bool row_live = ia < ci.na_str;   // waves past the last row only help with staging
     const int NB = ci.nb_str;
-    double2* row = lds_ci + ((nrank * 2 + 15) >> 4) + size_t(wave) * ci_wave_words(NB, ci.npairs);
+    double2* row = lds_ci + ((nrank * 2 + 15) >> 4) + size_t(rslot) * ci_wave_words(NB, ci.npairs);
     double2* wc = row + NB;                                   // pair coefficients (tb = 1, tb = 2)
     uint32_t* ww = reinterpret_cast<uint32_t*>(wc + ci.npairs);   // pair beta sign masks
     const double2* __restrict__ phi = s.lam;   // phi in string-product order
@@ -138,19 +144,22 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
     double lr[COLS], li[COLS];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
-        const int ib = lane + 64 * c;
+        const int ib = rt + 64 * W * c;
         ibc[c] = ib < NB ? ib : 0;   // a column past the end repeats column 0, unwritten
         sB[c] = ci.sb[ibc[c]];
         lr[c] = li[c] = 0.0;
     }
+    auto row_sync = [&]() {   // the row's LDS slice is shared by its W waves
+        if (W == 1)
+            wave_lds_sync();
+        else
+            __syncthreads();
+    };
     auto stage_row = [&](const double2* prow) {
-        __builtin_amdgcn_wave_barrier();   // the wave's reads of the previous row are done
-#pragma unroll
-        for (int c = 0; c < COLS; ++c) {
-            const int ib = lane + 64 * c;
-            if (ib < NB) row[ib] = prow[ib];
-        }
-        wave_lds_sync();
+        if (W == 1) __builtin_amdgcn_wave_barrier();   // reads of the previous row are done
+        else __syncthreads();
+        for (int ib = rt; ib < NB; ib += 64 * W) row[ib] = prow[ib];
+        row_sync();
     };
     // ---- beta-pair classes
     for (int pc = 0; row_live && pc < s.ci_npcls; ++pc) {
@@ -158,7 +167,7 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
         if (__popc(sA & P.xa) != P.half) continue;   // no in-sector partner row
         stage_row(phi + size_t(ci.rank_a[sA ^ P.xa]) * NB);
         const uint32_t ta = pext_mask(sA, P.xa);
-        for (int j = lane; j < ci.npairs; j += 64) {   // this row's coefficient of each pair
+        for (int j = rt; j < ci.npairs; j += 64 * W) {   // this row's coefficient of each pair
             const CiPairRec r = s.ci_precs[P.rec0 + j];
             double c1 = 0.0, c2 = 0.0;
             uint32_t wb = 0;
@@ -171,7 +180,7 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
             wc[j] = make_double2(c1, c2);
             ww[j] = wb;
         }
-        wave_lds_sync();
+        row_sync();
         const uint32_t* lst = ci.plist;
         for (int e = 0; e < ci.e1; ++e, lst += NB) {
 #pragma unroll
@@ -189,8 +198,7 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
         }
         for (int g = P.rest0; g < P.rest1; ++g) {   // the class's other groups
             const CiGroup G = ldc(s.ci_rgroups + g);
-            ci_group<COLS>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, false, nullptr, row, RB, NB, lane, lr,
-                           li);
+            ci_group<COLS, W>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, lr, li);
         }
     }
     // ---- generic groups, chunk by chunk
@@ -233,7 +241,7 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
                     if (!col_only) stage_row(prow);
                 }
             }
-            if (valid) ci_group<COLS>(G, sp, tab, sA, sB, col_only, prow, row, RB, NB, lane, lr, li);
+            if (valid) ci_group<COLS, W>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, lr, li);
             G = Gn;
         }
         if (ch + 1 < nch) tstore((ch + 1) & 1);   // the buffer read two chunks ago
@@ -245,7 +253,7 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
     double2* out = s.aux + size_t(ia) * NB;
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
-        const int ib = lane + 64 * c;
+        const int ib = rt + 64 * W * c;
         if (ib < NB) {
             out[ib] = make_double2(lr[c], li[c]);
             const double2 q = mine[ib];
@@ -253,7 +261,18 @@ __global__ void __launch_bounds__(R * 64) k_hx_ci(const StateDesc* __restrict__ 
         }
     }
     acc = wave_total(acc);
-    if (lane == 0) s.part_e[ia] = acc;
+    if (W == 1) {
+        if (lane == 0) s.part_e[ia] = acc;
+    } else {   // the row's wave totals in fixed order
+        if (lane == 0) ered[wr] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v += ered[w];
+            s.part_e[ia] = v;
+        }
+    }
 }
 
 __global__ void k_ci_scatter(const StateDesc* __restrict__ sd, const int32_t* __restrict__ perm,
@@ -284,48 +303,68 @@ void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64
                        sd, perm, size);
 }
 
-// Rows per workgroup: as many as fit 64 KiB of wave slices, at most 8.
-static int ci_rows(const CiArgs& ci) {
+// Launch shape: rows of up to 256 beta strings take one wave each, as many
+// rows per workgroup as fit 64 KiB of slices (at most 8); longer rows take
+// four waves each, one row per workgroup.
+struct CiShape {
+    int cols, rows, waves;
+};
+
+static CiShape ci_shape(const CiArgs& ci) {
+    CiShape sh;
+    if (ci.nb_str > 256) {
+        sh.waves = 4;
+        sh.rows = 1;
+        sh.cols = (ci.nb_str + 255) / 256;
+        return sh;
+    }
+    sh.waves = 1;
+    sh.cols = (ci.nb_str + 63) / 64;
     const size_t w = size_t(ci_wave_words(ci.nb_str, ci.npairs)) * sizeof(double2);
-    int r = 8;
-    while (r > 1 && size_t(r) * w > (64u << 10)) r >>= 1;
-    return r;
+    sh.rows = 8;
+    while (sh.rows > 1 && size_t(sh.rows) * w > (64u << 10)) sh.rows >>= 1;
+    return sh;
 }
 
 static size_t ci_lds(const CiArgs& ci) {
     const size_t rank_bytes = ((size_t(2) << ci.ob) + 15) & ~size_t(15);
-    return rank_bytes + size_t(ci_rows(ci)) * ci_wave_words(ci.nb_str, ci.npairs) * sizeof(double2);
+    return rank_bytes + size_t(ci_shape(ci).rows) * ci_wave_words(ci.nb_str, ci.npairs) * sizeof(double2);
 }
 
-template <int COLS, int R>
-static void launch_cr(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
+template <int COLS, int R, int W>
+static void launch_crw(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
     const dim3 grid((ci.na_str + R - 1) / R, count);
-    hipLaunchKernelGGL((k_hx_ci<COLS, R>), grid, dim3(R * 64), ci_lds(ci), st, sd, ci);
+    hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci);
 }
 
 template <int COLS>
 static void launch_c(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    switch (ci_rows(ci)) {
-        case 8: launch_cr<COLS, 8>(sd, count, ci, st); break;
-        case 4: launch_cr<COLS, 4>(sd, count, ci, st); break;
-        case 2: launch_cr<COLS, 2>(sd, count, ci, st); break;
-        default: launch_cr<COLS, 1>(sd, count, ci, st); break;
+    switch (ci_shape(ci).rows) {
+        case 8: launch_crw<COLS, 8, 1>(sd, count, ci, st); break;
+        case 4: launch_crw<COLS, 4, 1>(sd, count, ci, st); break;
+        case 2: launch_crw<COLS, 2, 1>(sd, count, ci, st); break;
+        default: launch_crw<COLS, 1, 1>(sd, count, ci, st); break;
     }
 }
 
 void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    const int cols = (ci.nb_str + 63) / 64;
-    if (cols <= 1) launch_c<1>(sd, count, ci, st);
-    else if (cols <= 2) launch_c<2>(sd, count, ci, st);
-    else if (cols <= 4) launch_c<4>(sd, count, ci, st);
-    else if (cols <= 8) launch_c<8>(sd, count, ci, st);
-    else launch_c<16>(sd, count, ci, st);
+    const CiShape sh = ci_shape(ci);
+    if (sh.waves > 1) {
+        if (sh.cols <= 1) launch_crw<1, 1, 4>(sd, count, ci, st);
+        else if (sh.cols <= 2) launch_crw<2, 1, 4>(sd, count, ci, st);
+        else if (sh.cols <= 3) launch_crw<3, 1, 4>(sd, count, ci, st);
+        else launch_crw<4, 1, 4>(sd, count, ci, st);
+        return;
+    }
+    if (sh.cols <= 1) launch_c<1>(sd, count, ci, st);
+    else if (sh.cols <= 2) launch_c<2>(sd, count, ci, st);
+    else launch_c<4>(sd, count, ci, st);
 }
 
 int ci_prepare(const CiArgs& ci) {
     const size_t lds = ci_lds(ci);
-    const size_t fixed = sizeof(double) * 2 * kCiChunkTabs;
-    if ((ci.nb_str + 63) / 64 > 16 || lds + fixed > (160u << 10)) return 1;
+    const size_t fixed = sizeof(double) * 2 * kCiChunkTabs + 64;
+    if (ci.nb_str > 1024 || lds + fixed > (160u << 10)) return 1;
     if (lds + fixed <= (64u << 10)) return 0;
     hipError_t e = hipSuccess;
     auto set = [&](const void* f) {
@@ -333,16 +372,18 @@ int ci_prepare(const CiArgs& ci) {
         if (r != hipSuccess) e = r;
     };
 #define VQE_CI_SET(C)                                                   \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 8>));                 \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 4>));                 \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 2>));                 \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 1>));
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 8, 1>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 4, 1>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 2, 1>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 1, 1>));
     VQE_CI_SET(1)
     VQE_CI_SET(2)
     VQE_CI_SET(4)
-    VQE_CI_SET(8)
-    VQE_CI_SET(16)
 #undef VQE_CI_SET
+    set(reinterpret_cast<const void*>(&k_hx_ci<1, 1, 4>));
+    set(reinterpret_cast<const void*>(&k_hx_ci<2, 1, 4>));
+    set(reinterpret_cast<const void*>(&k_hx_ci<3, 1, 4>));
+    set(reinterpret_cast<const void*>(&k_hx_ci<4, 1, 4>));
     return e == hipSuccess ? 0 : 1;
 }
 

@@ -374,3 +374,17 @@ def test_packed_run_thread_counts_agree(threads):
         vq.set_run_threads(n, False, 0, 0)
     assert abs(e - prob.energy(theta)) < TOL_E
     assert abs(e - e0) < 1e-12 and np.abs(g - g0).max() < 1e-12
+
+
+def test_string_product_long_rows_match_block_order():
+    """Beta-string rows longer than 256 take several waves per row in the
+    string-product H-apply; against the block-order H-apply (itself pinned to
+    the oracle above) at 22 qubits, 462 beta strings per row."""
+    n, ne = 22, 10
+    h0, h, g = random_integrals(n, 2201)
+    H = vq.Hamiltonian.from_integrals(n, h0, h, g)
+    theta = uniform_theta(2202, vq.Ansatz.uccsd(n, ne).n_params)
+    e2, g2 = _eval_layout(H, n, ne, theta, 2)
+    e1, g1 = _eval_layout(H, n, ne, theta, 1)
+    assert abs(e2 - e1) < 1e-12 * max(1.0, abs(e1)) * 10
+    assert np.abs(g2 - g1).max() < 1e-11
