@@ -301,6 +301,30 @@ __device__ __forceinline__ T ldc(const T* p) {
     return out;
 }
 
+// Loads and stores through the global address space.  Through a generic
+// pointer the compiler emits flat accesses, which also count as LDS traffic:
+// a later LDS access then waits for the global access to complete.
+__device__ __forceinline__ double2 ldg2(const double2* p) {
+    const __attribute__((address_space(1))) double* q =
+        reinterpret_cast<const __attribute__((address_space(1))) double*>(reinterpret_cast<uintptr_t>(p));
+    return make_double2(q[0], q[1]);
+}
+
+__device__ __forceinline__ void stg2(double2* p, double2 v) {
+    __attribute__((address_space(1))) double* q =
+        reinterpret_cast<__attribute__((address_space(1))) double*>(reinterpret_cast<uintptr_t>(p));
+    q[0] = v.x;
+    q[1] = v.y;
+}
+
+__device__ __forceinline__ double ldg64(const double* p) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) double*>(reinterpret_cast<uintptr_t>(p));
+}
+
+__device__ __forceinline__ uint32_t ldg32(const uint32_t* p) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(reinterpret_cast<uintptr_t>(p));
+}
+
 // Streaming (non-temporal) accesses for data with no reuse in L2.
 __device__ __forceinline__ double2 nt_load(const double2* p) {
     return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));

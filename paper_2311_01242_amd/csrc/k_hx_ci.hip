@@ -40,7 +40,7 @@ __host__ __device__ inline int ci_wave_words(int nb, int npairs) {
 
 // lambda += D_G(b) phi(partner) for one group over the wave's columns.
 // tab: the group's table base (LDS chunk or global); sp: its subgroups.
-template <int COLS, int W>
+template <int COLS, int W, bool GTAB>
 __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, const double* tab,
                                          uint32_t sA, const uint32_t (&sB)[COLS],
                                          const int (&ibc)[COLS], bool col_only,
@@ -56,7 +56,7 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
     if (col_only) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            p[c] = prow[ibc[c]];
+            p[c] = ldg2(prow + ibc[c]);
             ok[c] = true;
         }
     } else {   // all loads first, then the selects
@@ -84,7 +84,7 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
         const uint32_t par = uint32_t(__popc(sA & G.wa));
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            const double t = tab[G.tab + tix[c]];
+            const double t = GTAB ? ldg64(tab + G.tab + tix[c]) : tab[G.tab + tix[c]];
             const uint32_t flip = (uint32_t(__popc(sB[c] & G.wb)) + par) << 31;
             d[c] = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
         }
@@ -94,7 +94,7 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
         const uint32_t par = uint32_t(__popc(sA & S.wa));
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            const double t = tab[S.tab + tix[c]];
+            const double t = GTAB ? ldg64(tab + S.tab + tix[c]) : tab[S.tab + tix[c]];
             const uint32_t flip = (uint32_t(__popc(sB[c] & S.wb)) + par) << 31;
             d[c] += __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
         }
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     double2* wc = row + NB;                                   // pair coefficients (tb = 1, tb = 2)
     uint32_t* ww = reinterpret_cast<uint32_t*>(wc + ci.npairs);   // pair beta sign masks
     const double2* __restrict__ phi = s.lam;   // phi in string-product order
-    const uint32_t sA = uint32_t(__builtin_amdgcn_readfirstlane(int(ci.sa[row_live ? ia : 0])));
+    const uint32_t sA = ldc(ci.sa + (row_live ? ia : 0));
     uint32_t sB[COLS];
     int ibc[COLS];
     double lr[COLS], li[COLS];
@@ -156,16 +156,20 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             __syncthreads();
     };
     auto stage_row = [&](const double2* prow) {
+        double2 v[COLS];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) v[c] = ldg2(prow + ibc[c]);
         if (W == 1) __builtin_amdgcn_wave_barrier();   // reads of the previous row are done
         else __syncthreads();
-        for (int ib = rt; ib < NB; ib += 64 * W) row[ib] = prow[ib];
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) row[ibc[c]] = v[c];   // a repeated column 0 rewrites its own value
         row_sync();
     };
     // ---- beta-pair classes
     for (int pc = 0; row_live && pc < s.ci_npcls; ++pc) {
         const CiPairClass P = ldc(s.ci_pcls + pc);
         if (__popc(sA & P.xa) != P.half) continue;   // no in-sector partner row
-        stage_row(phi + size_t(ci.rank_a[sA ^ P.xa]) * NB);
+        stage_row(phi + size_t(ldc(ci.rank_a + (sA ^ P.xa))) * NB);
         const uint32_t ta = pext_mask(sA, P.xa);
         for (int j = rt; j < ci.npairs; j += 64 * W) {   // this row's coefficient of each pair
             const CiPairRec r = s.ci_precs[P.rec0 + j];
@@ -173,8 +177,8 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             uint32_t wb = 0;
             if (r.tab >= 0) {
                 const double sg = (__popc(sA & r.wa) & 1) ? -1.0 : 1.0;
-                c1 = sg * s.ci_ptabs[r.tab + int(ta | (1u << r.ka))];
-                c2 = sg * s.ci_ptabs[r.tab + int(ta | (2u << r.ka))];
+                c1 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (1u << r.ka)));
+                c2 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (2u << r.ka)));
                 wb = r.wb;
             }
             wc[j] = make_double2(c1, c2);
@@ -185,7 +189,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         for (int e = 0; e < ci.e1; ++e, lst += NB) {
 #pragma unroll
             for (int c = 0; c < COLS; ++c) {
-                const uint32_t ent = lst[ibc[c]];
+                const uint32_t ent = ldg32(lst + ibc[c]);
                 const int pid = (ent >> 16) & 0xff;
                 const double2 cc = wc[pid];
                 const double2 p = row[ent & 0xffff];
@@ -198,7 +202,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         }
         for (int g = P.rest0; g < P.rest1; ++g) {   // the class's other groups
             const CiGroup G = ldc(s.ci_rgroups + g);
-            ci_group<COLS, W>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, lr, li);
+            ci_group<COLS, W, true>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, lr, li);
         }
     }
     // ---- generic groups, chunk by chunk
@@ -209,7 +213,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
         for (int k = 0; k < kTPer; ++k) {
             const int i = threadIdx.x + k * kT;
-            treg[k] = (i < ck.t1 - ck.t0) ? s.ci_tabs[ck.t0 + i] : 0.0;
+            treg[k] = (i < ck.t1 - ck.t0) ? ldg64(s.ci_tabs + ck.t0 + i) : 0.0;
         }
     };
     auto tstore = [&](int buf) {
@@ -237,11 +241,11 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                 valid = __popc(sA & G.xa) == (G.meta & 0xff);
                 col_only = (G.meta >> 16) & 1;
                 if (valid) {
-                    prow = phi + size_t(ci.rank_a[sA ^ G.xa]) * NB;
+                    prow = phi + size_t(ldc(ci.rank_a + (sA ^ G.xa))) * NB;
                     if (!col_only) stage_row(prow);
                 }
             }
-            if (valid) ci_group<COLS, W>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, lr, li);
+            if (valid) ci_group<COLS, W, false>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, lr, li);
             G = Gn;
         }
         if (ch + 1 < nch) tstore((ch + 1) & 1);   // the buffer read two chunks ago
@@ -255,8 +259,8 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     for (int c = 0; c < COLS; ++c) {
         const int ib = rt + 64 * W * c;
         if (ib < NB) {
-            out[ib] = make_double2(lr[c], li[c]);
-            const double2 q = mine[ib];
+            stg2(out + ib, make_double2(lr[c], li[c]));
+            const double2 q = ldg2(mine + ib);
             acc += q.x * lr[c] + q.y * li[c];
         }
     }

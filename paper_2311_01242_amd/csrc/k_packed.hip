@@ -91,34 +91,46 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const int64_t g0 = base[h0], g1 = base[h1];
     double2* shp = sh;
     double2* shl = sh + nE;
-#pragma unroll
-    for (int u = 0; u < 2 * EPT; ++u) {
-        const int k = tid + BS * u;
-        if (k < nE) {
-            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
-            shp[k] = s.phi[gi];
-            if (VEC == 2) shl[k] = s.lam[gi];
-        }
-    }
-    __syncthreads();
     const bool fwd = (VEC == 1);
     const int ng = run.g1 - run.g0;
     const int cls = B0.kA * (T.Lb + 1) + B0.kB;
-    // the first list entry of each thread is loaded one gate ahead
+    // the first list entry of each thread is loaded one gate ahead (issued
+    // before the tile loads, so that it has arrived when the gate loop starts)
     int2 li = ldc(run.info + size_t(fwd ? 0 : ng - 1) * run.ncls + cls);
-    uint32_t ecur = (tid < li.y) ? run.ent[li.x + tid] : 0u;
+    uint32_t ecur = (tid < li.y) ? ldg32(run.ent + li.x + tid) : 0u;
+    {   // all loads first (clamped into the tile), then the LDS stores
+        double2 vp[2 * EPT], vl[2 * EPT];
+#pragma unroll
+        for (int u = 0; u < 2 * EPT; ++u) {
+            const int k = min(tid + BS * u, nE - 1);
+            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            vp[u] = ldg2(s.phi + gi);
+            if (VEC == 2) vl[u] = ldg2(s.lam + gi);
+        }
+        // unconditional stores (a clamped slot rewrites the last entry with its
+        // own value), so that every load is waited for on every path
+#pragma unroll
+        for (int u = 0; u < 2 * EPT; ++u) {
+            const int k = min(tid + BS * u, nE - 1);
+            shp[k] = vp[u];
+            if (VEC == 2) shl[k] = vl[u];
+        }
+    }
+    __syncthreads();
     for (int t = 0; t < ng; ++t) {
         const int jl = fwd ? t : ng - 1 - t;
         int2 ln = make_int2(0, 0);
         if (t + 1 < ng) ln = ldc(run.info + size_t(fwd ? jl + 1 : jl - 1) * run.ncls + cls);
-        const uint32_t enext = (tid < ln.y) ? run.ent[ln.x + tid] : 0u;
+        const uint32_t enext = (tid < ln.y) ? ldg32(run.ent + ln.x + tid) : 0u;
         const PackedGate g = ldc(pg + jl);
-        const double2 cs = s.cs[run.g0 + jl];
+        // scalar load: a vector load here would make the wait for it also
+        // wait for the next gate's list entry, defeating the look-ahead
+        const double2 cs = ldc(s.cs + run.g0 + jl);
         const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);   // the tile's part of the sign
         const double ssin = sgn_hi * cs.y;
         double acc = 0.0;
         for (int i = tid; i < li.y; i += BS) {
-            const uint32_t e = (i == tid) ? ecur : run.ent[li.x + i];
+            const uint32_t e = (i == tid) ? ecur : ldg32(run.ent + li.x + i);
             const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
             const double ss = ((e >> 23) & 1u) ? -ssin : ssin;
             if (fwd) {
@@ -168,8 +180,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         const int k = tid + BS * u;
         if (k < nE) {
             const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
-            s.phi[gi] = shp[k];
-            if (VEC == 2) s.lam[gi] = shl[k];
+            stg2(s.phi + gi, shp[k]);
+            if (VEC == 2) stg2(s.lam + gi, shl[k]);
         }
     }
 }
