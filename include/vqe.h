@@ -116,6 +116,15 @@ int vqe_ansatz_from_rotations(int n_qubits, int32_t n_params, int64_t n_rot,
                               const int32_t* param_index, const double* scale,
                               vqe_ansatz** out);
 
+/* Sub-ansatz of a pool (ADAPT-VQE, Sec. 2.1): the gates of pool parameter
+ * param_index[0], then those of param_index[1], ..., each keeping the pool's
+ * gate order; parameter k of the result drives the gates of param_index[k],
+ * so an operator may appear more than once.  count = 0 gives the identity
+ * program (the HF state).  Errors: ERANGE for an index outside the pool's
+ * parameters or a negative count. */
+int vqe_ansatz_select(const vqe_ansatz* pool, int64_t count, const int32_t* param_index,
+                      vqe_ansatz** out);
+
 /* Sizes: qubits, parameters, gates, electrons of the reference (-1 if none). */
 int vqe_ansatz_info(const vqe_ansatz* A, int* n_qubits, int32_t* n_params,
                     int64_t* n_gates, int* n_electrons);
@@ -165,6 +174,19 @@ int vqe_expectation(const vqe_state* s, const vqe_hamiltonian* H, double* energy
  * NaN/Inf results return ENUMERIC (outputs still written). */
 int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
                     const double* theta, double* energy, double* grad, void* hip_stream);
+
+/* ADAPT-VQE pool gradient (Sec. 2.1, "ADAPT-VQE algorithm"): with
+ * psi = U_A(theta)|HF>, *energy = <psi|H|psi> and, for every parameter k of
+ * `pool`, pool_grad[k] = d/dt <psi_t|H|psi_t> at t = 0, where psi_t applies
+ * the pool's gates of parameter k at angle t after U_A(theta).  One forward
+ * pass, one H-apply and one reverse sweep of the pool at angle zero (which
+ * leaves psi and H psi unchanged).  theta: host, A's n_params; pool_grad:
+ * host, the pool's n_params.  The pool must act on the same qubits and
+ * reference as A; in the packed sector layout it must fit the layout chosen
+ * for A (EINVAL otherwise).  NaN/Inf results return ENUMERIC. */
+int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A, const vqe_ansatz* pool,
+                      int n_electrons, const double* theta, double* energy, double* pool_grad,
+                      void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Batched evaluation of many independent problems
@@ -269,6 +291,38 @@ int vqe_minimize_bfgs(int n, vqe_objective_fn fn, void* ctx, const double* x0,
 int vqe_run(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
             const double* theta0, const vqe_options* opts, double* theta_out,
             double* trace_out, vqe_result* res, void* hip_stream);
+
+typedef struct {
+    double grad_tol;      /* stop once the pool gradient's L2 norm < grad_tol */
+    double tie_tol;       /* |g| within tie_tol of the largest count as tied;
+                           * ties go to the lowest pool index */
+    int max_operators;    /* cap on operators added (>= 0) */
+    vqe_options vqe;      /* options of each re-optimisation */
+} vqe_adapt_options;
+
+typedef struct {
+    double energy;        /* energy of the final ansatz at its optimum */
+    double grad_norm;     /* pool-gradient L2 norm there */
+    int n_operators;      /* operators in the final ansatz */
+    int converged;        /* 1 if grad_norm < grad_tol */
+    int n_evals;          /* energy (+gradient) evaluations, pool gradients included */
+    int vqe_iters;        /* BFGS iterations summed over the re-optimisations */
+} vqe_adapt_result;
+
+/* ADAPT-VQE (Sec. 2.1, "ADAPT-VQE algorithm"; Fig. 2(b)) from the identity
+ * ansatz: evaluate the pool gradient at the current optimum; stop when its
+ * L2 norm is below grad_tol or max_operators are in; else append the
+ * selected pool operator (applied last, new angle 0, earlier angles kept)
+ * and run vqe_run over all angles.  Outputs (host): selected[k] and
+ * theta_out[k] for k < res->n_operators (capacity max_operators);
+ * energy_trace / grad_norm_trace (NULL allowed; capacity max_operators + 1)
+ * hold the energy and pool-gradient norm of the 0, 1, ... operator ansatz
+ * at its optimum.  vqe_ansatz_select(pool, n, selected) rebuilds the final
+ * ansatz.  Errors of the evaluations and of vqe_run are returned as is. */
+int vqe_adapt(const vqe_hamiltonian* H, const vqe_ansatz* pool, int n_electrons,
+              const vqe_adapt_options* opts, int32_t* selected, double* theta_out,
+              double* energy_trace, double* grad_norm_trace, vqe_adapt_result* res,
+              void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Warm-start MLP (a project addition beside the method: it predicts UCCSD

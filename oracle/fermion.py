@@ -353,3 +353,73 @@ class Problem:
         fun = lambda t: (self.energy(t), self.grad_shift(t))
         return scipy.optimize.minimize(fun, x0, jac=True, method="BFGS",
                                        options={"gtol": gtol, "maxiter": maxiter})
+
+
+# --------------------------------------------------------------------------
+# ADAPT-VQE (Sec. 2.1, "ADAPT-VQE algorithm"; Fig. 2(b))
+# --------------------------------------------------------------------------
+
+def _shift_rule(e):
+    """d/dt of a frequency-{1, 2} trigonometric polynomial at 0 from its
+    values e(+-pi/4), e(+-pi/2) (the four-term rule of Problem.grad_shift)."""
+    c2 = (math.sqrt(2.0) - 1.0) / 2.0
+    return (e(math.pi / 4) - e(-math.pi / 4)) - c2 * (e(math.pi / 2) - e(-math.pi / 2))
+
+
+def pool_gradient(problem: Problem, theta, pool):
+    """Energy of U(theta)|HF> and, for every pool operator A_k, the derivative
+    of the energy with respect to the angle of exp(t A_k) applied after
+    U(theta), at t = 0 (the quantity ADAPT-VQE ranks the pool by).
+
+    Each derivative is taken from the energy of the extended state at four
+    angles (exact for these generators), not from a commutator formula.
+    """
+    psi = problem.state(theta)
+    ham = problem.ham
+    e0 = ham.expectation(psi)
+    out = []
+    for op in pool:
+        out.append(_shift_rule(
+            lambda t: ham.expectation(apply_excitation(problem.space, psi, op, t))))
+    return e0, np.array(out)
+
+
+def adapt_select(grad, tie_tol):
+    """Index of the pool operator to add: the lowest index whose |gradient|
+    is within tie_tol of the largest (reading: ties, e.g. the alpha/beta
+    partners of a spin-adapted Hamiltonian, go to the lower index)."""
+    mag = np.abs(np.asarray(grad, dtype=np.float64))
+    return int(np.nonzero(mag >= mag.max() - tie_tol)[0][0])
+
+
+def adapt(n_qubits, n_electrons, h0, h, g, pool=None, grad_tol=1e-3, max_operators=None,
+          tie_tol=1e-10, gtol=1e-8, maxiter=400, record=None):
+    """ADAPT-VQE from the identity ansatz (the HF state).
+
+    Each round: pool gradients at the current optimum; stop when their L2
+    norm is below grad_tol (or max_operators are in); otherwise append the
+    selected operator (applied last, angle 0, earlier angles kept) and run
+    BFGS over all angles.  An operator may be selected more than once.
+    Returns (selected indices, final angles, energies, gradient norms), the
+    last two with one entry per ansatz size 0 .. len(selected).  If
+    ``record`` is a list, (angles, pool gradient) of every step are appended.
+    """
+    if pool is None:
+        pool = uccsd_excitations(n_qubits, n_electrons)
+    pool = list(pool)
+    cap = len(pool) if max_operators is None else int(max_operators)
+    sel, theta = [], np.zeros(0)
+    energies, norms = [], []
+    while True:
+        prob = Problem(n_qubits, n_electrons, h0, h, g, excs=[pool[i] for i in sel])
+        e, gp = pool_gradient(prob, theta, pool)
+        if record is not None:
+            record.append((theta.copy(), gp))
+        energies.append(e)
+        norms.append(float(np.linalg.norm(gp)))
+        if norms[-1] < grad_tol or len(sel) >= cap:
+            break
+        sel.append(adapt_select(gp, tie_tol))
+        prob = Problem(n_qubits, n_electrons, h0, h, g, excs=[pool[i] for i in sel])
+        theta = prob.vqe(theta0=np.append(theta, 0.0), gtol=gtol, maxiter=maxiter).x
+    return sel, theta, np.array(energies), np.array(norms)

@@ -153,6 +153,15 @@ class Ansatz:
                                                C.byref(out)))
         return cls(out)
 
+    def select(self, param_index):
+        """Sub-ansatz of this pool: the gates of pool parameter param_index[0],
+        then param_index[1], ... (one new parameter each)."""
+        idx = np.ascontiguousarray(param_index, dtype=np.int32)
+        out = C.c_void_p()
+        _check(lib().vqe_ansatz_select(self._h, idx.size, idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       C.byref(out)))
+        return Ansatz(out)
+
     def info(self):
         n, p, g, e = C.c_int(), C.c_int32(), C.c_int64(), C.c_int()
         _check(lib().vqe_ansatz_info(self._h, C.byref(n), C.byref(p), C.byref(g), C.byref(e)))
@@ -254,6 +263,18 @@ def energy_grad(ham: Hamiltonian, ansatz: Ansatz, n_electrons: int, theta, grad:
                                  _dptr(g) if grad else None,
                                  stream if stream is not None else current_stream()))
     return e.value, (g[:theta.size] if grad else None)
+
+
+def pool_gradient(ham: Hamiltonian, ansatz: Ansatz, pool: Ansatz, n_electrons: int, theta,
+                  stream=None):
+    """(E at theta, d E / d t of each pool operator appended at angle t = 0)."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    e = C.c_double()
+    g = np.empty(pool.n_params, np.float64)
+    _check(lib().vqe_pool_gradient(ham._h, ansatz._h, pool._h, int(n_electrons), _dptr(theta),
+                                   C.byref(e), _dptr(g),
+                                   stream if stream is not None else current_stream()))
+    return e.value, g
 
 
 def _energy_grad_fn():
@@ -394,3 +415,23 @@ def run_vqe(ham: Hamiltonian, ansatz: Ansatz, n_electrons: int, theta0=None, str
                          C.byref(o), _dptr(x), _dptr(trace), C.byref(res),
                          stream if stream is not None else current_stream()))
     return x, res, trace
+
+
+def run_adapt(ham: Hamiltonian, pool: Ansatz, n_electrons: int, grad_tol=1e-3, tie_tol=1e-10,
+              max_operators=None, stream=None, **opts):
+    """ADAPT-VQE from the identity ansatz over `pool`.  Returns (selected pool
+    indices, angles, energies, gradient norms, AdaptResult); the last two have
+    one entry per ansatz size 0 .. len(selected)."""
+    cap = pool.n_params if max_operators is None else int(max_operators)
+    o = _lib.AdaptOptions(float(grad_tol), float(tie_tol), cap, _options(**opts))
+    sel = np.empty(max(cap, 1), np.int32)
+    th = np.empty(max(cap, 1), np.float64)
+    es = np.empty(cap + 1, np.float64)
+    ns = np.empty(cap + 1, np.float64)
+    res = _lib.AdaptResult()
+    _check(lib().vqe_adapt(ham._h, pool._h, int(n_electrons), C.byref(o),
+                           sel.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(th), _dptr(es),
+                           _dptr(ns), C.byref(res),
+                           stream if stream is not None else current_stream()))
+    k = res.n_operators
+    return sel[:k].tolist(), th[:k].copy(), es[:k + 1].copy(), ns[:k + 1].copy(), res

@@ -21,6 +21,16 @@ class Result(C.Structure):
     _fields_ = [("energy", c_double), ("iters", c_int), ("n_evals", c_int), ("converged", c_int)]
 
 
+class AdaptOptions(C.Structure):
+    _fields_ = [("grad_tol", c_double), ("tie_tol", c_double), ("max_operators", c_int),
+                ("vqe", Options)]
+
+
+class AdaptResult(C.Structure):
+    _fields_ = [("energy", c_double), ("grad_norm", c_double), ("n_operators", c_int),
+                ("converged", c_int), ("n_evals", c_int), ("vqe_iters", c_int)]
+
+
 OBJECTIVE = C.CFUNCTYPE(c_int, vp, c_int, P(c_double), P(c_double), P(c_double))
 
 # name -> (restype, argtypes); the order follows include/vqe.h
@@ -35,6 +45,7 @@ SIGNATURES = {
     "vqe_ansatz_uccsd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
     "vqe_ansatz_from_rotations": (c_int, [c_int, c_int32, c_int64, P(c_uint32), P(c_uint32),
                                           P(c_int32), P(c_double), P(vp)]),
+    "vqe_ansatz_select": (c_int, [vp, c_int64, P(c_int32), P(vp)]),
     "vqe_ansatz_info": (c_int, [vp, P(c_int), P(c_int32), P(c_int64), P(c_int)]),
     "vqe_ansatz_excitations": (c_int, [vp, P(c_int64), P(c_int32)]),
     "vqe_ansatz_free": (None, [vp]),
@@ -47,6 +58,7 @@ SIGNATURES = {
     "vqe_apply_ansatz": (c_int, [vp, vp, P(c_double)]),
     "vqe_expectation": (c_int, [vp, vp, P(c_double)]),
     "vqe_energy_grad": (c_int, [vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
+    "vqe_pool_gradient": (c_int, [vp, vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
     "vqe_batch_create": (c_int, [c_int, P(vp), P(vp), P(c_int), vp, P(vp)]),
     "vqe_batch_offsets": (c_int, [vp, P(c_int64)]),
     "vqe_batch_energy_grad": (c_int, [vp, P(c_double), P(c_double), P(c_double)]),
@@ -69,6 +81,8 @@ SIGNATURES = {
                                   P(c_double), P(Result)]),
     "vqe_run": (c_int, [vp, vp, c_int, P(c_double), P(Options), P(c_double), P(c_double),
                         P(Result), vp]),
+    "vqe_adapt": (c_int, [vp, vp, c_int, P(AdaptOptions), P(c_int32), P(c_double), P(c_double),
+                          P(c_double), P(AdaptResult), vp]),
 }
 
 _lib = None

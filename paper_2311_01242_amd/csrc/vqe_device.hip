@@ -1579,25 +1579,31 @@ extern "C" int vqe_expectation(const vqe_state* s, const vqe_hamiltonian* H, dou
     return VQE_OK;
 }
 
-extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne,
-                               const double* theta, double* energy, double* grad, void* stream) {
-    if (int rc = check_pair(H, A, ne)) return rc;
-    if (!energy) return fail(VQE_EINVAL, "null energy pointer");
-    if (A->n_params > 0 && !theta) return fail(VQE_EINVAL, "null theta");
-    if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
-    hipStream_t st = (hipStream_t)stream;
+namespace {
+// Set-up of a single-state evaluation: plan, workspace, descriptor (uploaded
+// with theta); `extra` reserves more scratch for the caller.
+struct SingleEval {
+    EvalPlan ep;
+    DevHam* dh = nullptr;
+    DevAnsatz* da = nullptr;
+    Workspace* ws = nullptr;
+    Carver cv{nullptr};
+    StateDesc sd{};
+    StateDesc* sd_dev = nullptr;
+};
+
+int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const double* theta,
+                 hipStream_t st, const ScratchSize& extra, SingleEval* e) {
     const int n = H->n;
     const int64_t M = int64_t(A->gates.size()), P = A->n_params;
-    DevHam* dh;
-    if (int rc = dev_ham(H, &dh)) return rc;
-    EvalPlan ep;
-    if (int rc = make_eval_plan(A, ne, false, &ep)) return rc;
-    DevAnsatz* da;
-    if (int rc = dev_ansatz(A, &da)) return rc;
+    if (int rc = dev_ham(H, &e->dh)) return rc;
+    if (int rc = make_eval_plan(A, ne, false, &e->ep)) return rc;
+    if (int rc = dev_ansatz(A, &e->da)) return rc;
+    const EvalPlan& ep = e->ep;
     HxWork* hw = nullptr;
     if (ep.sector)
-        if (int rc = ham_chunks(H, dh, ep.hx.L, &hw)) return rc;
-    ScratchSize sz;
+        if (int rc = ham_chunks(H, e->dh, ep.hx.L, &hw)) return rc;
+    ScratchSize sz = extra;
     sz.add<double>(P);
     sz.add<double2>(M);
     sz.add<double>(ep.nblk_e);
@@ -1605,8 +1611,8 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     sz.add<double>(1);
     sz.add<double>(M);
     sz.add<StateDesc>(1);
-    Workspace* ws;
-    if (int rc = workspace(stream, sizeof(double2) * size_t(ep.elems), sz.s, &ws)) return rc;
+    if (int rc = workspace(st, sizeof(double2) * size_t(ep.elems), sz.s, &e->ws)) return rc;
+    Workspace* ws = e->ws;
     // the full-layout sector H-apply writes only in-sector entries: lambda
     // must be zero elsewhere (the packed layout holds nothing else)
     if (ep.packed) {
@@ -1617,14 +1623,15 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     } else if (!ep.sector) {
         ws->lam_zero_key = -1;
     }
-    Carver cv{ws->scratch};
-    StateDesc sd{};
+    e->cv = Carver{ws->scratch};
+    StateDesc& sd = e->sd;
+    sd = StateDesc{};
     sd.phi = ws->phi;
     sd.lam = ws->lam;
     sd.aux = ws->aux;
     if (ep.ci) {
         CiHam* ch;
-        if (int rc = ci_ham(H, dh, &ch)) return rc;
+        if (int rc = ci_ham(H, e->dh, &ch)) return rc;
         sd.ci_chunks = ch->chunks;
         sd.ci_groups = ch->groups;
         sd.ci_subs = ch->subs;
@@ -1637,12 +1644,13 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
         sd.ci_ptabs = ch->ptabs;
         sd.ci_npcls = ch->npcls;
     }
-    sd.gates = da->gates;
+    Carver& cv = e->cv;
+    sd.gates = e->da->gates;
     sd.theta = cv.take<double>(P);
     sd.cs = cv.take<double2>(M);
-    sd.groups = dh->groups;
-    sd.subs = dh->subs;
-    sd.tabs = dh->tabs;
+    sd.groups = e->dh->groups;
+    sd.subs = e->dh->subs;
+    sd.tabs = e->dh->tabs;
     if (hw) {
         sd.chunks = hw->chunks;
         sd.cgroups = hw->cgroups;
@@ -1658,16 +1666,30 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     sd.M = int32_t(M);
     sd.ne = ne;
     sd.gstride = ep.gstride;
-    StateDesc* sd_dev = cv.take<StateDesc>(1);
+    e->sd_dev = cv.take<StateDesc>(1);
     if (P > 0)
         HIPCHK(hipMemcpyAsync(const_cast<double*>(sd.theta), theta, sizeof(double) * P,
                               hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(sd_dev, &sd, sizeof(StateDesc), hipMemcpyHostToDevice, st));
-    if (int rc = enqueue_eval(ep, sd_dev, 1, grad != nullptr, st)) return rc;
+    HIPCHK(hipMemcpyAsync(e->sd_dev, &sd, sizeof(StateDesc), hipMemcpyHostToDevice, st));
+    return VQE_OK;
+}
+}  // namespace
+
+extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne,
+                               const double* theta, double* energy, double* grad, void* stream) {
+    if (int rc = check_pair(H, A, ne)) return rc;
+    if (!energy) return fail(VQE_EINVAL, "null energy pointer");
+    if (A->n_params > 0 && !theta) return fail(VQE_EINVAL, "null theta");
+    if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t M = int64_t(A->gates.size()), P = A->n_params;
+    SingleEval e;
+    if (int rc = setup_single(H, A, ne, theta, st, ScratchSize{}, &e)) return rc;
+    if (int rc = enqueue_eval(e.ep, e.sd_dev, 1, grad != nullptr, st)) return rc;
     std::vector<double> raw(std::max<int64_t>(M, 1));
-    HIPCHK(hipMemcpyAsync(energy, sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(energy, e.sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
     if (grad && M > 0)
-        HIPCHK(hipMemcpyAsync(raw.data(), sd.out_g, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(raw.data(), e.sd.out_g, sizeof(double) * M, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     bool ok = std::isfinite(*energy);
     if (grad) {
@@ -1675,6 +1697,92 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
         ok = ok && finite_all(grad, P);
     }
     if (!ok) return fail(VQE_ENUMERIC, "non-finite energy or gradient");
+    return VQE_OK;
+}
+
+extern "C" int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A,
+                                 const vqe_ansatz* pool, int ne, const double* theta,
+                                 double* energy, double* pool_grad, void* stream) {
+    if (int rc = check_pair(H, A, ne)) return rc;
+    if (!pool || !energy || !pool_grad) return fail(VQE_EINVAL, "null pointer argument");
+    if (pool->n != H->n) return fail(VQE_EINVAL, "pool and Hamiltonian qubit counts differ");
+    if (pool->n_electrons >= 0 && pool->n_electrons != ne)
+        return fail(VQE_EINVAL, "n_electrons differs from the pool's reference");
+    if (pool->n_params < 1) return fail(VQE_ERANGE, "pool has no parameters");
+    if (A->n_params > 0 && !theta) return fail(VQE_EINVAL, "null theta");
+    if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = H->n;
+    const int64_t Mp = int64_t(pool->gates.size()), Pp = pool->n_params;
+    // the pool's reverse-sweep plan in the evaluation's layout
+    EvalPlan probe;
+    if (int rc = make_eval_plan(A, ne, false, &probe)) return rc;
+    DevAnsatz* dp;
+    if (int rc = dev_ansatz(pool, &dp)) return rc;
+    const Tuning tn = tuning_for(n, false);
+    PackedPlan* ppool = nullptr;
+    AnsatzPlan* apool = nullptr;
+    if (probe.packed) {
+        const int need = packed_min_L(pool, ne);
+        if (need < 0 || need > probe.hx.L || !pool->sector_conserving)
+            return fail(VQE_EINVAL, "pool does not fit the packed sector evaluation of this ansatz");
+        if (int rc = packed_plan(pool, dp, *probe.lay, tn, &ppool)) return rc;
+    } else {
+        if (int rc = get_plan(pool, dp, tn, &apool)) return rc;
+    }
+    const int32_t gstride_p = probe.packed ? ppool->gstride : apool->gstride;
+    ScratchSize extra;
+    extra.add<double>(Pp);                                       // zero angles
+    extra.add<double2>(Mp);                                      // their (cos, sin)
+    extra.add<double>(size_t(Mp) * size_t(gstride_p));           // pool partials
+    extra.add<double>(Mp);                                       // pool raw sums
+    extra.add<StateDesc>(1);
+    SingleEval e;
+    if (int rc = setup_single(H, A, ne, theta, st, extra, &e)) return rc;
+    StateDesc sp = e.sd;   // the same phi, lambda; the pool's gates, angles and partials
+    sp.gates = dp->gates;
+    sp.theta = e.cv.take<double>(Pp);
+    sp.cs = e.cv.take<double2>(Mp);
+    sp.part_g = e.cv.take<double>(size_t(Mp) * size_t(gstride_p));
+    sp.out_g = e.cv.take<double>(Mp);
+    sp.M = int32_t(Mp);
+    sp.gstride = gstride_p;
+    StateDesc* sp_dev = e.cv.take<StateDesc>(1);
+    const std::vector<double> zeros(size_t(Pp), 0.0);
+    HIPCHK(hipMemcpyAsync(const_cast<double*>(sp.theta), zeros.data(), sizeof(double) * Pp,
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sp_dev, &sp, sizeof(StateDesc), hipMemcpyHostToDevice, st));
+    const EvalPlan& ep = e.ep;
+    // phi = U(theta)|HF>, lambda = H phi, then the pool's gates at angle 0
+    // swept on (phi, lambda): each leaves both unchanged and yields
+    // Re <lambda|A_k phi>, the derivative of appending A_k after U(theta)
+    enqueue_phase(ep, e.sd_dev, 1, kPhaseFwd, false, st);
+    enqueue_phase(ep, e.sd_dev, 1, kPhaseHx, true, st);
+    launch_angles(sp_dev, 1, int(Mp), st);
+    if (probe.packed) {
+        for (size_t r = 0; r < ppool->runs.size(); ++r)
+            launch_packed_run(sp_dev, 1, ppool->runs[r], ppool->d_gates + ppool->off[r], ep.hxt,
+                              ep.lay->d_base, true, st);
+    } else {
+        const uint64_t N = uint64_t(1) << n;
+        for (auto it = apool->adj_steps.rbegin(); it != apool->adj_steps.rend(); ++it) {
+            if (it->first == 0)
+                launch_run_adj(sp_dev, 1, apool->adj_runs[it->second],
+                               apool->d_adj_tg + apool->adj_off[it->second], st);
+            else
+                launch_adj_pauli(sp_dev, 1, it->second, N, apool->gcnt[it->second], st);
+        }
+    }
+    launch_reduce_e(e.sd_dev, 1, ep.nblk_e, st);
+    launch_reduce_g(sp_dev, 1, int(Mp), probe.packed ? ppool->d_gcnt : apool->d_gcnt, 0, st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> raw(static_cast<size_t>(Mp));
+    HIPCHK(hipMemcpyAsync(energy, e.sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(raw.data(), sp.out_g, sizeof(double) * Mp, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    accumulate_grad(pool, raw.data(), pool_grad);
+    if (!std::isfinite(*energy) || !finite_all(pool_grad, Pp))
+        return fail(VQE_ENUMERIC, "non-finite energy or pool gradient");
     return VQE_OK;
 }
 

@@ -358,6 +358,37 @@ extern "C" int vqe_ansatz_uccsd(int n, int ne, vqe_ansatz** out, int32_t* n_para
     return VQE_OK;
 }
 
+extern "C" int vqe_ansatz_select(const vqe_ansatz* pool, int64_t count, const int32_t* param_index,
+                                 vqe_ansatz** out) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!pool) return fail(VQE_EINVAL, "null pool");
+    if (count < 0 || count > (int64_t(1) << 30)) return fail(VQE_ERANGE, "count out of range");
+    if (count > 0 && !param_index) return fail(VQE_EINVAL, "null param_index");
+    for (int64_t k = 0; k < count; ++k)
+        if (param_index[k] < 0 || param_index[k] >= pool->n_params)
+            return fail(VQE_ERANGE, "param_index out of range of the pool");
+    // gates of each pool parameter, in the pool's order
+    std::vector<std::vector<size_t>> of(size_t(pool->n_params));
+    for (size_t j = 0; j < pool->gates.size(); ++j) of[size_t(pool->gates[j].param)].push_back(j);
+    const bool has_exc = pool->exc.size() == 4 * pool->gates.size();
+    auto* A = new (std::nothrow) vqe_ansatz();
+    if (!A) return fail(VQE_ENOMEM, "host allocation failed");
+    A->n = pool->n;
+    A->n_electrons = pool->n_electrons;
+    A->sector_conserving = pool->sector_conserving;
+    A->n_params = int32_t(count);
+    for (int64_t k = 0; k < count; ++k)
+        for (size_t j : of[size_t(param_index[k])]) {
+            GateDesc g = pool->gates[j];
+            g.param = int32_t(k);
+            A->gates.push_back(g);
+            if (has_exc) A->exc.insert(A->exc.end(), pool->exc.begin() + 4 * j, pool->exc.begin() + 4 * j + 4);
+        }
+    *out = A;
+    return VQE_OK;
+}
+
 extern "C" int vqe_ansatz_from_rotations(int n, int32_t n_params, int64_t n_rot, const uint32_t* x,
                                          const uint32_t* z, const int32_t* param_index,
                                          const double* scale, vqe_ansatz** out) {
@@ -686,4 +717,82 @@ extern "C" int vqe_run(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_elec
     RunCtx ctx{H, A, n_electrons, hip_stream};
     return vqe_minimize_bfgs(A->n_params, run_objective, &ctx, theta0, opts, theta_out, trace_out,
                              res);
+}
+
+// ============================================================== ADAPT-VQE
+
+namespace {
+struct AnsatzHandle {
+    vqe_ansatz* a = nullptr;
+    ~AnsatzHandle() { vqe_ansatz_free(a); }
+};
+}  // namespace
+
+// Sec. 2.1, "ADAPT-VQE algorithm": start from the identity ansatz, add the
+// pool operator with the largest energy gradient (applied last, angle 0),
+// re-optimise every angle, stop once the pool gradient is small.
+extern "C" int vqe_adapt(const vqe_hamiltonian* H, const vqe_ansatz* pool, int n_electrons,
+                         const vqe_adapt_options* opts, int32_t* selected, double* theta_out,
+                         double* energy_trace, double* grad_norm_trace, vqe_adapt_result* res,
+                         void* hip_stream) {
+    if (!H || !pool || !opts || !res) return fail(VQE_EINVAL, "null pointer argument");
+    if (opts->max_operators < 0) return fail(VQE_ERANGE, "max_operators is negative");
+    if (opts->max_operators > 0 && (!selected || !theta_out))
+        return fail(VQE_EINVAL, "null selected or theta_out");
+    if (!(opts->grad_tol >= 0.0) || !(opts->tie_tol >= 0.0))
+        return fail(VQE_EINVAL, "grad_tol and tie_tol must be non-negative");
+    if (pool->n_params < 1) return fail(VQE_ERANGE, "pool has no parameters");
+    *res = vqe_adapt_result{};
+    const int cap = opts->max_operators;
+    const size_t P = size_t(pool->n_params);
+    std::vector<int32_t> sel;
+    std::vector<double> theta, next, g(P);
+    int evals = 0;
+    for (;;) {
+        AnsatzHandle A;
+        if (int rc = vqe_ansatz_select(pool, int64_t(sel.size()), sel.data(), &A.a)) return rc;
+        double e = 0.0;
+        if (int rc = vqe_pool_gradient(H, A.a, pool, n_electrons, theta.data(), &e, g.data(),
+                                       hip_stream))
+            return rc;
+        ++evals;
+        double norm2 = 0.0, gmax = 0.0;
+        for (double v : g) {
+            norm2 += v * v;
+            gmax = std::max(gmax, std::fabs(v));
+        }
+        const double norm = std::sqrt(norm2);
+        const size_t k = sel.size();
+        if (energy_trace) energy_trace[k] = e;
+        if (grad_norm_trace) grad_norm_trace[k] = norm;
+        res->energy = e;
+        res->grad_norm = norm;
+        res->n_operators = int32_t(k);
+        res->n_evals = evals;
+        if (norm < opts->grad_tol) {
+            res->converged = 1;
+            break;
+        }
+        if (int(k) >= cap) break;
+        // the lowest pool index within tie_tol of the largest |gradient|
+        size_t pick = 0;
+        while (std::fabs(g[pick]) < gmax - opts->tie_tol) ++pick;
+        sel.push_back(int32_t(pick));
+        theta.push_back(0.0);
+        AnsatzHandle B;
+        if (int rc = vqe_ansatz_select(pool, int64_t(sel.size()), sel.data(), &B.a)) return rc;
+        next.assign(theta.size(), 0.0);
+        vqe_result r{};
+        if (int rc = vqe_run(H, B.a, n_electrons, theta.data(), &opts->vqe, next.data(), nullptr, &r,
+                             hip_stream))
+            return rc;
+        evals += r.n_evals;
+        theta.swap(next);
+        res->vqe_iters += r.iters;
+    }
+    for (size_t k = 0; k < sel.size(); ++k) {
+        selected[k] = sel[k];
+        theta_out[k] = theta[k];
+    }
+    return VQE_OK;
 }

@@ -246,3 +246,77 @@ def test_adam_first_step_closed_form():
     g = np.array([0.1, -3.0, 0.0])
     p1, m, v = NN.adam_step(p, g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-8)
     assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- ADAPT-VQE
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (6, 3), (8, 4)])
+def test_pool_gradient_at_identity_is_hf_closed_form(n, ne):
+    h0, h, g = random_integrals(n, 11)
+    pool = F.uccsd_excitations(n, ne)
+    e, got = F.pool_gradient(F.Problem(n, ne, h0, h, g, excs=[]), np.zeros(0), pool)
+    assert abs(e - F.hf_energy_closed_form(n, ne, h0, h, g)) < 1e-12
+    assert np.abs(got - F.grad_at_hf_closed_form(ne, pool, h, g)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,ne", [(5, 2), (6, 3)])
+def test_pool_gradient_matches_fock_space_commutator(n, ne):
+    """d/dt <psi|e^{-tG} H e^{tG}|psi> at 0 = <psi|[H, G]|psi> = 2 Re <H psi|G psi>,
+    with G = T - T^dag built from the occupation-number ladder matrices."""
+    h0, h, g = random_integrals(n, 5)
+    pool = F.uccsd_excitations(n, ne)
+    rng = np.random.default_rng(9)
+    sel = [int(k) for k in rng.integers(0, len(pool), 4)]
+    prob = F.Problem(n, ne, h0, h, g, excs=[pool[k] for k in sel])
+    theta = rng.uniform(-0.6, 0.6, len(sel))
+    e, got = F.pool_gradient(prob, theta, pool)
+    psi = prob.space.to_statevector(prob.state(theta))
+    Hb = B.hamiltonian(n, h0, h, g)
+    hpsi = Hb @ psi
+    ref = [2.0 * np.real(np.vdot(hpsi, B.excitation_generator(n, op) @ psi)) for op in pool]
+    assert abs(e - np.real(np.vdot(psi, hpsi))) < 1e-11
+    assert np.abs(got - np.array(ref)).max() < 1e-11
+
+
+def test_pool_gradient_of_a_repeated_operator_vanishes_at_optimum():
+    """Appending the last operator again adds to its angle: at a stationary
+    point of E in that angle the pool gradient of the operator is zero."""
+    h0, h, g = random_integrals(6, 3)
+    pool = F.uccsd_excitations(6, 3)
+    prob = F.Problem(6, 3, h0, h, g, excs=[pool[4]])
+    th = prob.vqe(theta0=np.zeros(1), gtol=1e-12).x
+    _, gp = F.pool_gradient(prob, th, pool)
+    assert abs(gp[4]) < 1e-9
+    assert np.abs(gp).max() > 1e-3
+
+
+def test_adapt_select_tie_rule():
+    assert F.adapt_select([0.1, -0.3, 0.3, 0.2], 1e-10) == 1
+    assert F.adapt_select([0.1, -0.3, 0.3 + 1e-12, 0.2], 1e-10) == 1
+    assert F.adapt_select([0.1, -0.3, 0.3 + 1e-6, 0.2], 1e-10) == 2
+    assert F.adapt_select([0.0, 0.0], 1e-10) == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_adapt_4q_reaches_fci(seed):
+    h0, h, g = random_integrals(4, seed)
+    sel, theta, es, norms = F.adapt(4, 2, h0, h, g, grad_tol=1e-6)
+    fci = F.Problem(4, 2, h0, h, g).fci()
+    assert abs(es[-1] - fci) < 1e-9
+    assert norms[-1] < 1e-6
+    assert len(sel) == len(theta) == len(es) - 1
+
+
+def test_adapt_invariants_6q():
+    """Energies never rise (each ansatz contains the previous one at its
+    optimum), stay above the sector FCI, start at the HF energy, and the first
+    operator is the closed-form HF gradient's pick."""
+    h0, h, g = random_integrals(6, 4)
+    pool = F.uccsd_excitations(6, 4)
+    sel, theta, es, norms = F.adapt(6, 4, h0, h, g, grad_tol=1e-5)
+    fci = F.Problem(6, 4, h0, h, g).fci()
+    assert abs(es[0] - F.hf_energy_closed_form(6, 4, h0, h, g)) < 1e-12
+    assert np.all(np.diff(es) <= 1e-12)
+    assert es.min() >= fci - 1e-10
+    assert abs(es[-1] - fci) < 1e-7
+    assert sel[0] == F.adapt_select(F.grad_at_hf_closed_form(4, pool, h, g), 1e-10)
