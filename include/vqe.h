@@ -179,14 +179,26 @@ int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electro
  * psi = U_A(theta)|HF>, *energy = <psi|H|psi> and, for every parameter k of
  * `pool`, pool_grad[k] = d/dt <psi_t|H|psi_t> at t = 0, where psi_t applies
  * the pool's gates of parameter k at angle t after U_A(theta).  One forward
- * pass, one H-apply and one reverse sweep of the pool at angle zero (which
- * leaves psi and H psi unchanged).  theta: host, A's n_params; pool_grad:
+ * pass, one H-apply and one sweep of the pool at angle zero, where every
+ * gate is the identity: psi and H psi are only read, and in the packed
+ * layout the whole pool is one launch.  theta: host, A's n_params; pool_grad:
  * host, the pool's n_params.  The pool must act on the same qubits and
  * reference as A; in the packed sector layout it must fit the layout chosen
  * for A (EINVAL otherwise).  NaN/Inf results return ENUMERIC. */
 int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A, const vqe_ansatz* pool,
                       int n_electrons, const double* theta, double* energy, double* pool_grad,
                       void* hip_stream);
+
+/* vqe_pool_gradient timed with HIP events on hip_stream, repeated reps
+ * times: ms[0..3] = mean milliseconds of the forward pass, the H-apply, the
+ * pool sweep and the reductions; work[0] = forward algorithmic bytes,
+ * work[1] = 0, work[2] = pool-sweep algorithmic bytes (packed layout: phi
+ * and lambda of every live tile of every run, read once; full layout: read
+ * and written by each reverse-sweep launch), work[3] = pool-sweep launches.
+ * All host arrays of 4 doubles. */
+int vqe_pool_gradient_profile(const vqe_hamiltonian* H, const vqe_ansatz* A,
+                              const vqe_ansatz* pool, int n_electrons, const double* theta,
+                              int reps, double* ms, double* work, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Batched evaluation of many independent problems

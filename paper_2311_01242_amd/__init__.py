@@ -277,6 +277,20 @@ def pool_gradient(ham: Hamiltonian, ansatz: Ansatz, pool: Ansatz, n_electrons: i
     return e.value, g
 
 
+def pool_gradient_profile(ham: Hamiltonian, ansatz: Ansatz, pool: Ansatz, n_electrons: int, theta,
+                          reps: int = 3, stream=None):
+    """(ms, work) of the pool gradient: per-phase milliseconds (forward,
+    H-apply, pool sweep, reductions) and (forward bytes, 0, pool-sweep bytes,
+    pool-sweep launches)."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    ms = np.empty(4, np.float64)
+    w = np.empty(4, np.float64)
+    _check(lib().vqe_pool_gradient_profile(ham._h, ansatz._h, pool._h, int(n_electrons),
+                                           _dptr(theta), int(reps), _dptr(ms), _dptr(w),
+                                           stream if stream is not None else current_stream()))
+    return ms, w
+
+
 def _energy_grad_fn():
     import torch
 

@@ -59,6 +59,8 @@ SIGNATURES = {
     "vqe_expectation": (c_int, [vp, vp, P(c_double)]),
     "vqe_energy_grad": (c_int, [vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
     "vqe_pool_gradient": (c_int, [vp, vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
+    "vqe_pool_gradient_profile": (c_int, [vp, vp, vp, c_int, P(c_double), c_int, P(c_double),
+                                          P(c_double), vp]),
     "vqe_batch_create": (c_int, [c_int, P(vp), P(vp), P(c_int), vp, P(vp)]),
     "vqe_batch_offsets": (c_int, [vp, P(c_int64)]),
     "vqe_batch_energy_grad": (c_int, [vp, P(c_double), P(c_double), P(c_double)]),

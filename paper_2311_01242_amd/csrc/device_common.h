@@ -406,6 +406,20 @@ void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, con
                        const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st);
 // Launch shape covering blocks of max_block entries with at least min_threads
 // threads per tile if there is one (else any), or -1.
+// Single-launch zero-angle sweep of a pool's packed runs (pool gradients):
+// block b covers tile b - blk0[r] of run r = blk_run[b]; runs[r].g0 indexes
+// the pool's gates.
+struct PoolSweep {
+    const PackedRun* runs;
+    const int32_t* blk_run;
+    const int32_t* blk0;
+    const PackedGate* gates;
+    int32_t nblk;
+    int32_t shape;
+    size_t lds;
+};
+void launch_pool_sweep(const StateDesc* sd, int count, const PoolSweep& ps, const HxTables* tabs,
+                       const int32_t* base, hipStream_t st);
 int packed_shape(int max_block, int min_threads);
 int packed_shape_threads(int shape);
 int packed_enable_lds(size_t bytes);  // 0 on success

@@ -186,6 +186,87 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     }
 }
 
+// Zero-angle reverse sweep of a gate pool (ADAPT-VQE pool gradients): every
+// gate at angle 0 is the identity, so phi and lambda are only read and the
+// gates are independent.  One launch covers every (run, tile): block b works
+// on tile b - blk0[r] of run r = blk_run[b]; after staging the tile, each
+// wave takes whole gates (w, w + BS/64, ...) and its 64 lanes split the
+// gate's pair list, so a gate's tile partial of Re <lambda|A_j phi> is one
+// wave total, stored without a block barrier.
+template <int BS, int EPT>
+__global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
+                                              const PackedRun* __restrict__ runs,
+                                              const int32_t* __restrict__ blk_run,
+                                              const int32_t* __restrict__ blk0,
+                                              const PackedGate* __restrict__ pg_all,
+                                              const HxTables* __restrict__ tabsrc,
+                                              const int32_t* __restrict__ base) {
+    extern __shared__ double2 sh[];
+    __shared__ HxTables T;
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
+        for (int i = threadIdx.x; i < int(sizeof(HxTables) / 4); i += BS) dst[i] = src[i];
+    }
+    __syncthreads();
+    const StateDesc& s = sd[blockIdx.y];
+    const int r = ldc(blk_run + blockIdx.x);
+    const PackedRun run = ldc(runs + r);
+    const int o = int(blockIdx.x) - ldc(blk0 + r);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ng = run.g1 - run.g0;
+    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi);
+    const uint32_t h1 = h0 | run.khi;
+    const uint32_t hb0 = h0 << run.L;
+    const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
+    const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
+    if (B0.cnt == 0 || B1.cnt == 0) {
+        for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + o] = 0.0;
+        return;
+    }
+    const int c0 = B0.cnt;
+    const int c1 = run.khi ? B1.cnt : 0;
+    const int nE = c0 + c1;
+    const int64_t g0 = base[h0], g1 = base[h1];
+    double2* shp = sh;
+    double2* shl = sh + nE;
+    {
+        double2 vp[2 * EPT], vl[2 * EPT];
+#pragma unroll
+        for (int u = 0; u < 2 * EPT; ++u) {
+            const int k = min(tid + BS * u, nE - 1);
+            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            vp[u] = ldg2(s.phi + gi);
+            vl[u] = ldg2(s.lam + gi);
+        }
+#pragma unroll
+        for (int u = 0; u < 2 * EPT; ++u) {
+            const int k = min(tid + BS * u, nE - 1);
+            shp[k] = vp[u];
+            shl[k] = vl[u];
+        }
+    }
+    __syncthreads();
+    const int cls = B0.kA * (T.Lb + 1) + B0.kB;
+    const PackedGate* pg = pg_all + run.g0;
+    for (int jl = w; jl < ng; jl += BS / 64) {
+        const int2 li = ldc(run.info + size_t(jl) * run.ncls + cls);
+        const PackedGate g = ldc(pg + jl);
+        const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);
+        double acc = 0.0;
+        for (int i = lane; i < li.y; i += 64) {
+            const uint32_t e = ldg32(run.ent + li.x + i);
+            const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
+            const double sg_t = ((e >> 23) & 1u) ? -sgn_hi : sgn_hi;
+            const double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
+            acc += sg_t * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
+        }
+        acc = wave_total(acc);
+        if (lane == 0) s.part_g[size_t(run.g0 + jl) * s.gstride + o] = acc;
+    }
+}
+
 // Launch shapes (threads per tile, entries per thread).
 #define VQE_PACKED_SHAPES(X)                                                                  \
     X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(256, 1) X(256, 2) X(256, 3) X(256, 5) X(512, 1)     \
@@ -238,6 +319,25 @@ void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, con
         kFwdLaunch[run.shape](sd, count, run, pg, tabs, base, st);
 }
 
+using PoolLauncher = void (*)(const StateDesc*, int, const PoolSweep&, const HxTables*,
+                              const int32_t*, hipStream_t);
+
+template <int BS, int EPT>
+static void launch_pool_one(const StateDesc* sd, int count, const PoolSweep& ps,
+                            const HxTables* tabs, const int32_t* base, hipStream_t st) {
+    hipLaunchKernelGGL((k_ppool<BS, EPT>), dim3(ps.nblk, count), dim3(BS), ps.lds, st, sd, ps.runs,
+                       ps.blk_run, ps.blk0, ps.gates, tabs, base);
+}
+
+#define VQE_POOL_ENTRY(B, E) &launch_pool_one<B, E>,
+static const PoolLauncher kPoolLaunch[] = {VQE_PACKED_SHAPES(VQE_POOL_ENTRY)};
+#undef VQE_POOL_ENTRY
+
+void launch_pool_sweep(const StateDesc* sd, int count, const PoolSweep& ps, const HxTables* tabs,
+                       const int32_t* base, hipStream_t st) {
+    if (ps.nblk > 0) kPoolLaunch[ps.shape](sd, count, ps, tabs, base, st);
+}
+
 void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st) {
     const int nblk = blocks_for(uint64_t(size));
     hipLaunchKernelGGL(k_packed_hf, dim3(nblk, count), dim3(kBlock), 0, st, sd, size);
@@ -251,7 +351,8 @@ int packed_enable_lds(size_t bytes) {
     };
 #define VQE_SET_ENTRY(B, E)                                          \
     set(reinterpret_cast<const void*>(&k_prun<1, B, E>));            \
-    set(reinterpret_cast<const void*>(&k_prun<2, B, E>));
+    set(reinterpret_cast<const void*>(&k_prun<2, B, E>));            \
+    set(reinterpret_cast<const void*>(&k_ppool<B, E>));
     VQE_PACKED_SHAPES(VQE_SET_ENTRY)
 #undef VQE_SET_ENTRY
     return e == hipSuccess ? 0 : 1;

@@ -132,6 +132,11 @@ struct PackedPlan {
     int32_t gstride = 1;
     size_t max_lds = 0;
     double fwd_bytes = 0.0, adj_bytes = 0.0;   // algorithmic traffic of one evaluation
+    // single-launch zero-angle sweep (built on first use as a pool)
+    PackedRun* d_runs = nullptr;
+    int32_t* d_blk = nullptr;    // run of each block, then the first block of each run
+    PoolSweep sweep{};
+    double sweep_bytes = 0.0;    // phi and lambda entries of every live tile, read once
 };
 
 struct DevAnsatz {
@@ -1037,6 +1042,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         p->max_lds = std::max(p->max_lds, size_t(maxe) * sizeof(double2) * 2);
         p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved);
         p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved);
+        p->sweep_bytes += 2.0 * double(sizeof(double2)) * double(moved);
         p->runs.push_back(r);
         j = j2;
     }
@@ -1393,6 +1399,8 @@ vqe_ansatz::~vqe_ansatz() {
             (void)hipFree(pl.second->d_gcnt);
             (void)hipFree(pl.second->d_info);
             (void)hipFree(pl.second->d_ent);
+            (void)hipFree(pl.second->d_runs);
+            (void)hipFree(pl.second->d_blk);
             delete pl.second;
         }
         delete kv.second;
@@ -1700,9 +1708,56 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     return VQE_OK;
 }
 
-extern "C" int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A,
-                                 const vqe_ansatz* pool, int ne, const double* theta,
-                                 double* energy, double* pool_grad, void* stream) {
+// The single-launch zero-angle sweep of a packed plan (pool gradients).
+static int pool_sweep(const vqe_ansatz* pool, PackedPlan* p, const PoolSweep** out) {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    if (p->d_runs) {
+        *out = &p->sweep;
+        return VQE_OK;
+    }
+    std::vector<int32_t> blk, first;
+    int maxe = 1;
+    for (size_t r = 0; r < p->runs.size(); ++r) {
+        first.push_back(int32_t(blk.size()));
+        blk.insert(blk.end(), size_t(p->runs[r].ntiles), int32_t(r));
+        maxe = std::max(maxe, p->runs[r].max_entries);
+    }
+    if (blk.size() > size_t(1) << 30) return fail(VQE_ERANGE, "pool sweep: too many tiles");
+    const int nblk = int(blk.size());
+    blk.insert(blk.end(), first.begin(), first.end());
+    PoolSweep ps{};
+    ps.shape = packed_shape(maxe, 256);
+    if (ps.shape < 0) return fail(VQE_EINVAL, "pool sweep: block too large for the run kernels");
+    PackedRun* d_runs = nullptr;
+    int32_t* d_blk = nullptr;
+    int rc = upload(&d_runs, p->runs.data(), p->runs.size());
+    if (!rc) rc = upload(&d_blk, blk.data(), blk.size());
+    if (rc) {
+        (void)hipFree(d_runs);
+        (void)hipFree(d_blk);
+        return rc;
+    }
+    ps.runs = d_runs;
+    ps.blk_run = d_blk;
+    ps.blk0 = d_blk + nblk;
+    ps.gates = p->d_gates;
+    ps.nblk = nblk;
+    ps.lds = size_t(maxe) * sizeof(double2) * 2;
+    p->d_runs = d_runs;
+    p->d_blk = d_blk;
+    p->sweep = ps;
+    *out = &p->sweep;
+    return VQE_OK;
+}
+
+namespace {
+// The pool gradient, optionally timed: with reps > 0 the whole sequence runs
+// reps times with HIP events between its phases (forward, H-apply, pool
+// sweep, reductions); ms receives their means and work the forward and
+// pool-sweep algorithmic bytes and the sweep's launch count.
+int pool_gradient_impl(const vqe_hamiltonian* H, const vqe_ansatz* A, const vqe_ansatz* pool,
+                       int ne, const double* theta, double* energy, double* pool_grad,
+                       void* stream, int reps, double* ms, double* work) {
     if (int rc = check_pair(H, A, ne)) return rc;
     if (!pool || !energy || !pool_grad) return fail(VQE_EINVAL, "null pointer argument");
     if (pool->n != H->n) return fail(VQE_EINVAL, "pool and Hamiltonian qubit counts differ");
@@ -1721,12 +1776,14 @@ extern "C" int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A,
     if (int rc = dev_ansatz(pool, &dp)) return rc;
     const Tuning tn = tuning_for(n, false);
     PackedPlan* ppool = nullptr;
+    const PoolSweep* psw = nullptr;
     AnsatzPlan* apool = nullptr;
     if (probe.packed) {
         const int need = packed_min_L(pool, ne);
         if (need < 0 || need > probe.hx.L || !pool->sector_conserving)
             return fail(VQE_EINVAL, "pool does not fit the packed sector evaluation of this ansatz");
         if (int rc = packed_plan(pool, dp, *probe.lay, tn, &ppool)) return rc;
+        if (int rc = pool_sweep(pool, ppool, &psw)) return rc;
     } else {
         if (int rc = get_plan(pool, dp, tn, &apool)) return rc;
     }
@@ -1755,27 +1812,68 @@ extern "C" int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A,
     const EvalPlan& ep = e.ep;
     // phi = U(theta)|HF>, lambda = H phi, then the pool's gates at angle 0
     // swept on (phi, lambda): each leaves both unchanged and yields
-    // Re <lambda|A_k phi>, the derivative of appending A_k after U(theta)
-    enqueue_phase(ep, e.sd_dev, 1, kPhaseFwd, false, st);
-    enqueue_phase(ep, e.sd_dev, 1, kPhaseHx, true, st);
-    launch_angles(sp_dev, 1, int(Mp), st);
-    if (probe.packed) {
-        for (size_t r = 0; r < ppool->runs.size(); ++r)
-            launch_packed_run(sp_dev, 1, ppool->runs[r], ppool->d_gates + ppool->off[r], ep.hxt,
-                              ep.lay->d_base, true, st);
-    } else {
-        const uint64_t N = uint64_t(1) << n;
-        for (auto it = apool->adj_steps.rbegin(); it != apool->adj_steps.rend(); ++it) {
-            if (it->first == 0)
-                launch_run_adj(sp_dev, 1, apool->adj_runs[it->second],
-                               apool->d_adj_tg + apool->adj_off[it->second], st);
-            else
-                launch_adj_pauli(sp_dev, 1, it->second, N, apool->gcnt[it->second], st);
+    // Re <lambda|A_k phi>, the derivative of appending A_k after U(theta).
+    // Packed layout: one read-only launch over every run and tile; full
+    // layout: the reverse-sweep kernels at zero angles.
+    auto phase = [&](int ph) {
+        if (ph == 0) {
+            enqueue_phase(ep, e.sd_dev, 1, kPhaseFwd, false, st);
+        } else if (ph == 1) {
+            enqueue_phase(ep, e.sd_dev, 1, kPhaseHx, true, st);
+        } else if (ph == 2) {
+            if (probe.packed) {
+                launch_pool_sweep(sp_dev, 1, *psw, ep.hxt, ep.lay->d_base, st);
+            } else {
+                launch_angles(sp_dev, 1, int(Mp), st);
+                const uint64_t N = uint64_t(1) << n;
+                for (auto it = apool->adj_steps.rbegin(); it != apool->adj_steps.rend(); ++it) {
+                    if (it->first == 0)
+                        launch_run_adj(sp_dev, 1, apool->adj_runs[it->second],
+                                       apool->d_adj_tg + apool->adj_off[it->second], st);
+                    else
+                        launch_adj_pauli(sp_dev, 1, it->second, N, apool->gcnt[it->second], st);
+                }
+            }
+        } else {
+            launch_reduce_e(e.sd_dev, 1, ep.nblk_e, st);
+            launch_reduce_g(sp_dev, 1, int(Mp), probe.packed ? ppool->d_gcnt : apool->d_gcnt, 0,
+                            st);
         }
+    };
+    if (reps <= 0) {
+        for (int ph = 0; ph < 4; ++ph) phase(ph);
+        HIPCHK(hipGetLastError());
+    } else {
+        hipEvent_t ev[5];
+        for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+        double acc[4] = {0, 0, 0, 0};
+        int rc = VQE_OK;
+        for (int r = 0; r < reps && rc == VQE_OK; ++r) {
+            (void)hipEventRecord(ev[0], st);
+            for (int ph = 0; ph < 4; ++ph) {
+                phase(ph);
+                (void)hipEventRecord(ev[ph + 1], st);
+            }
+            hipError_t err = hipEventSynchronize(ev[4]);
+            if (err == hipSuccess) err = hipGetLastError();
+            if (err != hipSuccess) {
+                rc = fail(VQE_EDEVICE, std::string("profile: ") + hipGetErrorString(err));
+                break;
+            }
+            for (int ph = 0; ph < 4; ++ph) {
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, ev[ph], ev[ph + 1]);
+                acc[ph] += t;
+            }
+        }
+        for (auto& x : ev) (void)hipEventDestroy(x);
+        if (rc) return rc;
+        for (int ph = 0; ph < 4; ++ph) ms[ph] = acc[ph] / reps;
+        work[0] = ep.fwd_bytes;
+        work[1] = 0.0;
+        work[2] = probe.packed ? ppool->sweep_bytes : apool->adj_bytes;
+        work[3] = double(probe.packed ? 1 : apool->adj_steps.size());
     }
-    launch_reduce_e(e.sd_dev, 1, ep.nblk_e, st);
-    launch_reduce_g(sp_dev, 1, int(Mp), probe.packed ? ppool->d_gcnt : apool->d_gcnt, 0, st);
-    HIPCHK(hipGetLastError());
     std::vector<double> raw(static_cast<size_t>(Mp));
     HIPCHK(hipMemcpyAsync(energy, e.sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(raw.data(), sp.out_g, sizeof(double) * Mp, hipMemcpyDeviceToHost, st));
@@ -1784,6 +1882,26 @@ extern "C" int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A,
     if (!std::isfinite(*energy) || !finite_all(pool_grad, Pp))
         return fail(VQE_ENUMERIC, "non-finite energy or pool gradient");
     return VQE_OK;
+}
+
+}  // namespace
+
+extern "C" int vqe_pool_gradient(const vqe_hamiltonian* H, const vqe_ansatz* A,
+                                 const vqe_ansatz* pool, int ne, const double* theta,
+                                 double* energy, double* pool_grad, void* stream) {
+    return pool_gradient_impl(H, A, pool, ne, theta, energy, pool_grad, stream, 0, nullptr,
+                              nullptr);
+}
+
+extern "C" int vqe_pool_gradient_profile(const vqe_hamiltonian* H, const vqe_ansatz* A,
+                                         const vqe_ansatz* pool, int ne, const double* theta,
+                                         int reps, double* ms, double* work, void* stream) {
+    if (!ms || !work) return fail(VQE_EINVAL, "null pointer argument");
+    if (reps < 1) return fail(VQE_ERANGE, "reps must be >= 1");
+    if (!pool) return fail(VQE_EINVAL, "null pool");
+    double e = 0.0;
+    std::vector<double> g(static_cast<size_t>(std::max(pool->n_params, 1)));
+    return pool_gradient_impl(H, A, pool, ne, theta, &e, g.data(), stream, reps, ms, work);
 }
 
 // ===================================================================== batch
