@@ -119,7 +119,10 @@ struct CiArgs {
     const uint32_t* plist;
     int32_t na_str, nb_str, ob;
     int32_t npairs, e1;      // beta pairs C(ob, 2); list entries per column
-    int32_t pad[3];
+    // the groups are split over nsplit workgroups per row (grid z); split z
+    // writes its partial lambda to aux plane z (na_str * nb_str entries each)
+    int32_t nsplit;
+    int32_t pad[2];
 };
 
 // A fused tile pass over consecutive excitation gates [g0, g1) that share
@@ -397,7 +400,8 @@ void launch_fill_zero(double2* p, uint64_t n, hipStream_t st);
 void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
                        hipStream_t st);
 void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
-                      hipStream_t st);
+                      int nsplit, hipStream_t st);
+int ci_choose_splits(const CiArgs& ci);
 // lambda (aux) = H phi (lam) in string-product order, energy partial per row.
 void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st);
 int ci_prepare(const CiArgs& ci);   // 0 when the kernel can launch for these sizes

@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     int16_t* RB = reinterpret_cast<int16_t*>(lds_ci);
     for (int i = threadIdx.x; i < nrank; i += kT) RB[i] = ci.rank_b[i];
     const StateDesc& s = sd[blockIdx.y];
+    const int split = blockIdx.z, nsplit = ci.nsplit;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int rslot = wave / W, wr = wave % W;   // row slot in the block, wave within the row
     const int rt = wr * 64 + lane;               // thread within the row
@@ -166,7 +167,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         row_sync();
     };
     // ---- beta-pair classes
-    for (int pc = 0; row_live && pc < s.ci_npcls; ++pc) {
+    for (int pc = split; row_live && pc < s.ci_npcls; pc += nsplit) {
         const CiPairClass P = ldc(s.ci_pcls + pc);
         if (__popc(sA & P.xa) != P.half) continue;   // no in-sector partner row
         stage_row(phi + size_t(ldc(ci.rank_a + (sA ^ P.xa))) * NB);
@@ -205,7 +206,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             ci_group<COLS, W, true>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, lr, li);
         }
     }
-    // ---- generic groups, chunk by chunk
+    // ---- generic groups, chunk by chunk (chunks split, split + nsplit, ...)
     const int nch = s.ci_nchunks;
     double treg[kTPer];
     auto tload = [&](int c) {
@@ -220,15 +221,18 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
         for (int k = 0; k < kTPer; ++k) tstage[buf][threadIdx.x + k * kT] = treg[k];
     };
-    tload(0);
-    tstore(0);
+    if (split < nch) {
+        tload(split);
+        tstore(0);
+    }
     __syncthreads();
     uint32_t cur_xa = 0xffffffffu;   // class whose partner row is staged
     bool valid = false, col_only = false;
     const double2* prow = phi;
-    for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) tload(ch + 1);   // in flight during this chunk
-        const double* tab = tstage[ch & 1];
+    for (int ch = split, it = 0; ch < nch; ch += nsplit, ++it) {
+        const int chn = ch + nsplit;
+        if (chn < nch) tload(chn);   // in flight during this chunk
+        const double* tab = tstage[it & 1];
         const CiChunk ck = ldc(s.ci_chunks + ch);
         const CiGroup* gp = s.ci_groups + ck.g0;
         const CiSub* sp = s.ci_subs + ck.s0;
@@ -248,13 +252,13 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             if (valid) ci_group<COLS, W, false>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, lr, li);
             G = Gn;
         }
-        if (ch + 1 < nch) tstore((ch + 1) & 1);   // the buffer read two chunks ago
+        if (chn < nch) tstore((it + 1) & 1);   // the buffer read two chunks ago
         __syncthreads();
     }
     if (!row_live) return;
     double acc = 0.0;
     const double2* mine = phi + size_t(ia) * NB;
-    double2* out = s.aux + size_t(ia) * NB;
+    double2* out = s.aux + size_t(split) * size_t(ci.na_str) * NB + size_t(ia) * NB;
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const int ib = rt + 64 * W * c;
@@ -266,7 +270,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     }
     acc = wave_total(acc);
     if (W == 1) {
-        if (lane == 0) s.part_e[ia] = acc;
+        if (lane == 0) s.part_e[split * ci.na_str + ia] = acc;
     } else {   // the row's wave totals in fixed order
         if (lane == 0) ered[wr] = acc;
         __syncthreads();
@@ -274,7 +278,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             double v = 0.0;
 #pragma unroll
             for (int w = 0; w < W; ++w) v += ered[w];
-            s.part_e[ia] = v;
+            s.part_e[split * ci.na_str + ia] = v;
         }
     }
 }
@@ -287,12 +291,21 @@ __global__ void k_ci_scatter(const StateDesc* __restrict__ sd, const int32_t* __
         s.lam[perm[k]] = s.phi[k];
 }
 
+// lambda in block order: the sum of the split planes, in plane order.
 __global__ void k_ci_gather(const StateDesc* __restrict__ sd, const int32_t* __restrict__ perm,
-                            int64_t size) {
+                            int64_t size, int nsplit) {
     const StateDesc& s = sd[blockIdx.y];
     for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
-         k += int64_t(gridDim.x) * blockDim.x)
-        s.lam[k] = s.aux[perm[k]];
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t q = perm[k];
+        double2 v = s.aux[q];
+        for (int z = 1; z < nsplit; ++z) {
+            const double2 w = s.aux[size_t(z) * size + q];
+            v.x += w.x;
+            v.y += w.y;
+        }
+        s.lam[k] = v;
+    }
 }
 
 void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
@@ -302,9 +315,9 @@ void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int6
 }
 
 void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
-                      hipStream_t st) {
+                      int nsplit, hipStream_t st) {
     hipLaunchKernelGGL(k_ci_gather, dim3(blocks_for(uint64_t(size)), count), dim3(kBlock), 0, st,
-                       sd, perm, size);
+                       sd, perm, size, nsplit);
 }
 
 // Launch shape: rows of up to 256 beta strings take one wave each, as many
@@ -330,6 +343,14 @@ static CiShape ci_shape(const CiArgs& ci) {
     return sh;
 }
 
+// Splits of one state's groups so that a lone state still occupies the
+// chip: about 2048 waves (two per SIMD), at most 8 splits.
+int ci_choose_splits(const CiArgs& ci) {
+    const CiShape sh = ci_shape(ci);
+    const int waves = ci.na_str * sh.waves;
+    return std::max(1, std::min(8, (2048 + waves - 1) / std::max(waves, 1)));
+}
+
 static size_t ci_lds(const CiArgs& ci) {
     const size_t rank_bytes = ((size_t(2) << ci.ob) + 15) & ~size_t(15);
     return rank_bytes + size_t(ci_shape(ci).rows) * ci_wave_words(ci.nb_str, ci.npairs) * sizeof(double2);
@@ -337,7 +358,7 @@ static size_t ci_lds(const CiArgs& ci) {
 
 template <int COLS, int R, int W>
 static void launch_crw(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    const dim3 grid((ci.na_str + R - 1) / R, count);
+    const dim3 grid((ci.na_str + R - 1) / R, count, ci.nsplit);
     hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci);
 }
 

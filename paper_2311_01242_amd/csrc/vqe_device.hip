@@ -580,6 +580,7 @@ struct CiSpace {
         a.nb_str = NB;
         a.ob = ob;
         a.npairs = npairs;
+        a.nsplit = 1;
         a.e1 = e1;
         return a;
     }
@@ -1082,7 +1083,8 @@ struct Workspace {
     size_t state_bytes = 0;
     double2* phi = nullptr;
     double2* lam = nullptr;
-    double2* aux = nullptr;      // lambda in string-product order (packed path)
+    double2* aux = nullptr;      // lambda in string-product order (packed path), per split
+    size_t aux_bytes = 0;
     int64_t lam_zero_key = -1;   // sector for which lambda is zero outside it
     size_t scratch_bytes = 0;
     char* scratch = nullptr;     // theta, cs, partials, outputs, descriptor
@@ -1100,7 +1102,8 @@ static int fits_device(size_t bytes) {
     return VQE_OK;
 }
 
-static int workspace(void* stream, size_t state_bytes, size_t scratch_bytes, Workspace** out) {
+static int workspace(void* stream, size_t state_bytes, size_t aux_bytes, size_t scratch_bytes,
+                     Workspace** out) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
     std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -1110,15 +1113,22 @@ static int workspace(void* stream, size_t state_bytes, size_t scratch_bytes, Wor
         HIPCHK(hipStreamSynchronize((hipStream_t)stream));
         (void)hipFree(ws->phi);
         (void)hipFree(ws->lam);
-        (void)hipFree(ws->aux);
-        ws->phi = ws->lam = ws->aux = nullptr;
+        ws->phi = ws->lam = nullptr;
         ws->state_bytes = 0;
         ws->lam_zero_key = -1;
-        if (int rc = fits_device(state_bytes * 3)) return rc;
+        if (int rc = fits_device(state_bytes * 2)) return rc;
         HIPCHK(hipMalloc(&ws->phi, state_bytes));
         HIPCHK(hipMalloc(&ws->lam, state_bytes));
-        HIPCHK(hipMalloc(&ws->aux, state_bytes));
         ws->state_bytes = state_bytes;
+    }
+    if (ws->aux_bytes < aux_bytes) {
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+        (void)hipFree(ws->aux);
+        ws->aux = nullptr;
+        ws->aux_bytes = 0;
+        if (int rc = fits_device(aux_bytes)) return rc;
+        HIPCHK(hipMalloc(&ws->aux, aux_bytes));
+        ws->aux_bytes = aux_bytes;
     }
     if (ws->scratch_bytes < scratch_bytes) {
         HIPCHK(hipStreamSynchronize((hipStream_t)stream));
@@ -1227,8 +1237,9 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
                     if (int rc = layout_perm(ep->lay, *cs, *host_tables(ep->hx.L))) return rc;
                     ep->ci = true;
                     ep->ciargs = cs->args();
+                    ep->ciargs.nsplit = batched ? 1 : ci_choose_splits(ep->ciargs);
                     ep->perm = ep->lay->d_perm;
-                    ep->nblk_e = cs->NA;
+                    ep->nblk_e = cs->NA * ep->ciargs.nsplit;
                     if (ci_prepare(ep->ciargs) != 0)
                         return fail(VQE_EDEVICE, "could not enable the string-product LDS size");
                 }
@@ -1256,7 +1267,7 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
         if (ep.ci) {
             launch_ci_scatter(sd, count, ep.perm, ep.lay->size, st);
             launch_hx_ci(sd, count, ep.ciargs, st);
-            launch_ci_gather(sd, count, ep.perm, ep.lay->size, st);
+            launch_ci_gather(sd, count, ep.perm, ep.lay->size, ep.ciargs.nsplit, st);
         } else {
             launch_hx_packed(sd, count, ep.hx, ep.hxt, ep.lay->d_base, st);
         }
@@ -1477,7 +1488,7 @@ int begin_state_call(const vqe_state* s, int64_t M, int64_t P, int nblk_e, State
     sz.add<double>(nblk_e);
     sz.add<double>(1);
     sz.add<StateDesc>(1);
-    if (int rc = workspace(s->st, 0, sz.s, &c->ws)) return rc;
+    if (int rc = workspace(s->st, 0, 0, sz.s, &c->ws)) return rc;
     c->cv = Carver{c->ws->scratch};
     std::memset(&c->sd, 0, sizeof(StateDesc));
     c->sd.phi = s->ptr;
@@ -1619,7 +1630,9 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
     sz.add<double>(1);
     sz.add<double>(M);
     sz.add<StateDesc>(1);
-    if (int rc = workspace(st, sizeof(double2) * size_t(ep.elems), sz.s, &e->ws)) return rc;
+    const size_t sbytes = sizeof(double2) * size_t(ep.elems);
+    if (int rc = workspace(st, sbytes, ep.ci ? sbytes * size_t(ep.ciargs.nsplit) : sbytes, sz.s,
+                           &e->ws)) return rc;
     Workspace* ws = e->ws;
     // the full-layout sector H-apply writes only in-sector entries: lambda
     // must be zero elsewhere (the packed layout holds nothing else)
