@@ -9,9 +9,10 @@ HIP-graph launch (the library's batched path), inputs resident on the device.
 
 Other workloads: ``single24`` (one 24-qubit, 12-electron instance),
 ``scan12`` (the 20-point 12-qubit bond-stretch family, one energy + gradient
-per geometry), ``warmstart16`` (the learned warm start) and ``adapt20``
+per geometry), ``warmstart16`` (the learned warm start), ``adapt20``
 (ADAPT-VQE on one 20-qubit, 10-electron problem; a step is one pool-gradient
-evaluation over the 875-operator UCCSD pool).
+evaluation over the 875-operator UCCSD pool) and ``puccd11`` (pUCCD in the
+hard-core-boson form, 11 qubits / 28 parameters, 512 geometries per step).
 
 Prints one JSON line (see the repository's design doc for the roofline
 accounting and the CPU-oracle sampling).
@@ -38,7 +39,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch512",
-                    choices=["batch512", "single24", "scan12", "warmstart16", "adapt20"])
+                    choices=["batch512", "single24", "scan12", "warmstart16", "adapt20", "puccd11"])
     ap.add_argument("--scan-points", type=int, default=200)
     ap.add_argument("--mlp-steps", type=int, default=4000)
     ap.add_argument("--states", type=int, default=512)
@@ -159,7 +160,7 @@ def sector_pairs(H, n, ne):
     return float(np.sum(np.where(ok, cnt, 0.0)))
 
 
-def roofline(b, theta, reps, Hs, nes):
+def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
     """Rooflines of the three phases from one eager, HIP-event-timed
     evaluation of the batch (the graph replays interleave the size classes on
     forked streams, so phases cannot be timed there); the dominant phase's
@@ -168,9 +169,11 @@ def roofline(b, theta, reps, Hs, nes):
     H-apply: 4 lane-operations per in-sector (output, term) pair against the
     vector-ALU lane rate.  `traffic` is the rocprof FETCH+WRITE measurement of
     the kernel, reported only while its source still matches the measured one."""
+    kernels = PHASE_KERNELS if kernels is None else kernels
     phase_ms = b.profile(theta, reps=reps)
     w = b.work()
-    pairs = sum(sector_pairs(H, H.info()[0], ne) for H, ne in zip(Hs, nes))
+    if pairs is None:
+        pairs = sum(sector_pairs(H, H.info()[0], ne) for H, ne in zip(Hs, nes))
     traffic = {}
     if os.path.exists(TRAFFIC):
         with open(TRAFFIC) as f:
@@ -179,7 +182,7 @@ def roofline(b, theta, reps, Hs, nes):
     for i, (phase, work, launches) in enumerate(
             [("forward", w[0], w[4]), ("h_apply", OPS_PER_PAIR * pairs, w[5]),
              ("adjoint", w[2], w[6])]):
-        kernel, src, bound = PHASE_KERNELS[phase]
+        kernel, src, bound = kernels[phase]
         t_s = phase_ms[i] * 1e-3
         if bound == "hbm":
             achieved, peak, unit = work / t_s / 1e9, HBM_PEAK_GBS, "GB/s"
@@ -252,6 +255,79 @@ def run_batch(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(spec)
     return out
+
+
+# full-vector kernels of programs that leave the alpha/beta sector structure
+DENSE_KERNELS = {
+    "forward": ("k_run_fwd (full-vector forward gate runs)", "k_gates.hip", "hbm"),
+    "h_apply": ("k_hx_dense (full-vector H-apply by x-mask group)", "k_hamiltonian.hip", "alu"),
+    "adjoint": ("k_run_adj (full-vector reverse-sweep gate runs)", "k_gates.hip", "hbm"),
+}
+
+
+def run_puccd11(args):
+    """pUCCD in the hard-core-boson form (Sec. 2.1, ansatz list) at the size
+    the paper runs CH3F with (11 orbitals = 11 qubits, 7 pairs, 28
+    parameters): 512 geometries of a seeded stretch family h, g = A + B e^-lam
+    (lam in [0.8, 2.5]), theta ~ U(-0.1, 0.1); one step = energy + adjoint
+    gradient of all 512 in one HIP-graph launch."""
+    import torch
+    import paper_2311_01242_amd as vq
+    from vqe_inputs import scan_integrals, uniform_theta
+    n_orb, n_pairs, S = 11, 7, args.states
+    fam = scan_integrals(2 * n_orb, 8)
+    lams = np.linspace(0.8, 2.5, S)
+    Hs = [vq.Hamiltonian.pairs_from_integrals(n_orb, *fam(l)) for l in lams]
+    A = vq.Ansatz.puccd(n_orb, n_pairs)
+    b = vq.Batch(Hs, [A] * S, [n_pairs] * S)
+    th = np.concatenate([uniform_theta(50000 + i, A.n_params) for i in range(S)])
+    for _ in range(args.warmup):
+        b.energy_grad(th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, g = b.energy_grad(th)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
+    pairs = float(sum((1 << n_orb) * H.info()[1] for H in Hs))
+    roof = roofline(b, th, args.profile_reps, Hs, [n_pairs] * S, kernels=DENSE_KERNELS, pairs=pairs)
+    out = {
+        "metric": "energy+adjoint-grad evals/s", "value": round(S * args.steps / dt, 2),
+        "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
+        "config": {"workload": f"pUCCD hard-core bosons, 11 qubits, 7 pairs, 28 params, {S} geometries "
+                               "per step, one HIP-graph launch", "states": S},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_puccd(fam, lams, th, n_orb, n_pairs)
+    return out
+
+
+def cpu_baseline_puccd(fam, lams, th, n_orb, n_pairs, budget_s=15.0):
+    """Oracle pair-space energy + shift-rule gradient, timed on the first
+    geometries until budget_s, scaled to the batch."""
+    from oracle import hcb as HB
+    m = len(HB.puccd_excitations(n_orb, n_pairs))
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(lams) and time.perf_counter() - t0 < budget_s:
+        prob = HB.Problem(n_orb, n_pairs, *fam(lams[k]))
+        t = th[m * k:m * (k + 1)]
+        prob.energy(t)
+        prob.grad_shift(t)
+        k += 1
+    t = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": k / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle pUCCD energy + four-term shift-rule gradient (operator set-up "
+                      f"included) on the first {k} of {len(lams)} geometries ({t:.1f} s)"}
 
 
 def run_single24(args):
@@ -470,7 +546,8 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_per_launch": a.numel() * 16, "launches": 3}))
         return
     fn = {"batch512": run_batch, "single24": run_single24, "scan12": run_scan12,
-          "warmstart16": run_warmstart16, "adapt20": run_adapt20}[args.workload]
+          "warmstart16": run_warmstart16, "adapt20": run_adapt20,
+          "puccd11": run_puccd11}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

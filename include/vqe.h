@@ -77,6 +77,20 @@ const char* vqe_last_error(void);
 int vqe_hamiltonian_from_integrals(int n_qubits, double h0, const double* h,
                                    const double* g, vqe_hamiltonian** out);
 
+/* Eq. 2 projected onto the seniority-zero space, in the hard-core-boson
+ * form used by pUCCD (Sec. 2.1, ansatz list): qubit p is spatial orbital p
+ * (n_orbitals qubits, half the Jordan-Wigner count), bit p = 1 when both
+ * of its spin orbitals are occupied.  With N_p the pair number and b_p the
+ * pair annihilator,
+ *   H = h0 + sum_p (2 h_pp + (pp|pp)) N_p
+ *          + sum_{p<q} 2 [2 (pp|qq) - (pq|qp)] N_p N_q
+ *          + sum_{p<q} (pq|pq) (b_p^dag b_q + b_q^dag b_p),
+ * N_p = (1 - Z_p)/2, b_p^dag b_q + h.c. = (X_p X_q + Y_p Y_q)/2.  h is
+ * [n][n] and g [n][n][n][n] chemist integrals, with the same checks as
+ * vqe_hamiltonian_from_integrals.  |c'| <= 1e-12 terms are dropped. */
+int vqe_hamiltonian_pairs_from_integrals(int n_orbitals, double h0, const double* h,
+                                         const double* g, vqe_hamiltonian** out);
+
 /* Hamiltonian sum_k coef[k] X^{x[k]} Z^{z[k]} in folded form (see above).
  * Masks must fit n_qubits bits (ERANGE); duplicate (x, z) pairs are summed;
  * a nonzero term with odd popcount(x&z) makes H non-symmetric and is
@@ -107,6 +121,15 @@ void vqe_hamiltonian_free(vqe_hamiltonian* H);
  * U_M ... U_1 with all singles first (a outer, i inner) and then doubles
  * ((a, b) outer, (i, j) inner), ascending.  *n_params receives M. */
 int vqe_ansatz_uccsd(int n_qubits, int n_electrons, vqe_ansatz** out, int32_t* n_params);
+
+/* pUCCD (Sec. 2.1, ansatz list) in the hard-core-boson form on n_orbitals
+ * qubits: for occupied pairs i < n_pairs and empty orbitals a >= n_pairs
+ * (a outer, i inner, ascending), U = exp(theta (b_a^dag b_i - b_i^dag b_a)),
+ * the Givens rotation of D (bit i set, bit a clear) and D ^ (2^i + 2^a)
+ * with T|D> = +|D ^ ...>.  The reference is the n_pairs lowest qubits
+ * (pass n_electrons = n_pairs to the evaluation calls).  Evaluated on full
+ * 2^n vectors.  *n_params receives n_pairs (n_orbitals - n_pairs). */
+int vqe_ansatz_puccd(int n_orbitals, int n_pairs, vqe_ansatz** out, int32_t* n_params);
 
 /* Ansatz of explicit Pauli rotations applied in the given order:
  * gate k is exp(-i (scale[k] * theta[param_index[k]]) / 2 * P(x[k], z[k]))

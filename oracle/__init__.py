@@ -26,4 +26,6 @@ Modules
 ``pauli``    dense-Pauli mode (n <= 14): own Jordan-Wigner via Hermitian Pauli
              algebra, own Pauli-rotation statevector evolution.
 ``mlp``      float64 MLP forward/backward with bfloat16 rounding emulation.
+``hcb``      pUCCD on the hard-core-boson (pair) space: projected
+             Hamiltonian from Slater-Condon rules, pair Givens rotations.
 """

@@ -95,6 +95,16 @@ class Hamiltonian:
         return cls(out)
 
     @classmethod
+    def pairs_from_integrals(cls, n_orbitals: int, h0: float, h, g):
+        """Hard-core-boson (pUCCD) Hamiltonian on n_orbitals qubits."""
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        out = C.c_void_p()
+        _check(lib().vqe_hamiltonian_pairs_from_integrals(int(n_orbitals), float(h0), _dptr(h),
+                                                          _dptr(g), C.byref(out)))
+        return cls(out)
+
+    @classmethod
     def from_paulis(cls, n_qubits: int, x, z, coef):
         x = np.ascontiguousarray(x, dtype=np.uint32)
         z = np.ascontiguousarray(z, dtype=np.uint32)
@@ -139,6 +149,14 @@ class Ansatz:
         out = C.c_void_p()
         m = C.c_int32()
         _check(lib().vqe_ansatz_uccsd(int(n_qubits), int(n_electrons), C.byref(out), C.byref(m)))
+        return cls(out)
+
+    @classmethod
+    def puccd(cls, n_orbitals: int, n_pairs: int):
+        """pUCCD on the pair space (evaluate with n_electrons = n_pairs)."""
+        out = C.c_void_p()
+        m = C.c_int32()
+        _check(lib().vqe_ansatz_puccd(int(n_orbitals), int(n_pairs), C.byref(out), C.byref(m)))
         return cls(out)
 
     @classmethod

@@ -39,10 +39,13 @@ SIGNATURES = {
     "vqe_last_error": (C.c_char_p, []),
     "vqe_hamiltonian_from_integrals": (c_int, [c_int, c_double, P(c_double), P(c_double), P(vp)]),
     "vqe_hamiltonian_from_paulis": (c_int, [c_int, c_int64, P(c_uint32), P(c_uint32), P(c_double), P(vp)]),
+    "vqe_hamiltonian_pairs_from_integrals": (c_int, [c_int, c_double, P(c_double), P(c_double),
+                                                     P(vp)]),
     "vqe_hamiltonian_info": (c_int, [vp, P(c_int), P(c_int64), P(c_int64)]),
     "vqe_hamiltonian_terms": (c_int, [vp, P(c_int64), P(c_uint32), P(c_uint32), P(c_double)]),
     "vqe_hamiltonian_free": (None, [vp]),
     "vqe_ansatz_uccsd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
+    "vqe_ansatz_puccd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
     "vqe_ansatz_from_rotations": (c_int, [c_int, c_int32, c_int64, P(c_uint32), P(c_uint32),
                                           P(c_int32), P(c_double), P(vp)]),
     "vqe_ansatz_select": (c_int, [vp, c_int64, P(c_int32), P(vp)]),

@@ -185,16 +185,8 @@ extern "C" int vqe_abi_version(void) { return VQE_ABI_VERSION; }
 
 extern "C" const char* vqe_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h, const double* g,
-                                              vqe_hamiltonian** out) {
-    if (!out || !h || !g) return fail(VQE_EINVAL, "null pointer argument");
-    *out = nullptr;
-    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
-    if (!std::isfinite(h0)) return fail(VQE_EINVAL, "h0 is not finite");
-    const int ns = (n + 1) / 2;
-    const int64_t n2 = int64_t(ns) * ns, n4 = n2 * n2;
-    if (!finite_all(h, n2)) return fail(VQE_EINVAL, "h has a non-finite entry");
-    if (!finite_all(g, n4)) return fail(VQE_EINVAL, "g has a non-finite entry");
+// h symmetric and g 8-fold symmetric within 1e-12 (EINVAL otherwise).
+static int check_integral_symmetry(int ns, const double* h, const double* g) {
     auto H1 = [&](int p, int q) { return h[p * ns + q]; };
     auto G = [&](int p, int q, int r, int s) { return g[((int64_t(p) * ns + q) * ns + r) * ns + s]; };
     const double tol = 1e-12;
@@ -212,6 +204,22 @@ extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h,
                         std::fabs(v - G(r, s, p, q)) > tol)
                         return fail(VQE_EINVAL, "g lacks the 8-fold symmetry of real (pq|rs)");
                 }
+    return VQE_OK;
+}
+
+extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h, const double* g,
+                                              vqe_hamiltonian** out) {
+    if (!out || !h || !g) return fail(VQE_EINVAL, "null pointer argument");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (!std::isfinite(h0)) return fail(VQE_EINVAL, "h0 is not finite");
+    const int ns = (n + 1) / 2;
+    const int64_t n2 = int64_t(ns) * ns, n4 = n2 * n2;
+    if (!finite_all(h, n2)) return fail(VQE_EINVAL, "h has a non-finite entry");
+    if (!finite_all(g, n4)) return fail(VQE_EINVAL, "g has a non-finite entry");
+    auto H1 = [&](int p, int q) { return h[p * ns + q]; };
+    auto G = [&](int p, int q, int r, int s) { return g[((int64_t(p) * ns + q) * ns + r) * ns + s]; };
+    if (int rc = check_integral_symmetry(ns, h, g)) return rc;
 
     TermMap m;
     m.reserve(size_t(n) * n * n * n);
@@ -255,6 +263,53 @@ extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h,
                             }
                 }
             }
+        }
+    auto* H = new (std::nothrow) vqe_hamiltonian();
+    if (!H) return fail(VQE_ENOMEM, "host allocation failed");
+    H->n = n;
+    finish_terms(H, m, 1e-12);
+    *out = H;
+    return VQE_OK;
+}
+
+// Eq. 2 on the seniority-zero space (pUCCD's hard-core-boson form): qubit p
+// is spatial orbital p, bit p = 1 when its pair is present.  With N_p the
+// pair number and b_p the pair annihilator (Slater-Condon rules for whole
+// pairs; moving a pair q -> p is the double excitation with element (pq|pq)
+// and sign +1, since the orbitals below each ladder operator hold pairs):
+//   H = h0 + sum_p e_p N_p + sum_{p<q} w_pq N_p N_q + sum_{p<q} v_pq (b_p^dag b_q + h.c.),
+//   e_p = 2 h_pp + (pp|pp), w_pq = 2 [2 (pp|qq) - (pq|qp)], v_pq = (pq|pq);
+// N_p = (1 - Z_p)/2 and b_p^dag b_q + h.c. = (X_p X_q + Y_p Y_q)/2.
+extern "C" int vqe_hamiltonian_pairs_from_integrals(int n, double h0, const double* h,
+                                                    const double* g, vqe_hamiltonian** out) {
+    if (!out || !h || !g) return fail(VQE_EINVAL, "null pointer argument");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_orbitals must be in [1, 32]");
+    if (!std::isfinite(h0)) return fail(VQE_EINVAL, "h0 is not finite");
+    const int64_t n2 = int64_t(n) * n, n4 = n2 * n2;
+    if (!finite_all(h, n2)) return fail(VQE_EINVAL, "h has a non-finite entry");
+    if (!finite_all(g, n4)) return fail(VQE_EINVAL, "g has a non-finite entry");
+    if (int rc = check_integral_symmetry(n, h, g)) return rc;
+    auto H1 = [&](int p, int q) { return h[p * n + q]; };
+    auto G = [&](int p, int q, int r, int s) { return g[((int64_t(p) * n + q) * n + r) * n + s]; };
+    TermMap m;
+    m[key(0, 0)] += h0;
+    for (int p = 0; p < n; ++p) {
+        const double e = 2.0 * H1(p, p) + G(p, p, p, p);
+        m[key(0, 0)] += 0.5 * e;
+        m[key(0, 1u << p)] -= 0.5 * e;
+    }
+    for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q) {
+            const uint32_t bp = 1u << p, bq = 1u << q;
+            const double w = 2.0 * (2.0 * G(p, p, q, q) - G(p, q, q, p));
+            m[key(0, 0)] += 0.25 * w;
+            m[key(0, bp)] -= 0.25 * w;
+            m[key(0, bq)] -= 0.25 * w;
+            m[key(0, bp | bq)] += 0.25 * w;
+            const double v = G(p, q, p, q);
+            m[key(bp | bq, 0)] += 0.5 * v;            // X_p X_q
+            m[key(bp | bq, bp | bq)] -= 0.5 * v;      // Y_p Y_q = -X_p X_q Z_p Z_q
         }
     auto* H = new (std::nothrow) vqe_hamiltonian();
     if (!H) return fail(VQE_ENOMEM, "host allocation failed");
@@ -352,6 +407,41 @@ extern "C" int vqe_ansatz_uccsd(int n, int ne, vqe_ansatz** out, int32_t* n_para
                         excitation_gate(ops, 4, occ, occ | (1u << a) | (1u << b), p++));
                     A->exc.insert(A->exc.end(), {i, j, a, b});
                 }
+    A->n_params = p;
+    if (n_params) *n_params = p;
+    *out = A;
+    return VQE_OK;
+}
+
+// pUCCD (Sec. 2.1, ansatz list) on the pair space: for occupied pairs i and
+// empty orbitals a of the reference (a outer, i inner, ascending),
+// exp(theta (b_a^dag b_i - b_i^dag b_a)), a Givens rotation of (D, D ^ x)
+// for D with bit i set and bit a clear, T|D> = +|E> (no parity string:
+// pairs are bosons).
+extern "C" int vqe_ansatz_puccd(int n, int n_pairs, vqe_ansatz** out, int32_t* n_params) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_orbitals must be in [1, 32]");
+    if (n_pairs < 0 || n_pairs > n) return fail(VQE_ERANGE, "n_pairs must be in [0, n_orbitals]");
+    auto* A = new (std::nothrow) vqe_ansatz();
+    if (!A) return fail(VQE_ENOMEM, "host allocation failed");
+    A->n = n;
+    A->n_electrons = n_pairs;
+    A->sector_conserving = false;   // conserves the pair count, not alpha and beta separately
+    int32_t p = 0;
+    for (int a = n_pairs; a < n; ++a)
+        for (int i = 0; i < n_pairs; ++i) {
+            GateDesc gd{};
+            gd.type = kExcitation;
+            gd.x = (1u << i) | (1u << a);
+            gd.pd = 1u << i;
+            gd.chain = 0;
+            gd.csign = 1.0;
+            gd.param = p++;
+            gd.scale = 1.0;
+            A->gates.push_back(gd);
+            A->exc.insert(A->exc.end(), {i, a, -1, -1});
+        }
     A->n_params = p;
     if (n_params) *n_params = p;
     *out = A;

@@ -14,8 +14,9 @@ Two sub-commands, both reading the CSV files rocprofv3 writes with
             phase, with the sha256 of the kernel source it was measured on)
             and prints a markdown table.
 
-Phase of a kernel: k_prun<1,...> forward, k_prun<2,...> adjoint,
-k_hx_ci / k_ci_scatter / k_ci_gather / k_hx_packed / k_hx_sector H-apply.
+Phase of a kernel: k_prun<1,...> / k_run_fwd forward, k_prun<2,...> /
+k_run_adj adjoint, k_ppool pool sweep, k_hx_ci / k_ci_scatter / k_ci_gather /
+k_hx_packed / k_hx_sector / k_hx_dense H-apply.
 """
 from __future__ import annotations
 
@@ -33,12 +34,14 @@ COPY_BYTES = 2 ** 31
 
 
 def phase_of(name: str):
-    if "k_prun<1" in name:
+    if "k_prun<1" in name or "k_run_fwd" in name:
         return "forward"
-    if "k_prun<2" in name:
+    if "k_prun<2" in name or "k_run_adj" in name:
         return "adjoint"
+    if "k_ppool" in name:
+        return "pool_sweep"
     if any(k in name for k in ("k_hx_ci", "k_ci_scatter", "k_ci_gather", "k_hx_packed",
-                               "k_hx_sector")):
+                               "k_hx_sector", "k_hx_dense")):
         return "h_apply"
     return None
 

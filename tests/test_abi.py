@@ -172,3 +172,47 @@ def test_bfgs_budgets_and_errors():
     # wall-clock budget of (nearly) zero: stops at once, not converged, not an error
     x, res, _ = vq.minimize_bfgs(f, np.zeros(3), max_seconds=1e-12)
     assert res.converged == 0 and res.iters == 0
+
+
+def _folded_matrix(n, x, z, c):
+    """Dense matrix of sum c_k X^{x_k} Z^{z_k} (bit q of an index = qubit q)."""
+    X = np.array([[0.0, 1.0], [1.0, 0.0]])
+    Z = np.diag([1.0, -1.0])
+    m = np.zeros((1 << n, 1 << n))
+    for xx, zz, cc in zip(x, z, c):
+        op = np.eye(1)
+        for q in reversed(range(n)):          # kron with the highest qubit first
+            f = np.eye(2)
+            if (xx >> q) & 1:
+                f = f @ X
+            if (zz >> q) & 1:
+                f = f @ Z
+            op = np.kron(op, f)
+        m += cc * op
+    return m
+
+
+@pytest.mark.parametrize("n_orb,n_pairs,seed", [(3, 1, 1), (4, 2, 2), (5, 2, 3), (6, 3, 4)])
+def test_pair_hamiltonian_terms_match_oracle(n_orb, n_pairs, seed):
+    """The exported hard-core-boson terms, as a dense matrix, equal the
+    oracle's pair Hamiltonian on every pair-number sector they connect."""
+    from oracle import hcb as HB
+    h0, h, g = random_integrals(2 * n_orb, seed)
+    H = vq.Hamiltonian.pairs_from_integrals(n_orb, 0.4, h, g)
+    x, z, c = H.terms()
+    m = _folded_matrix(n_orb, x.tolist(), z.tolist(), c)
+    pop = np.array([bin(b).count("1") for b in range(1 << n_orb)])
+    assert np.abs(m[np.not_equal.outer(pop, pop)]).max() < 1e-14   # conserves the pair count
+    for k in range(n_orb + 1):
+        sp = HB.Space(n_orb, k)
+        ref = HB.hamiltonian_matrix(sp, 0.4, h, g)
+        assert np.abs(m[np.ix_(sp.bits, sp.bits)] - ref).max() < 1e-12
+    assert H.info()[0] == n_orb
+
+
+def test_puccd_program_matches_oracle():
+    from oracle import hcb as HB
+    for n_orb, n_pairs in [(2, 1), (5, 2), (11, 7)]:
+        A = vq.Ansatz.puccd(n_orb, n_pairs)
+        assert A.excitations() == HB.puccd_excitations(n_orb, n_pairs)
+        assert A.info() == (n_orb, n_pairs * (n_orb - n_pairs), n_pairs * (n_orb - n_pairs), n_pairs)

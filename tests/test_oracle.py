@@ -320,3 +320,81 @@ def test_adapt_invariants_6q():
     assert es.min() >= fci - 1e-10
     assert abs(es[-1] - fci) < 1e-7
     assert sel[0] == F.adapt_select(F.grad_at_hf_closed_form(4, pool, h, g), 1e-10)
+
+
+# ------------------------------------------------ pUCCD (hard-core bosons)
+
+from oracle import hcb as HB  # noqa: E402
+
+
+def _seniority_zero(space: F.Space, n_orb):
+    """Indices of the determinants with every spatial orbital doubly occupied or
+    empty, and the pair pattern of each."""
+    idx, pats = [], []
+    for k, b in enumerate(space.bits):
+        b = int(b)
+        pat = 0
+        ok = True
+        for p in range(n_orb):
+            a_, b_ = (b >> (2 * p)) & 1, (b >> (2 * p + 1)) & 1
+            if a_ != b_:
+                ok = False
+                break
+            pat |= a_ << p
+        if ok:
+            idx.append(k)
+            pats.append(pat)
+    return np.array(idx), pats
+
+
+@pytest.mark.parametrize("n_orb,n_pairs", [(2, 1), (3, 1), (4, 2), (5, 2), (6, 3)])
+def test_hcb_matrix_is_projected_fermion_hamiltonian(n_orb, n_pairs):
+    """The pair Hamiltonian equals the fermionic sector Hamiltonian restricted
+    to seniority-zero determinants (entry by entry, signs included)."""
+    h0, h, g = random_integrals(2 * n_orb, 17 + n_orb)
+    fs = F.Space(2 * n_orb, 2 * n_pairs)
+    Hf = F.Hamiltonian(fs, h0, h, g).matrix()
+    idx, pats = _seniority_zero(fs, n_orb)
+    sp = HB.Space(n_orb, n_pairs)
+    assert len(idx) == sp.ndet
+    order = [sp.index[p] for p in pats]
+    Hb = HB.hamiltonian_matrix(sp, h0, h, g)
+    assert np.abs(Hf[np.ix_(idx, idx)].real - Hb[np.ix_(order, order)]).max() < 1e-12
+    assert np.abs(Hf[np.ix_(idx, idx)].imag).max() < 1e-14
+
+
+@pytest.mark.parametrize("n_orb,n_pairs", [(3, 1), (4, 2), (5, 2)])
+def test_puccd_energy_matches_fermion_pair_doubles(n_orb, n_pairs):
+    """pUCCD on the pair space = the fermionic ansatz of the same pair double
+    excitations (2i, 2i+1 -> 2a, 2a+1) applied to HF, at the same angles."""
+    h0, h, g = random_integrals(2 * n_orb, 23 + n_orb)
+    prob = HB.Problem(n_orb, n_pairs, h0, h, g)
+    excs = [(2 * i, 2 * i + 1, 2 * a, 2 * a + 1) for i, a in prob.excs]
+    fprob = F.Problem(2 * n_orb, 2 * n_pairs, h0, h, g, excs=excs)
+    theta = np.random.default_rng(n_orb).uniform(-0.8, 0.8, prob.n_params)
+    assert abs(prob.energy(theta) - fprob.energy(theta)) < 1e-12
+    assert abs(prob.energy(np.zeros(prob.n_params)) -
+               F.hf_energy_closed_form(2 * n_orb, 2 * n_pairs, h0, h, g)) < 1e-12
+    assert np.abs(prob.grad_shift(theta) - fprob.grad_fd(theta, h=1e-5)).max() < 1e-8
+
+
+def test_puccd_counts_ch3f():
+    """11 active orbitals with 7 pairs: 28 parameters, 11 qubits."""
+    assert len(HB.puccd_excitations(11, 7)) == 28
+    assert HB.Space(11, 7).ndet == 330
+
+
+def test_hcb_ground_state_above_fermion_fci():
+    """The pair space is a subspace of the sector: its lowest energy is an
+    upper bound to the sector FCI; the pUCCD optimum lies above both."""
+    import scipy.optimize
+    n_orb, n_pairs = 4, 2
+    h0, h, g = random_integrals(8, 5)
+    prob = HB.Problem(n_orb, n_pairs, h0, h, g)
+    fci = F.Problem(8, 4, h0, h, g).fci()
+    e0 = prob.ground()
+    assert e0 >= fci - 1e-12
+    res = scipy.optimize.minimize(lambda t: (prob.energy(t), prob.grad_shift(t)),
+                                  np.zeros(prob.n_params), jac=True, method="BFGS")
+    assert res.fun >= e0 - 1e-10
+    assert res.fun < prob.energy(np.zeros(prob.n_params))
