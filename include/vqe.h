@@ -122,6 +122,23 @@ void vqe_hamiltonian_free(vqe_hamiltonian* H);
  * ((a, b) outer, (i, j) inner), ascending.  *n_params receives M. */
 int vqe_ansatz_uccsd(int n_qubits, int n_electrons, vqe_ansatz** out, int32_t* n_params);
 
+/* UCCSD with `steps` Trotter steps (the UCCSD depth of Sec. 2.1's ansatz
+ * list): the vqe_ansatz_uccsd product with every angle theta_j / steps,
+ * repeated steps times (1 <= steps <= 64; parameters shared).  Excitations
+ * are reported once per repetition. */
+int vqe_ansatz_uccsd_trotter(int n_qubits, int n_electrons, int steps, vqe_ansatz** out,
+                             int32_t* n_params);
+
+/* k-UpCCGSD (Sec. 2.1, ansatz list) on the HF reference: a layer holds every
+ * generalised single T = a+_q a_p (p < q, equal spin; q outer, p inner,
+ * ascending), reported as (p, q, -1, -1), then every pair double
+ * T = a+_{2q} a+_{2q+1} a_{2p+1} a_{2p} (spatial p < q with both spin
+ * orbitals; q outer, p inner), reported as (2p, 2p+1, 2q, 2q+1);
+ * U_j = exp(theta_j (T_j - T_j^dag)); k layers (1..64) with their own
+ * angles.  n_qubits in [2, 32]. */
+int vqe_ansatz_kupccgsd(int n_qubits, int n_electrons, int k, vqe_ansatz** out,
+                        int32_t* n_params);
+
 /* pUCCD (Sec. 2.1, ansatz list) in the hard-core-boson form on n_orbitals
  * qubits: for occupied pairs i < n_pairs and empty orbitals a >= n_pairs
  * (a outer, i inner, ascending), U = exp(theta (b_a^dag b_i - b_i^dag b_a)),

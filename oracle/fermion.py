@@ -141,6 +141,31 @@ def uccsd_excitations(n_qubits: int, n_electrons: int):
     return singles + doubles
 
 
+def kupccgsd_layer(n_qubits: int):
+    """One k-UpCCGSD layer (Sec. 2.1, ansatz list), in application order
+    (reading): generalised singles (p, q) = a_q^dag a_p for p < q of equal
+    spin (q outer, p inner), then pair doubles (2p, 2p+1, 2q, 2q+1) =
+    a_2q^dag a_2q+1^dag a_2p+1 a_2p for spatial p < q with both spin
+    orbitals (q outer, p inner)."""
+    singles = [(p, q) for q in range(n_qubits) for p in range(q) if p % 2 == q % 2]
+    npair = n_qubits // 2
+    doubles = [(2 * p, 2 * p + 1, 2 * q, 2 * q + 1) for q in range(npair) for p in range(q)]
+    return singles + doubles
+
+
+def kupccgsd_excitations(n_qubits: int, k: int):
+    """k layers, each with its own angles."""
+    return kupccgsd_layer(n_qubits) * k
+
+
+def trotter_expand(excs, theta, steps: int):
+    """UCC with `steps` Trotter steps (reading of the UCCSD depth): the product
+    over excs with angles theta / steps, repeated steps times.  Returns the
+    expanded excitation list and angles."""
+    theta = np.asarray(theta, dtype=np.float64)
+    return list(excs) * steps, np.tile(theta / steps, steps)
+
+
 def excitation_ops(exc):
     """T of an excitation as a ladder-operator string (left to right)."""
     if len(exc) == 2:
@@ -423,3 +448,35 @@ def adapt(n_qubits, n_electrons, h0, h, g, pool=None, grad_tol=1e-3, max_operato
         prob = Problem(n_qubits, n_electrons, h0, h, g, excs=[pool[i] for i in sel])
         theta = prob.vqe(theta0=np.append(theta, 0.0), gtol=gtol, maxiter=maxiter).x
     return sel, theta, np.array(energies), np.array(norms)
+
+
+# --------------------------------------------------------------------------
+# Trotter steps (Sec. 2.1, ansatz list: the depth of UCCSD)
+# --------------------------------------------------------------------------
+
+class TrotterProblem:
+    """UCCSD (or any excitation list) with `steps` Trotter steps and shared
+    angles.  The gradient is the chain rule over the expanded product: each
+    angle appears `steps` times with weight 1/steps, and each appearance's
+    derivative is exact (shift rule of the expanded problem)."""
+
+    def __init__(self, n_qubits, n_electrons, h0, h, g, steps, excs=None):
+        self.base = Problem(n_qubits, n_electrons, h0, h, g, excs=excs)
+        self.steps = int(steps)
+        self.excs = self.base.excs
+        self.expanded = Problem(n_qubits, n_electrons, h0, h, g,
+                                excs=trotter_expand(self.excs, np.zeros(len(self.excs)), steps)[0])
+
+    @property
+    def n_params(self):
+        return len(self.excs)
+
+    def state(self, theta):
+        return self.expanded.state(trotter_expand(self.excs, theta, self.steps)[1])
+
+    def energy(self, theta):
+        return self.expanded.energy(trotter_expand(self.excs, theta, self.steps)[1])
+
+    def grad(self, theta):
+        g = self.expanded.grad_shift(trotter_expand(self.excs, theta, self.steps)[1])
+        return g.reshape(self.steps, -1).sum(axis=0) / self.steps

@@ -152,6 +152,24 @@ class Ansatz:
         return cls(out)
 
     @classmethod
+    def uccsd_trotter(cls, n_qubits: int, n_electrons: int, steps: int):
+        """UCCSD with `steps` Trotter steps (angles theta / steps, shared)."""
+        out = C.c_void_p()
+        m = C.c_int32()
+        _check(lib().vqe_ansatz_uccsd_trotter(int(n_qubits), int(n_electrons), int(steps),
+                                              C.byref(out), C.byref(m)))
+        return cls(out)
+
+    @classmethod
+    def kupccgsd(cls, n_qubits: int, n_electrons: int, k: int):
+        """k-UpCCGSD: k layers of generalised singles and pair doubles."""
+        out = C.c_void_p()
+        m = C.c_int32()
+        _check(lib().vqe_ansatz_kupccgsd(int(n_qubits), int(n_electrons), int(k), C.byref(out),
+                                         C.byref(m)))
+        return cls(out)
+
+    @classmethod
     def puccd(cls, n_orbitals: int, n_pairs: int):
         """pUCCD on the pair space (evaluate with n_electrons = n_pairs)."""
         out = C.c_void_p()

@@ -45,6 +45,8 @@ SIGNATURES = {
     "vqe_hamiltonian_terms": (c_int, [vp, P(c_int64), P(c_uint32), P(c_uint32), P(c_double)]),
     "vqe_hamiltonian_free": (None, [vp]),
     "vqe_ansatz_uccsd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
+    "vqe_ansatz_uccsd_trotter": (c_int, [c_int, c_int, c_int, P(vp), P(c_int32)]),
+    "vqe_ansatz_kupccgsd": (c_int, [c_int, c_int, c_int, P(vp), P(c_int32)]),
     "vqe_ansatz_puccd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
     "vqe_ansatz_from_rotations": (c_int, [c_int, c_int32, c_int64, P(c_uint32), P(c_uint32),
                                           P(c_int32), P(c_double), P(vp)]),

@@ -197,7 +197,7 @@ struct HxChunk {
 // the tile (bits 11-22), parity of the D string's low chain bits (bit 23).
 struct PackedRun {
     int32_t g0, g1;
-    uint32_t khi, free_hi;
+    uint32_t khi, dhi, free_hi;   // high parts of the created and annihilated orbitals; free bits
     int32_t ntiles, L, na, nb;
     int32_t shape, shape_adj;   // launch shapes of the forward and reverse passes
     int32_t max_entries;

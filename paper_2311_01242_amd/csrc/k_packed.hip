@@ -10,13 +10,15 @@
 // of their popcounts, and blocks follow each other in increasing h from
 // base[h].  Empty blocks take no space.  The reference is entry 0.
 //
-// With L no smaller than the number of electrons, the annihilated orbitals
-// of every UCCSD excitation lie in the low bits.  A gate then pairs D in
-// block h (created orbitals empty, annihilated ones occupied) with
-// E = D ^ x in block h | khi, khi being the high part of the created
-// orbitals.  Consecutive gates with the same khi form a run, applied tile by
-// tile: a tile is the block pair (h, h | khi) (one block when khi = 0),
-// staged in LDS, all the run's gates applied, written back.
+// L is at least the number of electrons, so the reference lies in block 0.
+// A gate pairs D (annihilated orbitals occupied, created ones empty) with
+// E = D ^ x.  With dhi and khi the high parts of the annihilated and the
+// created orbitals, D lies in a block h that holds dhi and none of khi, and E
+// in block (h & ~dhi) | khi (for UCCSD on the reference dhi = 0: occupied
+// orbitals are low; generalised excitations may annihilate high orbitals).
+// Consecutive gates with the same (dhi, khi) form a run, applied tile by
+// tile: a tile is that block pair (one block when both are 0), staged in
+// LDS, all the run's gates applied, written back.
 #include "device_common.h"
 
 namespace vqe {
@@ -72,8 +74,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const StateDesc& s = sd[blockIdx.y];
     const int o = blockIdx.x;
     const int tid = threadIdx.x;
-    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi);
-    const uint32_t h1 = h0 | run.khi;
+    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi) | run.dhi;
+    const uint32_t h1 = (h0 & ~run.dhi) | run.khi;
     const uint32_t hb0 = h0 << run.L;
     const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
     const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
@@ -84,10 +86,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         return;
     }
     const int c0 = B0.cnt;
-    const int c1 = run.khi ? B1.cnt : 0;
+    const int c1 = (run.khi | run.dhi) ? B1.cnt : 0;
     const int nE = c0 + c1;
-    const int eoff = run.khi ? c0 : 0;   // E entries: block h | khi, or block h itself
-    const int cBE = B1.cB;
     const int64_t g0 = base[h0], g1 = base[h1];
     double2* shp = sh;
     double2* shl = sh + nE;
@@ -216,8 +216,8 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ng = run.g1 - run.g0;
-    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi);
-    const uint32_t h1 = h0 | run.khi;
+    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi) | run.dhi;
+    const uint32_t h1 = (h0 & ~run.dhi) | run.khi;
     const uint32_t hb0 = h0 << run.L;
     const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
     const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
         return;
     }
     const int c0 = B0.cnt;
-    const int c1 = run.khi ? B1.cnt : 0;
+    const int c1 = (run.khi | run.dhi) ? B1.cnt : 0;
     const int nE = c0 + c1;
     const int64_t g0 = base[h0], g1 = base[h1];
     double2* shp = sh;

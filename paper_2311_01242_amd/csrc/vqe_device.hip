@@ -915,16 +915,14 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
 // reference of ne electrons is entry 0 (block 0), or -1.
 static int packed_min_L(const vqe_ansatz* A, int ne) {
     if (A->n > 31) return -1;   // the packed H-apply relies on bit 31 of a string being 0
-    int need = std::max(1, ne);
     for (const GateDesc& g : A->gates) {
         if (g.type != kExcitation || g.pd == 0) return -1;
         const uint32_t key = g.x & ~g.pd;
         if (__builtin_popcount(g.pd & 0x55555555u) != __builtin_popcount(key & 0x55555555u) ||
             __builtin_popcount(g.pd & 0xAAAAAAAAu) != __builtin_popcount(key & 0xAAAAAAAAu))
             return -1;
-        need = std::max(need, 32 - __builtin_clz(g.pd));
     }
-    return need;
+    return std::max(1, ne);   // the reference in block 0
 }
 
 static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& lay,
@@ -951,16 +949,17 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     int64_t j = 0;
     while (j < M) {
         const GateDesc& g = A->gates[j];
-        const uint32_t khi = (g.x & ~g.pd) >> L;
+        const uint32_t khi = (g.x & ~g.pd) >> L, dhi = g.pd >> L;
         int64_t j2 = j + 1;
         while (j2 < M && j2 - j < kMaxRunGates &&
-               ((A->gates[j2].x & ~A->gates[j2].pd) >> L) == khi)
+               ((A->gates[j2].x & ~A->gates[j2].pd) >> L) == khi && (A->gates[j2].pd >> L) == dhi)
             ++j2;
         PackedRun r{};
         r.g0 = int32_t(j);
         r.g1 = int32_t(j2);
         r.khi = khi;
-        r.free_hi = hmask & ~khi;
+        r.dhi = dhi;
+        r.free_hi = hmask & ~(khi | dhi);
         r.ntiles = int32_t(1u << __builtin_popcount(r.free_hi));
         r.L = L;
         r.na = lay.na;
@@ -969,15 +968,16 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         int64_t moved = 0;
         std::vector<char> used(size_t(ncls), 0);   // first-block classes of live tiles
         for (int32_t o = 0; o < r.ntiles; ++o) {
-            uint32_t h0 = 0, bits = r.free_hi, v = uint32_t(o);
+            uint32_t h0 = dhi, bits = r.free_hi, v = uint32_t(o);
             while (bits) {
                 const uint32_t low = bits & (~bits + 1u);
                 if (v & 1u) h0 |= low;
                 v >>= 1;
                 bits &= bits - 1;
             }
-            const int c0 = lay.bsize[h0], c1 = khi ? lay.bsize[h0 | khi] : 0;
-            if (c0 == 0 || (khi && c1 == 0)) continue;
+            const bool two = (khi | dhi) != 0;   // D and E in different blocks
+            const int c0 = lay.bsize[h0], c1 = two ? lay.bsize[(h0 & ~dhi) | khi] : 0;
+            if (c0 == 0 || (two && c1 == 0)) continue;
             maxb = std::max(maxb, std::max(c0, c1));
             maxe = std::max(maxe, c0 + c1);
             moved += c0 + c1;
@@ -988,20 +988,22 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         }
         r.ncls = ncls;
         info0.push_back(info.size());
-        const uint32_t khb = khi << L;
-        const int dA = __builtin_popcount(khb & 0x55555555u), dB = __builtin_popcount(khb & 0xAAAAAAAAu);
+        // beta electrons the high parts move from block h to block h ^ x_hi
+        // (the alpha ranks come from the per-popcount table)
+        const uint32_t khb = khi << L, dhb = dhi << L;
+        const int dB = __builtin_popcount(khb & 0xAAAAAAAAu) - __builtin_popcount(dhb & 0xAAAAAAAAu);
         for (int64_t k = j; k < j2; ++k) {
             const GateDesc& h = A->gates[k];
-            const uint32_t pd = h.pd, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
+            const uint32_t pd = h.pd & lowmask, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
             for (int cls = 0; cls < ncls; ++cls) {
                 int2 rec = make_int2(int(ent.size()), 0);
                 if (used[size_t(cls)]) {
                     const int kA0 = cls / (T.Lb + 1), kB0 = cls % (T.Lb + 1);
-                    const int kA1 = kA0 - dA, kB1 = kB0 - dB;
+                    const int kB1 = kB0 - dB;
                     const int cB0 = T.offB[kB0 + 1] - T.offB[kB0];
                     const int c0 = (T.offA[kA0 + 1] - T.offA[kA0]) * cB0;
                     const int cB1 = T.offB[kB1 + 1] - T.offB[kB1];
-                    const int eoff = khi ? c0 : 0;
+                    const int eoff = (khi | dhi) ? c0 : 0;
                     for (int e = 0; e < c0; ++e) {   // D entries of the first block, rank order
                         const uint32_t rd = uint32_t(T.unA[T.offA[kA0] + e / cB0] | T.unB[T.offB[kB0] + e % cB0]);
                         if ((rd & (pd | klo)) != pd) continue;

@@ -418,6 +418,71 @@ extern "C" int vqe_ansatz_uccsd(int n, int ne, vqe_ansatz** out, int32_t* n_para
 // exp(theta (b_a^dag b_i - b_i^dag b_a)), a Givens rotation of (D, D ^ x)
 // for D with bit i set and bit a clear, T|D> = +|E> (no parity string:
 // pairs are bosons).
+// UCCSD with `steps` Trotter steps (Sec. 2.1, ansatz list: the depth of
+// UCCSD): the UCCSD product with angles theta_j / steps, repeated steps
+// times; the parameters are shared by the repetitions.
+extern "C" int vqe_ansatz_uccsd_trotter(int n, int ne, int steps, vqe_ansatz** out,
+                                        int32_t* n_params) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (steps < 1 || steps > 64) return fail(VQE_ERANGE, "steps must be in [1, 64]");
+    vqe_ansatz* base = nullptr;
+    if (int rc = vqe_ansatz_uccsd(n, ne, &base, n_params)) return rc;
+    const std::vector<GateDesc> one = base->gates;
+    const std::vector<int32_t> exc = base->exc;
+    base->gates.clear();
+    base->exc.clear();
+    for (int s = 0; s < steps; ++s) {
+        for (GateDesc g : one) {
+            g.scale = 1.0 / steps;
+            base->gates.push_back(g);
+        }
+        base->exc.insert(base->exc.end(), exc.begin(), exc.end());
+    }
+    *out = base;
+    return VQE_OK;
+}
+
+// k-UpCCGSD (Sec. 2.1, ansatz list): each layer holds every generalised
+// single T = a+_q a_p (p < q, equal spin; q outer, p inner, ascending) and
+// every pair double T = a+_{2q} a+_{2q+1} a_{2p+1} a_{2p} (spatial p < q,
+// both spin orbitals present; q outer, p inner), U_j = exp(theta_j (T_j -
+// T_j^dag)); k layers with their own angles, applied in order.
+extern "C" int vqe_ansatz_kupccgsd(int n, int ne, int k, vqe_ansatz** out, int32_t* n_params) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 2 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [2, 32]");
+    if (ne < 0 || ne > n) return fail(VQE_ERANGE, "n_electrons must be in [0, n_qubits]");
+    if (k < 1 || k > 64) return fail(VQE_ERANGE, "k must be in [1, 64]");
+    auto* A = new (std::nothrow) vqe_ansatz();
+    if (!A) return fail(VQE_ENOMEM, "host allocation failed");
+    A->n = n;
+    A->n_electrons = ne;
+    A->sector_conserving = true;
+    const int npair = n / 2;   // spatial orbitals with both spin orbitals
+    int32_t prm = 0;
+    for (int layer = 0; layer < k; ++layer) {
+        for (int q = 0; q < n; ++q)
+            for (int p = 0; p < q; ++p) {
+                if ((p & 1) != (q & 1)) continue;
+                const int ops[2][2] = {{q, +1}, {p, -1}};
+                A->gates.push_back(excitation_gate(ops, 2, 1u << p, (1u << p) | (1u << q), prm++));
+                A->exc.insert(A->exc.end(), {p, q, -1, -1});
+            }
+        for (int q = 0; q < npair; ++q)
+            for (int p = 0; p < q; ++p) {
+                const int ops[4][2] = {{2 * q, +1}, {2 * q + 1, +1}, {2 * p + 1, -1}, {2 * p, -1}};
+                const uint32_t occ = 3u << (2 * p);
+                A->gates.push_back(excitation_gate(ops, 4, occ, occ | (3u << (2 * q)), prm++));
+                A->exc.insert(A->exc.end(), {2 * p, 2 * p + 1, 2 * q, 2 * q + 1});
+            }
+    }
+    A->n_params = prm;
+    if (n_params) *n_params = prm;
+    *out = A;
+    return VQE_OK;
+}
+
 extern "C" int vqe_ansatz_puccd(int n, int n_pairs, vqe_ansatz** out, int32_t* n_params) {
     if (!out) return fail(VQE_EINVAL, "null output pointer");
     *out = nullptr;

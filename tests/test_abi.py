@@ -216,3 +216,22 @@ def test_puccd_program_matches_oracle():
         A = vq.Ansatz.puccd(n_orb, n_pairs)
         assert A.excitations() == HB.puccd_excitations(n_orb, n_pairs)
         assert A.info() == (n_orb, n_pairs * (n_orb - n_pairs), n_pairs * (n_orb - n_pairs), n_pairs)
+
+
+@pytest.mark.parametrize("n,ne,k", [(4, 2, 1), (7, 3, 2), (12, 6, 1), (20, 10, 2)])
+def test_kupccgsd_program_matches_oracle(n, ne, k):
+    A = vq.Ansatz.kupccgsd(n, ne, k)
+    ref = F.kupccgsd_excitations(n, k)
+    assert A.excitations() == ref
+    assert A.info() == (n, len(ref), len(ref), ne)
+
+
+def test_trotter_program_repeats_uccsd():
+    A = vq.Ansatz.uccsd_trotter(6, 3, 3)
+    base = F.uccsd_excitations(6, 3)
+    assert A.excitations() == base * 3
+    assert A.info() == (6, len(base), 3 * len(base), 3)
+    with pytest.raises(vq.VQEError):
+        vq.Ansatz.uccsd_trotter(6, 3, 0)
+    with pytest.raises(vq.VQEError):
+        vq.Ansatz.kupccgsd(6, 3, 0)

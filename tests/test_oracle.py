@@ -398,3 +398,81 @@ def test_hcb_ground_state_above_fermion_fci():
                                   np.zeros(prob.n_params), jac=True, method="BFGS")
     assert res.fun >= e0 - 1e-10
     assert res.fun < prob.energy(np.zeros(prob.n_params))
+
+
+# ------------------------------------------- Trotter steps, k-UpCCGSD
+
+def _sector_generator(space, exc):
+    """T - T^dag on the sector, from the brute-force Fock matrices."""
+    G = B.excitation_generator(space.n, exc)
+    return G[np.ix_(space.bits, space.bits)]
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (6, 3)])
+def test_trotter_converges_to_the_unfactorised_exponential(n, ne):
+    """U_steps -> exp(sum_j theta_j (T_j - T_j^dag)) as steps grows (first-order
+    Trotter: error ~ 1/steps); steps = 1 is plain UCCSD."""
+    import scipy.linalg
+    h0, h, g = random_integrals(n, 31)
+    excs = F.uccsd_excitations(n, ne)
+    theta = np.random.default_rng(3).uniform(-0.5, 0.5, len(excs))
+    space = F.Space(n, ne)
+    K = sum(t * _sector_generator(space, e) for t, e in zip(theta, excs))
+    exact = scipy.linalg.expm(K) @ space.hf()
+    errs = []
+    for steps in (1, 2, 8, 64):
+        tp = F.TrotterProblem(n, ne, h0, h, g, steps)
+        errs.append(np.linalg.norm(tp.state(theta) - exact))
+    assert np.linalg.norm(F.TrotterProblem(n, ne, h0, h, g, 1).state(theta) -
+                          F.Problem(n, ne, h0, h, g).state(theta)) < 1e-14
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < errs[0] / 20
+
+
+@pytest.mark.parametrize("n,ne,steps", [(4, 2, 2), (5, 2, 3), (6, 3, 2)])
+def test_trotter_gradient_vs_central_difference(n, ne, steps):
+    h0, h, g = random_integrals(n, 41)
+    tp = F.TrotterProblem(n, ne, h0, h, g, steps)
+    theta = np.random.default_rng(7).uniform(-0.5, 0.5, tp.n_params)
+    fd = []
+    for j in range(tp.n_params):
+        a, b = theta.copy(), theta.copy()
+        a[j] += 1e-5
+        b[j] -= 1e-5
+        fd.append((tp.energy(a) - tp.energy(b)) / 2e-5)
+    assert np.abs(tp.grad(theta) - np.array(fd)).max() < 1e-8
+
+
+def test_kupccgsd_layer_counts_and_generators():
+    """Counts: 2 C(n/2, 2) singles (even n) + C(n/2, 2) pair doubles; every
+    gate equals expm(theta (T - T^dag)) on the sector, including singles that
+    annihilate empty orbitals of the reference and pair moves between
+    virtual orbitals."""
+    import scipy.linalg
+    assert len(F.kupccgsd_layer(4)) == 2 + 1
+    assert len(F.kupccgsd_layer(8)) == 2 * 6 + 6
+    assert len(F.kupccgsd_layer(7)) == 6 + 3 + 3   # 4 alpha, 3 beta orbitals; 3 pairs
+    n, ne = 6, 2
+    space = F.Space(n, ne)
+    psi = np.random.default_rng(1).normal(size=space.ndet) + 0j
+    psi /= np.linalg.norm(psi)
+    for exc in F.kupccgsd_layer(n):
+        ref = scipy.linalg.expm(0.37 * _sector_generator(space, exc)) @ psi
+        assert np.abs(F.apply_excitation(space, psi, exc, 0.37) - ref).max() < 1e-12
+
+
+def test_kupccgsd_vqe_bounds():
+    """E(0) = E_HF; a 2-layer optimum lies between FCI and E_HF and below the
+    1-layer optimum (the 2-layer ansatz contains the 1-layer one)."""
+    n, ne = 4, 2
+    h0, h, g = random_integrals(n, 9)
+    fci = F.Problem(n, ne, h0, h, g).fci()
+    res = []
+    for k in (1, 2):
+        prob = F.Problem(n, ne, h0, h, g, excs=F.kupccgsd_excitations(n, k))
+        assert abs(prob.energy(np.zeros(prob.n_params)) -
+                   F.hf_energy_closed_form(n, ne, h0, h, g)) < 1e-12
+        th0 = np.random.default_rng(2).uniform(-0.1, 0.1, prob.n_params)
+        res.append(prob.vqe(theta0=th0, gtol=1e-9).fun)
+    assert res[1] >= fci - 1e-10
+    assert res[1] <= res[0] + 1e-9
