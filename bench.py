@@ -48,6 +48,11 @@ def _parse():
                     help="adapt20: operators the ADAPT loop may add before the timed steps")
     ap.add_argument("--profile-reps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--mapping", default="jw", choices=["jw", "bk"],
+                    help="scan12: fermion-to-qubit mapping")
+    ap.add_argument("--ansatz", default="uccsd", choices=list(ANSATZE),
+                    help="batch512: the ansatz of every state (UCCSD, UCCSD with 2 Trotter "
+                         "steps, or k-UpCCGSD with k = 2)")
     ap.add_argument("--profile-only", action="store_true",
                     help="batch512: only the eager HIP-event phase profile (for rocprof runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -55,32 +60,59 @@ def _parse():
     return ap.parse_args()
 
 
-def build_batch(n_states):
+# ansatz families of the batched workload
+ANSATZE = {
+    "uccsd": lambda vq, n, ne: vq.Ansatz.uccsd(n, ne),
+    "uccsd-trotter2": lambda vq, n, ne: vq.Ansatz.uccsd_trotter(n, ne, 2),
+    "kupccgsd2": lambda vq, n, ne: vq.Ansatz.kupccgsd(n, ne, 2),
+}
+
+
+BATCH_NAMES = {"uccsd": "UCCSD", "uccsd-trotter2": "UCCSD (2 Trotter steps)",
+               "kupccgsd2": "k-UpCCGSD (k=2)"}
+
+
+def oracle_problem(ansatz, n, ne, h0, h, g):
+    """The oracle problem of one batch state and the energies one energy +
+    gradient evaluation costs it (four-term shift rule per gate)."""
+    from oracle import fermion as F
+    if ansatz == "kupccgsd2":
+        prob = F.Problem(n, ne, h0, h, g, excs=F.kupccgsd_excitations(n, 2))
+        return prob, 1 + 4 * prob.n_params
+    if ansatz == "uccsd-trotter2":
+        tp = F.TrotterProblem(n, ne, h0, h, g, 2)
+        return tp, 1 + 4 * 2 * tp.n_params
+    prob = F.Problem(n, ne, h0, h, g)
+    return prob, 1 + 4 * prob.n_params
+
+
+def build_batch(n_states, ansatz="uccsd"):
     import paper_2311_01242_amd as vq
     from vqe_inputs import batch_spec, random_integrals, uniform_theta
     spec = batch_spec(n_states)
     ans = {}
+    make = ANSATZE[ansatz]
     Hs, As, nes, thetas = [], [], [], []
     for i, (n, ne, seed) in enumerate(spec):
         h0, h, g = random_integrals(n, seed)
         Hs.append(vq.Hamiltonian.from_integrals(n, h0, h, g))
         if n not in ans:
-            ans[n] = vq.Ansatz.uccsd(n, ne)
+            ans[n] = make(vq, n, ne)
         As.append(ans[n])
         nes.append(ne)
         thetas.append(uniform_theta(40000 + i, ans[n].n_params))
     return spec, Hs, As, nes, np.concatenate(thetas)
 
 
-def cpu_baseline_batch(spec, budget_s=20.0):
+def cpu_baseline_batch(spec, budget_s=20.0, ansatz="uccsd"):
     """Oracle (CPU) energy + shift-rule gradient throughput on the batch.
 
     The oracle's gradient is the four-term shift rule: 4 M energies per
-    gradient, so one energy + gradient evaluation costs (1 + 4M) oracle
+    gradient (M gates of the product, Trotter repetitions included), so one
+    energy + gradient evaluation costs (1 + 4M) oracle
     energies.  Sample: one energy of the first state of each qubit count,
     timed; the batch time is the sum over all 512 states of (1 + 4M_n) times
     the measured energy time for its n."""
-    from oracle import fermion as F
     from vqe_inputs import random_integrals, uniform_theta
     seen = {}
     t_all = time.perf_counter()
@@ -88,7 +120,7 @@ def cpu_baseline_batch(spec, budget_s=20.0):
         if n in seen:
             continue
         h0, h, g = random_integrals(n, seed)
-        prob = F.Problem(n, ne, h0, h, g)
+        prob, cost = oracle_problem(ansatz, n, ne, h0, h, g)
         th = uniform_theta(1, prob.n_params)
         prob.energy(th)                       # builds the operator caches (not timed)
         t0 = time.perf_counter()
@@ -98,13 +130,13 @@ def cpu_baseline_batch(spec, budget_s=20.0):
             reps += 1
             if time.perf_counter() - t0 > 0.5 or reps >= 20:
                 break
-        seen[n] = ((time.perf_counter() - t0) / reps, prob.n_params)
+        seen[n] = ((time.perf_counter() - t0) / reps, cost)
         if time.perf_counter() - t_all > budget_s:
             break
     total = 0.0
     for n, _, _ in spec:
-        te, m = seen.get(n, seen[max(seen)])
-        total += te * (1 + 4 * m)
+        te, cost = seen.get(n, seen[max(seen)])
+        total += te * cost
     try:
         from threadpoolctl import threadpool_info
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
@@ -212,13 +244,14 @@ def run_batch(args):
     import torch
     import paper_2311_01242_amd as vq
     from paper_2311_01242_amd import autotune
-    spec, Hs, As, nes, theta = build_batch(args.states)
+    spec, Hs, As, nes, theta = build_batch(args.states, args.ansatz)
     if not args.no_autotune:
         offs = np.cumsum([0] + [a.n_params for a in As])
         t0 = time.perf_counter()
         tuned = autotune.autotune_batch(
             Hs, As, nes, theta, offs, cache=TUNE_CACHE,
-            log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+            log=lambda m: print("# " + m, file=sys.stderr, flush=True),
+            tag="" if args.ansatz == "uccsd" else args.ansatz)
         print(f"# autotune {time.perf_counter() - t0:.1f}s: "
               + " ".join(f"n{n}=" + ",".join(str(v) for v in vals) for n, vals in sorted(tuned.items())),
               file=sys.stderr, flush=True)
@@ -246,14 +279,14 @@ def run_batch(args):
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "complex128", "data": "synthetic",
-        "config": {"workload": f"batched UCCSD energy+adjoint gradient, {args.states} states, "
+        "config": {"workload": f"batched {BATCH_NAMES[args.ansatz]} energy+adjoint gradient, {args.states} states, "
                                "n~U{12..20}, n_e=n/2, seeded integrals, one HIP-graph launch",
                    "states": args.states, "qubits": "12-20", "global_batch": args.states,
                    "parallelism": "single GPU"},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batch(spec)
+        out["cpu_baseline"] = cpu_baseline_batch(spec, ansatz=args.ansatz)
     return out
 
 
@@ -365,8 +398,8 @@ def run_scan12(args):
     import paper_2311_01242_amd as vq
     from vqe_inputs import SCAN12_LAMBDAS, scan_integrals, uniform_theta
     fam = scan_integrals(12, 2)
-    A = vq.Ansatz.uccsd(12, 6)
-    Hs = [vq.Hamiltonian.from_integrals(12, *fam(l)) for l in SCAN12_LAMBDAS]
+    A = vq.Ansatz.uccsd_map(12, 6, args.mapping)
+    Hs = [vq.Hamiltonian.from_integrals_map(12, args.mapping, *fam(l)) for l in SCAN12_LAMBDAS]
     b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
     th = np.concatenate([uniform_theta(7, A.n_params)] * len(Hs))
     for _ in range(args.warmup):
@@ -383,7 +416,10 @@ def run_scan12(args):
         "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
-        "config": {"workload": "12-qubit bond-stretch scan, 20 geometries per step"},
+        "config": {"workload": "12-qubit bond-stretch scan, 20 geometries per step, "
+                               + {"jw": "Jordan-Wigner (packed sector kernels)",
+                                  "bk": "Bravyi-Kitaev (full-vector Pauli-rotation kernels)"}[args.mapping],
+                   "mapping": args.mapping},
         "roofline": {"phase_ms": [round(x, 3) for x in phase_ms]},
     }
 

@@ -77,6 +77,21 @@ const char* vqe_last_error(void);
 int vqe_hamiltonian_from_integrals(int n_qubits, double h0, const double* h,
                                    const double* g, vqe_hamiltonian** out);
 
+/* Fermion-to-qubit mappings (Sec. 2.1.1 names Jordan-Wigner and
+ * Bravyi-Kitaev).  Both are linear encodings b = beta n (mod 2) of the
+ * occupation vector n: JW beta = 1; BK qubit j holds the parity of orbitals
+ * j + 1 - lowbit(j + 1) .. j (Fenwick-tree rows). */
+#define VQE_MAP_JW 0
+#define VQE_MAP_BK 1
+
+/* vqe_hamiltonian_from_integrals under `mapping` (VQE_MAP_JW gives the same
+ * terms as vqe_hamiltonian_from_integrals).  With beta as above,
+ * a_P = X^{c_P} Z^{s_P} (1 - Z^{r_P})/2 and a+_P = X^{c_P} Z^{s_P} (1 + Z^{r_P})/2
+ * (c_P column P of beta, r_P row P of beta^{-1}, s_P the XOR of rows P' < P
+ * of beta^{-1}).  ERANGE for an unknown mapping. */
+int vqe_hamiltonian_from_integrals_map(int n_qubits, int mapping, double h0, const double* h,
+                                       const double* g, vqe_hamiltonian** out);
+
 /* Eq. 2 projected onto the seniority-zero space, in the hard-core-boson
  * form used by pUCCD (Sec. 2.1, ansatz list): qubit p is spatial orbital p
  * (n_orbitals qubits, half the Jordan-Wigner count), bit p = 1 when both
@@ -121,6 +136,19 @@ void vqe_hamiltonian_free(vqe_hamiltonian* H);
  * U_M ... U_1 with all singles first (a outer, i inner) and then doubles
  * ((a, b) outer, (i, j) inner), ascending.  *n_params receives M. */
 int vqe_ansatz_uccsd(int n_qubits, int n_electrons, vqe_ansatz** out, int32_t* n_params);
+
+/* UCCSD under `mapping`: VQE_MAP_JW is vqe_ansatz_uccsd; otherwise each
+ * generator T - T^dag is written with the encoded ladder operators as
+ * sum_k i d_k P_k (commuting Hermitian strings) and applied as the Pauli
+ * rotations exp(-i (-2 d_k theta) / 2 P_k), on full 2^n vectors, from the
+ * encoded reference beta (2^n_electrons - 1) (vqe_ansatz_reference).
+ * Excitations are reported as for vqe_ansatz_uccsd. */
+int vqe_ansatz_uccsd_map(int n_qubits, int n_electrons, int mapping, vqe_ansatz** out,
+                         int32_t* n_params);
+
+/* Basis index of the reference the evaluation calls prepare for this ansatz:
+ * 2^n_electrons - 1 unless a mapping moved it.  EINVAL without a reference. */
+int vqe_ansatz_reference(const vqe_ansatz* A, uint64_t* index);
 
 /* UCCSD with `steps` Trotter steps (the UCCSD depth of Sec. 2.1's ansatz
  * list): the vqe_ansatz_uccsd product with every angle theta_j / steps,
@@ -196,6 +224,9 @@ void vqe_state_free(vqe_state* s);
 /* |HF> = the basis state with the lowest n_electrons spin orbitals occupied
  * (index 2^n_e - 1), the reference |0> of Eq. 1. */
 int vqe_prepare_hf(vqe_state* s, int n_electrons);
+
+/* |index>, a computational basis state (ERANGE beyond 2^n_qubits). */
+int vqe_prepare_basis(vqe_state* s, uint64_t index);
 
 /* psi <- exp(-i theta/2 P(x, z)) psi for a Hermitian Pauli string. */
 int vqe_apply_pauli_rotation(vqe_state* s, uint32_t x, uint32_t z, double theta);

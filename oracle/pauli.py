@@ -66,21 +66,73 @@ def sum_product(A, B, n):
     return out
 
 
-def ladder(n, P, dagger):
-    """a_P^dag = Z_0..Z_{P-1} (X_P - iY_P)/2, a_P = Z_0..Z_{P-1} (X_P + iY_P)/2."""
+def ladder(n, P, dagger, mapping="jw"):
+    """Jordan-Wigner: a_P^dag = Z_0..Z_{P-1} (X_P - iY_P)/2,
+    a_P = Z_0..Z_{P-1} (X_P + iY_P)/2.  Bravyi-Kitaev: see bk_ladder."""
+    if mapping == "bk":
+        return bk_ladder(n, P, dagger)
     chain = (1 << P) - 1
     s = -1j if dagger else 1j
     return {(1 << P, chain): 0.5, ((1 << P), chain | (1 << P)): 0.5 * s}
+
+
+# --- Bravyi-Kitaev (Sec. 2.1.1 names the mapping) --------------------------
+# Qubit j stores the parity of the orbitals of its Fenwick-tree node,
+# j & (j + 1) .. j.  With the published sets of the transformation (update
+# set U: nodes above j that also store n_j; parity set P: nodes whose
+# parities add up to n_0 + .. + n_{j-1}; flip set F: the nodes below j inside
+# j's own range, so that n_j = b_j + sum_F b; remainder R = P minus F):
+#   a_j^dag = 1/2 X_U (X_j Z_P - i Y_j Z_R),  a_j = 1/2 X_U (X_j Z_P + i Y_j Z_R).
+
+def bk_sets(n, j):
+    """(U, P, F, R) of orbital j as bit masks."""
+    U = 0
+    k = j | (j + 1)
+    while k < n:
+        U |= 1 << k
+        k = k | (k + 1)
+    P = 0
+    k = j - 1
+    while k >= 0:
+        P |= 1 << k
+        k = (k & (k + 1)) - 1
+    F = 0
+    lo = j & (j + 1)
+    k = j - 1
+    while k >= lo:
+        F |= 1 << k
+        k = (k & (k + 1)) - 1
+    return U, P, F, P & ~F
+
+
+def bk_encode(n, occ):
+    """Qubit register of the occupation bits occ."""
+    b = 0
+    for j in range(n):
+        par = 0
+        for k in range(j & (j + 1), j + 1):
+            par ^= (occ >> k) & 1
+        b |= par << j
+    return b
+
+
+def bk_ladder(n, j, dagger):
+    U, P, _, R = bk_sets(n, j)
+    e = 1 << j
+    s = -1j if dagger else 1j
+    # X on U and j with Z on P; X on U, Y on j (x = z = 1 there), Z on R
+    return {(U | e, P): 0.5, (U | e, R | e): 0.5 * s}
 
 
 def _clean(S, tol=1e-12):
     return {k: v for k, v in S.items() if abs(v) > tol}
 
 
-def jw_hamiltonian(n, h0, h, g, tol=1e-12):
-    """Qubit form of Eq. 2 (chemist integrals, factor 1/2; see fermion.py)."""
-    cr = [ladder(n, P, True) for P in range(n)]
-    an = [ladder(n, P, False) for P in range(n)]
+def jw_hamiltonian(n, h0, h, g, tol=1e-12, mapping="jw"):
+    """Qubit form of Eq. 2 (chemist integrals, factor 1/2; see fermion.py)
+    under the Jordan-Wigner (default) or Bravyi-Kitaev mapping."""
+    cr = [ladder(n, P, True, mapping) for P in range(n)]
+    an = [ladder(n, P, False, mapping) for P in range(n)]
     H = defaultdict(complex)
     H[(0, 0)] += h0
     sp = lambda P: P // 2
@@ -154,10 +206,10 @@ def matrix(S, n):
     return m
 
 
-def excitation_generator(n, exc):
+def excitation_generator(n, exc, mapping="jw"):
     """T - T^dag as a Pauli sum (T = a_a^dag a_i or a_a^dag a_b^dag a_j a_i)."""
-    cr = lambda P: ladder(n, P, True)
-    an = lambda P: ladder(n, P, False)
+    cr = lambda P: ladder(n, P, True, mapping)
+    an = lambda P: ladder(n, P, False, mapping)
     if len(exc) == 2:
         i, a = exc
         T = sum_product(cr(a), an(i), n)
@@ -174,12 +226,12 @@ def excitation_generator(n, exc):
     return _clean(G)
 
 
-def excitation_rotations(n, exc):
+def excitation_rotations(n, exc, mapping="jw"):
     """T - T^dag = i sum_k b_k P_k (b_k real, commuting P_k), hence
     exp(theta (T - T^dag)) = prod_k exp(-i (phi_k / 2) P_k) with phi_k = -2 b_k theta.
     Returns [(x, z, scale_k)] with phi_k = scale_k * theta."""
     out = []
-    for (x, z), c in sorted(excitation_generator(n, exc).items()):
+    for (x, z), c in sorted(excitation_generator(n, exc, mapping).items()):
         if abs(c.real) > 1e-14:
             raise AssertionError("generator coefficient not imaginary")
         out.append((x, z, -2.0 * c.imag))
@@ -191,11 +243,12 @@ def apply_rotation(psi, n, key, phi):
     return math.cos(phi / 2) * psi - 1j * math.sin(phi / 2) * apply_string(key, psi, n)
 
 
-def prepare(n, n_electrons, excs, theta):
+def prepare(n, n_electrons, excs, theta, mapping="jw"):
     psi = np.zeros(1 << n, dtype=np.complex128)
-    psi[(1 << n_electrons) - 1] = 1.0
+    ref = (1 << n_electrons) - 1
+    psi[bk_encode(n, ref) if mapping == "bk" else ref] = 1.0
     for exc, t in zip(excs, theta):
-        for x, z, sc in excitation_rotations(n, exc):
+        for x, z, sc in excitation_rotations(n, exc, mapping):
             psi = apply_rotation(psi, n, (x, z), sc * float(t))
     return psi
 

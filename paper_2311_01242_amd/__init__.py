@@ -49,6 +49,9 @@ def set_packed(mode=True):
     _check(lib().vqe_set_packed(m))
 
 
+_MAPS = {"jw": 0, "bk": 1}
+
+
 class VQEError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"[{code}] {msg}")
@@ -92,6 +95,16 @@ class Hamiltonian:
         out = C.c_void_p()
         _check(lib().vqe_hamiltonian_from_integrals(int(n_qubits), float(h0), _dptr(h), _dptr(g),
                                                     C.byref(out)))
+        return cls(out)
+
+    @classmethod
+    def from_integrals_map(cls, n_qubits: int, mapping: str, h0: float, h, g):
+        """Qubit Hamiltonian of Eq. 2 under mapping "jw" or "bk"."""
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        out = C.c_void_p()
+        _check(lib().vqe_hamiltonian_from_integrals_map(int(n_qubits), _MAPS[mapping], float(h0),
+                                                        _dptr(h), _dptr(g), C.byref(out)))
         return cls(out)
 
     @classmethod
@@ -150,6 +163,20 @@ class Ansatz:
         m = C.c_int32()
         _check(lib().vqe_ansatz_uccsd(int(n_qubits), int(n_electrons), C.byref(out), C.byref(m)))
         return cls(out)
+
+    @classmethod
+    def uccsd_map(cls, n_qubits: int, n_electrons: int, mapping: str):
+        """UCCSD under mapping "jw" (excitation gates) or "bk" (Pauli rotations)."""
+        out = C.c_void_p()
+        m = C.c_int32()
+        _check(lib().vqe_ansatz_uccsd_map(int(n_qubits), int(n_electrons), _MAPS[mapping],
+                                          C.byref(out), C.byref(m)))
+        return cls(out)
+
+    def reference(self) -> int:
+        v = C.c_uint64()
+        _check(lib().vqe_ansatz_reference(self._h, C.byref(v)))
+        return v.value
 
     @classmethod
     def uccsd_trotter(cls, n_qubits: int, n_electrons: int, steps: int):
@@ -263,6 +290,9 @@ class State:
 
     def prepare_hf(self, n_electrons: int):
         _check(lib().vqe_prepare_hf(self._h, int(n_electrons)))
+
+    def prepare_basis(self, index: int):
+        _check(lib().vqe_prepare_basis(self._h, C.c_uint64(int(index))))
 
     def apply_pauli_rotation(self, x: int, z: int, theta: float):
         _check(lib().vqe_apply_pauli_rotation(self._h, int(x), int(z), float(theta)))

@@ -39,12 +39,16 @@ SIGNATURES = {
     "vqe_last_error": (C.c_char_p, []),
     "vqe_hamiltonian_from_integrals": (c_int, [c_int, c_double, P(c_double), P(c_double), P(vp)]),
     "vqe_hamiltonian_from_paulis": (c_int, [c_int, c_int64, P(c_uint32), P(c_uint32), P(c_double), P(vp)]),
+    "vqe_hamiltonian_from_integrals_map": (c_int, [c_int, c_int, c_double, P(c_double),
+                                                   P(c_double), P(vp)]),
     "vqe_hamiltonian_pairs_from_integrals": (c_int, [c_int, c_double, P(c_double), P(c_double),
                                                      P(vp)]),
     "vqe_hamiltonian_info": (c_int, [vp, P(c_int), P(c_int64), P(c_int64)]),
     "vqe_hamiltonian_terms": (c_int, [vp, P(c_int64), P(c_uint32), P(c_uint32), P(c_double)]),
     "vqe_hamiltonian_free": (None, [vp]),
     "vqe_ansatz_uccsd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
+    "vqe_ansatz_uccsd_map": (c_int, [c_int, c_int, c_int, P(vp), P(c_int32)]),
+    "vqe_ansatz_reference": (c_int, [vp, P(C.c_uint64)]),
     "vqe_ansatz_uccsd_trotter": (c_int, [c_int, c_int, c_int, P(vp), P(c_int32)]),
     "vqe_ansatz_kupccgsd": (c_int, [c_int, c_int, c_int, P(vp), P(c_int32)]),
     "vqe_ansatz_puccd": (c_int, [c_int, c_int, P(vp), P(c_int32)]),
@@ -59,6 +63,7 @@ SIGNATURES = {
     "vqe_state_data": (c_int, [vp, P(vp)]),
     "vqe_state_free": (None, [vp]),
     "vqe_prepare_hf": (c_int, [vp, c_int]),
+    "vqe_prepare_basis": (c_int, [vp, C.c_uint64]),
     "vqe_apply_pauli_rotation": (c_int, [vp, c_uint32, c_uint32, c_double]),
     "vqe_apply_ansatz": (c_int, [vp, vp, P(c_double)]),
     "vqe_expectation": (c_int, [vp, vp, P(c_double)]),

@@ -108,8 +108,9 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None, packed=True):
 
 
 def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, max_per_class=64,
-                   log=None, packed=True):
+                   log=None, packed=True, tag=""):
     """Tune every size class of a batch and install the results (set_tuning).
+    `tag` names the ansatz family in the cache key (empty for UCCSD).
     Returns {n: (fwd, adj, L)}."""
     cache_data = {}
     if cache and os.path.exists(cache):
@@ -123,6 +124,8 @@ def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, 
     out = {}
     for (n, ne), idx in sorted(classes.items()):
         key = f"{dev}|{'packed' if packed else 'full'}|n={n}|ne={ne}|states={len(idx)}"
+        if tag:
+            key += f"|{tag}"
         if key in cache_data:
             vals = tuple(cache_data[key])
             set_tuning(n, True, *vals[:3])

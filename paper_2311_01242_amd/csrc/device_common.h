@@ -44,6 +44,7 @@ struct StateDesc {
     const double* ci_ptabs;              // tables of the pair classes (global offsets)
     double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
+    uint32_t ref;            // basis index of the reference (full-vector layout)
     int32_t nb;              // number of H-apply chunks
     int32_t gstride;         // stride of part_g between gates
     int32_t ci_nchunks;

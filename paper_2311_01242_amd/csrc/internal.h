@@ -88,6 +88,7 @@ struct DevAnsatz;
 struct vqe_ansatz {
     int n = 0;
     int n_electrons = -1;             // UCCSD reference, -1 for rotation lists
+    int64_t ref_bits = -1;            // reference basis index; -1: the lowest n_electrons qubits
     int32_t n_params = 0;
     bool sector_conserving = false;   // every gate conserves N and S_z
     std::vector<vqe::GateDesc> gates;

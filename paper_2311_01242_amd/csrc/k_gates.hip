@@ -38,7 +38,7 @@ __global__ void k_angles(const StateDesc* __restrict__ sd) {
 
 __global__ void k_hf(const StateDesc* __restrict__ sd, uint64_t N) {
     const StateDesc& s = sd[blockIdx.y];
-    const uint64_t hf = (uint64_t(1) << s.ne) - 1;
+    const uint64_t hf = s.ref;
     for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < N;
          b += uint64_t(gridDim.x) * blockDim.x)
         nt_store(&s.phi[b], make_double2(b == hf ? 1.0 : 0.0, 0.0));

@@ -1339,6 +1339,12 @@ static void accumulate_grad(const vqe_ansatz* A, const double* raw, double* grad
     }
 }
 
+// Basis index of the reference state: the ansatz's own (a mapping other than
+// Jordan-Wigner moves it), else the lowest ne qubits.
+static uint32_t reference_index(const vqe_ansatz* A, int ne) {
+    return A->ref_bits >= 0 ? uint32_t(A->ref_bits) : uint32_t((uint64_t(1) << ne) - 1);
+}
+
 static int check_pair(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne) {
     if (!H || !A) return fail(VQE_EINVAL, "null Hamiltonian or ansatz");
     if (H->n != A->n) return fail(VQE_EINVAL, "Hamiltonian and ansatz qubit counts differ");
@@ -1511,6 +1517,20 @@ extern "C" int vqe_prepare_hf(vqe_state* s, int ne) {
     StateCall c;
     if (int rc = begin_state_call(s, 0, 0, 1, &c)) return rc;
     c.sd.ne = ne;
+    c.sd.ref = uint32_t((uint64_t(1) << ne) - 1);
+    HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
+    launch_hf(c.sd_dev, 1, uint64_t(1) << s->n, s->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->st));
+    return VQE_OK;
+}
+
+extern "C" int vqe_prepare_basis(vqe_state* s, uint64_t index) {
+    if (!s) return fail(VQE_EINVAL, "null state");
+    if (index >> s->n) return fail(VQE_ERANGE, "basis index beyond 2^n_qubits");
+    StateCall c;
+    if (int rc = begin_state_call(s, 0, 0, 1, &c)) return rc;
+    c.sd.ref = uint32_t(index);
     HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
     launch_hf(c.sd_dev, 1, uint64_t(1) << s->n, s->st);
     HIPCHK(hipGetLastError());
@@ -1688,6 +1708,7 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
     sd.G = int32_t(H->groups.size());
     sd.M = int32_t(M);
     sd.ne = ne;
+    sd.ref = reference_index(A, ne);
     sd.gstride = ep.gstride;
     e->sd_dev = cv.take<StateDesc>(1);
     if (P > 0)
@@ -2112,6 +2133,7 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         sd.G = int32_t(H[i]->groups.size());
         sd.M = int32_t(M);
         sd.ne = ne[i];
+        sd.ref = reference_index(A[i], ne[i]);
         sd.gstride = ep.gstride;
         b->work[0] += ep.fwd_bytes;
         b->work[2] += ep.adj_bytes;

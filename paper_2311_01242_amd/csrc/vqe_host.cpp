@@ -43,10 +43,65 @@ struct XZ {
     double c;
 };
 
-static void ladder(int P, bool dagger, XZ out[2]) {
-    const uint32_t e = 1u << P;
-    out[0] = {e, below(P), 0.5};
-    out[1] = {e, below(P) | e, dagger ? 0.5 : -0.5};
+// Linear encodings of the occupation vector n into the qubit register
+// b = beta n (mod 2): Jordan-Wigner (beta = 1) and Bravyi-Kitaev (qubit j
+// holds the parity of orbitals j + 1 - lowbit(j + 1) .. j, the Fenwick-tree
+// rows; Sec. 2.1.1 names both mappings).  Then
+//   a_P = X^{c_P} Z^{s_P} (1 - Z^{r_P}) / 2,  a+_P = X^{c_P} Z^{s_P} (1 + Z^{r_P}) / 2,
+// with c_P = column P of beta (the qubits that flip with n_P), r_P = row P of
+// beta^{-1} (n_P as a parity of qubits) and s_P = the XOR of rows P' < P of
+// beta^{-1} (the sign parity of the orbitals below P).
+struct Encoding {
+    uint32_t c[32], r[32], s[32];
+};
+
+static bool make_encoding(int n, int mapping, Encoding* e) {
+    uint32_t beta[32], inv[32];
+    for (int j = 0; j < n; ++j) {
+        if (mapping == VQE_MAP_JW) {
+            beta[j] = 1u << j;
+        } else {
+            const int lo = (j + 1) - ((j + 1) & -(j + 1));
+            beta[j] = 0;
+            for (int k = lo; k <= j; ++k) beta[j] |= 1u << k;
+        }
+        inv[j] = 1u << j;
+    }
+    // Gauss-Jordan over GF(2): rows of beta reduced to the identity; the same
+    // row operations turn the identity into beta^{-1}
+    uint32_t m[32];
+    std::copy(beta, beta + n, m);
+    for (int col = 0; col < n; ++col) {
+        int piv = -1;
+        for (int row = col; row < n; ++row)
+            if ((m[row] >> col) & 1u) {
+                piv = row;
+                break;
+            }
+        if (piv < 0) return false;
+        std::swap(m[piv], m[col]);
+        std::swap(inv[piv], inv[col]);
+        for (int row = 0; row < n; ++row)
+            if (row != col && ((m[row] >> col) & 1u)) {
+                m[row] ^= m[col];
+                inv[row] ^= inv[col];
+            }
+    }
+    uint32_t below = 0;
+    for (int P = 0; P < n; ++P) {
+        e->c[P] = 0;
+        for (int j = 0; j < n; ++j)
+            if ((beta[j] >> P) & 1u) e->c[P] |= 1u << j;
+        e->r[P] = inv[P];
+        e->s[P] = below;
+        below ^= inv[P];
+    }
+    return true;
+}
+
+static void ladder_enc(const Encoding& E, int P, bool dagger, XZ out[2]) {
+    out[0] = {E.c[P], E.s[P], 0.5};
+    out[1] = {E.c[P], E.s[P] ^ E.r[P], dagger ? 0.5 : -0.5};
 }
 
 static inline XZ mul(const XZ& a, const XZ& b) {
@@ -209,9 +264,17 @@ static int check_integral_symmetry(int ns, const double* h, const double* g) {
 
 extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h, const double* g,
                                               vqe_hamiltonian** out) {
+    return vqe_hamiltonian_from_integrals_map(n, VQE_MAP_JW, h0, h, g, out);
+}
+
+extern "C" int vqe_hamiltonian_from_integrals_map(int n, int mapping, double h0, const double* h,
+                                                  const double* g, vqe_hamiltonian** out) {
     if (!out || !h || !g) return fail(VQE_EINVAL, "null pointer argument");
     *out = nullptr;
     if (n < 1 || n > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (mapping != VQE_MAP_JW && mapping != VQE_MAP_BK) return fail(VQE_ERANGE, "unknown mapping");
+    Encoding E;
+    if (!make_encoding(n, mapping, &E)) return fail(VQE_EINVAL, "singular encoding");
     if (!std::isfinite(h0)) return fail(VQE_EINVAL, "h0 is not finite");
     const int ns = (n + 1) / 2;
     const int64_t n2 = int64_t(ns) * ns, n4 = n2 * n2;
@@ -226,8 +289,8 @@ extern "C" int vqe_hamiltonian_from_integrals(int n, double h0, const double* h,
     m[key(0, 0)] += h0;
     XZ cr[32][2], an[32][2];
     for (int P = 0; P < n; ++P) {
-        ladder(P, true, cr[P]);
-        ladder(P, false, an[P]);
+        ladder_enc(E, P, true, cr[P]);
+        ladder_enc(E, P, false, an[P]);
     }
     // one-body: sum_PQ h_pq a+_P a_Q over equal spins
     for (int P = 0; P < n; ++P)
@@ -532,6 +595,7 @@ extern "C" int vqe_ansatz_select(const vqe_ansatz* pool, int64_t count, const in
     A->n = pool->n;
     A->n_electrons = pool->n_electrons;
     A->sector_conserving = pool->sector_conserving;
+    A->ref_bits = pool->ref_bits;
     A->n_params = int32_t(count);
     for (int64_t k = 0; k < count; ++k)
         for (size_t j : of[size_t(param_index[k])]) {
@@ -541,6 +605,90 @@ extern "C" int vqe_ansatz_select(const vqe_ansatz* pool, int64_t count, const in
             if (has_exc) A->exc.insert(A->exc.end(), pool->exc.begin() + 4 * j, pool->exc.begin() + 4 * j + 4);
         }
     *out = A;
+    return VQE_OK;
+}
+
+// UCCSD under an encoding other than Jordan-Wigner: each generator
+// T - T^dag, written with the encoded ladder operators, is a sum of
+// commuting anti-Hermitian folded strings c X^x Z^z (odd |x & z|), i.e.
+// i d P with P the Hermitian string of the same masks and
+// d = c (-1)^((|x & z| + 1) / 2); exp(theta (T - T^dag)) is then the product
+// of the rotations exp(-i (-2 d theta) / 2 P).  The reference is beta times
+// the lowest n_electrons occupations.
+extern "C" int vqe_ansatz_uccsd_map(int n, int ne, int mapping, vqe_ansatz** out,
+                                    int32_t* n_params) {
+    if (!out) return fail(VQE_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (mapping == VQE_MAP_JW) return vqe_ansatz_uccsd(n, ne, out, n_params);
+    if (mapping != VQE_MAP_BK) return fail(VQE_ERANGE, "unknown mapping");
+    vqe_ansatz* base = nullptr;
+    if (int rc = vqe_ansatz_uccsd(n, ne, &base, n_params)) return rc;
+    Encoding E;
+    if (!make_encoding(n, mapping, &E)) {
+        vqe_ansatz_free(base);
+        return fail(VQE_EINVAL, "singular encoding");
+    }
+    auto* A = new (std::nothrow) vqe_ansatz();
+    if (!A) {
+        vqe_ansatz_free(base);
+        return fail(VQE_ENOMEM, "host allocation failed");
+    }
+    A->n = n;
+    A->n_electrons = ne;
+    A->n_params = base->n_params;
+    A->sector_conserving = false;   // encoded basis states do not split into alpha/beta bits
+    A->exc = base->exc;
+    uint32_t ref = 0;
+    for (int P = 0; P < ne; ++P) ref ^= E.c[P];
+    A->ref_bits = int64_t(ref);
+    const size_t M = base->exc.size() / 4;
+    for (size_t k = 0; k < M; ++k) {
+        const int32_t* o = &base->exc[4 * k];
+        // T as a product of encoded ladder sums, rightmost operator first
+        std::vector<std::pair<int, bool>> ops;   // (orbital, dagger), left to right
+        if (o[2] < 0)
+            ops = {{o[1], true}, {o[0], false}};
+        else
+            ops = {{o[2], true}, {o[3], true}, {o[1], false}, {o[0], false}};
+        std::vector<XZ> t = {{0u, 0u, 1.0}};
+        for (auto& op : ops) {
+            XZ l[2];
+            ladder_enc(E, op.first, op.second, l);
+            std::vector<XZ> nt;
+            for (auto& a : t)
+                for (auto& b : l) nt.push_back(mul(a, b));
+            t.swap(nt);
+        }
+        TermMap m;
+        for (auto& a : t) m[key(a.x, a.z)] += a.c;
+        std::vector<std::pair<uint64_t, double>> terms(m.begin(), m.end());
+        std::sort(terms.begin(), terms.end());
+        for (auto& kv : terms) {
+            const uint32_t x = uint32_t(kv.first >> 32), z = uint32_t(kv.first);
+            const int y = popc(x & z);
+            if (!(y & 1)) continue;   // Hermitian part: cancels in T - T^dag
+            const double g = 2.0 * kv.second;   // T - T^dag doubles the anti-Hermitian part
+            if (std::fabs(g) <= 1e-14) continue;
+            const double d = (((y + 1) / 2) & 1) ? -g : g;
+            GateDesc gd{};
+            gd.type = kPauli;
+            gd.x = x;
+            gd.chain = z;
+            gd.param = int32_t(k);
+            gd.scale = -2.0 * d;
+            gd.csign = 1.0;
+            A->gates.push_back(gd);
+        }
+    }
+    vqe_ansatz_free(base);
+    *out = A;
+    return VQE_OK;
+}
+
+extern "C" int vqe_ansatz_reference(const vqe_ansatz* A, uint64_t* index) {
+    if (!A || !index) return fail(VQE_EINVAL, "null pointer argument");
+    if (A->n_electrons < 0) return fail(VQE_EINVAL, "ansatz has no reference");
+    *index = A->ref_bits >= 0 ? uint64_t(A->ref_bits) : ((uint64_t(1) << A->n_electrons) - 1);
     return VQE_OK;
 }
 

@@ -235,3 +235,30 @@ def test_trotter_program_repeats_uccsd():
         vq.Ansatz.uccsd_trotter(6, 3, 0)
     with pytest.raises(vq.VQEError):
         vq.Ansatz.kupccgsd(6, 3, 0)
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2), (6, 3), (8, 5), (11, 6)])
+def test_bk_terms_match_oracle(n, seed):
+    """Host Bravyi-Kitaev terms (linear-encoding form) = the oracle's
+    (Fenwick update/parity/remainder sets), term by term."""
+    h0, h, g = random_integrals(n, seed)
+    H = vq.Hamiltonian.from_integrals_map(n, "bk", 0.2, h, g)
+    x, z, c = H.terms()
+    ref = P.folded_terms(P.jw_hamiltonian(n, 0.2, h, g, mapping="bk"))
+    got = {(int(a), int(b)): float(v) for a, b, v in zip(x, z, c)}
+    assert set(got) == set(ref)
+    assert max(abs(got[k] - ref[k]) for k in ref) < 1e-12
+    Hj = vq.Hamiltonian.from_integrals_map(n, "jw", 0.2, h, g)
+    assert Hj.info()[1] == vq.Hamiltonian.from_integrals(n, 0.2, h, g).info()[1]
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (7, 3), (12, 6), (13, 7)])
+def test_bk_uccsd_reference_and_excitations(n, ne):
+    A = vq.Ansatz.uccsd_map(n, ne, "bk")
+    assert A.reference() == P.bk_encode(n, (1 << ne) - 1)
+    assert A.excitations() == F.uccsd_excitations(n, ne)
+    assert vq.Ansatz.uccsd_map(n, ne, "jw").reference() == (1 << ne) - 1
+    nq, m, gates, e = A.info()
+    # every generator is a sum of 2 (single) or 8 (double) strings under any mapping
+    ex = F.uccsd_excitations(n, ne)
+    assert gates == sum(2 if len(t) == 2 else 8 for t in ex)

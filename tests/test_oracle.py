@@ -476,3 +476,54 @@ def test_kupccgsd_vqe_bounds():
         res.append(prob.vqe(theta0=th0, gtol=1e-9).fun)
     assert res[1] >= fci - 1e-10
     assert res[1] <= res[0] + 1e-9
+
+
+# ------------------------------------------------------- Bravyi-Kitaev
+
+def _bk_permutation(n):
+    """Pi |occupation bits> = |BK register>, from the Fenwick rows written out."""
+    dim = 1 << n
+    Pi = np.zeros((dim, dim))
+    for occ in range(dim):
+        b = 0
+        for j in range(n):
+            lo = j + 1 - ((j + 1) & -(j + 1))
+            b |= (sum((occ >> k) & 1 for k in range(lo, j + 1)) & 1) << j
+        Pi[b, occ] = 1.0
+    return Pi
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 8])
+def test_bk_ladder_is_permuted_fock_ladder(n):
+    """The BK ladder operators equal the occupation-number ladder matrices in
+    the encoded basis (Pi a Pi^T), for every orbital; the encoding is a
+    permutation of the basis."""
+    cr, an = B.ladder(n)
+    Pi = _bk_permutation(n)
+    assert np.array_equal(Pi @ Pi.T, np.eye(1 << n))
+    for j in range(n):
+        got_c = P.matrix(P.bk_ladder(n, j, True), n)
+        got_a = P.matrix(P.bk_ladder(n, j, False), n)
+        assert np.abs(got_c - Pi @ cr[j].toarray() @ Pi.T).max() < 1e-14
+        assert np.abs(got_a - Pi @ an[j].toarray() @ Pi.T).max() < 1e-14
+    for occ in range(1 << n):
+        assert Pi[P.bk_encode(n, occ), occ] == 1.0
+
+
+@pytest.mark.parametrize("n,ne", [(4, 2), (5, 2), (6, 3)])
+def test_bk_hamiltonian_and_uccsd_match_jw(n, ne):
+    """Same spectrum (the mapping only relabels the basis), and the BK UCCSD
+    state is the permuted JW state with the same energy."""
+    h0, h, g = random_integrals(n, 51 + n)
+    Hj = P.matrix(P.jw_hamiltonian(n, h0, h, g), n)
+    Hb = P.matrix(P.jw_hamiltonian(n, h0, h, g, mapping="bk"), n)
+    assert np.abs(np.linalg.eigvalsh(Hj) - np.linalg.eigvalsh(Hb)).max() < 1e-11
+    Pi = _bk_permutation(n)
+    assert np.abs(Hb - Pi @ Hj @ Pi.T).max() < 1e-12
+    excs = F.uccsd_excitations(n, ne)
+    theta = np.random.default_rng(n).uniform(-0.5, 0.5, len(excs))
+    pj = P.prepare(n, ne, excs, theta)
+    pb = P.prepare(n, ne, excs, theta, mapping="bk")
+    assert np.abs(pb - Pi @ pj).max() < 1e-12
+    prob = F.Problem(n, ne, h0, h, g)
+    assert abs(np.real(np.vdot(pb, Hb @ pb)) - prob.energy(theta)) < 1e-11
