@@ -196,6 +196,9 @@ struct HxChunk {
 // cls = kA * (Lb + 1) + kB, the entries listed in ent[off, off + cnt) with
 // {off, cnt} = info[(j - g0) * ncls + cls]: D index (bits 0-10), E index in
 // the tile (bits 11-22), parity of the D string's low chain bits (bit 23).
+// Padding of a gate's pair list up to its class's stride.
+constexpr uint32_t kPairNone = 0xffffffffu;
+
 struct PackedRun {
     int32_t g0, g1;
     uint32_t khi, dhi, free_hi;   // high parts of the created and annihilated orbitals; free bits
@@ -203,8 +206,8 @@ struct PackedRun {
     int32_t shape, shape_adj;   // launch shapes of the forward and reverse passes
     int32_t max_entries;
     int32_t ncls;
-    const int2* info;
-    const uint32_t* ent;
+    const int2* info;        // per first-block class: {offset, stride} of the padded lists
+    const uint32_t* ent;     // gate g of class c: ent[info[c].x + g * info[c].y + i]
 };
 
 // One excitation of a packed run: annihilated orbitals pd and created

@@ -116,23 +116,37 @@ __device__ __forceinline__ void wave_lds_sync() {
 // R rows per workgroup, W waves per row (R = 1 when W > 1), COLS beta
 // strings per lane: lane l of the row's wave w holds columns
 // (64 w + l) + 64 W c.  The waves of a row share its LDS slice.
+//
+// xs > 0 (a batch of xs >= 8 states): the grid is one-dimensional and
+// workgroup id b (dispatched to XCD b mod 8) takes a row block of state
+// 8 q + (b mod 8), q = (b / 8) / nrb: all rows of a state run on one XCD,
+// whose L2 then serves the partner rows every pair class and chunk reads
+// again.  Workgroups past the last state exit at once.
 template <int COLS, int R, int W>
-__global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci) {
+__global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci,
+                                                      int xs, int nrb) {
     static_assert(R == 1 || W == 1, "several rows of one wave each, or one row of several waves");
     constexpr int kT = R * W * 64;
     constexpr int kTPer = (kCiChunkTabs + kT - 1) / kT;
     extern __shared__ double2 lds_ci[];
     __shared__ double tstage[2][kCiChunkTabs];
     __shared__ double ered[W];
+    int rblk = blockIdx.x, sidx = blockIdx.y;
+    if (xs > 0) {
+        const int slot = int(blockIdx.x >> 3), q = slot / nrb;
+        rblk = slot - q * nrb;
+        sidx = 8 * q + int(blockIdx.x & 7);
+        if (sidx >= xs) return;   // the whole workgroup, before any barrier
+    }
     const int nrank = 1 << ci.ob;
     int16_t* RB = reinterpret_cast<int16_t*>(lds_ci);
     for (int i = threadIdx.x; i < nrank; i += kT) RB[i] = ci.rank_b[i];
-    const StateDesc& s = sd[blockIdx.y];
+    const StateDesc& s = sd[sidx];
     const int split = blockIdx.z, nsplit = ci.nsplit;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int rslot = wave / W, wr = wave % W;   // row slot in the block, wave within the row
     const int rt = wr * 64 + lane;               // thread within the row
-    const int ia = blockIdx.x * R + rslot;
+    const int ia = rblk * R + rslot;
     const bool row_live = ia < ci.na_str;   // waves past the last row only help with staging
     const int NB = ci.nb_str;
     double2* row = lds_ci + ((nrank * 2 + 15) >> 4) + size_t(rslot) * ci_wave_words(NB, ci.npairs);
@@ -358,8 +372,16 @@ static size_t ci_lds(const CiArgs& ci) {
 
 template <int COLS, int R, int W>
 static void launch_crw(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    const dim3 grid((ci.na_str + R - 1) / R, count, ci.nsplit);
-    hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci);
+    const int nrb = (ci.na_str + R - 1) / R;
+    if (count >= 8 && ci.nsplit == 1) {   // XCD-grouped batch
+        const dim3 grid(unsigned(8 * ((count + 7) / 8) * nrb), 1, 1);
+        hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci,
+                           count, nrb);
+        return;
+    }
+    const dim3 grid(unsigned(nrb), count, ci.nsplit);
+    hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci, 0,
+                       nrb);
 }
 
 template <int COLS>

@@ -94,10 +94,14 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const bool fwd = (VEC == 1);
     const int ng = run.g1 - run.g0;
     const int cls = B0.kA * (T.Lb + 1) + B0.kB;
-    // the first list entry of each thread is loaded one gate ahead (issued
-    // before the tile loads, so that it has arrived when the gate loop starts)
-    int2 li = ldc(run.info + size_t(fwd ? 0 : ng - 1) * run.ncls + cls);
-    uint32_t ecur = (tid < li.y) ? ldg32(run.ent + li.x + tid) : 0u;
+    // the tile class's pair lists: gate j's list at lbase + j * stride, padded
+    // with kPairNone; the first entry of each thread is loaded one gate ahead
+    // (issued before the tile loads, so that it has arrived when the gate loop
+    // starts), and needs no per-gate descriptor
+    const int2 lc = ldc(run.info + cls);
+    const uint32_t* lbase = run.ent + lc.x;
+    const int stride = lc.y;
+    uint32_t ecur = (tid < stride) ? ldg32(lbase + size_t(fwd ? 0 : ng - 1) * stride + tid) : kPairNone;
     {   // all loads first (clamped into the tile), then the LDS stores
         double2 vp[2 * EPT], vl[2 * EPT];
 #pragma unroll
@@ -116,21 +120,31 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             if (VEC == 2) shl[k] = vl[u];
         }
     }
+    // the gate descriptor and (cos, sin) are read one gate ahead as well, through
+    // the scalar cache (a vector load would make the wait for it also wait for
+    // the next gate's list entry)
+    PackedGate gcur = ldc(pg + (fwd ? 0 : ng - 1));
+    double2 cscur = ldc(s.cs + run.g0 + (fwd ? 0 : ng - 1));
     __syncthreads();
     for (int t = 0; t < ng; ++t) {
         const int jl = fwd ? t : ng - 1 - t;
-        int2 ln = make_int2(0, 0);
-        if (t + 1 < ng) ln = ldc(run.info + size_t(fwd ? jl + 1 : jl - 1) * run.ncls + cls);
-        const uint32_t enext = (tid < ln.y) ? ldg32(run.ent + ln.x + tid) : 0u;
-        const PackedGate g = ldc(pg + jl);
-        // scalar load: a vector load here would make the wait for it also
-        // wait for the next gate's list entry, defeating the look-ahead
-        const double2 cs = ldc(s.cs + run.g0 + jl);
+        const int jn = fwd ? jl + 1 : jl - 1;
+        const bool more = t + 1 < ng;
+        const uint32_t enext = (more && tid < stride) ? ldg32(lbase + size_t(jn) * stride + tid) : kPairNone;
+        PackedGate gnext = gcur;
+        double2 csnext = cscur;
+        if (more) {
+            gnext = ldc(pg + jn);
+            csnext = ldc(s.cs + run.g0 + jn);
+        }
+        const PackedGate g = gcur;
+        const double2 cs = cscur;
         const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);   // the tile's part of the sign
         const double ssin = sgn_hi * cs.y;
         double acc = 0.0;
-        for (int i = tid; i < li.y; i += BS) {
-            const uint32_t e = (i == tid) ? ecur : ldg32(run.ent + li.x + i);
+        for (int i = tid; i < stride; i += BS) {
+            const uint32_t e = (i == tid) ? ecur : ldg32(lbase + size_t(jl) * stride + i);
+            if (e == kPairNone) break;   // the padding: the rest of the list is padding too
             const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
             const double ss = ((e >> 23) & 1u) ? -ssin : ssin;
             if (fwd) {
@@ -162,8 +176,9 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             }
         }
         __syncthreads();
-        li = ln;
         ecur = enext;
+        gcur = gnext;
+        cscur = csnext;
     }
     if (!fwd) {
         if (tid == 0) {
@@ -250,13 +265,15 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
     __syncthreads();
     const int cls = B0.kA * (T.Lb + 1) + B0.kB;
     const PackedGate* pg = pg_all + run.g0;
+    const int2 lc = ldc(run.info + cls);
     for (int jl = w; jl < ng; jl += BS / 64) {
-        const int2 li = ldc(run.info + size_t(jl) * run.ncls + cls);
+        const uint32_t* lst = run.ent + lc.x + size_t(jl) * lc.y;
         const PackedGate g = ldc(pg + jl);
         const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);
         double acc = 0.0;
-        for (int i = lane; i < li.y; i += 64) {
-            const uint32_t e = ldg32(run.ent + li.x + i);
+        for (int i = lane; i < lc.y; i += 64) {
+            const uint32_t e = ldg32(lst + i);
+            if (e == kPairNone) break;
             const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
             const double sg_t = ((e >> 23) & 1u) ? -sgn_hi : sgn_hi;
             const double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];

@@ -125,7 +125,7 @@ struct PackedPlan {
     std::vector<PackedRun> runs;
     std::vector<int> off;             // PackedGate offset per run
     PackedGate* d_gates = nullptr;
-    int2* d_info = nullptr;           // pair-list index: {offset, count} per run, gate, class
+    int2* d_info = nullptr;           // pair-list index: {offset, stride} per run and class
     uint32_t* d_ent = nullptr;        // pair lists
     std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
     int32_t* d_gcnt = nullptr;
@@ -943,7 +943,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     p->L = L;
     p->gcnt.assign(size_t(M), 1);
     std::vector<PackedGate> pg;
-    std::vector<int2> info;       // per run, gate and first-block class: {offset, count}
+    std::vector<int2> info;       // per run and first-block class: {offset, stride}
     std::vector<uint32_t> ent;    // pair lists
     std::vector<size_t> info0;    // offset of each run's info table
     int64_t j = 0;
@@ -992,35 +992,55 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         // (the alpha ranks come from the per-popcount table)
         const uint32_t khb = khi << L, dhb = dhi << L;
         const int dB = __builtin_popcount(khb & 0xAAAAAAAAu) - __builtin_popcount(dhb & 0xAAAAAAAAu);
+        // pair lists per (gate, first-block class); laid out per class with every
+        // gate's list padded to the class's longest (kPairNone), so that gate g's
+        // list starts at offset + g * stride and needs no per-gate descriptor
+        const int64_t ng = j2 - j;
+        std::vector<std::vector<uint32_t>> lists(size_t(ng) * size_t(ncls));
         for (int64_t k = j; k < j2; ++k) {
             const GateDesc& h = A->gates[k];
             const uint32_t pd = h.pd & lowmask, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
             for (int cls = 0; cls < ncls; ++cls) {
-                int2 rec = make_int2(int(ent.size()), 0);
-                if (used[size_t(cls)]) {
-                    const int kA0 = cls / (T.Lb + 1), kB0 = cls % (T.Lb + 1);
-                    const int kB1 = kB0 - dB;
-                    const int cB0 = T.offB[kB0 + 1] - T.offB[kB0];
-                    const int c0 = (T.offA[kA0 + 1] - T.offA[kA0]) * cB0;
-                    const int cB1 = T.offB[kB1 + 1] - T.offB[kB1];
-                    const int eoff = (khi | dhi) ? c0 : 0;
-                    for (int e = 0; e < c0; ++e) {   // D entries of the first block, rank order
-                        const uint32_t rd = uint32_t(T.unA[T.offA[kA0] + e / cB0] | T.unB[T.offB[kB0] + e % cB0]);
-                        if ((rd & (pd | klo)) != pd) continue;
-                        const uint32_t re = rd ^ pd ^ klo;
-                        const int ie = eoff + int(T.rankA[compact_even_host(re)]) * cB1 +
-                                       int(T.rankB[compact_even_host(re >> 1)]);
-                        const uint32_t par = uint32_t(__builtin_popcount(rd & chlo) & 1);
-                        if (e >= 2048 || ie >= 4096) {
-                            delete p;
-                            return fail(VQE_EINVAL, "packed layout: tile too large for the pair lists");
-                        }
-                        ent.push_back(uint32_t(e) | (uint32_t(ie) << 11) | (par << 23));
+                if (!used[size_t(cls)]) continue;
+                std::vector<uint32_t>& lst = lists[size_t(k - j) * ncls + cls];
+                const int kA0 = cls / (T.Lb + 1), kB0 = cls % (T.Lb + 1);
+                const int kB1 = kB0 - dB;
+                const int cB0 = T.offB[kB0 + 1] - T.offB[kB0];
+                const int c0 = (T.offA[kA0 + 1] - T.offA[kA0]) * cB0;
+                const int cB1 = T.offB[kB1 + 1] - T.offB[kB1];
+                const int eoff = (khi | dhi) ? c0 : 0;
+                for (int e = 0; e < c0; ++e) {   // D entries of the first block, rank order
+                    const uint32_t rd = uint32_t(T.unA[T.offA[kA0] + e / cB0] | T.unB[T.offB[kB0] + e % cB0]);
+                    if ((rd & (pd | klo)) != pd) continue;
+                    const uint32_t re = rd ^ pd ^ klo;
+                    const int ie = eoff + int(T.rankA[compact_even_host(re)]) * cB1 +
+                                   int(T.rankB[compact_even_host(re >> 1)]);
+                    const uint32_t par = uint32_t(__builtin_popcount(rd & chlo) & 1);
+                    if (e >= 2048 || ie >= 4096) {
+                        delete p;
+                        return fail(VQE_EINVAL, "packed layout: tile too large for the pair lists");
                     }
-                    rec.y = int(ent.size()) - rec.x;
+                    lst.push_back(uint32_t(e) | (uint32_t(ie) << 11) | (par << 23));
                 }
-                info.push_back(rec);
             }
+        }
+        for (int cls = 0; cls < ncls; ++cls) {
+            int2 rec = make_int2(int(ent.size()), 0);
+            if (used[size_t(cls)]) {
+                size_t stride = 0;
+                for (int64_t g = 0; g < ng; ++g) stride = std::max(stride, lists[size_t(g) * ncls + cls].size());
+                for (int64_t g = 0; g < ng; ++g) {
+                    const std::vector<uint32_t>& lst = lists[size_t(g) * ncls + cls];
+                    ent.insert(ent.end(), lst.begin(), lst.end());
+                    ent.insert(ent.end(), stride - lst.size(), kPairNone);
+                }
+                rec.y = int(stride);
+            }
+            info.push_back(rec);
+        }
+        if (ent.size() > size_t(1) << 31) {
+            delete p;
+            return fail(VQE_ERANGE, "packed layout: pair lists too large");
         }
         r.shape = packed_shape(maxb, tn.fwd_threads);
         r.shape_adj = packed_shape(maxb, tn.adj_threads);
