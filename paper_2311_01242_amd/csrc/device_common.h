@@ -60,16 +60,25 @@ struct StateDesc {
 // sorted into classes by the alpha part of their flip mask, so whether a
 // group can pair the row with an in-sector partner row is the same for all
 // lanes.
+//
+// A linear group (meta bit 17) has subgroups whose sign masks differ from a
+// common w0 by at most one orbital t (a hop with its n_t-weighted two-body
+// parts): its coefficient is sign(w0) [S(p) - 2 sum over occupied t of
+// T_t(p)], S the sum of all its tables.  Then wa, wb hold w0; s0, s1 the
+// compact alpha and beta orbitals t that have a table; tab the start of
+// S, followed by the tables -2 T_t of alpha orbital i at tab + (1 + i) nt and
+// of beta orbital i at tab + (1 + oa + i) nt (nt = pad[0] & 255 entries,
+// oa = pad[0] >> 8).
 struct CiGroup {
     uint32_t xa;             // compact alpha flip mask (the group's class)
     uint32_t xb;             // compact beta flip mask
     uint32_t tbb;            // compact beta table positions, 4 x 5 bits (31 = none)
     uint32_t tba;            // compact alpha table positions (mask)
-    int32_t meta;            // |xa| / 2 | ka << 8 | col_only << 16
-    int32_t s0, s1;          // subgroup range, local to the chunk
-    uint32_t wa, wb;         // the first subgroup (s0), repeated here
+    int32_t meta;            // |xa| / 2 | ka << 8 | col_only << 16 | linear << 17
+    int32_t s0, s1;          // subgroup range, local to the chunk (linear: orbital masks)
+    uint32_t wa, wb;         // the first subgroup (s0), repeated here (linear: w0)
     int32_t tab;
-    int32_t pad[2];
+    int32_t pad[2];          // linear: pad[0] = nt | oa << 8
 };
 
 // Table index: (alpha pattern) | (beta pattern << ka), patterns in ascending

@@ -80,7 +80,25 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
         tix[c] = ta | (tb << ka);
     }
     double d[COLS];
-    {   // the first subgroup comes with the group record
+    if ((G.meta >> 17) & 1) {   // linear group: sums over the occupied orbitals with tables
+        const int nt = G.pad[0] & 0xff, oa = G.pad[0] >> 8;
+        const uint32_t par = uint32_t(__popc(sA & G.wa));
+        const uint32_t occa = sA & uint32_t(G.s0);   // the same for every lane
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            double acc = GTAB ? ldg64(tab + G.tab + tix[c]) : tab[G.tab + tix[c]];
+            for (uint32_t m = occa; m; m &= m - 1) {
+                const int o = G.tab + (1 + __ffs(m) - 1) * nt + int(tix[c]);
+                acc += GTAB ? ldg64(tab + o) : tab[o];
+            }
+            for (uint32_t m = sB[c] & uint32_t(G.s1); m; m &= m - 1) {
+                const int o = G.tab + (oa + __ffs(m)) * nt + int(tix[c]);
+                acc += GTAB ? ldg64(tab + o) : tab[o];
+            }
+            const uint32_t flip = (uint32_t(__popc(sB[c] & G.wb)) + par) << 31;
+            d[c] = __hiloint2double(__double2hiint(acc) ^ int(flip), __double2loint(acc));
+        }
+    } else {   // the first subgroup comes with the group record
         const uint32_t par = uint32_t(__popc(sA & G.wa));
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
@@ -89,7 +107,7 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
             d[c] = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
         }
     }
-    for (int si = G.s0 + 1; si < G.s1; ++si) {
+    for (int si = G.s0 + 1; !((G.meta >> 17) & 1) && si < G.s1; ++si) {
         const CiSub S = ldc(sp + si);
         const uint32_t par = uint32_t(__popc(sA & S.wa));
 #pragma unroll

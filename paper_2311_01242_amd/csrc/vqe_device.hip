@@ -752,6 +752,47 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         g.meta = (__builtin_popcount(o.xa) / 2) | (l.ka << 8) | (col_only << 16);
         return g;
     };
+    // Linear form of a group (4 or more subgroups whose masks all differ from
+    // one of them, w0, by at most one orbital): tables S, then -2 T_t per
+    // alpha and per beta orbital (see CiGroup).
+    const int oa_all = (H->n + 1) / 2;
+    auto linear_form = [&](const GroupDesc& gd, const Layout& l, std::vector<double>& t,
+                           CiGroup& g) -> bool {
+        if (gd.sub_end - gd.sub_begin < 4) return false;
+        for (int c = gd.sub_begin; c < gd.sub_end; ++c) {
+            const uint32_t w0 = H->subs[c].w;
+            bool ok = true;
+            for (int si = gd.sub_begin; si < gd.sub_end && ok; ++si)
+                ok = __builtin_popcount(H->subs[si].w ^ w0) <= 1;
+            if (!ok) continue;
+            const int nt = 1 << l.k;
+            std::vector<double> T(size_t(1 + oa_all + ob) * nt, 0.0);
+            uint32_t ma = 0, mb = 0;
+            for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+                std::vector<double> one;
+                push_table(l, H->subs[si], one);
+                for (int e = 0; e < nt; ++e) T[size_t(e)] += one[size_t(e)];
+                const uint32_t dq = H->subs[si].w ^ w0;
+                if (!dq) continue;
+                const int q = __builtin_ctz(dq);
+                const int slot = (q % 2 == 0) ? 1 + q / 2 : 1 + oa_all + q / 2;
+                if (q % 2 == 0)
+                    ma |= 1u << (q / 2);
+                else
+                    mb |= 1u << (q / 2);
+                for (int e = 0; e < nt; ++e) T[size_t(slot) * nt + e] += -2.0 * one[size_t(e)];
+            }
+            t.insert(t.end(), T.begin(), T.end());
+            g.meta |= 1 << 17;
+            g.wa = compact_even_host(w0);
+            g.wb = compact_even_host(w0 >> 1);
+            g.s0 = int32_t(ma);
+            g.s1 = int32_t(mb);
+            g.pad[0] = nt | (oa_all << 8);
+            return true;
+        }
+        return false;
+    };
     std::map<uint32_t, int> is_pair;   // xa -> the class has a beta-pair group
     for (const G& o : order)
         if (pair_eligible(o)) is_pair[o.xa] = 1;
@@ -786,6 +827,13 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
                     push_table(l, sd, ptab);
                 } else {
                     CiGroup g = make_group(o, l, 0);
+                    std::vector<double> lt;
+                    if (linear_form(gd, l, lt, g)) {
+                        g.tab = int32_t(ptab.size());
+                        ptab.insert(ptab.end(), lt.begin(), lt.end());
+                        rgrp.push_back(g);
+                        continue;
+                    }
                     g.s0 = int32_t(rsub.size());
                     for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
                         const SubDesc& sd = H->subs[si];
@@ -837,6 +885,26 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         const Layout l = layout(gd);
         const int nt = 1 << l.k;
         const CiGroup g = make_group(o, l, col_only[o.xa]);
+        {   // a linear group: one unit of (1 + oa + ob) nt table entries
+            CiGroup lg = g;
+            std::vector<double> lt;
+            if (linear_form(gd, l, lt, lg)) {
+                if (open && (int(grp.size()) - cur.g0 >= kCiChunkGroups ||
+                             int(tab.size()) - cur.t0 + int(lt.size()) > kCiChunkTabs))
+                    close();
+                if (!open) {
+                    cur = CiChunk{};
+                    cur.g0 = int32_t(grp.size());
+                    cur.s0 = int32_t(sub.size());
+                    cur.t0 = int32_t(tab.size());
+                    open = true;
+                }
+                lg.tab = int32_t(tab.size()) - cur.t0;
+                tab.insert(tab.end(), lt.begin(), lt.end());
+                grp.push_back(lg);
+                continue;
+            }
+        }
         int si = gd.sub_begin;
         while (si < gd.sub_end) {
             if (open && (int(grp.size()) - cur.g0 >= kCiChunkGroups ||
