@@ -298,6 +298,14 @@ DENSE_KERNELS = {
 }
 
 
+# Pauli-rotation programs (a mapping other than Jordan-Wigner) on full vectors
+ROTATION_KERNELS = {
+    "forward": ("k_pauli (one launch per Pauli rotation)", "k_gates.hip", "hbm"),
+    "h_apply": ("k_hx_dense (full-vector H-apply by x-mask group)", "k_hamiltonian.hip", "alu"),
+    "adjoint": ("k_adj_pauli (one launch per Pauli rotation, phi and lambda)", "k_gates.hip", "hbm"),
+}
+
+
 def run_puccd11(args):
     """pUCCD in the hard-core-boson form (Sec. 2.1, ansatz list) at the size
     the paper runs CH3F with (11 orbitals = 11 qubits, 7 pairs, 28
@@ -410,8 +418,13 @@ def run_scan12(args):
         b.energy_grad(th)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    phase_ms = b.profile(th, reps=args.profile_reps)
-    return {
+    if args.mapping == "bk":
+        roof = roofline(b, th, args.profile_reps, Hs, [6] * len(Hs), kernels=ROTATION_KERNELS,
+                        pairs=float(sum((1 << 12) * H.info()[1] for H in Hs)))
+    else:
+        roof = roofline(b, th, args.profile_reps, Hs, [6] * len(Hs))
+    roof["traffic"] = None
+    out = {
         "metric": "energy+adjoint-grad evals/s", "value": round(len(Hs) * args.steps / dt, 2),
         "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
@@ -420,8 +433,35 @@ def run_scan12(args):
                                + {"jw": "Jordan-Wigner (packed sector kernels)",
                                   "bk": "Bravyi-Kitaev (full-vector Pauli-rotation kernels)"}[args.mapping],
                    "mapping": args.mapping},
-        "roofline": {"phase_ms": [round(x, 3) for x in phase_ms]},
+        "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_scan(fam, SCAN12_LAMBDAS, th[:A.n_params])
+    return out
+
+
+def cpu_baseline_scan(fam, lams, theta, budget_s=15.0):
+    """Oracle energy + four-term shift-rule gradient ((1 + 4M) energies) on
+    the first geometry, timed; the mapping does not change the energies, so
+    the oracle is the same for both."""
+    from oracle import fermion as F
+    prob = F.Problem(12, 6, *fam(lams[0]))
+    prob.energy(theta)                        # operator caches (not timed)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 0.5 and reps < 20:
+        prob.energy(theta)
+        reps += 1
+    te = (time.perf_counter() - t0) / reps
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": 1.0 / (te * (1 + 4 * prob.n_params)), "unit": "evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle energy timed {reps} times at the first geometry; energy + gradient = "
+                      f"(1 + 4 x {prob.n_params}) energies"}
 
 
 def run_warmstart16(args):

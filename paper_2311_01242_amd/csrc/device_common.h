@@ -147,12 +147,14 @@ struct RunDesc {
     int32_t m;               // popcount(inner)
     int32_t contiguous;      // inner == 2^m - 1 (pdep is the identity)
     int32_t ntiles;          // 2^popcount(outer)
-    int32_t pad;
+    int32_t kind;            // 0: excitations (tile 2^(m+1): key 0 and 1); 1: Pauli rotations (tile 2^m)
 };
 
 // One excitation gate of a run, with its masks compressed into the tile's
 // inner coordinates (r-space).  Sign of pair D: csign * (-1)^{popcount(D & chain)}
-// split into the outer part (uniform per tile) and the r-space part.
+// split into the outer part (uniform per tile) and the r-space part.  For a
+// Pauli rotation exp(-i phi/2 P(x, z)): xr = x in r-space, pdr = z in r-space,
+// chr = |x & z| mod 4 (the Y count), chain_out = z outside the tile.
 struct TileGate {
     uint32_t xr, pdr, chr, chain_out;
     double csign;

@@ -381,6 +381,153 @@ __global__ void __launch_bounds__(kRunThreads) k_run_adj(const StateDesc* __rest
     }
 }
 
+// ------------------------------------------------ fused Pauli-rotation runs
+
+// A run of consecutive rotations exp(-i phi/2 P(x, z)) whose flip masks all
+// lie in the tile's inner bits: one block per (state, tile), the tile of 2^m
+// amplitudes (outer bits fixed) staged in LDS, every rotation applied there
+// (pairs (r, r ^ x_r), or a phase when x = 0), written back once.  The sign
+// (-1)^{|b & z|} splits into the tile's outer part and the r-space part.
+__device__ __forceinline__ uint32_t rot_index(const RunDesc& run, uint32_t o_dep, uint32_t e) {
+    return o_dep | (run.contiguous ? e : pdep32(e, run.inner));
+}
+
+template <int EPT>
+__device__ __forceinline__ void rot_load(double2* __restrict__ dst, const double2* __restrict__ src,
+                                         const RunDesc& run, uint32_t o_dep, uint32_t T) {
+    double2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t e = threadIdx.x + k * kRunThreads;
+        if (e < T) v[k] = nt_load(&src[rot_index(run, o_dep, e)]);
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t e = threadIdx.x + k * kRunThreads;
+        if (e < T) dst[e] = v[k];
+    }
+}
+
+template <int EPT>
+__device__ __forceinline__ void rot_store(double2* __restrict__ dst, const double2* __restrict__ src,
+                                          const RunDesc& run, uint32_t o_dep, uint32_t T) {
+    double2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t e = threadIdx.x + k * kRunThreads;
+        if (e < T) v[k] = src[e];
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const uint32_t e = threadIdx.x + k * kRunThreads;
+        if (e < T) nt_store(&dst[rot_index(run, o_dep, e)], v[k]);
+    }
+}
+
+// exp(-i phi/2 P) (s = sin(phi/2)) or its inverse (s < 0) on the LDS tile.
+__device__ __forceinline__ void rot_tile(double2* __restrict__ sh, const TileGate& t, uint32_t T,
+                                         double c, double s) {
+    if (t.xr == 0) {
+        for (uint32_t e = threadIdx.x; e < T; e += kRunThreads) {
+            const double ss = s * parity_sign(e & t.pdr);
+            const double2 a = sh[e];
+            sh[e] = make_double2(c * a.x + ss * a.y, c * a.y - ss * a.x);
+        }
+        return;
+    }
+    const uint32_t low = t.xr & (~t.xr + 1u);
+    const double2 f = minus_i_times_i_pow(int(t.chr));
+    for (uint32_t p = threadIdx.x; p < (T >> 1); p += kRunThreads) {
+        const uint32_t r0 = uint32_t(insert_zeros(p, low)), r1 = r0 ^ t.xr;
+        const double2 a0 = sh[r0], a1 = sh[r1];
+        const double s0 = s * parity_sign(r1 & t.pdr), s1 = s * parity_sign(r0 & t.pdr);
+        const double2 t0 = cmul(f, a1), t1 = cmul(f, a0);
+        sh[r0] = make_double2(c * a0.x + s0 * t0.x, c * a0.y + s0 * t0.y);
+        sh[r1] = make_double2(c * a1.x + s1 * t1.x, c * a1.y + s1 * t1.y);
+    }
+}
+
+template <int EPT>
+__global__ void __launch_bounds__(kRunThreads) k_rot_fwd(const StateDesc* __restrict__ sd, RunDesc run,
+                                                         const TileGate* __restrict__ tg, int total) {
+    extern __shared__ double2 sh[];
+    const uint32_t T = 1u << run.m;
+    const int id = blockIdx.x;
+    if (id >= total) return;
+    const StateDesc& s = sd[id / run.ntiles];
+    const uint32_t o_dep = pdep32(id % run.ntiles, run.outer);
+    rot_load<EPT>(sh, s.phi, run, o_dep, T);
+    __syncthreads();
+    for (int j = run.g0; j < run.g1; ++j) {
+        const TileGate t = tg[j - run.g0];
+        const double2 cs = s.cs[j];
+        rot_tile(sh, t, T, cs.x, cs.y * parity_sign(o_dep & t.chain_out));
+        __syncthreads();
+    }
+    rot_store<EPT>(s.phi, sh, run, o_dep, T);
+}
+
+// The reverse sweep of a rotation run on phi and lambda: per gate the
+// partial of Im <lambda|P phi> over the tile, then the inverse rotation.
+template <int EPT>
+__global__ void __launch_bounds__(kRunThreads) k_rot_adj(const StateDesc* __restrict__ sd, RunDesc run,
+                                                         const TileGate* __restrict__ tg, int total) {
+    extern __shared__ double2 sh[];
+    __shared__ double red[kMaxRunGates][kRunThreads / 64];
+    const uint32_t T = 1u << run.m;
+    double2* shp = sh;
+    double2* shl = sh + T;
+    const int id = blockIdx.x;
+    if (id >= total) return;
+    const StateDesc& s = sd[id / run.ntiles];
+    const int o = id % run.ntiles;
+    const uint32_t o_dep = pdep32(o, run.outer);
+    rot_load<EPT>(shp, s.phi, run, o_dep, T);
+    rot_load<EPT>(shl, s.lam, run, o_dep, T);
+    __syncthreads();
+    for (int j = run.g1 - 1; j >= run.g0; --j) {
+        const TileGate t = tg[j - run.g0];
+        const double2 cs = s.cs[j];
+        const double so = parity_sign(o_dep & t.chain_out);
+        double acc = 0.0;
+        if (t.xr == 0) {
+            for (uint32_t e = threadIdx.x; e < T; e += kRunThreads) {
+                const double sg = so * parity_sign(e & t.pdr);
+                const double2 f = shp[e], l = shl[e];
+                acc += sg * (l.x * f.y - l.y * f.x);   // Im(conj(l) (P phi)[b])
+            }
+        } else {
+            const uint32_t low = t.xr & (~t.xr + 1u);
+            const int y = int(t.chr);
+            const double2 iy = (y == 0) ? make_double2(1, 0)
+                             : (y == 1) ? make_double2(0, 1)
+                             : (y == 2) ? make_double2(-1, 0) : make_double2(0, -1);
+            for (uint32_t p = threadIdx.x; p < (T >> 1); p += kRunThreads) {
+                const uint32_t r0 = uint32_t(insert_zeros(p, low)), r1 = r0 ^ t.xr;
+                const double2 f0 = shp[r0], f1 = shp[r1], l0 = shl[r0], l1 = shl[r1];
+                // (P phi)[b] = i^y sigma(b') phi[b'],  (P phi)[b'] = i^y sigma(b) phi[b]
+                const double2 p0 = cmul(iy, f1), p1 = cmul(iy, f0);
+                const double s0 = so * parity_sign(r1 & t.pdr), s1 = so * parity_sign(r0 & t.pdr);
+                acc += s0 * (l0.x * p0.y - l0.y * p0.x) + s1 * (l1.x * p1.y - l1.y * p1.x);
+            }
+        }
+        __syncthreads();   // every partial read this gate's inputs before they change
+        rot_tile(shp, t, T, cs.x, -cs.y * so);
+        rot_tile(shl, t, T, cs.x, -cs.y * so);
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) red[j - run.g0][threadIdx.x >> 6] = acc;
+        __syncthreads();
+    }
+    for (int jl = threadIdx.x; jl < run.g1 - run.g0; jl += kRunThreads) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < kRunThreads / 64; ++w) r += red[jl][w];
+        s.part_g[size_t(run.g0 + jl) * s.gstride + o] = r;
+    }
+    rot_store<EPT>(s.phi, shp, run, o_dep, T);
+    rot_store<EPT>(s.lam, shl, run, o_dep, T);
+}
+
 // ------------------------------------------------------------ launchers
 
 void launch_angles(const StateDesc* sd, int count, int M, hipStream_t st) {
@@ -470,14 +617,35 @@ static int run_grid(size_t lds, int total) {
         else hipLaunchKernelGGL(KERNEL<32>, grid, block, lds, st, sd, run, tg, total);           \
     } while (0)
 
+#define VQE_ROT_DISPATCH(KERNEL, VEC)                                                           \
+    do {                                                                                        \
+        const uint32_t T = 1u << run.m;                                                         \
+        const int ept = int((T + kRunThreads - 1) / kRunThreads);                              \
+        const int total = run.ntiles * count;                                                   \
+        const size_t lds = size_t(T) * sizeof(double2) * VEC;                                  \
+        const dim3 grid(total), block(kRunThreads);                                             \
+        if (ept <= 1) hipLaunchKernelGGL(KERNEL<1>, grid, block, lds, st, sd, run, tg, total);   \
+        else if (ept <= 2) hipLaunchKernelGGL(KERNEL<2>, grid, block, lds, st, sd, run, tg, total); \
+        else if (ept <= 4) hipLaunchKernelGGL(KERNEL<4>, grid, block, lds, st, sd, run, tg, total); \
+        else if (ept <= 8) hipLaunchKernelGGL(KERNEL<8>, grid, block, lds, st, sd, run, tg, total); \
+        else if (ept <= 16) hipLaunchKernelGGL(KERNEL<16>, grid, block, lds, st, sd, run, tg, total); \
+        else hipLaunchKernelGGL(KERNEL<32>, grid, block, lds, st, sd, run, tg, total);           \
+    } while (0)
+
 void launch_run_fwd(const StateDesc* sd, int count, const RunDesc& run, const TileGate* tg,
                     hipStream_t st) {
-    VQE_RUN_DISPATCH(k_run_fwd, 1);
+    if (run.kind == 1)
+        VQE_ROT_DISPATCH(k_rot_fwd, 1);
+    else
+        VQE_RUN_DISPATCH(k_run_fwd, 1);
 }
 
 void launch_run_adj(const StateDesc* sd, int count, const RunDesc& run, const TileGate* tg,
                     hipStream_t st) {
-    VQE_RUN_DISPATCH(k_run_adj, 2);
+    if (run.kind == 1)
+        VQE_ROT_DISPATCH(k_rot_adj, 2);
+    else
+        VQE_RUN_DISPATCH(k_run_adj, 2);
 }
 
 // Largest tile (elements = 2^(m+1)) a run kernel may be asked for: the
@@ -503,6 +671,18 @@ int enable_large_lds(size_t bytes) {
     set(reinterpret_cast<const void*>(&k_run_adj<8>));
     set(reinterpret_cast<const void*>(&k_run_adj<16>));
     set(reinterpret_cast<const void*>(&k_run_adj<32>));
+    set(reinterpret_cast<const void*>(&k_rot_fwd<1>));
+    set(reinterpret_cast<const void*>(&k_rot_fwd<2>));
+    set(reinterpret_cast<const void*>(&k_rot_fwd<4>));
+    set(reinterpret_cast<const void*>(&k_rot_fwd<8>));
+    set(reinterpret_cast<const void*>(&k_rot_fwd<16>));
+    set(reinterpret_cast<const void*>(&k_rot_fwd<32>));
+    set(reinterpret_cast<const void*>(&k_rot_adj<1>));
+    set(reinterpret_cast<const void*>(&k_rot_adj<2>));
+    set(reinterpret_cast<const void*>(&k_rot_adj<4>));
+    set(reinterpret_cast<const void*>(&k_rot_adj<8>));
+    set(reinterpret_cast<const void*>(&k_rot_adj<16>));
+    set(reinterpret_cast<const void*>(&k_rot_adj<32>));
     return e == hipSuccess ? 0 : -1;
 }
 

@@ -286,13 +286,60 @@ static void plan_direction(const vqe_ansatz* A, int64_t budget, int vectors,
     auto tile_bytes = [&](uint32_t inner) {
         return (int64_t(2) << __builtin_popcount(inner)) * int64_t(sizeof(double2)) * vectors;
     };
+    auto rot_bytes = [&](uint32_t inner) {   // a Pauli-rotation tile: 2^m amplitudes
+        return (int64_t(1) << __builtin_popcount(inner)) * int64_t(sizeof(double2)) * vectors;
+    };
     int64_t j = 0;
     while (j < M) {
         const GateDesc& g = A->gates[j];
         if (g.type != kExcitation) {
-            steps.push_back({1, int(j)});
-            bytes += 2.0 * vectors * double(sizeof(double2)) * double(uint64_t(1) << n);
-            ++j;
+            // consecutive rotations whose flip masks fit one tile of the budget
+            const uint32_t low3 = std::min<uint32_t>(7u, full);
+            uint32_t inner = g.x | low3;
+            if (rot_bytes(inner) > budget || __builtin_popcount(inner) > 14) {
+                steps.push_back({1, int(j)});
+                bytes += 2.0 * vectors * double(sizeof(double2)) * double(uint64_t(1) << n);
+                ++j;
+                continue;
+            }
+            int64_t j2 = j + 1;
+            while (j2 < M && A->gates[j2].type != kExcitation && j2 - j < kMaxRunGates) {
+                const uint32_t cand = inner | A->gates[j2].x;
+                if (rot_bytes(cand) > budget || __builtin_popcount(cand) > 14) break;
+                inner = cand;
+                ++j2;
+            }
+            for (int q = 0; q < n; ++q) {
+                const uint32_t bit = 1u << q;
+                if (inner & bit) continue;
+                if (rot_bytes(inner | bit) > budget || __builtin_popcount(inner | bit) > 14) break;
+                inner |= bit;
+            }
+            RunDesc r{};
+            r.g0 = int32_t(j);
+            r.g1 = int32_t(j2);
+            r.inner = inner;
+            r.key = 0;
+            r.outer = full & ~inner;
+            r.m = __builtin_popcount(inner);
+            r.contiguous = (inner == ((1u << r.m) - 1u)) ? 1 : 0;
+            r.ntiles = int32_t(1u << __builtin_popcount(r.outer));
+            r.kind = 1;
+            offs.push_back(int(tgs.size()));
+            for (int64_t k = j; k < j2; ++k) {
+                const GateDesc& h = A->gates[k];
+                TileGate t{};
+                t.xr = pext_host(h.x, inner);
+                t.pdr = pext_host(h.chain, inner);
+                t.chr = uint32_t(__builtin_popcount(h.x & h.chain) & 3);
+                t.chain_out = h.chain & r.outer;
+                t.csign = 1.0;
+                tgs.push_back(t);
+            }
+            steps.push_back({0, int(runs.size())});
+            runs.push_back(r);
+            bytes += 2.0 * double(rot_bytes(inner)) * double(r.ntiles);
+            j = j2;
             continue;
         }
         const uint32_t key = g.x & ~g.pd;
@@ -373,10 +420,11 @@ static int get_plan(const vqe_ansatz* A, DevAnsatz* da, const Tuning& tn, Ansatz
         }
     }
     p->gstride = gstride;
+    // tiles: 2^(m+1) amplitudes for excitation runs, 2^m for rotation runs
     for (auto& r : p->fwd_runs)
-        p->max_lds = std::max(p->max_lds, (size_t(2) << r.m) * sizeof(double2));
+        p->max_lds = std::max(p->max_lds, (size_t(r.kind == 1 ? 1 : 2) << r.m) * sizeof(double2));
     for (auto& r : p->adj_runs)
-        p->max_lds = std::max(p->max_lds, (size_t(2) << r.m) * sizeof(double2) * 2);
+        p->max_lds = std::max(p->max_lds, (size_t(r.kind == 1 ? 1 : 2) << r.m) * sizeof(double2) * 2);
     int rc = upload(&p->d_fwd_tg, tf.data(), tf.size());
     if (!rc) rc = upload(&p->d_adj_tg, ta.data(), ta.size());
     if (!rc) rc = upload(&p->d_gcnt, p->gcnt.data(), p->gcnt.size());
