@@ -300,9 +300,9 @@ DENSE_KERNELS = {
 
 # Pauli-rotation programs (a mapping other than Jordan-Wigner) on full vectors
 ROTATION_KERNELS = {
-    "forward": ("k_pauli (one launch per Pauli rotation)", "k_gates.hip", "hbm"),
+    "forward": ("k_rot_fwd (fused Pauli-rotation runs on full-vector tiles)", "k_gates.hip", "hbm"),
     "h_apply": ("k_hx_dense (full-vector H-apply by x-mask group)", "k_hamiltonian.hip", "alu"),
-    "adjoint": ("k_adj_pauli (one launch per Pauli rotation, phi and lambda)", "k_gates.hip", "hbm"),
+    "adjoint": ("k_rot_adj (fused rotation runs reverse-swept on phi and lambda)", "k_gates.hip", "hbm"),
 }
 
 
