@@ -42,6 +42,8 @@ struct StateDesc {
     const struct CiGroup* ci_rgroups;    // their other groups
     const struct CiSub* ci_rsubs;
     const double* ci_ptabs;              // tables of the pair classes (global offsets)
+    const struct CiRowMove* ci_rm;       // row moves of each alpha string
+    const int32_t* ci_rm_off;            // [na_str + 1] offsets into ci_rm
     double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
     uint32_t ref;            // basis index of the reference (full-vector layout)
@@ -79,6 +81,17 @@ struct CiGroup {
     uint32_t wa, wb;         // the first subgroup (s0), repeated here (linear: w0)
     int32_t tab;
     int32_t pad[2];          // linear: pad[0] = nt | oa << 8
+};
+
+// A row move: a group that flips alpha orbitals only, with one subgroup whose
+// table bits are its flip bits, pairs row a with row a ^ xa in every column
+// with a coefficient fixed by the row (table entry of a's pattern, sign of a's
+// chain bits) times (-1)^{|b & wb|}.  The moves valid for row a (half of xa
+// occupied) are listed per row.
+struct CiRowMove {
+    double coef;
+    int32_t partner;         // rank of the partner alpha string
+    uint32_t wb;
 };
 
 // Table index: (alpha pattern) | (beta pattern << ka), patterns in ascending

@@ -238,6 +238,44 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             ci_group<COLS, W, true>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, lr, li);
         }
     }
+    // ---- row moves: the row's own list, partners read in place
+    if (row_live) {
+        constexpr int kU = COLS <= 2 ? 4 : 2;   // moves in flight per pass
+        const int m1 = ldc(s.ci_rm_off + ia + 1);
+        int m = ldc(s.ci_rm_off + ia) + split;
+        for (; m + (kU - 1) * nsplit < m1; m += kU * nsplit) {
+            CiRowMove e[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) e[u] = ldc(s.ci_rm + m + u * nsplit);
+            double2 p[kU][COLS];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) p[u][c] = ldg2(phi + size_t(e[u].partner) * NB + ibc[c]);
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    const uint32_t flip = uint32_t(__popc(sB[c] & e[u].wb)) << 31;
+                    const double cf = __hiloint2double(__double2hiint(e[u].coef) ^ int(flip),
+                                                       __double2loint(e[u].coef));
+                    lr[c] += cf * p[u][c].x;
+                    li[c] += cf * p[u][c].y;
+                }
+        }
+        for (; m < m1; m += nsplit) {
+            const CiRowMove e = ldc(s.ci_rm + m);
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const double2 pv = ldg2(phi + size_t(e.partner) * NB + ibc[c]);
+                const uint32_t flip = uint32_t(__popc(sB[c] & e.wb)) << 31;
+                const double cf = __hiloint2double(__double2hiint(e.coef) ^ int(flip),
+                                                   __double2loint(e.coef));
+                lr[c] += cf * pv.x;
+                li[c] += cf * pv.y;
+            }
+        }
+    }
     // ---- generic groups, chunk by chunk (chunks split, split + nsplit, ...)
     const int nch = s.ci_nchunks;
     double treg[kTPer];

@@ -96,7 +96,20 @@ struct AnsatzPlan {
 
 // String-product H-apply plan of a Hamiltonian (groups sorted into classes
 // by the alpha part of their flip mask; see k_hx_ci.hip).
+// Row-move groups of a Hamiltonian (host) and their per-row lists for one
+// alpha-string space (device).
+struct RowMoveGroup {
+    uint32_t xa = 0, tba = 0, wa = 0, wb = 0;
+    std::vector<double> tab;   // by alpha pattern of the table positions
+};
+struct RowMoves {
+    CiRowMove* d_rm = nullptr;
+    int32_t* d_off = nullptr;
+};
+
 struct CiHam {
+    std::vector<RowMoveGroup> rmg;
+    std::map<std::pair<int, int>, RowMoves*> rm;   // by (alpha orbitals, alpha electrons)
     CiChunk* chunks = nullptr;
     CiGroup* groups = nullptr;
     CiSub* subs = nullptr;
@@ -841,6 +854,35 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         }
         return false;
     };
+    // groups that flip alpha orbitals only, with one subgroup over all their
+    // flip bits: listed per row (CiRowMove) instead of visited by every row
+    auto row_move = [&](const G& o) {
+        const GroupDesc& gd = H->groups[o.gi];
+        const Layout l = layout(gd);
+        return o.xb == 0 && o.xa != 0 && gd.sub_end - gd.sub_begin == 1 &&
+               l.k == __builtin_popcount(H->groups[o.gi].x);
+    };
+    std::vector<RowMoveGroup> rmg;
+    {
+        std::vector<G> kept;
+        for (const G& o : order) {
+            if (!row_move(o)) {
+                kept.push_back(o);
+                continue;
+            }
+            const GroupDesc& gd = H->groups[o.gi];
+            const Layout l = layout(gd);
+            RowMoveGroup r{};
+            r.xa = o.xa;
+            for (int i = 0; i < l.ka; ++i) r.tba |= 1u << l.pa[i];
+            const SubDesc& sd = H->subs[gd.sub_begin];
+            r.wa = compact_even_host(sd.w);
+            r.wb = compact_even_host(sd.w >> 1);
+            push_table(l, sd, r.tab);
+            rmg.push_back(std::move(r));
+        }
+        order.swap(kept);
+    }
     std::map<uint32_t, int> is_pair;   // xa -> the class has a beta-pair group
     for (const G& o : order)
         if (pair_eligible(o)) is_pair[o.xa] = 1;
@@ -999,6 +1041,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     c->nchunks = int(chunks.size());
     c->ob = ob;
     c->npcls = int(pcls.size());
+    c->rmg.swap(rmg);
     int rc = upload(&c->chunks, chunks.data(), chunks.size());
     if (!rc) rc = upload(&c->groups, grp.data(), grp.size());
     if (!rc) rc = upload(&c->subs, sub.data(), sub.size());
@@ -1210,6 +1253,50 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     return VQE_OK;
 }
 
+// Per-row lists of the row moves for the alpha strings of `cs`.
+static int ci_rowmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, RowMoves** out) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    const auto key = std::make_pair(cs.oa, cs.NA);
+    auto it = c->rm.find(key);
+    if (it != c->rm.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    std::vector<CiRowMove> rm;
+    std::vector<int32_t> off;
+    for (int ia = 0; ia < cs.NA; ++ia) {
+        off.push_back(int32_t(rm.size()));
+        const uint32_t a = cs.sa[size_t(ia)];
+        for (const RowMoveGroup& g : c->rmg) {
+            if (2 * __builtin_popcount(a & g.xa) != __builtin_popcount(g.xa)) continue;
+            uint32_t pat = 0;   // a's bits at the table positions, in ascending order
+            int k = 0;
+            for (uint32_t m = g.tba; m; m &= m - 1, ++k)
+                pat |= ((a >> __builtin_ctz(m)) & 1u) << k;
+            const double sg = (__builtin_popcount(a & g.wa) & 1) ? -1.0 : 1.0;
+            CiRowMove e{};
+            e.coef = sg * g.tab[size_t(pat)];
+            e.partner = cs.rank_a[size_t(a ^ g.xa)];
+            e.wb = g.wb;
+            if (e.partner < 0 || e.coef == 0.0) continue;
+            rm.push_back(e);
+        }
+    }
+    off.push_back(int32_t(rm.size()));
+    auto* r = new RowMoves();
+    int rc = upload(&r->d_off, off.data(), off.size());
+    if (!rc && !rm.empty()) rc = upload(&r->d_rm, rm.data(), rm.size());
+    if (rc) {
+        (void)hipFree(r->d_off);
+        (void)hipFree(r->d_rm);
+        delete r;
+        return rc;
+    }
+    c->rm[key] = r;
+    *out = r;
+    return VQE_OK;
+}
+
 // 0: full 2^n vectors; 1: packed layout with the block-order H-apply;
 // 2: packed layout with the string-product H-apply where it applies.
 static std::atomic<int> g_packed_enabled{2};
@@ -1321,6 +1408,7 @@ struct EvalPlan {
     double fwd_bytes = 0.0, adj_bytes = 0.0;
     size_t fwd_steps = 0, adj_steps = 0;
     bool ci = false;         // packed path with the string-product H-apply
+    const CiSpace* cspace = nullptr;
     CiArgs ciargs{};
     const int32_t* perm = nullptr;
 };
@@ -1374,6 +1462,7 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
                 if (cs->NB <= kCiMaxCols) {
                     if (int rc = layout_perm(ep->lay, *cs, *host_tables(ep->hx.L))) return rc;
                     ep->ci = true;
+                    ep->cspace = cs;
                     ep->ciargs = cs->args();
                     ep->ciargs.nsplit = batched ? 1 : ci_choose_splits(ep->ciargs);
                     ep->perm = ep->lay->d_perm;
@@ -1530,6 +1619,11 @@ vqe_hamiltonian::~vqe_hamiltonian() {
             (void)hipFree(c->rgroups);
             (void)hipFree(c->rsubs);
             (void)hipFree(c->ptabs);
+            for (auto& r : c->rm) {
+                (void)hipFree(r.second->d_rm);
+                (void)hipFree(r.second->d_off);
+                delete r.second;
+            }
             delete c;
         }
         delete kv.second;
@@ -1822,6 +1916,10 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         sd.ci_rsubs = ch->rsubs;
         sd.ci_ptabs = ch->ptabs;
         sd.ci_npcls = ch->npcls;
+        RowMoves* rm;
+        if (int rc = ci_rowmoves(H, ch, *ep.cspace, &rm)) return rc;
+        sd.ci_rm = rm->d_rm;
+        sd.ci_rm_off = rm->d_off;
     }
     Carver& cv = e->cv;
     sd.gates = e->da->gates;
@@ -2252,6 +2350,10 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.ci_rsubs = ch->rsubs;
             sd.ci_ptabs = ch->ptabs;
             sd.ci_npcls = ch->npcls;
+            RowMoves* rm;
+            if (int rc = ci_rowmoves(H[i], ch, *ep.cspace, &rm)) return rc;
+            sd.ci_rm = rm->d_rm;
+            sd.ci_rm_off = rm->d_off;
         }
         launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
