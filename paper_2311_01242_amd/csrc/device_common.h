@@ -44,6 +44,7 @@ struct StateDesc {
     const double* ci_ptabs;              // tables of the pair classes (global offsets)
     const struct CiRowMove* ci_rm;       // row moves of each alpha string
     const int32_t* ci_rm_off;            // [na_str + 1] offsets into ci_rm
+    const struct CiColMove* ci_cm;       // column moves, entry-major [ci_ncm][nb_str]
     double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
     uint32_t ref;            // basis index of the reference (full-vector layout)
@@ -51,6 +52,7 @@ struct StateDesc {
     int32_t gstride;         // stride of part_g between gates
     int32_t ci_nchunks;
     int32_t ci_npcls;
+    int32_t ci_ncm;          // column moves per column
 };
 
 // String-product ("CI") order of the sector: the amplitude of alpha string a
@@ -92,6 +94,17 @@ struct CiRowMove {
     double coef;
     int32_t partner;         // rank of the partner alpha string
     uint32_t wb;
+};
+
+// A column move: a group that flips beta orbitals only, with one subgroup
+// whose table bits are its flip bits, pairs column b with column b ^ xb in
+// every row with the coefficient (table entry of b's pattern, sign of b's
+// chain bits) times (-1)^{|a & wa|}.  Each column lists its valid moves,
+// padded to one count with zero coefficients (partner: the column itself).
+struct CiColMove {
+    double coef;
+    int32_t partner;         // rank of the partner beta string
+    uint32_t wa;
 };
 
 // Table index: (alpha pattern) | (beta pattern << ka), patterns in ascending

@@ -276,6 +276,23 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             }
         }
     }
+    // ---- column moves: the own row staged, each lane walks its column's list
+    if (row_live && s.ci_ncm > 0) {
+        stage_row(phi + size_t(ia) * NB);
+        const double2* cmv = reinterpret_cast<const double2*>(s.ci_cm);
+        for (int e = split; e < s.ci_ncm; e += nsplit) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const double2 q = ldg2(cmv + size_t(e) * NB + ibc[c]);   // {coef, partner | wa << 32}
+                const uint64_t pw = uint64_t(__double_as_longlong(q.y));
+                const double2 pv = row[int(uint32_t(pw))];
+                const uint32_t flip = uint32_t(__popc(sA & uint32_t(pw >> 32))) << 31;
+                const double cf = __hiloint2double(__double2hiint(q.x) ^ int(flip), __double2loint(q.x));
+                lr[c] += cf * pv.x;
+                li[c] += cf * pv.y;
+            }
+        }
+    }
     // ---- generic groups, chunk by chunk (chunks split, split + nsplit, ...)
     const int nch = s.ci_nchunks;
     double treg[kTPer];

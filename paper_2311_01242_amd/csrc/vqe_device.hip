@@ -106,10 +106,20 @@ struct RowMoves {
     CiRowMove* d_rm = nullptr;
     int32_t* d_off = nullptr;
 };
+struct ColMoveGroup {
+    uint32_t xb = 0, tbb = 0, wa = 0, wb = 0;   // tbb: compact beta table positions (mask)
+    std::vector<double> tab;                    // by beta pattern of the table positions
+};
+struct ColMoves {
+    CiColMove* d_cm = nullptr;
+    int ncm = 0;
+};
 
 struct CiHam {
     std::vector<RowMoveGroup> rmg;
     std::map<std::pair<int, int>, RowMoves*> rm;   // by (alpha orbitals, alpha electrons)
+    std::vector<ColMoveGroup> cmg;
+    std::map<std::pair<int, int>, ColMoves*> cm;   // by (beta orbitals, beta strings)
     CiChunk* chunks = nullptr;
     CiGroup* groups = nullptr;
     CiSub* subs = nullptr;
@@ -862,10 +872,31 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         return o.xb == 0 && o.xa != 0 && gd.sub_end - gd.sub_begin == 1 &&
                l.k == __builtin_popcount(H->groups[o.gi].x);
     };
+    // and the same for beta orbitals only: listed per column (CiColMove)
+    auto col_move = [&](const G& o) {
+        const GroupDesc& gd = H->groups[o.gi];
+        const Layout l = layout(gd);
+        return o.xa == 0 && o.xb != 0 && gd.sub_end - gd.sub_begin == 1 &&
+               l.k == __builtin_popcount(H->groups[o.gi].x);
+    };
     std::vector<RowMoveGroup> rmg;
+    std::vector<ColMoveGroup> cmg;
     {
         std::vector<G> kept;
         for (const G& o : order) {
+            if (col_move(o)) {
+                const GroupDesc& gd = H->groups[o.gi];
+                const Layout l = layout(gd);
+                ColMoveGroup r{};
+                r.xb = o.xb;
+                for (int i = 0; i < l.kb; ++i) r.tbb |= 1u << l.pb[i];
+                const SubDesc& sd = H->subs[gd.sub_begin];
+                r.wa = compact_even_host(sd.w);
+                r.wb = compact_even_host(sd.w >> 1);
+                push_table(l, sd, r.tab);
+                cmg.push_back(std::move(r));
+                continue;
+            }
             if (!row_move(o)) {
                 kept.push_back(o);
                 continue;
@@ -1042,6 +1073,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     c->ob = ob;
     c->npcls = int(pcls.size());
     c->rmg.swap(rmg);
+    c->cmg.swap(cmg);
     int rc = upload(&c->chunks, chunks.data(), chunks.size());
     if (!rc) rc = upload(&c->groups, grp.data(), grp.size());
     if (!rc) rc = upload(&c->subs, sub.data(), sub.size());
@@ -1293,6 +1325,53 @@ static int ci_rowmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, Ro
         return rc;
     }
     c->rm[key] = r;
+    *out = r;
+    return VQE_OK;
+}
+
+// Per-column lists of the column moves for the beta strings of `cs`,
+// entry-major and padded to the longest list.
+static int ci_colmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, ColMoves** out) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    const auto key = std::make_pair(cs.ob, cs.NB);
+    auto it = c->cm.find(key);
+    if (it != c->cm.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    std::vector<std::vector<CiColMove>> per(size_t(cs.NB));
+    size_t ncm = 0;
+    for (int ib = 0; ib < cs.NB; ++ib) {
+        const uint32_t b = cs.sb[size_t(ib)];
+        for (const ColMoveGroup& g : c->cmg) {
+            if (2 * __builtin_popcount(b & g.xb) != __builtin_popcount(g.xb)) continue;
+            uint32_t pat = 0;   // b's bits at the table positions, in ascending order
+            int k = 0;
+            for (uint32_t m = g.tbb; m; m &= m - 1, ++k)
+                pat |= ((b >> __builtin_ctz(m)) & 1u) << k;
+            const double sg = (__builtin_popcount(b & g.wb) & 1) ? -1.0 : 1.0;
+            CiColMove e{};
+            e.coef = sg * g.tab[size_t(pat)];
+            e.partner = cs.rank_b[size_t(b ^ g.xb)];
+            e.wa = g.wa;
+            if (e.partner < 0 || e.coef == 0.0) continue;
+            per[size_t(ib)].push_back(e);
+        }
+        ncm = std::max(ncm, per[size_t(ib)].size());
+    }
+    std::vector<CiColMove> cm(ncm * size_t(cs.NB));
+    for (int ib = 0; ib < cs.NB; ++ib)
+        for (size_t e = 0; e < ncm; ++e)
+            cm[e * size_t(cs.NB) + size_t(ib)] =
+                e < per[size_t(ib)].size() ? per[size_t(ib)][e] : CiColMove{0.0, ib, 0u};
+    auto* r = new ColMoves();
+    r->ncm = int(ncm);
+    if (!cm.empty())
+        if (int rc = upload(&r->d_cm, cm.data(), cm.size())) {
+            delete r;
+            return rc;
+        }
+    c->cm[key] = r;
     *out = r;
     return VQE_OK;
 }
@@ -1624,6 +1703,10 @@ vqe_hamiltonian::~vqe_hamiltonian() {
                 (void)hipFree(r.second->d_off);
                 delete r.second;
             }
+            for (auto& r : c->cm) {
+                (void)hipFree(r.second->d_cm);
+                delete r.second;
+            }
             delete c;
         }
         delete kv.second;
@@ -1920,6 +2003,10 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         if (int rc = ci_rowmoves(H, ch, *ep.cspace, &rm)) return rc;
         sd.ci_rm = rm->d_rm;
         sd.ci_rm_off = rm->d_off;
+        ColMoves* cm;
+        if (int rc = ci_colmoves(H, ch, *ep.cspace, &cm)) return rc;
+        sd.ci_cm = cm->d_cm;
+        sd.ci_ncm = cm->ncm;
     }
     Carver& cv = e->cv;
     sd.gates = e->da->gates;
@@ -2354,6 +2441,10 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             if (int rc = ci_rowmoves(H[i], ch, *ep.cspace, &rm)) return rc;
             sd.ci_rm = rm->d_rm;
             sd.ci_rm_off = rm->d_off;
+            ColMoves* cm;
+            if (int rc = ci_colmoves(H[i], ch, *ep.cspace, &cm)) return rc;
+            sd.ci_cm = cm->d_cm;
+            sd.ci_ncm = cm->ncm;
         }
         launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
