@@ -45,6 +45,8 @@ struct StateDesc {
     const struct CiRowMove* ci_rm;       // row moves of each alpha string
     const int32_t* ci_rm_off;            // [na_str + 1] offsets into ci_rm
     const struct CiColMove* ci_cm;       // column moves, entry-major [ci_ncm][nb_str]
+    const struct CiBetaHop* ci_bh;       // beta hops, entry-major [ci_nbh][nb_str]
+    const double* ci_hopa;               // their alpha tables [pair][16][2]
     double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
     uint32_t ref;            // basis index of the reference (full-vector layout)
@@ -53,6 +55,7 @@ struct StateDesc {
     int32_t ci_nchunks;
     int32_t ci_npcls;
     int32_t ci_ncm;          // column moves per column
+    int32_t ci_nbh;          // beta hops per column
 };
 
 // String-product ("CI") order of the sector: the amplitude of alpha string a
@@ -104,6 +107,20 @@ struct CiRowMove {
 struct CiColMove {
     double coef;
     int32_t partner;         // rank of the partner beta string
+    uint32_t wa;
+};
+
+// A beta hop: a linear group (see CiGroup) flipping two beta orbitals p < q
+// only.  Its coefficient in row a, column b is
+//   (-1)^{|a & wa0|} [coef + sb A_j(a, pi)],
+// coef = (-1)^{|b & wb0|} [S(pat) - 2 sum_{occupied beta t} T_t(pat)] (the
+// column's part), sb = (-1)^{|b & wb0|}, and A_j(a, pi) = -2 sum_{occupied
+// alpha t} T_t(pat), the row's part, from ci_hopa (pat = pi + 1: which of p,
+// q is occupied in b).  w = partner | j << 16 | pi << 24 | (sb < 0) << 25 |
+// live << 26 (padding entries have live = 0 and coef = 0).
+struct CiBetaHop {
+    double coef;
+    uint32_t w;
     uint32_t wa;
 };
 

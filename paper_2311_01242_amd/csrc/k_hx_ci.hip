@@ -276,9 +276,42 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             }
         }
     }
-    // ---- column moves: the own row staged, each lane walks its column's list
+    // ---- column moves and beta hops: the own row staged, each lane walks its
+    // column's lists
+    if (row_live && (s.ci_ncm > 0 || s.ci_nbh > 0)) stage_row(phi + size_t(ia) * NB);
+    if (row_live && s.ci_nbh > 0) {
+        // the row's alpha part of every hop, by beta pair: wc[j] = {pat 1, pat 2}
+        for (int j = rt; j < ci.npairs; j += 64 * W) {
+            double a1 = 0.0, a2 = 0.0;
+            const double* ha = s.ci_hopa + size_t(j) * 32;
+            for (uint32_t m = sA; m; m &= m - 1) {
+                const int t = __ffs(m) - 1;
+                a1 += ldg64(ha + 2 * t);
+                a2 += ldg64(ha + 2 * t + 1);
+            }
+            wc[j] = make_double2(a1, a2);
+        }
+        row_sync();
+        const double2* bhv = reinterpret_cast<const double2*>(s.ci_bh);
+        for (int e = split; e < s.ci_nbh; e += nsplit) {
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const double2 q = ldg2(bhv + size_t(e) * NB + ibc[c]);   // {coef, w | wa << 32}
+                const uint64_t ww2 = uint64_t(__double_as_longlong(q.y));
+                const uint32_t w = uint32_t(ww2);
+                const double2 A = wc[(w >> 16) & 0xffu];
+                double av = ((w >> 24) & 1u) ? A.y : A.x;
+                av = ((w >> 26) & 1u) ? (((w >> 25) & 1u) ? -av : av) : 0.0;
+                const double v = q.x + av;
+                const uint32_t flip = uint32_t(__popc(sA & uint32_t(ww2 >> 32))) << 31;
+                const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
+                const double2 pv = row[w & 0xffffu];
+                lr[c] += cf * pv.x;
+                li[c] += cf * pv.y;
+            }
+        }
+    }
     if (row_live && s.ci_ncm > 0) {
-        stage_row(phi + size_t(ia) * NB);
         const double2* cmv = reinterpret_cast<const double2*>(s.ci_cm);
         for (int e = split; e < s.ci_ncm; e += nsplit) {
 #pragma unroll

@@ -114,12 +114,25 @@ struct ColMoves {
     CiColMove* d_cm = nullptr;
     int ncm = 0;
 };
+struct BetaHopGroup {
+    int pair = 0;                           // pair index of its two beta orbitals
+    uint32_t xb = 0, lo = 0, hi = 0, wa0 = 0, wb0 = 0;
+    double S[4] = {0, 0, 0, 0};             // by beta pattern (bit 0: orbital lo)
+    std::vector<double> Tb, Ta;             // -2 T_t, [orbital][4]
+};
+struct BetaHops {
+    CiBetaHop* d_bh = nullptr;
+    int nbh = 0;
+};
 
 struct CiHam {
     std::vector<RowMoveGroup> rmg;
     std::map<std::pair<int, int>, RowMoves*> rm;   // by (alpha orbitals, alpha electrons)
     std::vector<ColMoveGroup> cmg;
     std::map<std::pair<int, int>, ColMoves*> cm;   // by (beta orbitals, beta strings)
+    std::vector<BetaHopGroup> bhg;
+    double* d_hopa = nullptr;                      // alpha tables of the beta hops
+    std::map<std::pair<int, int>, BetaHops*> bh;   // by (beta orbitals, beta strings)
     CiChunk* chunks = nullptr;
     CiGroup* groups = nullptr;
     CiSub* subs = nullptr;
@@ -879,11 +892,53 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         return o.xa == 0 && o.xb != 0 && gd.sub_end - gd.sub_begin == 1 &&
                l.k == __builtin_popcount(H->groups[o.gi].x);
     };
+    // linear groups flipping two beta orbitals only: column lists with a per-row
+    // alpha part (CiBetaHop)
+    auto beta_hop = [&](const G& o, BetaHopGroup* out) {
+        const GroupDesc& gd = H->groups[o.gi];
+        const Layout l = layout(gd);
+        if (o.xa != 0 || __builtin_popcount(o.xb) != 2 || l.k != 2 || l.kb != 2) return false;
+        for (int c = gd.sub_begin; c < gd.sub_end; ++c) {
+            const uint32_t w0 = H->subs[c].w;
+            bool ok = true;
+            for (int si = gd.sub_begin; si < gd.sub_end && ok; ++si)
+                ok = __builtin_popcount(H->subs[si].w ^ w0) <= 1;
+            if (!ok) continue;
+            BetaHopGroup r{};
+            r.xb = o.xb;
+            r.lo = uint32_t(__builtin_ctz(o.xb));
+            r.hi = uint32_t(31 - __builtin_clz(o.xb));
+            r.pair = pair_index(int(r.lo), int(r.hi), ob);
+            r.wa0 = compact_even_host(w0);
+            r.wb0 = compact_even_host(w0 >> 1);
+            r.Tb.assign(size_t(ob) * 4, 0.0);
+            r.Ta.assign(size_t(oa_all) * 4, 0.0);
+            for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+                std::vector<double> one;
+                push_table(l, H->subs[si], one);   // by beta pattern (ka = 0)
+                for (int e = 0; e < 4; ++e) r.S[e] += one[size_t(e)];
+                const uint32_t dq = H->subs[si].w ^ w0;
+                if (!dq) continue;
+                const int q = __builtin_ctz(dq);
+                std::vector<double>& T = (q % 2 == 0) ? r.Ta : r.Tb;
+                for (int e = 0; e < 4; ++e) T[size_t(q / 2) * 4 + e] += -2.0 * one[size_t(e)];
+            }
+            *out = std::move(r);
+            return true;
+        }
+        return false;
+    };
     std::vector<RowMoveGroup> rmg;
     std::vector<ColMoveGroup> cmg;
+    std::vector<BetaHopGroup> bhg;
     {
         std::vector<G> kept;
         for (const G& o : order) {
+            BetaHopGroup bg;
+            if (beta_hop(o, &bg)) {
+                bhg.push_back(std::move(bg));
+                continue;
+            }
             if (col_move(o)) {
                 const GroupDesc& gd = H->groups[o.gi];
                 const Layout l = layout(gd);
@@ -1074,7 +1129,14 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     c->npcls = int(pcls.size());
     c->rmg.swap(rmg);
     c->cmg.swap(cmg);
-    int rc = upload(&c->chunks, chunks.data(), chunks.size());
+    std::vector<double> hopa(size_t(std::max(npairs, 1)) * 16 * 2, 0.0);
+    for (const BetaHopGroup& g : bhg)
+        for (int t = 0; t < oa_all && t < 16; ++t)
+            for (int pi = 0; pi < 2; ++pi)
+                hopa[(size_t(g.pair) * 16 + t) * 2 + pi] = g.Ta[size_t(t) * 4 + pi + 1];
+    c->bhg.swap(bhg);
+    int rc = upload(&c->d_hopa, hopa.data(), hopa.size());
+    if (!rc) rc = upload(&c->chunks, chunks.data(), chunks.size());
     if (!rc) rc = upload(&c->groups, grp.data(), grp.size());
     if (!rc) rc = upload(&c->subs, sub.data(), sub.size());
     if (!rc) rc = upload(&c->tabs, tab.data(), tab.size());
@@ -1093,6 +1155,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         (void)hipFree(c->rgroups);
         (void)hipFree(c->rsubs);
         (void)hipFree(c->ptabs);
+        (void)hipFree(c->d_hopa);
         delete c;
         return rc;
     }
@@ -1372,6 +1435,56 @@ static int ci_colmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, Co
             return rc;
         }
     c->cm[key] = r;
+    *out = r;
+    return VQE_OK;
+}
+
+// Per-column lists of the beta hops for the beta strings of `cs`, entry-major
+// and padded to the longest list.
+static int ci_betahops(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, BetaHops** out) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    const auto key = std::make_pair(cs.ob, cs.NB);
+    auto it = c->bh.find(key);
+    if (it != c->bh.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    std::vector<std::vector<CiBetaHop>> per(size_t(cs.NB));
+    size_t nbh = 0;
+    for (int ib = 0; ib < cs.NB; ++ib) {
+        const uint32_t b = cs.sb[size_t(ib)];
+        for (const BetaHopGroup& g : c->bhg) {
+            const uint32_t plo = (b >> g.lo) & 1u, phi_ = (b >> g.hi) & 1u;
+            if (plo == phi_) continue;
+            const int pat = int(plo | (phi_ << 1));
+            const bool neg = __builtin_popcount(b & g.wb0) & 1;
+            double v = g.S[pat];
+            for (uint32_t m = b & ~g.xb; m; m &= m - 1)
+                v += g.Tb[size_t(__builtin_ctz(m)) * 4 + size_t(pat)];
+            CiBetaHop e{};
+            e.coef = neg ? -v : v;
+            const int partner = cs.rank_b[size_t(b ^ g.xb)];
+            if (partner < 0) continue;
+            e.w = uint32_t(partner) | (uint32_t(g.pair) << 16) | (uint32_t(pat - 1) << 24) |
+                  (uint32_t(neg) << 25) | (1u << 26);
+            e.wa = g.wa0;
+            per[size_t(ib)].push_back(e);
+        }
+        nbh = std::max(nbh, per[size_t(ib)].size());
+    }
+    std::vector<CiBetaHop> bh(nbh * size_t(cs.NB));
+    for (int ib = 0; ib < cs.NB; ++ib)
+        for (size_t e = 0; e < nbh; ++e)
+            bh[e * size_t(cs.NB) + size_t(ib)] =
+                e < per[size_t(ib)].size() ? per[size_t(ib)][e] : CiBetaHop{0.0, uint32_t(ib), 0u};
+    auto* r = new BetaHops();
+    r->nbh = int(nbh);
+    if (!bh.empty())
+        if (int rc = upload(&r->d_bh, bh.data(), bh.size())) {
+            delete r;
+            return rc;
+        }
+    c->bh[key] = r;
     *out = r;
     return VQE_OK;
 }
@@ -1707,6 +1820,11 @@ vqe_hamiltonian::~vqe_hamiltonian() {
                 (void)hipFree(r.second->d_cm);
                 delete r.second;
             }
+            for (auto& r : c->bh) {
+                (void)hipFree(r.second->d_bh);
+                delete r.second;
+            }
+            (void)hipFree(c->d_hopa);
             delete c;
         }
         delete kv.second;
@@ -2007,6 +2125,11 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         if (int rc = ci_colmoves(H, ch, *ep.cspace, &cm)) return rc;
         sd.ci_cm = cm->d_cm;
         sd.ci_ncm = cm->ncm;
+        BetaHops* bh;
+        if (int rc = ci_betahops(H, ch, *ep.cspace, &bh)) return rc;
+        sd.ci_bh = bh->d_bh;
+        sd.ci_nbh = bh->nbh;
+        sd.ci_hopa = ch->d_hopa;
     }
     Carver& cv = e->cv;
     sd.gates = e->da->gates;
@@ -2445,6 +2568,11 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             if (int rc = ci_colmoves(H[i], ch, *ep.cspace, &cm)) return rc;
             sd.ci_cm = cm->d_cm;
             sd.ci_ncm = cm->ncm;
+            BetaHops* bh;
+            if (int rc = ci_betahops(H[i], ch, *ep.cspace, &bh)) return rc;
+            sd.ci_bh = bh->d_bh;
+            sd.ci_nbh = bh->nbh;
+            sd.ci_hopa = ch->d_hopa;
         }
         launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
