@@ -47,6 +47,9 @@ struct StateDesc {
     const struct CiColMove* ci_cm;       // column moves, entry-major [ci_ncm][nb_str]
     const struct CiBetaHop* ci_bh;       // beta hops, entry-major [ci_nbh][nb_str]
     const double* ci_hopa;               // their alpha tables [pair][16][2]
+    const double* ci_dgr;                // diagonal in occupation form: row part [na_str]
+    const double* ci_dgc;                // column part (with the constant) [nb_str]
+    const double* ci_dgx;                // alpha-beta pair coefficients [alpha][16]; null: none
     double2* aux;            // packed path: lambda in string-product order
     int32_t n, G, M, ne;
     uint32_t ref;            // basis index of the reference (full-vector layout)

@@ -33,9 +33,10 @@ __device__ __forceinline__ uint32_t pext_mask(uint32_t v, uint32_t mask) {
 }
 
 // Words of a wave's LDS slice: its staged row, then the beta-pair
-// coefficient records of the current pair class.
+// coefficient records of the current pair class, then 16 doubles for the
+// row's part of the diagonal's alpha-beta terms.
 __host__ __device__ inline int ci_wave_words(int nb, int npairs) {
-    return nb + npairs + (npairs * 4 + 15) / 16;   // in double2 (16-byte) units
+    return nb + npairs + (npairs * 4 + 15) / 16 + 8;   // in double2 (16-byte) units
 }
 
 // lambda += D_G(b) phi(partner) for one group over the wave's columns.
@@ -276,9 +277,30 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             }
         }
     }
-    // ---- column moves and beta hops: the own row staged, each lane walks its
-    // column's lists
-    if (row_live && (s.ci_ncm > 0 || s.ci_nbh > 0)) stage_row(phi + size_t(ia) * NB);
+    // ---- column moves, beta hops and the diagonal: the own row staged, each
+    // lane walks its column's lists
+    const bool diag = s.ci_dgx != nullptr && split == 0;
+    if (row_live && (s.ci_ncm > 0 || s.ci_nbh > 0 || diag)) stage_row(phi + size_t(ia) * NB);
+    if (row_live && diag) {
+        // E(a, b) = R(a) + C(b) + sum over occupied alpha t, beta u of X[t][u]:
+        // the row's sums over t per beta orbital u, then per lane its u
+        double* dv = reinterpret_cast<double*>(row + NB + ci.npairs + (ci.npairs * 4 + 15) / 16);
+        for (int u = rt; u < ci.ob; u += 64 * W) {
+            double v = 0.0;
+            for (uint32_t m = sA; m; m &= m - 1) v += ldg64(s.ci_dgx + (__ffs(m) - 1) * 16 + u);
+            dv[u] = v;
+        }
+        row_sync();
+        const double ra = ldg64(s.ci_dgr + ia);
+#pragma unroll
+        for (int c = 0; c < COLS; ++c) {
+            double d = ra + ldg64(s.ci_dgc + ibc[c]);
+            for (uint32_t m = sB[c]; m; m &= m - 1) d += dv[__ffs(m) - 1];
+            const double2 pv = row[ibc[c]];
+            lr[c] += d * pv.x;
+            li[c] += d * pv.y;
+        }
+    }
     if (row_live && s.ci_nbh > 0) {
         // the row's alpha part of every hop, by beta pair: wc[j] = {pat 1, pat 2}
         for (int j = rt; j < ci.npairs; j += 64 * W) {

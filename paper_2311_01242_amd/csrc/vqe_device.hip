@@ -96,6 +96,8 @@ struct AnsatzPlan {
 
 // String-product H-apply plan of a Hamiltonian (groups sorted into classes
 // by the alpha part of their flip mask; see k_hx_ci.hip).
+struct CiSpace;
+
 // Row-move groups of a Hamiltonian (host) and their per-row lists for one
 // alpha-string space (device).
 struct RowMoveGroup {
@@ -124,15 +126,30 @@ struct BetaHops {
     CiBetaHop* d_bh = nullptr;
     int nbh = 0;
 };
+// The diagonal group in occupation form: K + sum_t L_t n_t + sum_{t<u} Q_tu n_t n_u
+// (its Z_t and Z_t Z_u strings with Z = 1 - 2n), and its row and column parts
+// for one string space.
+struct DiagForm {
+    bool on = false;
+    double K = 0.0;
+    std::vector<double> L, Q;   // [n], [n][n] (t < u)
+};
+struct DiagParts {
+    double* d_row = nullptr;
+    double* d_col = nullptr;
+};
 
 struct CiHam {
     std::vector<RowMoveGroup> rmg;
-    std::map<std::pair<int, int>, RowMoves*> rm;   // by (alpha orbitals, alpha electrons)
+    std::map<const CiSpace*, RowMoves*> rm;        // by string space
     std::vector<ColMoveGroup> cmg;
-    std::map<std::pair<int, int>, ColMoves*> cm;   // by (beta orbitals, beta strings)
+    std::map<const CiSpace*, ColMoves*> cm;
     std::vector<BetaHopGroup> bhg;
     double* d_hopa = nullptr;                      // alpha tables of the beta hops
-    std::map<std::pair<int, int>, BetaHops*> bh;   // by (beta orbitals, beta strings)
+    std::map<const CiSpace*, BetaHops*> bh;
+    DiagForm diag;
+    double* d_dgx = nullptr;                       // alpha-beta pair coefficients [alpha][16]
+    std::map<const CiSpace*, DiagParts*> dg;
     CiChunk* chunks = nullptr;
     CiGroup* groups = nullptr;
     CiSub* subs = nullptr;
@@ -928,12 +945,40 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         }
         return false;
     };
+    // the diagonal group, when it holds only one- and two-orbital Z strings
+    DiagForm dform;
+    auto diag_form = [&](const G& o) {
+        if (o.xa != 0 || o.xb != 0) return false;
+        const GroupDesc& gd = H->groups[o.gi];
+        if ((gd.pos & 7) != 0) return false;
+        for (int si = gd.sub_begin; si < gd.sub_end; ++si)
+            if (__builtin_popcount(H->subs[si].w) > 2) return false;
+        const int n = H->n;
+        dform.on = true;
+        dform.L.assign(size_t(n), 0.0);
+        dform.Q.assign(size_t(n) * n, 0.0);
+        for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+            const uint32_t w = H->subs[si].w;
+            const double cc = H->tabs[size_t(H->subs[si].tab)];
+            dform.K += cc;
+            if (!w) continue;
+            const int t = __builtin_ctz(w);
+            dform.L[size_t(t)] += -2.0 * cc;
+            if (__builtin_popcount(w) == 2) {
+                const int u = 31 - __builtin_clz(w);
+                dform.L[size_t(u)] += -2.0 * cc;
+                dform.Q[size_t(t) * n + u] += 4.0 * cc;
+            }
+        }
+        return true;
+    };
     std::vector<RowMoveGroup> rmg;
     std::vector<ColMoveGroup> cmg;
     std::vector<BetaHopGroup> bhg;
     {
         std::vector<G> kept;
         for (const G& o : order) {
+            if (diag_form(o)) continue;
             BetaHopGroup bg;
             if (beta_hop(o, &bg)) {
                 bhg.push_back(std::move(bg));
@@ -1135,7 +1180,19 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
             for (int pi = 0; pi < 2; ++pi)
                 hopa[(size_t(g.pair) * 16 + t) * 2 + pi] = g.Ta[size_t(t) * 4 + pi + 1];
     c->bhg.swap(bhg);
+    std::vector<double> dgx;
+    if (dform.on) {
+        const int n = H->n;
+        dgx.assign(16 * 16, 0.0);
+        for (int t = 0; t < oa_all; ++t)
+            for (int u = 0; u < ob; ++u) {
+                const int qa = 2 * t, qb = 2 * u + 1;
+                dgx[size_t(t) * 16 + u] = dform.Q[size_t(std::min(qa, qb)) * n + std::max(qa, qb)];
+            }
+    }
+    c->diag = std::move(dform);
     int rc = upload(&c->d_hopa, hopa.data(), hopa.size());
+    if (!rc && !dgx.empty()) rc = upload(&c->d_dgx, dgx.data(), dgx.size());
     if (!rc) rc = upload(&c->chunks, chunks.data(), chunks.size());
     if (!rc) rc = upload(&c->groups, grp.data(), grp.size());
     if (!rc) rc = upload(&c->subs, sub.data(), sub.size());
@@ -1156,6 +1213,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         (void)hipFree(c->rsubs);
         (void)hipFree(c->ptabs);
         (void)hipFree(c->d_hopa);
+        (void)hipFree(c->d_dgx);
         delete c;
         return rc;
     }
@@ -1351,7 +1409,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
 // Per-row lists of the row moves for the alpha strings of `cs`.
 static int ci_rowmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, RowMoves** out) {
     std::lock_guard<std::mutex> lk(H->mu);
-    const auto key = std::make_pair(cs.oa, cs.NA);
+    const CiSpace* key = &cs;
     auto it = c->rm.find(key);
     if (it != c->rm.end()) {
         *out = it->second;
@@ -1396,7 +1454,7 @@ static int ci_rowmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, Ro
 // entry-major and padded to the longest list.
 static int ci_colmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, ColMoves** out) {
     std::lock_guard<std::mutex> lk(H->mu);
-    const auto key = std::make_pair(cs.ob, cs.NB);
+    const CiSpace* key = &cs;
     auto it = c->cm.find(key);
     if (it != c->cm.end()) {
         *out = it->second;
@@ -1443,7 +1501,7 @@ static int ci_colmoves(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, Co
 // and padded to the longest list.
 static int ci_betahops(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, BetaHops** out) {
     std::lock_guard<std::mutex> lk(H->mu);
-    const auto key = std::make_pair(cs.ob, cs.NB);
+    const CiSpace* key = &cs;
     auto it = c->bh.find(key);
     if (it != c->bh.end()) {
         *out = it->second;
@@ -1485,6 +1543,45 @@ static int ci_betahops(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, Be
             return rc;
         }
     c->bh[key] = r;
+    *out = r;
+    return VQE_OK;
+}
+
+// Row and column parts of the diagonal for the strings of `cs`.
+static int ci_diag(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, DiagParts** out) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    auto it = c->dg.find(&cs);
+    if (it != c->dg.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    const int n = H->n;
+    const DiagForm& d = c->diag;
+    auto part = [&](uint32_t s, int spin) {   // s: compact string of one spin
+        double v = 0.0;
+        for (uint32_t m = s; m; m &= m - 1) {
+            const int q = 2 * __builtin_ctz(m) + spin;
+            v += d.L[size_t(q)];
+            for (uint32_t m2 = m & (m - 1); m2; m2 &= m2 - 1) {
+                const int q2 = 2 * __builtin_ctz(m2) + spin;
+                v += d.Q[size_t(q) * n + q2];
+            }
+        }
+        return v;
+    };
+    std::vector<double> row(size_t(cs.NA)), col(size_t(cs.NB));
+    for (int ia = 0; ia < cs.NA; ++ia) row[size_t(ia)] = part(cs.sa[size_t(ia)], 0);
+    for (int ib = 0; ib < cs.NB; ++ib) col[size_t(ib)] = d.K + part(cs.sb[size_t(ib)], 1);
+    auto* r = new DiagParts();
+    int rc = upload(&r->d_row, row.data(), row.size());
+    if (!rc) rc = upload(&r->d_col, col.data(), col.size());
+    if (rc) {
+        (void)hipFree(r->d_row);
+        (void)hipFree(r->d_col);
+        delete r;
+        return rc;
+    }
+    c->dg[&cs] = r;
     *out = r;
     return VQE_OK;
 }
@@ -1825,6 +1922,12 @@ vqe_hamiltonian::~vqe_hamiltonian() {
                 delete r.second;
             }
             (void)hipFree(c->d_hopa);
+            (void)hipFree(c->d_dgx);
+            for (auto& r : c->dg) {
+                (void)hipFree(r.second->d_row);
+                (void)hipFree(r.second->d_col);
+                delete r.second;
+            }
             delete c;
         }
         delete kv.second;
@@ -2130,6 +2233,13 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         sd.ci_bh = bh->d_bh;
         sd.ci_nbh = bh->nbh;
         sd.ci_hopa = ch->d_hopa;
+        if (ch->diag.on) {
+            DiagParts* dp;
+            if (int rc = ci_diag(H, ch, *ep.cspace, &dp)) return rc;
+            sd.ci_dgr = dp->d_row;
+            sd.ci_dgc = dp->d_col;
+            sd.ci_dgx = ch->d_dgx;
+        }
     }
     Carver& cv = e->cv;
     sd.gates = e->da->gates;
@@ -2573,6 +2683,13 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.ci_bh = bh->d_bh;
             sd.ci_nbh = bh->nbh;
             sd.ci_hopa = ch->d_hopa;
+            if (ch->diag.on) {
+                DiagParts* dp;
+                if (int rc = ci_diag(H[i], ch, *ep.cspace, &dp)) return rc;
+                sd.ci_dgr = dp->d_row;
+                sd.ci_dgc = dp->d_col;
+                sd.ci_dgx = ch->d_dgx;
+            }
         }
         launch_fill_zero(sd.lam, uint64_t(ep.elems), b->st);
         if (int rc = dalloc(b, &sd.cs, M)) return rc;
