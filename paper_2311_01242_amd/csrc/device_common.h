@@ -47,6 +47,9 @@ struct StateDesc {
     const struct CiColMove* ci_cm;       // column moves, entry-major [ci_ncm][nb_str]
     const struct CiBetaHop* ci_bh;       // beta hops, entry-major [ci_nbh][nb_str]
     const double* ci_hopa;               // their alpha tables [pair][16][2]
+    const struct CiAlphaHop* ci_ah;      // alpha hops of each alpha string
+    const int32_t* ci_ah_off;            // [na_str + 1] offsets into ci_ah
+    const double* ci_ahb;                // their beta parts [alpha pair][2][nb_str]
     const double* ci_dgr;                // diagonal in occupation form: row part [na_str]
     const double* ci_dgc;                // column part (with the constant) [nb_str]
     const double* ci_dgx;                // alpha-beta pair coefficients [alpha][16]; null: none
@@ -125,6 +128,18 @@ struct CiBetaHop {
     double coef;
     uint32_t w;
     uint32_t wa;
+};
+
+// An alpha hop: a linear group flipping two alpha orbitals p < q only.  Row
+// a lists its valid hops (one of p, q occupied); the coefficient in column b
+// is (-1)^{|b & wb0|} [coef + sa B_j(b, pi)], coef = (-1)^{|a & wa0|}
+// [S(pat) - 2 sum_{occupied alpha t} T_t(pat)] (the row's part), sa =
+// (-1)^{|a & wa0|}, and B_j(b, pi) = -2 sum_{occupied beta u} T_u(pat) from
+// ci_ahb (pat = pi + 1).  w = partner | j << 16 | pi << 24 | (sa < 0) << 25.
+struct CiAlphaHop {
+    double coef;
+    uint32_t w;
+    uint32_t wb;
 };
 
 // Table index: (alpha pattern) | (beta pattern << ka), patterns in ascending

@@ -277,6 +277,32 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             }
         }
     }
+    // ---- alpha hops: the row's list, partners read in place, the column part
+    // of each hop read per lane
+    if (row_live) {
+        const int h1 = ldc(s.ci_ah_off + ia + 1);
+        for (int h = ldc(s.ci_ah_off + ia) + split; h < h1; h += nsplit) {
+            const CiAlphaHop e = ldc(s.ci_ah + h);
+            const double2* prow = phi + size_t(e.w & 0xffffu) * NB;
+            const double* bp = s.ci_ahb + (size_t((e.w >> 16) & 0xffu) * 2 + ((e.w >> 24) & 1u)) * NB;
+            const bool neg = (e.w >> 25) & 1u;
+            double2 pv[COLS];
+            double bv[COLS];
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                pv[c] = ldg2(prow + ibc[c]);
+                bv[c] = ldg64(bp + ibc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const double v = e.coef + (neg ? -bv[c] : bv[c]);
+                const uint32_t flip = uint32_t(__popc(sB[c] & e.wb)) << 31;
+                const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
+                lr[c] += cf * pv[c].x;
+                li[c] += cf * pv[c].y;
+            }
+        }
+    }
     // ---- column moves, beta hops and the diagonal: the own row staged, each
     // lane walks its column's lists
     const bool diag = s.ci_dgx != nullptr && split == 0;

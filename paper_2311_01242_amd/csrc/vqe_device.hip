@@ -126,6 +126,17 @@ struct BetaHops {
     CiBetaHop* d_bh = nullptr;
     int nbh = 0;
 };
+struct AlphaHopGroup {
+    int pair = 0;                           // pair index of its two alpha orbitals
+    uint32_t xa = 0, lo = 0, hi = 0, wa0 = 0, wb0 = 0;
+    double S[4] = {0, 0, 0, 0};             // by alpha pattern (bit 0: orbital lo)
+    std::vector<double> Ta, Tb;             // -2 T_t, [orbital][4]
+};
+struct AlphaHops {
+    CiAlphaHop* d_ah = nullptr;
+    int32_t* d_off = nullptr;
+    double* d_b = nullptr;
+};
 // The diagonal group in occupation form: K + sum_t L_t n_t + sum_{t<u} Q_tu n_t n_u
 // (its Z_t and Z_t Z_u strings with Z = 1 - 2n), and its row and column parts
 // for one string space.
@@ -147,6 +158,8 @@ struct CiHam {
     std::vector<BetaHopGroup> bhg;
     double* d_hopa = nullptr;                      // alpha tables of the beta hops
     std::map<const CiSpace*, BetaHops*> bh;
+    std::vector<AlphaHopGroup> ahg;
+    std::map<const CiSpace*, AlphaHops*> ah;
     DiagForm diag;
     double* d_dgx = nullptr;                       // alpha-beta pair coefficients [alpha][16]
     std::map<const CiSpace*, DiagParts*> dg;
@@ -972,13 +985,56 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         }
         return true;
     };
+    // linear groups flipping two alpha orbitals only: row lists with a per-column
+    // beta part (CiAlphaHop)
+    const int pairs_a = oa_all * (oa_all - 1) / 2;
+    auto alpha_hop = [&](const G& o, AlphaHopGroup* out) {
+        const GroupDesc& gd = H->groups[o.gi];
+        const Layout l = layout(gd);
+        if (o.xb != 0 || __builtin_popcount(o.xa) != 2 || l.k != 2 || l.ka != 2) return false;
+        for (int c = gd.sub_begin; c < gd.sub_end; ++c) {
+            const uint32_t w0 = H->subs[c].w;
+            bool ok = true;
+            for (int si = gd.sub_begin; si < gd.sub_end && ok; ++si)
+                ok = __builtin_popcount(H->subs[si].w ^ w0) <= 1;
+            if (!ok) continue;
+            AlphaHopGroup r{};
+            r.xa = o.xa;
+            r.lo = uint32_t(__builtin_ctz(o.xa));
+            r.hi = uint32_t(31 - __builtin_clz(o.xa));
+            r.pair = pair_index(int(r.lo), int(r.hi), oa_all);
+            r.wa0 = compact_even_host(w0);
+            r.wb0 = compact_even_host(w0 >> 1);
+            r.Ta.assign(size_t(oa_all) * 4, 0.0);
+            r.Tb.assign(size_t(std::max(ob, 1)) * 4, 0.0);
+            for (int si = gd.sub_begin; si < gd.sub_end; ++si) {
+                std::vector<double> one;
+                push_table(l, H->subs[si], one);   // by alpha pattern (kb = 0)
+                for (int e = 0; e < 4; ++e) r.S[e] += one[size_t(e)];
+                const uint32_t dq = H->subs[si].w ^ w0;
+                if (!dq) continue;
+                const int q = __builtin_ctz(dq);
+                std::vector<double>& T = (q % 2 == 0) ? r.Ta : r.Tb;
+                for (int e = 0; e < 4; ++e) T[size_t(q / 2) * 4 + e] += -2.0 * one[size_t(e)];
+            }
+            *out = std::move(r);
+            return true;
+        }
+        return false;
+    };
     std::vector<RowMoveGroup> rmg;
     std::vector<ColMoveGroup> cmg;
     std::vector<BetaHopGroup> bhg;
+    std::vector<AlphaHopGroup> ahg;
     {
         std::vector<G> kept;
         for (const G& o : order) {
             if (diag_form(o)) continue;
+            AlphaHopGroup agp;
+            if (pairs_a > 0 && alpha_hop(o, &agp)) {
+                ahg.push_back(std::move(agp));
+                continue;
+            }
             BetaHopGroup bg;
             if (beta_hop(o, &bg)) {
                 bhg.push_back(std::move(bg));
@@ -1180,6 +1236,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
             for (int pi = 0; pi < 2; ++pi)
                 hopa[(size_t(g.pair) * 16 + t) * 2 + pi] = g.Ta[size_t(t) * 4 + pi + 1];
     c->bhg.swap(bhg);
+    c->ahg.swap(ahg);
     std::vector<double> dgx;
     if (dform.on) {
         const int n = H->n;
@@ -1543,6 +1600,65 @@ static int ci_betahops(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, Be
             return rc;
         }
     c->bh[key] = r;
+    *out = r;
+    return VQE_OK;
+}
+
+// Per-row lists of the alpha hops and their per-column beta parts for the
+// strings of `cs`.
+static int ci_alphahops(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, AlphaHops** out) {
+    std::lock_guard<std::mutex> lk(H->mu);
+    auto it = c->ah.find(&cs);
+    if (it != c->ah.end()) {
+        *out = it->second;
+        return VQE_OK;
+    }
+    const int pairs_a = cs.oa * (cs.oa - 1) / 2;
+    std::vector<CiAlphaHop> ah;
+    std::vector<int32_t> off;
+    for (int ia = 0; ia < cs.NA; ++ia) {
+        off.push_back(int32_t(ah.size()));
+        const uint32_t a = cs.sa[size_t(ia)];
+        for (const AlphaHopGroup& g : c->ahg) {
+            const uint32_t plo = (a >> g.lo) & 1u, phi_ = (a >> g.hi) & 1u;
+            if (plo == phi_) continue;
+            const int pat = int(plo | (phi_ << 1));
+            const bool neg = __builtin_popcount(a & g.wa0) & 1;
+            double v = g.S[pat];
+            for (uint32_t m = a & ~g.xa; m; m &= m - 1)
+                v += g.Ta[size_t(__builtin_ctz(m)) * 4 + size_t(pat)];
+            const int partner = cs.rank_a[size_t(a ^ g.xa)];
+            if (partner < 0) continue;
+            CiAlphaHop e{};
+            e.coef = neg ? -v : v;
+            e.w = uint32_t(partner) | (uint32_t(g.pair) << 16) | (uint32_t(pat - 1) << 24) |
+                  (uint32_t(neg) << 25);
+            e.wb = g.wb0;
+            ah.push_back(e);
+        }
+    }
+    off.push_back(int32_t(ah.size()));
+    std::vector<double> bpart(size_t(std::max(pairs_a, 1)) * 2 * size_t(cs.NB), 0.0);
+    for (const AlphaHopGroup& g : c->ahg)
+        for (int pi = 0; pi < 2; ++pi)
+            for (int ib = 0; ib < cs.NB; ++ib) {
+                double v = 0.0;
+                for (uint32_t m = cs.sb[size_t(ib)]; m; m &= m - 1)
+                    v += g.Tb[size_t(__builtin_ctz(m)) * 4 + size_t(pi + 1)];
+                bpart[(size_t(g.pair) * 2 + pi) * cs.NB + ib] = v;
+            }
+    auto* r = new AlphaHops();
+    int rc = upload(&r->d_off, off.data(), off.size());
+    if (!rc && !ah.empty()) rc = upload(&r->d_ah, ah.data(), ah.size());
+    if (!rc) rc = upload(&r->d_b, bpart.data(), bpart.size());
+    if (rc) {
+        (void)hipFree(r->d_off);
+        (void)hipFree(r->d_ah);
+        (void)hipFree(r->d_b);
+        delete r;
+        return rc;
+    }
+    c->ah[&cs] = r;
     *out = r;
     return VQE_OK;
 }
@@ -1928,6 +2044,12 @@ vqe_hamiltonian::~vqe_hamiltonian() {
                 (void)hipFree(r.second->d_col);
                 delete r.second;
             }
+            for (auto& r : c->ah) {
+                (void)hipFree(r.second->d_ah);
+                (void)hipFree(r.second->d_off);
+                (void)hipFree(r.second->d_b);
+                delete r.second;
+            }
             delete c;
         }
         delete kv.second;
@@ -2233,6 +2355,11 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         sd.ci_bh = bh->d_bh;
         sd.ci_nbh = bh->nbh;
         sd.ci_hopa = ch->d_hopa;
+        AlphaHops* ahp;
+        if (int rc = ci_alphahops(H, ch, *ep.cspace, &ahp)) return rc;
+        sd.ci_ah = ahp->d_ah;
+        sd.ci_ah_off = ahp->d_off;
+        sd.ci_ahb = ahp->d_b;
         if (ch->diag.on) {
             DiagParts* dp;
             if (int rc = ci_diag(H, ch, *ep.cspace, &dp)) return rc;
@@ -2683,6 +2810,11 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.ci_bh = bh->d_bh;
             sd.ci_nbh = bh->nbh;
             sd.ci_hopa = ch->d_hopa;
+            AlphaHops* ahp;
+            if (int rc = ci_alphahops(H[i], ch, *ep.cspace, &ahp)) return rc;
+            sd.ci_ah = ahp->d_ah;
+            sd.ci_ah_off = ahp->d_off;
+            sd.ci_ahb = ahp->d_b;
             if (ch->diag.on) {
                 DiagParts* dp;
                 if (int rc = ci_diag(H[i], ch, *ep.cspace, &dp)) return rc;
