@@ -2687,15 +2687,27 @@ int dalloc(vqe_batch* b, T** p, size_t count) {
     return VQE_OK;
 }
 
-// One full evaluation of every class; classes run on forked streams.
+// One full evaluation of every class; classes run on forked streams, the
+// heaviest first, each on the stream with the least work so far (work: the
+// class's run traffic, which scales with its state size, gate count and
+// states), so that the largest class does not queue behind others.
 int enqueue_batch(vqe_batch* b) {
     const size_t C = b->classes.size();
     const size_t ns = b->side.size();
     HIPCHK(hipEventRecord(b->events[0], b->st));
     for (size_t i = 0; i < ns; ++i) HIPCHK(hipStreamWaitEvent(b->side[i], b->events[0], 0));
+    std::vector<size_t> ord(C);
+    std::vector<double> w(C), load(ns, 0.0);
     for (size_t i = 0; i < C; ++i) {
+        ord[i] = i;
+        w[i] = double(b->classes[i].count) * (b->classes[i].ep.fwd_bytes + b->classes[i].ep.adj_bytes);
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t c) { return w[a] > w[c]; });
+    for (size_t i : ord) {
         auto& c = b->classes[i];
-        if (int rc = enqueue_eval(c.ep, b->sd_dev + c.k0, c.count, true, b->side[i % ns])) return rc;
+        const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += w[i];
+        if (int rc = enqueue_eval(c.ep, b->sd_dev + c.k0, c.count, true, b->side[k])) return rc;
     }
     for (size_t i = 0; i < ns; ++i) {
         HIPCHK(hipEventRecord(b->events[1 + i], b->side[i]));
