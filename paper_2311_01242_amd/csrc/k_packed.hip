@@ -102,6 +102,17 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const uint32_t* lbase = run.ent + lc.x;
     const int stride = lc.y;
     uint32_t ecur = (tid < stride) ? ldg32(lbase + size_t(fwd ? 0 : ng - 1) * stride + tid) : kPairNone;
+    // per-gate parameters of this tile after the tile (2 double2 per gate):
+    // (cos, sgn sin) and (sgn, 0), sgn the gate's pair sign from the tile's
+    // high bits; staged once, read by broadcast in the gate loop
+    double2* gpar = sh + size_t(VEC) * run.max_entries;
+    for (int j = tid; j < ng; j += BS) {
+        const PackedGate g = pg[j];
+        const double2 cs = s.cs[run.g0 + j];
+        const double sgn = g.csign * parity_sign(hb0 & g.chhi);
+        gpar[2 * j] = make_double2(cs.x, sgn * cs.y);
+        gpar[2 * j + 1] = make_double2(sgn, 0.0);
+    }
     {   // all loads first (clamped into the tile), then the LDS stores
         double2 vp[2 * EPT], vl[2 * EPT];
 #pragma unroll
@@ -120,27 +131,15 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             if (VEC == 2) shl[k] = vl[u];
         }
     }
-    // the gate descriptor and (cos, sin) are read one gate ahead as well, through
-    // the scalar cache (a vector load would make the wait for it also wait for
-    // the next gate's list entry)
-    PackedGate gcur = ldc(pg + (fwd ? 0 : ng - 1));
-    double2 cscur = ldc(s.cs + run.g0 + (fwd ? 0 : ng - 1));
     __syncthreads();
     for (int t = 0; t < ng; ++t) {
         const int jl = fwd ? t : ng - 1 - t;
         const int jn = fwd ? jl + 1 : jl - 1;
         const bool more = t + 1 < ng;
         const uint32_t enext = (more && tid < stride) ? ldg32(lbase + size_t(jn) * stride + tid) : kPairNone;
-        PackedGate gnext = gcur;
-        double2 csnext = cscur;
-        if (more) {
-            gnext = ldc(pg + jn);
-            csnext = ldc(s.cs + run.g0 + jn);
-        }
-        const PackedGate g = gcur;
-        const double2 cs = cscur;
-        const double sgn_hi = g.csign * parity_sign(hb0 & g.chhi);   // the tile's part of the sign
-        const double ssin = sgn_hi * cs.y;
+        const double2 cs = gpar[2 * jl];                // (cos, sgn sin)
+        const double sgn_hi = gpar[2 * jl + 1].x;      // the tile's part of the sign
+        const double ssin = cs.y;
         double acc = 0.0;
         for (int i = tid; i < stride; i += BS) {
             const uint32_t e = (i == tid) ? ecur : ldg32(lbase + size_t(jl) * stride + i);
@@ -177,8 +176,6 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         }
         __syncthreads();
         ecur = enext;
-        gcur = gnext;
-        cscur = csnext;
     }
     if (!fwd) {
         if (tid == 0) {
@@ -316,7 +313,7 @@ using PackedLauncher = void (*)(const StateDesc*, int, const PackedRun&, const P
 template <int VEC, int BS, int EPT>
 static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, hipStream_t st) {
-    const size_t lds = size_t(run.max_entries) * sizeof(double2) * VEC;
+    const size_t lds = (size_t(run.max_entries) * VEC + 2 * size_t(run.g1 - run.g0)) * sizeof(double2);
     hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(run.ntiles, count), dim3(BS), lds, st, sd, run,
                        pg, tabs, base);
 }

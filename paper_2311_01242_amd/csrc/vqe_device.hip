@@ -1431,7 +1431,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             p->gcnt[k] = r.ntiles;
         }
         p->gstride = std::max(p->gstride, r.ntiles);
-        p->max_lds = std::max(p->max_lds, size_t(maxe) * sizeof(double2) * 2);
+        p->max_lds = std::max(p->max_lds, (size_t(maxe) * 2 + 2 * size_t(ng)) * sizeof(double2));
         p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved);
         p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved);
         p->sweep_bytes += 2.0 * double(sizeof(double2)) * double(moved);
