@@ -62,6 +62,11 @@ struct StateDesc {
     int32_t ci_npcls;
     int32_t ci_ncm;          // column moves per column
     int32_t ci_nbh;          // beta hops per column
+    // 1: every pair record's beta sign mask is (beta orbitals strictly between
+    // the pair) ^ (its class's wbc without the pair's two orbitals); the list
+    // entry carries the first part's parity for its column (bit 25) and the
+    // pair's occupied orbital (bits 26..30)
+    int32_t ci_psplit;
 };
 
 // String-product ("CI") order of the sector: the amplitude of alpha string a
@@ -171,7 +176,8 @@ struct CiPairClass {
     int32_t half;
     int32_t rec0;
     int32_t rest0, rest1;    // the class's other groups (CiGroup with global subgroups)
-    int32_t pad[3];
+    uint32_t wbc;            // with ci_psplit: the beta chain mask shared by the class's records
+    int32_t pad[2];
 };
 
 struct CiPairRec {

@@ -219,19 +219,45 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             ww[j] = wb;
         }
         row_sync();
+        // per list entry: the pair's coefficient for the entry's pattern (one
+        // double of wc) and the partner amplitude; the walk is bound by these
+        // LDS reads, so the beta sign comes, when the records allow it, from
+        // the entry (bit 25: chain between the pair's orbitals; bits 26..30:
+        // the pair's occupied orbital) and one mask per class instead of a
+        // per-pair mask in LDS
         const uint32_t* lst = ci.plist;
-        for (int e = 0; e < ci.e1; ++e, lst += NB) {
+        const double* wcd = reinterpret_cast<const double*>(wc);
+        if (s.ci_psplit) {
+            uint32_t cfl[COLS];
 #pragma unroll
-            for (int c = 0; c < COLS; ++c) {
-                const uint32_t ent = ldg32(lst + ibc[c]);
-                const int pid = (ent >> 16) & 0xff;
-                const double2 cc = wc[pid];
-                const double2 p = row[ent & 0xffff];
-                const double t = ((ent >> 24) & 1) ? cc.y : cc.x;
-                const uint32_t flip = uint32_t(__popc(sB[c] & ww[pid])) << 31;
-                const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
-                lr[c] += coef * p.x;
-                li[c] += coef * p.y;
+            for (int c = 0; c < COLS; ++c) cfl[c] = uint32_t(__popc(sB[c] & P.wbc)) << 31;
+            for (int e = 0; e < ci.e1; ++e, lst += NB) {
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    const uint32_t ent = ldg32(lst + ibc[c]);
+                    const double t = wcd[2 * ((ent >> 16) & 0xff) + ((ent >> 24) & 1)];
+                    const double2 p = row[ent & 0xffff];
+                    // bit 25 -> 31, and the class mask at the occupied orbital of the
+                    // pair (bits 26..30), which cfl counted and the record leaves out
+                    const uint32_t flip = ((ent << 6) & 0x80000000u) ^ cfl[c] ^ ((P.wbc >> (ent >> 26)) << 31);
+                    const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+                    lr[c] += coef * p.x;
+                    li[c] += coef * p.y;
+                }
+            }
+        } else {
+            for (int e = 0; e < ci.e1; ++e, lst += NB) {
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    const uint32_t ent = ldg32(lst + ibc[c]);
+                    const int pid = (ent >> 16) & 0xff;
+                    const double t = wcd[2 * pid + ((ent >> 24) & 1)];
+                    const double2 p = row[ent & 0xffff];
+                    const uint32_t flip = uint32_t(__popc(sB[c] & ww[pid])) << 31;
+                    const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
+                    lr[c] += coef * p.x;
+                    li[c] += coef * p.y;
+                }
             }
         }
         for (int g = P.rest0; g < P.rest1; ++g) {   // the class's other groups

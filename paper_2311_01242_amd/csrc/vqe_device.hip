@@ -175,6 +175,7 @@ struct CiHam {
     CiSub* rsubs = nullptr;
     double* ptabs = nullptr;
     int npcls = 0;
+    bool psplit = false;   // pair records' beta sign masks split (see StateDesc::ci_psplit)
 };
 
 struct DevHam {
@@ -749,8 +750,11 @@ static int ci_space(int n, int ne, CiSpace** out) {
                 const int bp = (b >> p) & 1, bq = (b >> q) & 1;
                 if (bp == bq) continue;
                 const int16_t r = c->rank_b[b ^ (1u << p) ^ (1u << q)];
+                const uint32_t between = ((1u << q) - 1u) & ~((2u << p) - 1u);   // orbitals p+1 .. q-1
                 plist[size_t(e) * c->NB + ib] = uint32_t(r) | (uint32_t(pair_index(p, q, c->ob)) << 16) |
-                                                (uint32_t(bq) << 24);
+                                                (uint32_t(bq) << 24) |
+                                                (uint32_t(__builtin_popcount(b & between) & 1) << 25) |
+                                                (uint32_t(bq ? q : p) << 26);
                 ++e;
             }
     }
@@ -1075,6 +1079,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         if (pair_eligible(o)) is_pair[o.xa] = 1;
     // ---- beta-pair classes
     std::vector<CiPairClass> pcls;
+    bool psplit = true;   // every class's records share one beta chain mask beyond their own pair
     std::vector<CiPairRec> precs;
     std::vector<CiGroup> rgrp;
     std::vector<CiSub> rsub;
@@ -1089,6 +1094,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
             pc.rec0 = int32_t(precs.size());
             precs.resize(precs.size() + size_t(npairs), CiPairRec{-1, 0u, 0u, 0});
             pc.rest0 = int32_t(rgrp.size());
+            uint32_t known = 0;   // bits of the class mask fixed by some record
             for (size_t t = i; t < j; ++t) {
                 const G& o = order[t];
                 const GroupDesc& gd = H->groups[o.gi];
@@ -1102,6 +1108,14 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
                     r.wb = compact_even_host(sd.w >> 1);
                     r.ka = l.ka;
                     push_table(l, sd, ptab);
+                    // the record's mask must be (orbitals strictly between p and q)
+                    // ^ (the class mask off p and q): bits p, q of the class mask
+                    // cancel in the kernel (a listed column has exactly one of them)
+                    const uint32_t between = ((1u << q) - 1u) & ~((2u << p) - 1u);
+                    const uint32_t pq = (1u << p) | (1u << q), m = r.wb ^ between;
+                    if ((m & pq) != 0 || ((m ^ pc.wbc) & known & ~pq) != 0) psplit = false;
+                    pc.wbc |= m & ~known & ~pq;
+                    known |= ~pq;
                 } else {
                     CiGroup g = make_group(o, l, 0);
                     std::vector<double> lt;
@@ -1228,6 +1242,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     c->nchunks = int(chunks.size());
     c->ob = ob;
     c->npcls = int(pcls.size());
+    c->psplit = psplit;
     c->rmg.swap(rmg);
     c->cmg.swap(cmg);
     std::vector<double> hopa(size_t(std::max(npairs, 1)) * 16 * 2, 0.0);
@@ -2342,6 +2357,7 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         sd.ci_rsubs = ch->rsubs;
         sd.ci_ptabs = ch->ptabs;
         sd.ci_npcls = ch->npcls;
+        sd.ci_psplit = ch->psplit ? 1 : 0;
         RowMoves* rm;
         if (int rc = ci_rowmoves(H, ch, *ep.cspace, &rm)) return rc;
         sd.ci_rm = rm->d_rm;
@@ -2809,6 +2825,7 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.ci_rsubs = ch->rsubs;
             sd.ci_ptabs = ch->ptabs;
             sd.ci_npcls = ch->npcls;
+            sd.ci_psplit = ch->psplit ? 1 : 0;
             RowMoves* rm;
             if (int rc = ci_rowmoves(H[i], ch, *ep.cspace, &rm)) return rc;
             sd.ci_rm = rm->d_rm;

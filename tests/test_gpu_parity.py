@@ -388,3 +388,50 @@ def test_string_product_long_rows_match_block_order():
     e1, g1 = _eval_layout(H, n, ne, theta, 1)
     assert abs(e2 - e1) < 1e-12 * max(1.0, abs(e1)) * 10
     assert np.abs(g2 - g1).max() < 1e-11
+
+
+@pytest.mark.parametrize("n,ne", [(8, 4), (11, 5)])
+def test_pair_records_off_the_chain_pattern(n, ne):
+    """The string-product H-apply takes the beta signs of its alpha-beta pair
+    records from the list entries when every record's mask is the chain
+    between the pair's orbitals plus one mask per class (the Jordan-Wigner
+    form), else from a per-pair mask.  Here every term of one alpha-beta
+    double shape gets an extra Z on a beta qubit inside its chain (still
+    Hermitian), which breaks that pattern: the packed path must match full
+    vectors and the oracle's dense Pauli sums (energy and gradient)."""
+    h0, h, g = random_integrals(n, 1300 + n)
+    S = dict(P.jw_hamiltonian(n, h0, h, g))
+    x0 = (1 << 0) | (1 << 2) | (1 << 3) | (1 << 7)   # alpha 0, 1 and beta 1, 3
+    keys = [k for k in S if k[0] == x0]
+    assert len(keys) >= 4 and all(k[1] & (1 << 5) for k in keys)   # beta 2 lies on the chain
+    for k in keys:
+        S[(k[0], k[1] ^ (1 << 5))] = S.pop(k)
+    fold = P.folded_terms(S)   # the boundary's real form c i^{#Y} X^x Z^z
+    H = vq.Hamiltonian.from_paulis(n, np.array([k[0] for k in fold], np.uint32),
+                                   np.array([k[1] for k in fold], np.uint32),
+                                   np.array(list(fold.values())))
+    A = vq.Ansatz.uccsd(n, ne)
+    excs = F.uccsd_excitations(n, ne)
+    theta = uniform_theta(n + 40, A.n_params, -0.4, 0.4)
+    out = {}
+    try:
+        for mode in (2, 0):
+            vq.set_packed(mode)
+            out[mode] = vq.energy_grad(H, A, ne, theta)
+    finally:
+        vq.set_packed(2)
+    e_or = P.energy(S, P.prepare(n, ne, excs, theta), n)
+    assert abs(out[2][0] - e_or) < TOL_E and abs(out[0][0] - e_or) < TOL_E
+    assert np.abs(out[2][1] - out[0][1]).max() < TOL_E
+    # the altered terms matter
+    e_jw = P.energy(P.jw_hamiltonian(n, h0, h, g), P.prepare(n, ne, excs, theta), n)
+    assert abs(e_or - e_jw) > 1e-6
+    # sampled gradient components against the oracle's shift rule
+    c2 = (math.sqrt(2.0) - 1.0) / 2.0
+    for j in (0, A.n_params // 2, A.n_params - 1):
+        def e(d):
+            t = theta.copy()
+            t[j] += d
+            return P.energy(S, P.prepare(n, ne, excs, t), n)
+        gj = (e(math.pi / 4) - e(-math.pi / 4)) - c2 * (e(math.pi / 2) - e(-math.pi / 2))
+        assert abs(out[2][1][j] - gj) < TOL_E
