@@ -13,6 +13,8 @@
 // xb = 0 read the partner in the same column straight from memory.  The
 // workgroup's rows share the group, subgroup and table data, staged chunk by
 // chunk in LDS with the next chunk's loads in flight during the current one.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace vqe {
@@ -307,27 +309,42 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     // of each hop read per lane
     if (row_live) {
         const int h1 = ldc(s.ci_ah_off + ia + 1);
-        for (int h = ldc(s.ci_ah_off + ia) + split; h < h1; h += nsplit) {
-            const CiAlphaHop e = ldc(s.ci_ah + h);
-            const double2* prow = phi + size_t(e.w & 0xffffu) * NB;
-            const double* bp = s.ci_ahb + (size_t((e.w >> 16) & 0xffu) * 2 + ((e.w >> 24) & 1u)) * NB;
-            const bool neg = (e.w >> 25) & 1u;
-            double2 pv[COLS];
-            double bv[COLS];
+        // kH hops per pass: their records (scalar loads) and then their
+        // partner and column-part loads all in flight together
+        constexpr int kH = COLS <= 2 ? 4 : 2;
+        int h = ldc(s.ci_ah_off + ia) + split;
+        auto hops = [&](auto nh) {
+            constexpr int NH = decltype(nh)::value;
+            CiAlphaHop e[NH];
 #pragma unroll
-            for (int c = 0; c < COLS; ++c) {
-                pv[c] = ldg2(prow + ibc[c]);
-                bv[c] = ldg64(bp + ibc[c]);
+            for (int u = 0; u < NH; ++u) e[u] = ldc(s.ci_ah + h + u * nsplit);
+            double2 pv[NH][COLS];
+            double bv[NH][COLS];
+#pragma unroll
+            for (int u = 0; u < NH; ++u) {
+                const double2* prow = phi + size_t(e[u].w & 0xffffu) * NB;
+                const double* bp = s.ci_ahb + (size_t((e[u].w >> 16) & 0xffu) * 2 + ((e[u].w >> 24) & 1u)) * NB;
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    pv[u][c] = ldg2(prow + ibc[c]);
+                    bv[u][c] = ldg64(bp + ibc[c]);
+                }
             }
 #pragma unroll
-            for (int c = 0; c < COLS; ++c) {
-                const double v = e.coef + (neg ? -bv[c] : bv[c]);
-                const uint32_t flip = uint32_t(__popc(sB[c] & e.wb)) << 31;
-                const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
-                lr[c] += cf * pv[c].x;
-                li[c] += cf * pv[c].y;
+            for (int u = 0; u < NH; ++u) {
+                const bool neg = (e[u].w >> 25) & 1u;
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) {
+                    const double v = e[u].coef + (neg ? -bv[u][c] : bv[u][c]);
+                    const uint32_t flip = uint32_t(__popc(sB[c] & e[u].wb)) << 31;
+                    const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
+                    lr[c] += cf * pv[u][c].x;
+                    li[c] += cf * pv[u][c].y;
+                }
             }
-        }
+        };
+        for (; h + (kH - 1) * nsplit < h1; h += kH * nsplit) hops(std::integral_constant<int, kH>{});
+        for (; h < h1; h += nsplit) hops(std::integral_constant<int, 1>{});
     }
     // ---- column moves, beta hops and the diagonal: the own row staged, each
     // lane walks its column's lists
@@ -387,18 +404,32 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     }
     if (row_live && s.ci_ncm > 0) {
         const double2* cmv = reinterpret_cast<const double2*>(s.ci_cm);
-        for (int e = split; e < s.ci_ncm; e += nsplit) {
+        auto move = [&](const double2 q, int c) {   // q = {coef, partner | wa << 32}
+            const uint64_t pw = uint64_t(__double_as_longlong(q.y));
+            const double2 pv = row[int(uint32_t(pw))];
+            const uint32_t flip = uint32_t(__popc(sA & uint32_t(pw >> 32))) << 31;
+            const double cf = __hiloint2double(__double2hiint(q.x) ^ int(flip), __double2loint(q.x));
+            lr[c] += cf * pv.x;
+            li[c] += cf * pv.y;
+        };
+        // the moves' records (per column, the same for every row) come from L2:
+        // kM of them in flight per pass
+        constexpr int kM = COLS <= 2 ? 4 : 2;
+        int e = split;
+        for (; e + (kM - 1) * nsplit < s.ci_ncm; e += kM * nsplit) {
+            double2 q[kM][COLS];
 #pragma unroll
-            for (int c = 0; c < COLS; ++c) {
-                const double2 q = ldg2(cmv + size_t(e) * NB + ibc[c]);   // {coef, partner | wa << 32}
-                const uint64_t pw = uint64_t(__double_as_longlong(q.y));
-                const double2 pv = row[int(uint32_t(pw))];
-                const uint32_t flip = uint32_t(__popc(sA & uint32_t(pw >> 32))) << 31;
-                const double cf = __hiloint2double(__double2hiint(q.x) ^ int(flip), __double2loint(q.x));
-                lr[c] += cf * pv.x;
-                li[c] += cf * pv.y;
-            }
+            for (int u = 0; u < kM; ++u)
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) q[u][c] = ldg2(cmv + size_t(e + u * nsplit) * NB + ibc[c]);
+#pragma unroll
+            for (int u = 0; u < kM; ++u)
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) move(q[u][c], c);
         }
+        for (; e < s.ci_ncm; e += nsplit)
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) move(ldg2(cmv + size_t(e) * NB + ibc[c]), c);
     }
     // ---- generic groups, chunk by chunk (chunks split, split + nsplit, ...)
     const int nch = s.ci_nchunks;
