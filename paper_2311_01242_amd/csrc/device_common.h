@@ -64,8 +64,7 @@ struct StateDesc {
     int32_t ci_nbh;          // beta hops per column
     // 1: every pair record's beta sign mask is (beta orbitals strictly between
     // the pair) ^ (its class's wbc without the pair's two orbitals); the list
-    // entry carries the first part's parity for its column (bit 25) and the
-    // pair's occupied orbital (bits 26..30)
+    // entry carries the first part's parity for its column (bit 31)
     int32_t ci_psplit;
 };
 
@@ -183,7 +182,8 @@ struct CiPairClass {
 struct CiPairRec {
     int32_t tab;             // table offset (-1: the class has no group for this pair)
     uint32_t wa, wb;
-    int32_t ka;              // alpha table bits: entry (alpha pattern) | (beta pattern << ka)
+    int32_t ka;              // bits 0..7: alpha table bits, entry (alpha pattern) | (beta pattern << ka);
+                             // bits 8..15 and 16..23: the pair's beta orbitals p < q
 };
 
 struct CiArgs {

@@ -212,21 +212,25 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             double c1 = 0.0, c2 = 0.0;
             uint32_t wb = 0;
             if (r.tab >= 0) {
+                const int ka = r.ka & 0xff;
                 const double sg = (__popc(sA & r.wa) & 1) ? -1.0 : 1.0;
-                c1 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (1u << r.ka)));
-                c2 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (2u << r.ka)));
+                c1 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (1u << ka)));
+                c2 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (2u << ka)));
                 wb = r.wb;
+                if (s.ci_psplit) {   // the class mask at the output's occupied orbital: p (c1) or q (c2)
+                    if ((P.wbc >> ((r.ka >> 8) & 0xff)) & 1u) c1 = -c1;
+                    if ((P.wbc >> ((r.ka >> 16) & 0xff)) & 1u) c2 = -c2;
+                }
             }
             wc[j] = make_double2(c1, c2);
             ww[j] = wb;
         }
         row_sync();
-        // per list entry: the pair's coefficient for the entry's pattern (one
-        // double of wc) and the partner amplitude; the walk is bound by these
-        // LDS reads, so the beta sign comes, when the records allow it, from
-        // the entry (bit 25: chain between the pair's orbitals; bits 26..30:
-        // the pair's occupied orbital) and one mask per class instead of a
-        // per-pair mask in LDS
+        // per list entry (partner column | (2 pair + pattern) << 16 | chain
+        // parity << 31): the pair's coefficient for the entry's pattern (one
+        // double of wc) and the partner amplitude; the beta sign comes, when
+        // the records allow it, from the entry and one mask per class instead
+        // of a per-pair mask in LDS
         const uint32_t* lst = ci.plist;
         const double* wcd = reinterpret_cast<const double*>(wc);
         if (s.ci_psplit) {
@@ -237,11 +241,12 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
                 for (int c = 0; c < COLS; ++c) {
                     const uint32_t ent = ldg32(lst + ibc[c]);
-                    const double t = wcd[2 * ((ent >> 16) & 0xff) + ((ent >> 24) & 1)];
+                    const double t = wcd[(ent >> 16) & 0x1ff];   // 2 pair + pattern
                     const double2 p = row[ent & 0xffff];
-                    // bit 25 -> 31, and the class mask at the occupied orbital of the
-                    // pair (bits 26..30), which cfl counted and the record leaves out
-                    const uint32_t flip = ((ent << 6) & 0x80000000u) ^ cfl[c] ^ ((P.wbc >> (ent >> 26)) << 31);
+                    // chain parity (bit 31) and the class mask over the column; the
+                    // class mask's bit at the pair's occupied orbital, which cfl
+                    // counted and the record leaves out, is in the coefficient
+                    const uint32_t flip = (ent & 0x80000000u) ^ cfl[c];
                     const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
                     lr[c] += coef * p.x;
                     li[c] += coef * p.y;
@@ -252,8 +257,8 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
                 for (int c = 0; c < COLS; ++c) {
                     const uint32_t ent = ldg32(lst + ibc[c]);
-                    const int pid = (ent >> 16) & 0xff;
-                    const double t = wcd[2 * pid + ((ent >> 24) & 1)];
+                    const int pid = (ent >> 17) & 0xff;
+                    const double t = wcd[(ent >> 16) & 0x1ff];
                     const double2 p = row[ent & 0xffff];
                     const uint32_t flip = uint32_t(__popc(sB[c] & ww[pid])) << 31;
                     const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));

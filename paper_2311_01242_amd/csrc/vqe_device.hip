@@ -751,10 +751,9 @@ static int ci_space(int n, int ne, CiSpace** out) {
                 if (bp == bq) continue;
                 const int16_t r = c->rank_b[b ^ (1u << p) ^ (1u << q)];
                 const uint32_t between = ((1u << q) - 1u) & ~((2u << p) - 1u);   // orbitals p+1 .. q-1
-                plist[size_t(e) * c->NB + ib] = uint32_t(r) | (uint32_t(pair_index(p, q, c->ob)) << 16) |
-                                                (uint32_t(bq) << 24) |
-                                                (uint32_t(__builtin_popcount(b & between) & 1) << 25) |
-                                                (uint32_t(bq ? q : p) << 26);
+                plist[size_t(e) * c->NB + ib] = uint32_t(r) |
+                                                (uint32_t(2 * pair_index(p, q, c->ob) + bq) << 16) |
+                                                (uint32_t(__builtin_popcount(b & between) & 1) << 31);
                 ++e;
             }
     }
@@ -1106,7 +1105,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
                     r.tab = int32_t(ptab.size());
                     r.wa = compact_even_host(sd.w);
                     r.wb = compact_even_host(sd.w >> 1);
-                    r.ka = l.ka;
+                    r.ka = l.ka | (p << 8) | (q << 16);
                     push_table(l, sd, ptab);
                     // the record's mask must be (orbitals strictly between p and q)
                     // ^ (the class mask off p and q): bits p, q of the class mask
