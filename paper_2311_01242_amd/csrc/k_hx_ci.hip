@@ -237,10 +237,18 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             uint32_t cfl[COLS];
 #pragma unroll
             for (int c = 0; c < COLS; ++c) cfl[c] = uint32_t(__popc(sB[c] & P.wbc)) << 31;
-            for (int e = 0; e < ci.e1; ++e, lst += NB) {
+            // the list through a buffer resource: the lane's byte offset is fixed
+            // and each step adds a scalar offset, so no per-lane address math
+            // (the resource also bounds the reads to the list)
+            const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint32_t*>(ci.plist), 0, int(uint32_t(ci.e1) * uint32_t(NB) * 4u), 0x00020000);
+            uint32_t voff[COLS];
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) voff[c] = uint32_t(ibc[c]) * 4u;
+            for (int e = 0; e < ci.e1; ++e) {
 #pragma unroll
                 for (int c = 0; c < COLS; ++c) {
-                    const uint32_t ent = ldg32(lst + ibc[c]);
+                    const uint32_t ent = __builtin_amdgcn_raw_buffer_load_b32(lrs, voff[c], e * NB * 4, 0);
                     const double t = wcd[(ent >> 16) & 0x1ff];   // 2 pair + pattern
                     const double2 p = row[ent & 0xffff];
                     // chain parity (bit 31) and the class mask over the column; the
