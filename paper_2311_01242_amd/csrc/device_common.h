@@ -42,6 +42,7 @@ struct StateDesc {
     const struct CiGroup* ci_rgroups;    // their other groups
     const struct CiSub* ci_rsubs;
     const double* ci_ptabs;              // tables of the pair classes (global offsets)
+    const double2* ci_pcoef;             // per class, alpha pattern and pair: the two coefficients
     const struct CiRowMove* ci_rm;       // row moves of each alpha string
     const int32_t* ci_rm_off;            // [na_str + 1] offsets into ci_rm
     const struct CiColMove* ci_cm;       // column moves, entry-major [ci_ncm][nb_str]
@@ -176,7 +177,8 @@ struct CiPairClass {
     int32_t rec0;
     int32_t rest0, rest1;    // the class's other groups (CiGroup with global subgroups)
     uint32_t wbc;            // with ci_psplit: the beta chain mask shared by the class's records
-    int32_t pad[2];
+    int32_t coef0;           // its block of ci_pcoef: [alpha pattern][pair] (c1, c2)
+    int32_t pad;
 };
 
 struct CiPairRec {

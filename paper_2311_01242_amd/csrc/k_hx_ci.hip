@@ -207,23 +207,14 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         if (__popc(sA & P.xa) != P.half) continue;   // no in-sector partner row
         stage_row(phi + size_t(ldc(ci.rank_a + (sA ^ P.xa))) * NB);
         const uint32_t ta = pext_mask(sA, P.xa);
-        for (int j = rt; j < ci.npairs; j += 64 * W) {   // this row's coefficient of each pair
-            const CiPairRec r = s.ci_precs[P.rec0 + j];
-            double c1 = 0.0, c2 = 0.0;
-            uint32_t wb = 0;
-            if (r.tab >= 0) {
-                const int ka = r.ka & 0xff;
-                const double sg = (__popc(sA & r.wa) & 1) ? -1.0 : 1.0;
-                c1 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (1u << ka)));
-                c2 = sg * ldg64(s.ci_ptabs + r.tab + int(ta | (2u << ka)));
-                wb = r.wb;
-                if (s.ci_psplit) {   // the class mask at the output's occupied orbital: p (c1) or q (c2)
-                    if ((P.wbc >> ((r.ka >> 8) & 0xff)) & 1u) c1 = -c1;
-                    if ((P.wbc >> ((r.ka >> 16) & 0xff)) & 1u) c2 = -c2;
-                }
-            }
-            wc[j] = make_double2(c1, c2);
-            ww[j] = wb;
+        // this row's coefficients of each pair: the class's precomputed pair for
+        // the row's alpha pattern, signed by the row's alpha chain parity
+        const double2* pco = s.ci_pcoef + P.coef0 + size_t(ta) * ci.npairs;
+        for (int j = rt; j < ci.npairs; j += 64 * W) {
+            const double2 cc = ldg2(pco + j);
+            const bool neg = __popc(sA & ldg32(&s.ci_precs[P.rec0 + j].wa)) & 1;
+            wc[j] = neg ? make_double2(-cc.x, -cc.y) : cc;
+            if (!s.ci_psplit) ww[j] = ldg32(&s.ci_precs[P.rec0 + j].wb);
         }
         row_sync();
         // per list entry (partner column | (2 pair + pattern) << 16 | chain

@@ -174,6 +174,7 @@ struct CiHam {
     CiGroup* rgroups = nullptr;
     CiSub* rsubs = nullptr;
     double* ptabs = nullptr;
+    double2* pcoef = nullptr;   // pair coefficients by class, alpha pattern and pair
     int npcls = 0;
     bool psplit = false;   // pair records' beta sign masks split (see StateDesc::ci_psplit)
 };
@@ -1237,6 +1238,28 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     }
     close();
     if (chunks.empty()) chunks.push_back(CiChunk{});   // nothing generic: one empty chunk
+    // the pair coefficients of every class for every alpha pattern of its flipped
+    // alpha orbitals (patterns 1 and 2 of the beta pair), from the tables; with
+    // psplit, each carries the class mask's bit at the pair orbital the output
+    // occupies (p for the first, q for the second)
+    std::vector<double2> pcoef;
+    for (CiPairClass& pc : pcls) {
+        const int ka = __builtin_popcount(pc.xa);
+        pc.coef0 = int32_t(pcoef.size());
+        for (uint32_t ta = 0; ta < (1u << ka); ++ta)
+            for (int jp = 0; jp < npairs; ++jp) {
+                const CiPairRec& r = precs[size_t(pc.rec0 + jp)];
+                double c1 = 0.0, c2 = 0.0;
+                if (r.tab >= 0) {
+                    const int rka = r.ka & 0xff, p = (r.ka >> 8) & 0xff, q = (r.ka >> 16) & 0xff;
+                    c1 = ptab[size_t(r.tab) + (ta | (1u << rka))];
+                    c2 = ptab[size_t(r.tab) + (ta | (2u << rka))];
+                    if (psplit && ((pc.wbc >> p) & 1u)) c1 = -c1;
+                    if (psplit && ((pc.wbc >> q) & 1u)) c2 = -c2;
+                }
+                pcoef.push_back(make_double2(c1, c2));
+            }
+    }
     auto* c = new CiHam();
     c->nchunks = int(chunks.size());
     c->ob = ob;
@@ -1273,6 +1296,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
     if (!rc) rc = upload(&c->rgroups, rgrp.data(), rgrp.size());
     if (!rc) rc = upload(&c->rsubs, rsub.data(), rsub.size());
     if (!rc) rc = upload(&c->ptabs, ptab.data(), ptab.size());
+    if (!rc) rc = upload(&c->pcoef, pcoef.data(), pcoef.size());
     if (rc) {
         (void)hipFree(c->chunks);
         (void)hipFree(c->groups);
@@ -1283,6 +1307,7 @@ static int ci_ham(const vqe_hamiltonian* H, DevHam* d, CiHam** out) {
         (void)hipFree(c->rgroups);
         (void)hipFree(c->rsubs);
         (void)hipFree(c->ptabs);
+        (void)hipFree(c->pcoef);
         (void)hipFree(c->d_hopa);
         (void)hipFree(c->d_dgx);
         delete c;
@@ -2038,6 +2063,7 @@ vqe_hamiltonian::~vqe_hamiltonian() {
             (void)hipFree(c->rgroups);
             (void)hipFree(c->rsubs);
             (void)hipFree(c->ptabs);
+            (void)hipFree(c->pcoef);
             for (auto& r : c->rm) {
                 (void)hipFree(r.second->d_rm);
                 (void)hipFree(r.second->d_off);
@@ -2355,6 +2381,7 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
         sd.ci_rgroups = ch->rgroups;
         sd.ci_rsubs = ch->rsubs;
         sd.ci_ptabs = ch->ptabs;
+        sd.ci_pcoef = ch->pcoef;
         sd.ci_npcls = ch->npcls;
         sd.ci_psplit = ch->psplit ? 1 : 0;
         RowMoves* rm;
@@ -2823,6 +2850,7 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
             sd.ci_rgroups = ch->rgroups;
             sd.ci_rsubs = ch->rsubs;
             sd.ci_ptabs = ch->ptabs;
+            sd.ci_pcoef = ch->pcoef;
             sd.ci_npcls = ch->npcls;
             sd.ci_psplit = ch->psplit ? 1 : 0;
             RowMoves* rm;
