@@ -155,6 +155,11 @@ CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
 # lane-operations per second of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_PAIR = 4   # sign parity (AND + BCNT) and a real-by-complex multiply-add (2 FMA)
+# published FP64 vector peak, and the floating-point work of one nonzero matrix
+# element applied to a complex amplitude (real element x complex value,
+# accumulated: two FMA)
+FP64_PEAK_TFLOPS = 78.6
+FLOPS_PER_ELEMENT = 4
 
 # phase -> (kernel, source file, bound)
 PHASE_KERNELS = {
@@ -176,12 +181,12 @@ def _binom(n, k):
     return comb(n, k, exact=False)
 
 
-def sector_pairs(H, n, ne):
-    """(output, term) pairs of the H-apply whose output and partner both lie in
-    the (N, S_z) sector of the reference: for a term X^x Z^z, the outputs that
-    have half of x's alpha bits and half of its beta bits occupied."""
+def sector_elements(H, n, ne):
+    """Nonzero matrix elements of H inside the (N, S_z) sector of the
+    reference: (output, distinct x-mask) pairs whose partner output ^ x is in
+    the sector too (the terms sharing an x-mask add up to one element)."""
     x, _, _ = H.terms()
-    x = x.astype(np.uint64)
+    x = np.unique(x).astype(np.uint64)
     pa = np.array([bin(int(v) & 0x55555555).count("1") for v in x])
     pb = np.array([bin(int(v) & 0xAAAAAAAA).count("1") for v in x])
     na, nb = (ne + 1) // 2, ne // 2
@@ -198,26 +203,35 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
     forked streams, so phases cannot be timed there); the dominant phase's
     kernel is reported as `roofline`.  Gate runs: algorithmic bytes from the
     launch plan (each live tile read and written once) against HBM peak.
-    H-apply: 4 lane-operations per in-sector (output, term) pair against the
-    vector-ALU lane rate.  `traffic` is the rocprof FETCH+WRITE measurement of
-    the kernel, reported only while its source still matches the measured one."""
+    H-apply on the sector: 4 FP64 flops per nonzero in-sector matrix element
+    (sector_elements) against the FP64 vector peak; a full-vector H-apply
+    (`pairs` given: every (amplitude, term) pair it evaluates) at 4
+    lane-operations per pair against the vector-ALU lane rate.  `traffic` is
+    the rocprof FETCH+WRITE measurement of the kernel, reported only while its
+    source still matches the measured one."""
     kernels = PHASE_KERNELS if kernels is None else kernels
     phase_ms = b.profile(theta, reps=reps)
     w = b.work()
-    if pairs is None:
-        pairs = sum(sector_pairs(H, H.info()[0], ne) for H, ne in zip(Hs, nes))
+    sector = pairs is None
+    if sector:
+        elements = sum(sector_elements(H, H.info()[0], ne) for H, ne in zip(Hs, nes))
+        h_work = FLOPS_PER_ELEMENT * elements
+    else:
+        h_work = OPS_PER_PAIR * pairs
     traffic = {}
     if os.path.exists(TRAFFIC):
         with open(TRAFFIC) as f:
             traffic = json.load(f).get("kernels", {})
     recs = {}
     for i, (phase, work, launches) in enumerate(
-            [("forward", w[0], w[4]), ("h_apply", OPS_PER_PAIR * pairs, w[5]),
+            [("forward", w[0], w[4]), ("h_apply", h_work, w[5]),
              ("adjoint", w[2], w[6])]):
         kernel, src, bound = kernels[phase]
         t_s = phase_ms[i] * 1e-3
         if bound == "hbm":
             achieved, peak, unit = work / t_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        elif sector:
+            achieved, peak, unit = work / t_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
         else:
             achieved, peak, unit = work / t_s / 1e12, VALU_PEAK_TOPS, "Top/s"
         t = traffic.get(phase)
@@ -225,7 +239,8 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
         recs[phase] = {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3 if bound == "alu" else 1),
                        "peak": round(peak, 2), "unit": unit, "frac": round(achieved / peak, 4),
                        "traffic": measured,
-                       ("algorithmic_bytes_per_launch" if bound == "hbm" else "algorithmic_ops_per_launch"):
+                       ("algorithmic_bytes_per_launch" if bound == "hbm" else
+                        "algorithmic_flops_per_launch" if sector else "algorithmic_ops_per_launch"):
                            round(work / launches, 1),
                        "avg_launch_us": round(1e3 * phase_ms[i] / launches, 2),
                        "launches_per_eval": int(launches), "phase_ms": round(phase_ms[i], 3)}
@@ -236,7 +251,10 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
                      for k, v in recs.items()}
     out["phase_ms"] = {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
                        "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}
-    out["in_sector_term_pairs_per_eval"] = pairs
+    if sector:
+        out["in_sector_matrix_elements_per_eval"] = elements
+    else:
+        out["term_pairs_per_eval"] = pairs
     return out
 
 
@@ -558,17 +576,17 @@ def run_adapt20(args):
     dt = time.perf_counter() - t0
     assert np.isfinite(e) and np.all(np.isfinite(gp))
     ms, w = vq.pool_gradient_profile(H, A, pool, ne, th, reps=args.profile_reps)
-    pairs = sector_pairs(H, n, ne)
+    elements = sector_elements(H, n, ne)
     recs = {}
     for i, (phase, work, bound, kernel) in enumerate([
             ("forward", w[0], "hbm", PHASE_KERNELS["forward"][0]),
-            ("h_apply", OPS_PER_PAIR * pairs, "alu", PHASE_KERNELS["h_apply"][0]),
+            ("h_apply", FLOPS_PER_ELEMENT * elements, "alu", PHASE_KERNELS["h_apply"][0]),
             ("pool_sweep", w[2], "hbm", "k_ppool<*,*> (one read-only launch: the pool at angle 0)")]):
         t_s = ms[i] * 1e-3
         if bound == "hbm":
             achieved, peak, unit = work / t_s / 1e9, HBM_PEAK_GBS, "GB/s"
         else:
-            achieved, peak, unit = work / t_s / 1e12, VALU_PEAK_TOPS, "Top/s"
+            achieved, peak, unit = work / t_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
         recs[phase] = {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3),
                        "peak": round(peak, 2), "unit": unit, "frac": round(achieved / peak, 4),
                        "traffic": None, "phase_ms": round(ms[i], 4)}

@@ -1,5 +1,5 @@
 """CPU checks of the benchmark's work accounting (no GPU): the in-sector
-(output, term) pair count used for the H-apply roofline against brute-force
+matrix-element count used for the H-apply roofline against brute-force
 enumeration of the sector."""
 import os
 import sys
@@ -12,7 +12,7 @@ sys.path.insert(0, ROOT)
 
 
 @pytest.mark.parametrize("n,ne,seed", [(6, 3, 1), (7, 3, 2), (8, 4, 3), (9, 5, 4)])
-def test_sector_pairs_match_enumeration(n, ne, seed):
+def test_sector_elements_match_enumeration(n, ne, seed):
     import bench
     import paper_2311_01242_amd as vq
     from vqe_inputs import random_integrals
@@ -25,5 +25,12 @@ def test_sector_pairs_match_enumeration(n, ne, seed):
         return bin(s & 0x55555555).count("1") == na and bin(s & 0xAAAAAAAA).count("1") == nb
 
     sector = [s for s in range(1 << n) if in_sector(s)]
-    brute = sum(1 for xi in x for s in sector if in_sector(s ^ int(xi)))
-    assert bench.sector_pairs(H, n, ne) == brute
+    # one element per (output, distinct x-mask) with the partner in the sector
+    brute = sum(1 for xi in set(int(v) for v in x) for s in sector if in_sector(s ^ xi))
+    assert bench.sector_elements(H, n, ne) == brute
+    # and the nonzero entries of the sector block of the oracle's dense matrix
+    # (random integrals: no element cancels), diagonal included
+    if n <= 8:
+        from oracle import pauli as P
+        m = P.matrix(P.jw_hamiltonian(n, h0, h, g), n)
+        assert np.count_nonzero(np.abs(m[np.ix_(sector, sector)]) > 1e-12) == brute
