@@ -388,23 +388,39 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         }
         row_sync();
         const double2* bhv = reinterpret_cast<const double2*>(s.ci_bh);
-        for (int e = split; e < s.ci_nbh; e += nsplit) {
+        const double* wcd = reinterpret_cast<const double*>(wc);
+        // branch-free decode (the row part is read for every entry, a padding
+        // entry's pair bits are 0, and zeroed by a mask), so that the records
+        // of a pass are all in flight before the first is used
+        auto hop = [&](const double2 q, int c) {   // q = {coef, w | wa << 32}
+            const uint64_t ww2 = uint64_t(__double_as_longlong(q.y));
+            const uint32_t w = uint32_t(ww2);
+            const double a = wcd[2 * ((w >> 16) & 0xffu) + ((w >> 24) & 1u)];
+            const int keep = -int((w >> 26) & 1u);             // all ones when the hop has a row part
+            const int hi = (__double2hiint(a) ^ int((w << 6) & 0x80000000u)) & keep;   // bit 25: sign
+            const double v = q.x + __hiloint2double(hi, __double2loint(a) & keep);
+            const uint32_t flip = uint32_t(__popc(sA & uint32_t(ww2 >> 32))) << 31;
+            const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
+            const double2 pv = row[w & 0xffffu];
+            lr[c] += cf * pv.x;
+            li[c] += cf * pv.y;
+        };
+        constexpr int kM = COLS <= 2 ? 4 : 2;
+        int e = split;
+        for (; e + (kM - 1) * nsplit < s.ci_nbh; e += kM * nsplit) {
+            double2 q[kM][COLS];
 #pragma unroll
-            for (int c = 0; c < COLS; ++c) {
-                const double2 q = ldg2(bhv + size_t(e) * NB + ibc[c]);   // {coef, w | wa << 32}
-                const uint64_t ww2 = uint64_t(__double_as_longlong(q.y));
-                const uint32_t w = uint32_t(ww2);
-                const double2 A = wc[(w >> 16) & 0xffu];
-                double av = ((w >> 24) & 1u) ? A.y : A.x;
-                av = ((w >> 26) & 1u) ? (((w >> 25) & 1u) ? -av : av) : 0.0;
-                const double v = q.x + av;
-                const uint32_t flip = uint32_t(__popc(sA & uint32_t(ww2 >> 32))) << 31;
-                const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
-                const double2 pv = row[w & 0xffffu];
-                lr[c] += cf * pv.x;
-                li[c] += cf * pv.y;
-            }
+            for (int u = 0; u < kM; ++u)
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) q[u][c] = ldg2(bhv + size_t(e + u * nsplit) * NB + ibc[c]);
+#pragma unroll
+            for (int u = 0; u < kM; ++u)
+#pragma unroll
+                for (int c = 0; c < COLS; ++c) hop(q[u][c], c);
         }
+        for (; e < s.ci_nbh; e += nsplit)
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) hop(ldg2(bhv + size_t(e) * NB + ibc[c]), c);
     }
     if (row_live && s.ci_ncm > 0) {
         const double2* cmv = reinterpret_cast<const double2*>(s.ci_cm);
