@@ -426,8 +426,13 @@ def run_scan12(args):
     fam = scan_integrals(12, 2)
     A = vq.Ansatz.uccsd_map(12, 6, args.mapping)
     Hs = [vq.Hamiltonian.from_integrals_map(12, args.mapping, *fam(l)) for l in SCAN12_LAMBDAS]
-    b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
     th = np.concatenate([uniform_theta(7, A.n_params)] * len(Hs))
+    if not args.no_autotune:   # tile budgets of this batch (cached per mapping)
+        from paper_2311_01242_amd import autotune
+        offs = np.cumsum([0] + [A.n_params] * len(Hs))
+        autotune.autotune_batch(Hs, [A] * len(Hs), [6] * len(Hs), th, offs, cache=TUNE_CACHE,
+                                packed=(args.mapping == "jw"), tag="scan-" + args.mapping)
+    b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
     for _ in range(args.warmup):
         b.energy_grad(th)
     torch.cuda.synchronize()
