@@ -320,7 +320,8 @@ int vqe_set_tuning(int n_qubits, int batched, int64_t fwd_lds_bytes, int64_t adj
  * run tile (64, 256, 512 or 1024) of the forward and of the reverse pass;
  * a tile too large for that count with the available shapes uses fewer
  * threads with more entries each.  Both <= 0 restores the built-in choice
- * (64).  Applies to plans made after the call.  Errors: ERANGE. */
+ * (64 for batch members, 256 for single states).  Applies to plans made after
+ * the call.  Errors: ERANGE. */
 int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_threads);
 
 /* Evaluation layout switch (process-wide, default 2).  With 1 or 2, energy

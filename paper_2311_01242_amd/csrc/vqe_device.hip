@@ -71,7 +71,12 @@ static Tuning default_tuning(int n, bool batched) {
 static Tuning tuning_for(int n, bool batched) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find({n, batched ? 1 : 0});
-    Tuning t = (it != g_tune.end()) ? it->second : default_tuning(n, batched);
+    Tuning t = default_tuning(n, batched);   // an override replaces the budgets and L only
+    if (it != g_tune.end()) {
+        t.fwd_budget = it->second.fwd_budget;
+        t.adj_budget = it->second.adj_budget;
+        t.L = it->second.L;
+    }
     auto th = g_threads.find({n, batched ? 1 : 0});
     if (th != g_threads.end()) {
         t.fwd_threads = th->second.first;
