@@ -262,3 +262,25 @@ def test_bk_uccsd_reference_and_excitations(n, ne):
     # every generator is a sum of 2 (single) or 8 (double) strings under any mapping
     ex = F.uccsd_excitations(n, ne)
     assert gates == sum(2 if len(t) == 2 else 8 for t in ex)
+
+
+def test_launch_overrides_validate_and_reset():
+    """Launch-parameter overrides (host state only): ranges are checked, and
+    all-zero arguments restore the built-in choice."""
+    with pytest.raises(vq.VQEError):
+        vq.set_tuning(0, True, 65536, 65536, 12)          # n_qubits out of range
+    with pytest.raises(vq.VQEError):
+        vq.set_tuning(20, True, 1024, 65536, 12)          # budget below 4 KiB
+    with pytest.raises(vq.VQEError):
+        vq.set_tuning(20, True, 65536, 200 << 10, 12)     # budget above 160 KiB
+    with pytest.raises(vq.VQEError):
+        vq.set_tuning(20, True, 65536, 65536, 15)         # tile bits above 14
+    with pytest.raises(vq.VQEError):
+        vq.set_run_threads(20, False, 128, 256)           # not a run shape
+    with pytest.raises(vq.VQEError):
+        vq.set_packed(3)
+    vq.set_tuning(20, False, 32768, 65536, 12)
+    vq.set_run_threads(20, False, 512, 512)
+    vq.set_tuning(20, False)                              # back to the built-in choice
+    vq.set_run_threads(20, False)
+    vq.set_packed(2)
