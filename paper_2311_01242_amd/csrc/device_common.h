@@ -288,6 +288,11 @@ struct PackedRun {
     int32_t ncls;
     const int2* info;        // per first-block class: {offset, stride} of the padded lists
     const uint32_t* ent;     // gate g of class c: ent[info[c].x + g * info[c].y + i]
+    // forward pass: the tiles that can hold a nonzero amplitude (starting from
+    // the reference, a tile stays zero until a run pairs it with a nonzero
+    // block); null when that is every tile
+    const int32_t* live;
+    int32_t nlive;
 };
 
 // One excitation of a packed run: annihilated orbitals pd and created

@@ -72,7 +72,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     }
     __syncthreads();
     const StateDesc& s = sd[blockIdx.y];
-    const int o = blockIdx.x;
+    // the forward pass covers the run's live tiles only (all of them without a list)
+    const int o = (VEC == 1 && run.live) ? ldc(run.live + blockIdx.x) : int(blockIdx.x);
     const int tid = threadIdx.x;
     const uint32_t h0 = pdep32(uint32_t(o), run.free_hi) | run.dhi;
     const uint32_t h1 = (h0 & ~run.dhi) | run.khi;
@@ -314,8 +315,10 @@ template <int VEC, int BS, int EPT>
 static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, hipStream_t st) {
     const size_t lds = (size_t(run.max_entries) * VEC + 2 * size_t(run.g1 - run.g0)) * sizeof(double2);
-    hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(run.ntiles, count), dim3(BS), lds, st, sd, run,
-                       pg, tabs, base);
+    const int nx = (VEC == 1 && run.live) ? run.nlive : run.ntiles;
+    if (nx == 0) return;   // a forward run with no live tile: nothing to do
+    hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg, tabs,
+                       base);
 }
 
 #define VQE_FWD_ENTRY(B, E) &launch_one<1, B, E>,

@@ -204,6 +204,7 @@ struct PackedPlan {
     PackedGate* d_gates = nullptr;
     int2* d_info = nullptr;           // pair-list index: {offset, stride} per run and class
     uint32_t* d_ent = nullptr;        // pair lists
+    int32_t* d_live = nullptr;        // forward live tiles of the runs that have a list
     std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
     int32_t* d_gcnt = nullptr;
     int32_t gstride = 1;
@@ -1363,6 +1364,18 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     std::vector<int2> info;       // per run and first-block class: {offset, stride}
     std::vector<uint32_t> ent;    // pair lists
     std::vector<size_t> info0;    // offset of each run's info table
+    // blocks that may hold a nonzero amplitude in the forward pass: first the
+    // reference's (entry 0, the lowest nonempty block), then every block of a
+    // tile that had one
+    std::vector<char> nz(size_t(hmask) + 1, 0);
+    for (uint32_t h = 0; h <= hmask; ++h)
+        if (lay.bsize[h] > 0) {
+            nz[h] = 1;
+            break;
+        }
+    std::vector<int32_t> live_all;
+    std::vector<std::pair<size_t, size_t>> live_of;   // per run: {offset, count}
+    constexpr size_t kNoList = ~size_t(0);
     int64_t j = 0;
     while (j < M) {
         const GateDesc& g = A->gates[j];
@@ -1382,7 +1395,8 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         r.na = lay.na;
         r.nb = lay.nb;
         int maxb = 1, maxe = 1;
-        int64_t moved = 0;
+        int64_t moved = 0, moved_live = 0;
+        const size_t live0 = live_all.size();
         std::vector<char> used(size_t(ncls), 0);   // first-block classes of live tiles
         for (int32_t o = 0; o < r.ntiles; ++o) {
             uint32_t h0 = dhi, bits = r.free_hi, v = uint32_t(o);
@@ -1398,6 +1412,14 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             maxb = std::max(maxb, std::max(c0, c1));
             maxe = std::max(maxe, c0 + c1);
             moved += c0 + c1;
+            {   // the run's gates leave a tile of zero blocks zero
+                const uint32_t h1 = two ? (h0 & ~dhi) | khi : h0;
+                if (nz[h0] || nz[h1]) {
+                    live_all.push_back(o);
+                    moved_live += c0 + c1;
+                    nz[h0] = nz[h1] = 1;
+                }
+            }
             const uint32_t hb = h0 << L;
             const int kA = lay.na - __builtin_popcount(hb & 0x55555555u);
             const int kB = lay.nb - __builtin_popcount(hb & 0xAAAAAAAAu);
@@ -1480,7 +1502,13 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         }
         p->gstride = std::max(p->gstride, r.ntiles);
         p->max_lds = std::max(p->max_lds, (size_t(maxe) * 2 + 2 * size_t(ng)) * sizeof(double2));
-        p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved);
+        if (live_all.size() - live0 == size_t(r.ntiles)) {   // every tile: no list
+            live_all.resize(live0);
+            live_of.emplace_back(live0, kNoList);
+        } else {
+            live_of.emplace_back(live0, live_all.size() - live0);
+        }
+        p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved_live);
         p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved);
         p->sweep_bytes += 2.0 * double(sizeof(double2)) * double(moved);
         p->runs.push_back(r);
@@ -1491,10 +1519,14 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     if (!rc) rc = upload(&p->d_gcnt, p->gcnt.data(), p->gcnt.size());
     if (!rc) rc = upload(&p->d_info, info.data(), info.size());
     if (!rc) rc = upload(&p->d_ent, ent.data(), ent.size());
+    if (!rc) rc = upload(&p->d_live, live_all.data(), live_all.size());
     if (!rc)
         for (size_t r = 0; r < p->runs.size(); ++r) {
             p->runs[r].info = p->d_info + info0[r];
             p->runs[r].ent = p->d_ent;
+            const bool listed = live_of[r].second != kNoList && p->d_live != nullptr;
+            p->runs[r].live = listed ? p->d_live + live_of[r].first : nullptr;
+            p->runs[r].nlive = listed ? int32_t(live_of[r].second) : p->runs[r].ntiles;
         }
     if (!rc && p->max_lds > (64u << 10) && packed_enable_lds(p->max_lds) != 0)
         rc = fail(VQE_EDEVICE, "could not enable " + std::to_string(p->max_lds) + " bytes of LDS");
@@ -1503,6 +1535,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         (void)hipFree(p->d_gcnt);
         (void)hipFree(p->d_info);
         (void)hipFree(p->d_ent);
+        (void)hipFree(p->d_live);
         delete p;
         return rc;
     }
@@ -2123,6 +2156,7 @@ vqe_ansatz::~vqe_ansatz() {
             (void)hipFree(pl.second->d_gcnt);
             (void)hipFree(pl.second->d_info);
             (void)hipFree(pl.second->d_ent);
+            (void)hipFree(pl.second->d_live);
             (void)hipFree(pl.second->d_runs);
             (void)hipFree(pl.second->d_blk);
             delete pl.second;
