@@ -293,6 +293,13 @@ struct PackedRun {
     // block); null when that is every tile
     const int32_t* live;
     int32_t nlive;
+    // the same as a flag per tile (null: every tile live).  The reverse sweep
+    // skips a tile that is not live: both its blocks are zero in phi before the
+    // run, so they are zero whenever an earlier gate is reached, and lambda on
+    // them is never paired with a nonzero phi (a tile that pairs a zero block
+    // with a nonzero one is live, and makes both nonzero); its gradient
+    // partials are zero
+    const uint8_t* tlive;
 };
 
 // One excitation of a packed run: annihilated orbitals pd and created

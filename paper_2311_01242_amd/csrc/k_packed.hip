@@ -80,7 +80,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const uint32_t hb0 = h0 << run.L;
     const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
     const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
-    if (B0.cnt == 0 || B1.cnt == 0) {   // no pair of the run has both ends in the sector
+    const bool dead = VEC == 2 && run.tlive && run.tlive[o] == 0;   // (see PackedRun::tlive)
+    if (dead || B0.cnt == 0 || B1.cnt == 0) {   // nothing to do; zero gradient partials
         if (VEC == 2)
             for (int jl = tid; jl < run.g1 - run.g0; jl += BS)
                 s.part_g[size_t(run.g0 + jl) * s.gstride + o] = 0.0;

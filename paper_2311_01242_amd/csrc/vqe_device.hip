@@ -205,6 +205,7 @@ struct PackedPlan {
     int2* d_info = nullptr;           // pair-list index: {offset, stride} per run and class
     uint32_t* d_ent = nullptr;        // pair lists
     int32_t* d_live = nullptr;        // forward live tiles of the runs that have a list
+    uint8_t* d_tlive = nullptr;       // the same as a flag per tile
     std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
     int32_t* d_gcnt = nullptr;
     int32_t gstride = 1;
@@ -1509,7 +1510,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             live_of.emplace_back(live0, live_all.size() - live0);
         }
         p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved_live);
-        p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved);
+        p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved_live);   // live tiles, as the forward
         p->sweep_bytes += 2.0 * double(sizeof(double2)) * double(moved);
         p->runs.push_back(r);
         j = j2;
@@ -1520,6 +1521,16 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     if (!rc) rc = upload(&p->d_info, info.data(), info.size());
     if (!rc) rc = upload(&p->d_ent, ent.data(), ent.size());
     if (!rc) rc = upload(&p->d_live, live_all.data(), live_all.size());
+    std::vector<uint8_t> tlive;        // per listed run: ntiles flags
+    std::vector<size_t> tlive_off(p->runs.size(), kNoList);
+    for (size_t r = 0; r < p->runs.size(); ++r) {
+        if (live_of[r].second == kNoList) continue;
+        tlive_off[r] = tlive.size();
+        tlive.resize(tlive.size() + size_t(p->runs[r].ntiles), 0);
+        for (size_t k = 0; k < live_of[r].second; ++k)
+            tlive[tlive_off[r] + size_t(live_all[live_of[r].first + k])] = 1;
+    }
+    if (!rc) rc = upload(&p->d_tlive, tlive.data(), tlive.size());
     if (!rc)
         for (size_t r = 0; r < p->runs.size(); ++r) {
             p->runs[r].info = p->d_info + info0[r];
@@ -1527,6 +1538,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             const bool listed = live_of[r].second != kNoList && p->d_live != nullptr;
             p->runs[r].live = listed ? p->d_live + live_of[r].first : nullptr;
             p->runs[r].nlive = listed ? int32_t(live_of[r].second) : p->runs[r].ntiles;
+            p->runs[r].tlive = (listed && p->d_tlive) ? p->d_tlive + tlive_off[r] : nullptr;
         }
     if (!rc && p->max_lds > (64u << 10) && packed_enable_lds(p->max_lds) != 0)
         rc = fail(VQE_EDEVICE, "could not enable " + std::to_string(p->max_lds) + " bytes of LDS");
@@ -1536,6 +1548,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         (void)hipFree(p->d_info);
         (void)hipFree(p->d_ent);
         (void)hipFree(p->d_live);
+        (void)hipFree(p->d_tlive);
         delete p;
         return rc;
     }
@@ -2157,6 +2170,7 @@ vqe_ansatz::~vqe_ansatz() {
             (void)hipFree(pl.second->d_info);
             (void)hipFree(pl.second->d_ent);
             (void)hipFree(pl.second->d_live);
+            (void)hipFree(pl.second->d_tlive);
             (void)hipFree(pl.second->d_runs);
             (void)hipFree(pl.second->d_blk);
             delete pl.second;
