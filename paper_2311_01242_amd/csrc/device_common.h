@@ -288,18 +288,17 @@ struct PackedRun {
     int32_t ncls;
     const int2* info;        // per first-block class: {offset, stride} of the padded lists
     const uint32_t* ent;     // gate g of class c: ent[info[c].x + g * info[c].y + i]
-    // forward pass: the tiles that can hold a nonzero amplitude (starting from
-    // the reference, a tile stays zero until a run pairs it with a nonzero
-    // block); null when that is every tile
+    // the tiles that can hold a nonzero amplitude (starting from the
+    // reference, a tile stays zero until a run pairs it with a nonzero block);
+    // null when that is every tile.  Both passes launch these only.  The
+    // reverse sweep may skip a tile that is not live: both its blocks are zero
+    // in phi before the run, so they are zero whenever an earlier gate is
+    // reached, and lambda on them is never paired with a nonzero phi (a tile
+    // that pairs a zero block with a nonzero one is live, and makes both
+    // nonzero); its gradient partials are zero.  Partials are stored by
+    // position in this list (by tile without a list).
     const int32_t* live;
     int32_t nlive;
-    // the same as a flag per tile (null: every tile live).  The reverse sweep
-    // skips a tile that is not live: both its blocks are zero in phi before the
-    // run, so they are zero whenever an earlier gate is reached, and lambda on
-    // them is never paired with a nonzero phi (a tile that pairs a zero block
-    // with a nonzero one is live, and makes both nonzero); its gradient
-    // partials are zero
-    const uint8_t* tlive;
 };
 
 // One excitation of a packed run: annihilated orbitals pd and created

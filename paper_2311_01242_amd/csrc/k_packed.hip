@@ -72,19 +72,20 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     }
     __syncthreads();
     const StateDesc& s = sd[blockIdx.y];
-    // the forward pass covers the run's live tiles only (all of them without a list)
-    const int o = (VEC == 1 && run.live) ? ldc(run.live + blockIdx.x) : int(blockIdx.x);
+    // both passes cover the run's live tiles only (all of them without a list);
+    // gradient partials go to the tile's position in the launch
+    const int o = run.live ? ldc(run.live + blockIdx.x) : int(blockIdx.x);
+    const int po = int(blockIdx.x);
     const int tid = threadIdx.x;
     const uint32_t h0 = pdep32(uint32_t(o), run.free_hi) | run.dhi;
     const uint32_t h1 = (h0 & ~run.dhi) | run.khi;
     const uint32_t hb0 = h0 << run.L;
     const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
     const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
-    const bool dead = VEC == 2 && run.tlive && run.tlive[o] == 0;   // (see PackedRun::tlive)
-    if (dead || B0.cnt == 0 || B1.cnt == 0) {   // nothing to do; zero gradient partials
+    if (B0.cnt == 0 || B1.cnt == 0) {   // an empty tile: zero gradient partials
         if (VEC == 2)
             for (int jl = tid; jl < run.g1 - run.g0; jl += BS)
-                s.part_g[size_t(run.g0 + jl) * s.gstride + o] = 0.0;
+                s.part_g[size_t(run.g0 + jl) * s.gstride + po] = 0.0;
         return;
     }
     const int c0 = B0.cnt;
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             gsum[0] = v;
         }
         __syncthreads();
-        for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + o] = gsum[jl];
+        for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + po] = gsum[jl];
     }
 #pragma unroll
     for (int u = 0; u < 2 * EPT; ++u) {
@@ -316,8 +317,8 @@ template <int VEC, int BS, int EPT>
 static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, hipStream_t st) {
     const size_t lds = (size_t(run.max_entries) * VEC + 2 * size_t(run.g1 - run.g0)) * sizeof(double2);
-    const int nx = (VEC == 1 && run.live) ? run.nlive : run.ntiles;
-    if (nx == 0) return;   // a forward run with no live tile: nothing to do
+    const int nx = run.live ? run.nlive : run.ntiles;
+    if (nx == 0) return;   // a run with no live tile: nothing to do, no partials
     hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg, tabs,
                        base);
 }

@@ -204,10 +204,10 @@ struct PackedPlan {
     PackedGate* d_gates = nullptr;
     int2* d_info = nullptr;           // pair-list index: {offset, stride} per run and class
     uint32_t* d_ent = nullptr;        // pair lists
-    int32_t* d_live = nullptr;        // forward live tiles of the runs that have a list
-    uint8_t* d_tlive = nullptr;       // the same as a flag per tile
+    int32_t* d_live = nullptr;        // live tiles of the runs that have a list
     std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
     int32_t* d_gcnt = nullptr;
+    int32_t* d_gcnt_live = nullptr;   // the same for the reverse sweep (live tiles of its run)
     int32_t gstride = 1;
     size_t max_lds = 0;
     double fwd_bytes = 0.0, adj_bytes = 0.0;   // algorithmic traffic of one evaluation
@@ -1521,16 +1521,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     if (!rc) rc = upload(&p->d_info, info.data(), info.size());
     if (!rc) rc = upload(&p->d_ent, ent.data(), ent.size());
     if (!rc) rc = upload(&p->d_live, live_all.data(), live_all.size());
-    std::vector<uint8_t> tlive;        // per listed run: ntiles flags
-    std::vector<size_t> tlive_off(p->runs.size(), kNoList);
-    for (size_t r = 0; r < p->runs.size(); ++r) {
-        if (live_of[r].second == kNoList) continue;
-        tlive_off[r] = tlive.size();
-        tlive.resize(tlive.size() + size_t(p->runs[r].ntiles), 0);
-        for (size_t k = 0; k < live_of[r].second; ++k)
-            tlive[tlive_off[r] + size_t(live_all[live_of[r].first + k])] = 1;
-    }
-    if (!rc) rc = upload(&p->d_tlive, tlive.data(), tlive.size());
+    std::vector<int32_t> gcnt_live(p->gcnt);
     if (!rc)
         for (size_t r = 0; r < p->runs.size(); ++r) {
             p->runs[r].info = p->d_info + info0[r];
@@ -1538,8 +1529,9 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             const bool listed = live_of[r].second != kNoList && p->d_live != nullptr;
             p->runs[r].live = listed ? p->d_live + live_of[r].first : nullptr;
             p->runs[r].nlive = listed ? int32_t(live_of[r].second) : p->runs[r].ntiles;
-            p->runs[r].tlive = (listed && p->d_tlive) ? p->d_tlive + tlive_off[r] : nullptr;
+            for (int k = p->runs[r].g0; k < p->runs[r].g1; ++k) gcnt_live[size_t(k)] = p->runs[r].nlive;
         }
+    if (!rc) rc = upload(&p->d_gcnt_live, gcnt_live.data(), gcnt_live.size());
     if (!rc && p->max_lds > (64u << 10) && packed_enable_lds(p->max_lds) != 0)
         rc = fail(VQE_EDEVICE, "could not enable " + std::to_string(p->max_lds) + " bytes of LDS");
     if (rc) {
@@ -1548,7 +1540,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         (void)hipFree(p->d_info);
         (void)hipFree(p->d_ent);
         (void)hipFree(p->d_live);
-        (void)hipFree(p->d_tlive);
+        (void)hipFree(p->d_gcnt_live);
         delete p;
         return rc;
     }
@@ -1950,7 +1942,7 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
             if (int rc = packed_layout(n, ne, ep->hx.L, &ep->lay)) return rc;
             if (int rc = packed_plan(A, da, *ep->lay, tn, &ep->pp)) return rc;
             ep->gstride = ep->pp->gstride;
-            ep->d_gcnt = ep->pp->d_gcnt;
+            ep->d_gcnt = ep->pp->d_gcnt_live;
             ep->elems = ep->lay->size;
             ep->fwd_bytes = ep->pp->fwd_bytes;
             ep->adj_bytes = ep->pp->adj_bytes;
@@ -2004,7 +1996,7 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
                               ep.lay->d_base, true, st);
     } else {
         launch_reduce_e(sd, count, ep.nblk_e, st);
-        if (grad) launch_reduce_g(sd, count, ep.M, pp.d_gcnt, 0, st);
+        if (grad) launch_reduce_g(sd, count, ep.M, pp.d_gcnt_live, 0, st);
     }
 }
 
@@ -2170,7 +2162,7 @@ vqe_ansatz::~vqe_ansatz() {
             (void)hipFree(pl.second->d_info);
             (void)hipFree(pl.second->d_ent);
             (void)hipFree(pl.second->d_live);
-            (void)hipFree(pl.second->d_tlive);
+            (void)hipFree(pl.second->d_gcnt_live);
             (void)hipFree(pl.second->d_runs);
             (void)hipFree(pl.second->d_blk);
             delete pl.second;
