@@ -14,8 +14,9 @@ per geometry), ``warmstart16`` (the learned warm start), ``adapt20``
 evaluation over the 875-operator UCCSD pool) and ``puccd11`` (pUCCD in the
 hard-core-boson form, 11 qubits / 28 parameters, 512 geometries per step).
 
-Prints one JSON line (see the repository's design doc for the roofline
-accounting and the CPU-oracle sampling).
+Prints one JSON line: the throughput, the dominant kernel's roofline
+(algorithmic bytes or flops per launch over its HIP-event launch time, against
+the MI355X peak) and the CPU oracle's rate on a bounded sample of the workload.
 """
 from __future__ import annotations
 

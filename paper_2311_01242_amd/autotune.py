@@ -37,7 +37,7 @@ def _hx_candidates(n):
 
 def _device_name():
     """Architecture and compute-unit count of device 0 (the marketing name
-    depends on the driver's ID tables and is not stable across tools)."""
+    depends on the kernel driver's device-ID tables and is not stable across tools)."""
     try:
         import torch
         p = torch.cuda.get_device_properties(0)
