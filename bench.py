@@ -152,6 +152,7 @@ def cpu_baseline_batch(spec, budget_s=20.0, ansatz="uccsd"):
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2311_01242_amd", "tuning_cache.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "batch512_hbm_traffic.json")
+TRAFFIC_WORKLOAD = "batch512-uccsd"   # the workload the counters were taken on
 CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
 # lane-operations per second of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -198,7 +199,7 @@ def sector_elements(H, n, ne):
     return float(np.sum(np.where(ok, cnt, 0.0)))
 
 
-def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
+def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None):
     """Rooflines of the three phases from one eager, HIP-event-timed
     evaluation of the batch (the graph replays interleave the size classes on
     forked streams, so phases cannot be timed there); the dominant phase's
@@ -208,8 +209,9 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
     (sector_elements) against the FP64 vector peak; a full-vector H-apply
     (`pairs` given: every (amplitude, term) pair it evaluates) at 4
     lane-operations per pair against the vector-ALU lane rate.  `traffic` is
-    the rocprof FETCH+WRITE measurement of the kernel, reported only while its
-    source still matches the measured one."""
+    the rocprof FETCH+WRITE measurement of the kernel, reported only for the
+    workload it was measured on (`traffic_key`) and while the kernel source
+    still matches the measured one."""
     kernels = PHASE_KERNELS if kernels is None else kernels
     phase_ms = b.profile(theta, reps=reps)
     w = b.work()
@@ -220,9 +222,11 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
     else:
         h_work = OPS_PER_PAIR * pairs
     traffic = {}
-    if os.path.exists(TRAFFIC):
+    if traffic_key is not None and os.path.exists(TRAFFIC):
         with open(TRAFFIC) as f:
-            traffic = json.load(f).get("kernels", {})
+            rec = json.load(f)
+        if rec.get("workload") == traffic_key:
+            traffic = rec.get("kernels", {})
     recs = {}
     for i, (phase, work, launches) in enumerate(
             [("forward", w[0], w[4]), ("h_apply", h_work, w[5]),
@@ -248,7 +252,8 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None):
     dom = max(recs, key=lambda k: recs[k]["phase_ms"])
     out = dict(recs[dom])
     out["dominant_phase"] = dom
-    out["phases"] = {k: {kk: v[kk] for kk in ("kernel", "bound", "achieved", "unit", "frac", "phase_ms")}
+    out["phases"] = {k: {kk: v[kk] for kk in ("kernel", "bound", "achieved", "unit", "frac", "traffic",
+                                               "phase_ms")}
                      for k, v in recs.items()}
     out["phase_ms"] = {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
                        "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}
@@ -289,7 +294,8 @@ def run_batch(args):
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
-    roof = roofline(b, theta, args.profile_reps, Hs, nes)
+    key = TRAFFIC_WORKLOAD if (args.states, args.ansatz) == (512, "uccsd") else None
+    roof = roofline(b, theta, args.profile_reps, Hs, nes, traffic_key=key)
     out = {
         "metric": "energy+adjoint-grad evals/s",
         "value": round(args.states * args.steps / dt, 2),

@@ -101,7 +101,7 @@ def cmd_traffic(args):
     kw = 3 * COPY_BYTES / (cw[copy_key] * 1024)
     out = {"calibration": {"fetch_factor": kf, "write_factor": kw,
                            "copy_bytes": COPY_BYTES, "copies": 3},
-           "evaluations": args.evals, "kernels": {}}
+           "evaluations": args.evals, "workload": args.workload, "kernels": {}}
     print(f"calibration: FETCH_SIZE factor {kf:.3f}, WRITE_SIZE factor {kw:.3f}")
     print()
     print("| phase | launches / eval | fetch GB / eval | write GB / eval | bytes per launch |")
@@ -133,6 +133,7 @@ def main():
     t.add_argument("--copy-write", required=True)
     t.add_argument("--evals", type=float, required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--workload", required=True, help="bench workload the counters were taken on")
     a = ap.parse_args()
     cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
 

@@ -34,3 +34,38 @@ def test_sector_elements_match_enumeration(n, ne, seed):
         from oracle import pauli as P
         m = P.matrix(P.jw_hamiltonian(n, h0, h, g), n)
         assert np.count_nonzero(np.abs(m[np.ix_(sector, sector)]) > 1e-12) == brute
+
+
+def test_traffic_reported_only_for_its_workload_and_source(tmp_path, monkeypatch):
+    """roofline.traffic comes from the counter file only for the workload it
+    was measured on and while the kernel source hash matches."""
+    import json
+    import bench
+
+    def write(workload, sha):
+        rec = {"workload": workload,
+               "kernels": {"adjoint": {"bytes_per_launch": 123.0, "source_sha256": sha}}}
+        f = tmp_path / "traffic.json"
+        f.write_text(json.dumps(rec))
+        monkeypatch.setattr(bench, "TRAFFIC", str(f))
+
+    class Batch:   # phase times (ms) and work counters of one evaluation
+        def profile(self, theta, reps):
+            return [1.0, 1.0, 2.0, 0.1]
+
+        def work(self):
+            return np.array([1e9, 0.0, 2e9, 0.0, 10.0, 1.0, 10.0, 0.0])
+
+    def adj_traffic(key):
+        r = bench.roofline(Batch(), None, 1, [], [], pairs=1000, traffic_key=key)
+        assert r["dominant_phase"] == "adjoint"
+        assert r["phases"]["adjoint"]["traffic"] == r["traffic"]
+        return r["traffic"]
+
+    sha = bench.source_hash(bench.PHASE_KERNELS["adjoint"][1])
+    write("w1", sha)
+    assert adj_traffic("w1") == 123.0
+    assert adj_traffic("w2") is None
+    assert adj_traffic(None) is None
+    write("w1", "0" * 64)   # kernel changed since the counters were taken
+    assert adj_traffic("w1") is None
