@@ -146,7 +146,7 @@ def cpu_baseline_batch(spec, budget_s=20.0, ansatz="uccsd"):
     sample = ("oracle energy timed once per qubit count (n=%s) on the first state of that n; "
               "energy+gradient = (1 + 4M) energies (four-term shift rule), summed over the 512 "
               "states" % ",".join(str(k) for k in sorted(seen)))
-    return {"value": len(spec) / total, "unit": "evals/s", "cores": cores, "kind": "oracle",
+    return {"value": len(spec) / total, "unit": "evals/s", "cores": cores, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": sample}
 
 
@@ -197,6 +197,54 @@ def sector_elements(H, n, ne):
     cnt = (_binom(pa, pa // 2) * _binom(oa - pa, na - pa // 2) *
            _binom(pb, pb // 2) * _binom(ob - pb, nb - pb // 2))
     return float(np.sum(np.where(ok, cnt, 0.0)))
+
+
+def copy_ceilings():
+    """Measured copy bandwidths (GB/s, bytes read + written) of one library
+    launch of repeated plain device copies: a 64 MB working set (two 32 MB
+    buffers, 200 passes: re-read from the last-level cache) and a 4 GB one
+    (two 2 GB buffers, 4 passes: streamed from HBM).  Median of 5 launches
+    after 2 warm-ups.  They are the measured denominators next to the vendor
+    HBM peak."""
+    import torch
+    import paper_2311_01242_amd as vq
+    out = {}
+    for key, half, passes in (("copy_64MB", 32 << 20, 200), ("copy_4GB", 2 << 30, 4)):
+        a = torch.ones(half // 16, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        times = []
+        for r in range(7):
+            ms = vq.copy_ceiling(a, b, passes)
+            if r >= 2:
+                times.append(ms)
+        ms = float(np.median(times))
+        out[key] = {"GB/s": round(2.0 * half * passes / (ms * 1e-3) / 1e9, 1),
+                    "working_set_bytes": 2 * half, "passes": passes, "ms": round(ms, 4)}
+        del a, b
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    """Model name of the host CPU (the cores the oracle baseline runs on)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def add_ceiling_fracs(roof, ceilings):
+    """Fractions of the HBM-bound phases' achieved GB/s against the measured
+    copy ceilings (the vendor-peak fraction stays in `frac`)."""
+    for rec in [roof] + list(roof.get("phases", {}).values()):
+        if rec.get("bound") == "hbm" and rec.get("unit") == "GB/s":
+            rec["frac_copy_64MB"] = round(rec["achieved"] / ceilings["copy_64MB"]["GB/s"], 4)
+            rec["frac_copy_4GB"] = round(rec["achieved"] / ceilings["copy_4GB"]["GB/s"], 4)
 
 
 def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None):
@@ -296,6 +344,8 @@ def run_batch(args):
     assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
     key = TRAFFIC_WORKLOAD if (args.states, args.ansatz) == (512, "uccsd") else None
     roof = roofline(b, theta, args.profile_reps, Hs, nes, traffic_key=key)
+    ceilings = copy_ceilings()
+    add_ceiling_fracs(roof, ceilings)
     out = {
         "metric": "energy+adjoint-grad evals/s",
         "value": round(args.states * args.steps / dt, 2),
@@ -309,6 +359,7 @@ def run_batch(args):
                    "states": args.states, "qubits": "12-20", "global_batch": args.states,
                    "parallelism": "single GPU"},
         "roofline": roof,
+        "ceilings": ceilings,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(spec, ansatz=args.ansatz)
@@ -391,7 +442,7 @@ def cpu_baseline_puccd(fam, lams, th, n_orb, n_pairs, budget_s=15.0):
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    return {"value": k / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+    return {"value": k / t, "unit": "evals/s", "cores": cores, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"oracle pUCCD energy + four-term shift-rule gradient (operator set-up "
                       f"included) on the first {k} of {len(lams)} geometries ({t:.1f} s)"}
 
@@ -416,6 +467,8 @@ def run_single24(args):
     b = vq.Batch([H], [A], [ne])
     roof = roofline(b, th, args.profile_reps, [H], [ne])
     roof["traffic"] = None
+    ceilings = copy_ceilings()
+    add_ceiling_fracs(roof, ceilings)
     return {
         "metric": "energy+adjoint-grad evals/s", "value": round(args.steps / dt, 3), "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
@@ -423,6 +476,7 @@ def run_single24(args):
         "data": "synthetic",
         "config": {"workload": "single 24-qubit UCCSD energy+adjoint gradient (12 e-, 1818 params)"},
         "roofline": roof,
+        "ceilings": ceilings,
     }
 
 

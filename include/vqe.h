@@ -337,6 +337,18 @@ int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_thre
  * Errors: ERANGE for other modes. */
 int vqe_set_packed(int mode);
 
+/* Measurement helper, not a step of the method: one launch that copies
+ * `bytes` (a positive multiple of 16) from device buffer src to device
+ * buffer dst (both 16-byte aligned, not overlapping, caller-owned) `passes`
+ * times (1..100000), timed with HIP events on hip_stream; *ms receives the
+ * launch time.  2 * bytes * passes / time is the measured copy bandwidth
+ * the gate kernels' rooflines are reported against (a buffer pair of about
+ * 64 MB stays in the last-level cache between passes; a pair of several GB
+ * streams from HBM).  Synchronises the stream.  Errors: EINVAL (null or
+ * misaligned), ERANGE (sizes), EDEVICE. */
+int vqe_copy_ceiling(const void* src, void* dst, int64_t bytes, int passes, void* hip_stream,
+                     double* ms);
+
 /* ---------------------------------------------------------------------------
  * BFGS and the VQE loop
  * ------------------------------------------------------------------------ */

@@ -23,7 +23,7 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
-    "set_packed", "set_run_threads",
+    "set_packed", "set_run_threads", "copy_ceiling",
 ]
 
 
@@ -47,6 +47,19 @@ def set_packed(mode=True):
     full 2^n vectors."""
     m = 2 if mode is True else (0 if mode is False else int(mode))
     _check(lib().vqe_set_packed(m))
+
+
+def copy_ceiling(src, dst, passes: int = 1) -> float:
+    """Milliseconds of one library launch that copies the bytes of device
+    tensor src into dst `passes` times (a measured bandwidth ceiling for the
+    rooflines, not a step of the method).  Same-size contiguous tensors."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous tensors of the same byte size")
+    ms = C.c_double()
+    _check(lib().vqe_copy_ceiling(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                  int(nbytes), int(passes), current_stream(), C.byref(ms)))
+    return ms.value
 
 
 _MAPS = {"jw": 0, "bk": 1}

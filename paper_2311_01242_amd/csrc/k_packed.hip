@@ -1,5 +1,5 @@
-// Ansatz kernels on the packed sector layout (Sec. 2.1.2, Eq. 1; gradient of
-// Eq. 3 by the reverse sweep).
+// Ansatz kernels on the packed sector layout (Sec. 2.1.2; the objective of
+// Sec. 2.1.1, Eq. 1, and its gradient by the reverse sweep).
 //
 // Every UCCSD gate conserves the alpha and beta electron counts, so a state
 // prepared from the reference |HF> has nonzero amplitudes only in the

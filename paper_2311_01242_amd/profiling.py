@@ -1,10 +1,13 @@
 """Summaries of rocprofv3 output for the benchmark's roofline accounting.
 
-Two sub-commands, both reading the CSV files rocprofv3 writes with
+Three sub-commands, both reading the CSV files rocprofv3 writes with
 ``--output-format csv``:
 
 ``stats``   kernel-trace statistics (``*_kernel_stats.csv``) grouped into the
             evaluation's phases, as a markdown table (stdout).
+
+``counters`` instruction mix and issue/wait fractions per kernel from the
+            SQ counters of several ``--pmc`` passes (summed over dispatches).
 
 ``traffic`` HBM bytes per launch of each phase's kernels from two ``--pmc``
             runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by
@@ -121,6 +124,66 @@ def cmd_traffic(args):
         json.dump(out, fo, indent=1, sort_keys=True)
 
 
+# derived per-kernel figures from summed SQ counters (all per dispatch sums
+# over the whole GPU): instruction mix per wave, and fractions of the waves'
+# resident time (SQ_WAVE_CYCLES) spent issuing or waiting
+ISSUE_ROWS = [
+    ("waves", lambda c, n: c["SQ_WAVES"] / n, "{:.0f}"),
+    ("VALU / wave", lambda c, n: c["SQ_INSTS_VALU"] / c["SQ_WAVES"], "{:.0f}"),
+    ("SALU / wave", lambda c, n: c["SQ_INSTS_SALU"] / c["SQ_WAVES"], "{:.0f}"),
+    ("LDS / wave", lambda c, n: c["SQ_INSTS_LDS"] / c["SQ_WAVES"], "{:.0f}"),
+    ("VMEM rd+wr / wave", lambda c, n: (c["SQ_INSTS_VMEM_RD"] + c["SQ_INSTS_VMEM_WR"]) / c["SQ_WAVES"],
+     "{:.1f}"),
+    ("SMEM / wave", lambda c, n: c["SQ_INSTS_SMEM"] / c["SQ_WAVES"], "{:.1f}"),
+    ("branch / wave", lambda c, n: c["SQ_INSTS_BRANCH"] / c["SQ_WAVES"], "{:.0f}"),
+    ("FP64 FMA / VALU", lambda c, n: c["SQ_INSTS_VALU_FMA_F64"] / c["SQ_INSTS_VALU"], "{:.3f}"),
+    ("issuing (ACTIVE_INST_ANY / WAVE_CYCLES)",
+     lambda c, n: c["SQ_ACTIVE_INST_ANY"] / c["SQ_WAVE_CYCLES"], "{:.3f}"),
+    ("VALU issuing (ACTIVE_INST_VALU / WAVE_CYCLES)",
+     lambda c, n: c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"], "{:.3f}"),
+    ("LDS issuing (ACTIVE_INST_LDS / WAVE_CYCLES)",
+     lambda c, n: c["SQ_ACTIVE_INST_LDS"] / c["SQ_WAVE_CYCLES"], "{:.3f}"),
+    ("waiting on a dependency (WAIT_INST_ANY / WAVE_CYCLES)",
+     lambda c, n: c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"], "{:.3f}"),
+    ("waiting on LDS (WAIT_INST_LDS / WAVE_CYCLES)",
+     lambda c, n: c["SQ_WAIT_INST_LDS"] / c["SQ_WAVE_CYCLES"], "{:.3f}"),
+    ("waiting, any reason incl. barriers (WAIT_ANY / WAVE_CYCLES)",
+     lambda c, n: c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"], "{:.3f}"),
+    ("LDS bank-conflict cycles / LDS active cycles",
+     lambda c, n: c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"], "{:.3f}"),
+    ("active lanes per VALU instruction (THREAD_CYCLES_VALU / ACTIVE_INST_VALU)",
+     lambda c, n: c["SQ_THREAD_CYCLES_VALU"] / c["SQ_ACTIVE_INST_VALU"], "{:.1f}"),
+]
+
+
+def cmd_counters(args):
+    """Sum every counter over the dispatches of each selected kernel (name
+    prefix match) across the given pmc CSV files and print the derived
+    figures that the collected counters allow."""
+    tot = {k: collections.defaultdict(float) for k in args.kernel}
+    disp = {k: set() for k in args.kernel}
+    for path in args.csv:
+        for r in csv.DictReader(open(path)):
+            name = short(r["Kernel_Name"]).replace(" ", "")
+            for k in args.kernel:
+                if name.startswith(k.replace(" ", "")):
+                    tot[k][r["Counter_Name"]] += float(r["Counter_Value"])
+                    disp[k].add((path, r["Dispatch_Id"]))
+    print("| figure | " + " | ".join(args.kernel) + " |")
+    print("|---|" + "---:|" * len(args.kernel))
+    nd = {k: max(1, len(disp[k]) // max(1, len(args.csv))) for k in args.kernel}
+    print("| dispatches | " + " | ".join(str(nd[k]) for k in args.kernel) + " |")
+    for label, fn, fmt in ISSUE_ROWS:
+        vals = []
+        for k in args.kernel:
+            try:
+                vals.append(fmt.format(fn(tot[k], nd[k])))
+            except (KeyError, ZeroDivisionError):
+                vals.append("-")
+        if any(v != "-" for v in vals):
+            print(f"| {label} | " + " | ".join(vals) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser(prog="python -m paper_2311_01242_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -134,8 +197,12 @@ def main():
     t.add_argument("--evals", type=float, required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--workload", required=True, help="bench workload the counters were taken on")
+    c = sub.add_parser("counters")
+    c.add_argument("--kernel", action="append", required=True,
+                   help="kernel name prefix as rocprof prints it, e.g. 'k_prun<2, 512, 3>'")
+    c.add_argument("csv", nargs="+", help="*_counter_collection.csv files of the pmc passes")
     a = ap.parse_args()
-    cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

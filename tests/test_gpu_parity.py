@@ -435,3 +435,31 @@ def test_pair_records_off_the_chain_pattern(n, ne):
             return P.energy(S, P.prepare(n, ne, excs, t), n)
         gj = (e(math.pi / 4) - e(-math.pi / 4)) - c2 * (e(math.pi / 2) - e(-math.pi / 2))
         assert abs(out[2][1][j] - gj) < TOL_E
+
+
+@pytest.mark.parametrize("k", [0, 5, 10, 15, 19])
+def test_scan12_geometries_match_oracle_and_fd(k):
+    """The 12-qubit bond-stretch family (20 geometries, one batch as bench.py
+    runs it): at every fifth geometry the energy and every gradient component
+    against the oracle (four-term shift rule, 1e-10), and every component
+    against central differences of the GPU energy (h = 1e-5, 1e-6)."""
+    from vqe_inputs import SCAN12_LAMBDAS
+    fam = scan_integrals(12, 2)
+    A = vq.Ansatz.uccsd(12, 6)
+    Hs = [vq.Hamiltonian.from_integrals(12, *fam(l)) for l in SCAN12_LAMBDAS]
+    theta = uniform_theta(7, A.n_params)
+    b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
+    e, g = b.energy_grad(np.concatenate([theta] * len(Hs)))
+    M = A.n_params
+    gk = g[k * M:(k + 1) * M]
+    prob = F.Problem(12, 6, *fam(SCAN12_LAMBDAS[k]))
+    assert abs(e[k] - prob.energy(theta)) < TOL_E
+    assert np.abs(gk - prob.grad_shift(theta)).max() < TOL_E
+    fd = np.empty(M)
+    for j in range(M):
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += 1e-5
+        tm[j] -= 1e-5
+        fd[j] = (vq.energy_grad(Hs[k], A, 6, tp, grad=False)[0] -
+                 vq.energy_grad(Hs[k], A, 6, tm, grad=False)[0]) / 2e-5
+    assert np.abs(gk - fd).max() < 1e-6

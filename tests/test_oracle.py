@@ -143,6 +143,21 @@ def test_fci_matches_brute_force_sector(n, ne):
     assert abs(prob.fci() - ref) < 1e-11
 
 
+def test_fci_lanczos_branch_one_body_closed_form():
+    """Above 2,500 determinants the sector FCI switches from dense eigh to
+    Lanczos (eigsh) on the sigma-vector.  With the two-body integrals zero
+    the ground energy has a closed form: the alpha and the beta electrons
+    fill the lowest eigenvalues of h (spin-adapted spatial orbitals).  16
+    qubits, 6 electrons: 3,136 determinants."""
+    n, ne = 16, 6
+    _, h, g = random_integrals(n, 1616)
+    prob = F.Problem(n, ne, 0.0, h, np.zeros_like(g))
+    assert prob.space.ndet > 2500
+    eps = np.linalg.eigvalsh(h)
+    na, nb = (ne + 1) // 2, ne // 2
+    assert abs(prob.fci() - (eps[:na].sum() + eps[:nb].sum())) < 1e-10
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_vqe_4q_reaches_fci(seed):
     h0, h, g = random_integrals(4, seed)
