@@ -337,6 +337,34 @@ int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_thre
  * Errors: ERANGE for other modes. */
 int vqe_set_packed(int mode);
 
+/* Persistent batch passes (process-wide, applies to batches created after
+ * the call).  mode 1: when every state of a batch runs on the
+ * packed sector layout and the device's XCDs can be identified (a probe
+ * launch reads the XCD id of its workgroups and must find one per 32 CUs),
+ * the forward and the reverse gate passes of all states are each ONE launch
+ * of one-wave workgroups that take (state, run, tile) items from per-XCD
+ * queues, every state's items on one XCD, an item starting once the state's
+ * earlier runs are done (bounded waits; a wait that gives up makes
+ * vqe_batch_energy_grad return EDEVICE).  All states then use block_bits
+ * (0 = 12; range 8..14) block bits.  mode 0 (default): one launch per run
+ * and size class.  Results agree to rounding.  Errors: ERANGE. */
+int vqe_set_persistent(int mode, int block_bits);
+
+/* Persistent-pass layout of a batch: info[8] receives {on, queues, forward
+ * grid, reverse grid, forward items, pair slots per lane, forward LDS bytes,
+ * reverse LDS bytes} (zeros when the batch does not use them).  Errors:
+ * EINVAL. */
+int vqe_batch_persistent(const vqe_batch* b, int* info);
+
+/* Test hook of the persistent passes' bounded waits: spin_limit > 0 sets the
+ * polls after which a dependency wait gives up (0: the default, about a
+ * second); poison = 1 makes the first forward item that has a dependency wait
+ * for a count that is never reached, so that the next evaluation reports
+ * EDEVICE after spin_limit polls while every kernel still exits; poison = 0
+ * restores it.  Synchronises the batch's stream.  Errors: EINVAL (no
+ * persistent passes), ERANGE. */
+int vqe_batch_test_wait(vqe_batch* b, int spin_limit, int poison);
+
 /* Measurement helper, not a step of the method: one launch that copies
  * `bytes` (a positive multiple of 16) from device buffer src to device
  * buffer dst (both 16-byte aligned, not overlapping, caller-owned) `passes`

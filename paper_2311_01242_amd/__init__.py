@@ -23,7 +23,7 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
-    "set_packed", "set_run_threads", "copy_ceiling",
+    "set_packed", "set_run_threads", "copy_ceiling", "set_persistent",
 ]
 
 
@@ -47,6 +47,13 @@ def set_packed(mode=True):
     full 2^n vectors."""
     m = 2 if mode is True else (0 if mode is False else int(mode))
     _check(lib().vqe_set_packed(m))
+
+
+def set_persistent(mode: bool = True, block_bits: int = 0):
+    """Persistent batch gate passes on or off (off by default); block_bits:
+    the common block bits of their packed layout (0 = 12).  Applies to
+    batches created afterwards."""
+    _check(lib().vqe_set_persistent(int(bool(mode)), int(block_bits)))
 
 
 def copy_ceiling(src, dst, passes: int = 1) -> float:
@@ -447,6 +454,19 @@ class Batch:
         w = np.empty(8, np.float64)
         _check(lib().vqe_batch_work(self._h, _dptr(w)))
         return w
+
+    def persistent(self):
+        """Persistent-pass layout: dict(on, queues, grid_fwd, grid_adj,
+        items_fwd, pmax, lds_fwd, lds_adj); on = 0 when the batch uses one
+        launch per run and size class."""
+        info = (C.c_int * 8)()
+        _check(lib().vqe_batch_persistent(self._h, info))
+        keys = ("on", "queues", "grid_fwd", "grid_adj", "items_fwd", "pmax", "lds_fwd", "lds_adj")
+        return dict(zip(keys, list(info)))
+
+    def test_wait(self, spin_limit: int = 0, poison: bool = False):
+        """Test hook of the persistent passes' bounded waits (see vqe.h)."""
+        _check(lib().vqe_batch_test_wait(self._h, int(spin_limit), int(bool(poison))))
 
     def close(self):
         if self._h:

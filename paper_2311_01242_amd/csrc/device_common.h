@@ -525,4 +525,49 @@ int packed_enable_lds(size_t bytes);  // 0 on success
 
 int blocks_for(uint64_t work);
 
+// ------------------------------------------------------- persistent passes
+//
+// One launch applies every run of every packed state of a batch (k_persist.hip).
+
+constexpr int kPqMaxXcc = 256;   // raw XCC ids the queue map covers
+
+struct BlockShape2 {
+    int kA, kB, cnt;
+};
+
+// A run of a class with what its tiles need besides the run descriptor.
+struct PqRun {
+    PackedRun r;
+    const PackedGate* pg;    // the run's gates
+    const int32_t* base;     // block offsets of the class's layout
+};
+
+// Tile `tile` (position in the run's live list) of run `run` (index into the
+// PqRun table) of state `state` (index into the StateDesc table); it may start
+// once `need` tiles of the state are done in this pass.
+struct PqItem {
+    int32_t state, run, tile, need;
+};
+
+struct PqArgs {
+    const StateDesc* sd;
+    const PqRun* runs;
+    const PqItem* items;     // the queues' items, concatenated
+    const int32_t* qoff;     // [nq + 1] item range of each queue
+    const int32_t* qmap;     // [kPqMaxXcc] raw XCC id -> queue (-1: none)
+    int32_t* head;           // [nq] next item of each queue, 0 at launch
+    int32_t* done;           // [states] finished tiles of each state, 0 at launch
+    int32_t* err;            // [nq] set when a wait gave up, 0 at launch
+    const HxTables* tabs;    // block tables of the common block bits
+    const int32_t* ctl;      // ctl[0]: polls before a dependency wait gives up
+    int32_t cap;             // tile entries the dynamic LDS holds (per vector)
+    int32_t max_ng;          // longest run (gate parameters and partials in LDS)
+};
+
+int pq_pmax_for(int max_stride);
+int pq_prepare(int vec, int pmax, size_t lds_bytes, int* blocks_per_cu);   // 0 on success
+void launch_pq(int vec, int pmax, const PqArgs& a, int grid, size_t lds_bytes, hipStream_t st);
+void launch_pq_reset(int32_t* p, int n, hipStream_t st);
+void launch_xcc_probe(int32_t* out, int blocks, hipStream_t st);
+
 }  // namespace vqe

@@ -210,6 +210,10 @@ struct PackedPlan {
     int32_t* d_gcnt_live = nullptr;   // the same for the reverse sweep (live tiles of its run)
     int32_t gstride = 1;
     size_t max_lds = 0;
+    int max_entries = 0;              // largest tile (entries per vector)
+    int max_stride = 0;               // longest padded pair list of a gate in a tile
+    int max_gates = 0;                // longest run
+    std::vector<double> run_work;     // per run: live-tile entries x gates (load balance)
     double fwd_bytes = 0.0, adj_bytes = 0.0;   // algorithmic traffic of one evaluation
     // single-launch zero-angle sweep (built on first use as a pool)
     PackedRun* d_runs = nullptr;
@@ -1475,6 +1479,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
                     ent.insert(ent.end(), stride - lst.size(), kPairNone);
                 }
                 rec.y = int(stride);
+                p->max_stride = std::max(p->max_stride, int(stride));
             }
             info.push_back(rec);
         }
@@ -1503,6 +1508,9 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         }
         p->gstride = std::max(p->gstride, r.ntiles);
         p->max_lds = std::max(p->max_lds, (size_t(maxe) * 2 + 2 * size_t(ng)) * sizeof(double2));
+        p->max_entries = std::max(p->max_entries, maxe);
+        p->max_gates = std::max(p->max_gates, int(ng));
+        p->run_work.push_back(double(moved_live) * double(ng));
         if (live_all.size() - live0 == size_t(r.ntiles)) {   // every tile: no list
             live_all.resize(live0);
             live_of.emplace_back(live0, kNoList);
@@ -1908,13 +1916,16 @@ static bool sector_path(const vqe_ansatz* A, int ne) {
     return A->sector_conserving && A->n_electrons == ne;
 }
 
-static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* ep) {
+// force_L > 0: block bits of the packed layout (and sector H-apply tile)
+// regardless of the tuning (the persistent batch passes use one common value).
+static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* ep, int force_L = 0) {
     const int n = A->n;
     ep->n = n;
     ep->ne = ne;
     ep->M = int(A->gates.size());
     ep->A = A;
-    const Tuning tn = tuning_for(n, batched);
+    Tuning tn = tuning_for(n, batched);
+    if (force_L > 0) tn.L = force_L;
     DevAnsatz* da;
     if (int rc = dev_ansatz(A, &da)) return rc;
     if (int rc = get_plan(A, da, tn, &ep->ap)) return rc;
@@ -2714,6 +2725,72 @@ extern "C" int vqe_pool_gradient_profile(const vqe_hamiltonian* H, const vqe_ans
 
 // ===================================================================== batch
 
+namespace vqe {
+
+// Persistent batch passes (k_persist.hip): mode 1 = on where the device
+// reports its XCDs, 0 = one launch per run and size class (default: measured
+// faster on the 512-state batch).
+static std::atomic<int> g_persist_mode{0};
+static std::atomic<int> g_persist_L{12};
+static std::atomic<int> g_persist_spin{1 << 20};
+
+// Queue of each raw XCC id on a device: a probe launch of many one-wave
+// workgroups records the id each ran on; ids are numbered in ascending order.
+// The persistent passes are used only when the probe finds as many distinct
+// ids as the device has XCDs of 32 CUs (every workgroup of one queue then
+// shares one L2).
+struct XccMap {
+    int nq = 0;
+    std::vector<int32_t> map;   // [kPqMaxXcc]
+    int32_t* d_map = nullptr;
+};
+static std::mutex g_xcc_mu;
+static std::map<int, XccMap*> g_xcc;
+
+static int xcc_map(XccMap** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_xcc_mu);
+    XccMap*& m = g_xcc[dev];
+    if (m) {
+        *out = m;
+        return VQE_OK;
+    }
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int blocks = 4096;
+    int32_t* d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(int32_t) * blocks));
+    launch_xcc_probe(d, blocks, nullptr);
+    std::vector<int32_t> ids(blocks, -1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(ids.data(), d, sizeof(int32_t) * blocks, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    HIPCHK(e);
+    auto* x = new XccMap();
+    x->map.assign(kPqMaxXcc, -1);
+    std::vector<int32_t> seen;
+    bool ok = true;
+    for (int32_t v : ids) {
+        if (v < 0 || v >= kPqMaxXcc) ok = false;
+        else if (std::find(seen.begin(), seen.end(), v) == seen.end()) seen.push_back(v);
+    }
+    std::sort(seen.begin(), seen.end());
+    if (ok && cus % 32 == 0 && int(seen.size()) == cus / 32) {
+        for (size_t i = 0; i < seen.size(); ++i) x->map[size_t(seen[i])] = int32_t(i);
+        x->nq = int(seen.size());
+        if (int rc = upload(&x->d_map, x->map.data(), x->map.size())) {
+            delete x;
+            return rc;
+        }
+    }
+    m = x;
+    *out = m;
+    return VQE_OK;
+}
+
+}  // namespace vqe
+
 struct vqe_batch {
     int S = 0;
     int dev = 0;
@@ -2741,6 +2818,19 @@ struct vqe_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double work[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // algorithmic work of one evaluation
+    // persistent gate passes (every class's runs in one launch per direction)
+    struct Persist {
+        bool on = false;
+        int nq = 0, pmax = 1;
+        size_t lds[2] = {0, 0};      // forward, reverse
+        int grid[2] = {0, 0};
+        PqArgs args[2]{};
+        int32_t* cnt = nullptr;      // [head nq | done S] x 2 passes, then err [2 nq]
+        int ncnt = 0;
+        int32_t* err_h = nullptr;    // pinned copy of the error flags
+        std::vector<PqItem> items[2];   // host copies (tests may alter one need)
+        std::vector<int32_t> qoff[2];
+    } pq;
     ~vqe_batch() {
         int cur = 0;
         (void)hipGetDevice(&cur);
@@ -2755,6 +2845,7 @@ struct vqe_batch {
         (void)hipHostFree(theta_h);
         (void)hipHostFree(e_h);
         (void)hipHostFree(g_h);
+        (void)hipHostFree(pq.err_h);
         (void)hipSetDevice(cur);
     }
 };
@@ -2778,11 +2869,225 @@ int dalloc(vqe_batch* b, T** p, size_t count) {
     return VQE_OK;
 }
 
+// Work queues of the persistent passes: every state goes to one queue (one
+// XCD), heaviest first to the queue with the least work so far (work: the
+// class's live-tile entries times gates over its runs); a queue lists, run
+// step by run step, the live tiles of each of its states (forward: run r at
+// step r; reverse: run R - 1 - step), each with the count of the state's
+// tiles that must be done before it starts (all tiles of the runs before it
+// in that pass).
+int build_persist(vqe_batch* b, const XccMap& xm) {
+    auto& P = b->pq;
+    const int S = b->S, nq = xm.nq;
+    const size_t C = b->classes.size();
+    std::vector<PqRun> runs;
+    std::vector<size_t> run0(C);
+    size_t cap = 1;
+    int max_stride = 1, max_ng = 1;
+    std::vector<double> cw(C, 0.0);
+    std::vector<std::vector<int32_t>> pre(C), suf(C);   // tiles before / after each run
+    for (size_t c = 0; c < C; ++c) {
+        const EvalPlan& ep = b->classes[c].ep;
+        const PackedPlan& pp = *ep.pp;
+        run0[c] = runs.size();
+        const size_t R = pp.runs.size();
+        pre[c].assign(R + 1, 0);
+        suf[c].assign(R + 1, 0);
+        for (size_t r = 0; r < R; ++r) {
+            PqRun q{};
+            q.r = pp.runs[r];
+            q.pg = pp.d_gates + pp.off[r];
+            q.base = ep.lay->d_base;
+            runs.push_back(q);
+            pre[c][r + 1] = pre[c][r] + pp.runs[r].nlive;
+            cw[c] += pp.run_work[r];
+        }
+        for (size_t r = R; r-- > 0;) suf[c][r] = suf[c][r + 1] + pp.runs[r].nlive;
+        cap = std::max(cap, size_t(pp.max_entries));
+        max_stride = std::max(max_stride, pp.max_stride);
+        max_ng = std::max(max_ng, pp.max_gates);
+    }
+    std::vector<int> cls_of(S, -1);
+    for (size_t c = 0; c < C; ++c)
+        for (int k = b->classes[c].k0; k < b->classes[c].k0 + b->classes[c].count; ++k) cls_of[k] = int(c);
+    std::vector<int> ord(S);
+    for (int k = 0; k < S; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cw[cls_of[x]] > cw[cls_of[y]]; });
+    std::vector<double> load(nq, 0.0);
+    std::vector<std::vector<int>> qs(nq);
+    for (int k : ord) {
+        const int q = int(std::min_element(load.begin(), load.end()) - load.begin());
+        load[q] += cw[cls_of[k]];
+        qs[q].push_back(k);
+    }
+    for (auto& v : qs) std::sort(v.begin(), v.end());
+    for (int pass = 0; pass < 2; ++pass) {
+        auto& items = P.items[pass];
+        auto& qoff = P.qoff[pass];
+        items.clear();
+        qoff.assign(1, 0);
+        for (int q = 0; q < nq; ++q) {
+            size_t maxR = 0;
+            for (int k : qs[q]) maxR = std::max(maxR, b->classes[cls_of[k]].ep.pp->runs.size());
+            for (size_t step = 0; step < maxR; ++step)
+                for (int k : qs[q]) {
+                    const int c = cls_of[k];
+                    const PackedPlan& pp = *b->classes[c].ep.pp;
+                    const size_t R = pp.runs.size();
+                    if (step >= R) continue;
+                    const size_t r = pass == 0 ? step : R - 1 - step;
+                    const int32_t need = pass == 0 ? pre[c][r] : suf[c][r + 1];
+                    for (int32_t t = 0; t < pp.runs[r].nlive; ++t)
+                        items.push_back(PqItem{int32_t(k), int32_t(run0[c] + r), t, need});
+                }
+            if (items.size() > size_t(INT32_MAX)) return fail(VQE_ERANGE, "persistent pass: too many items");
+            qoff.push_back(int32_t(items.size()));
+        }
+    }
+    PqRun* d_runs = nullptr;
+    PqItem* d_items[2] = {nullptr, nullptr};
+    int32_t* d_qoff[2] = {nullptr, nullptr};
+    if (int rc = dalloc(b, &d_runs, runs.size())) return rc;
+    HIPCHK(hipMemcpy(d_runs, runs.data(), sizeof(PqRun) * runs.size(), hipMemcpyHostToDevice));
+    for (int pass = 0; pass < 2; ++pass) {
+        if (int rc = dalloc(b, &d_items[pass], P.items[pass].size())) return rc;
+        if (int rc = dalloc(b, &d_qoff[pass], P.qoff[pass].size())) return rc;
+        HIPCHK(hipMemcpy(d_items[pass], P.items[pass].data(), sizeof(PqItem) * P.items[pass].size(),
+                         hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_qoff[pass], P.qoff[pass].data(), sizeof(int32_t) * P.qoff[pass].size(),
+                         hipMemcpyHostToDevice));
+    }
+    // counters: ctl[1] | per pass: head[nq], done[S] | err[2 nq]
+    P.ncnt = 1 + 2 * (nq + S) + 2 * nq;
+    if (int rc = dalloc(b, &P.cnt, size_t(P.ncnt))) return rc;
+    HIPCHK(hipMemset(P.cnt, 0, sizeof(int32_t) * size_t(P.ncnt)));
+    const int32_t spin = g_persist_spin.load();
+    HIPCHK(hipMemcpy(P.cnt, &spin, sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipHostMalloc(&P.err_h, sizeof(int32_t) * 2 * nq));
+    P.nq = nq;
+    P.pmax = pq_pmax_for(max_stride);
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->dev));
+    for (int pass = 0; pass < 2; ++pass) {
+        PqArgs& a = P.args[pass];
+        a.sd = b->sd_dev;
+        a.runs = d_runs;
+        a.items = d_items[pass];
+        a.qoff = d_qoff[pass];
+        a.qmap = xm.d_map;
+        a.head = P.cnt + 1 + pass * (nq + S);
+        a.done = a.head + nq;
+        a.err = P.cnt + 1 + 2 * (nq + S) + pass * nq;
+        a.tabs = b->classes[0].ep.hxt;
+        a.ctl = P.cnt;
+        a.cap = int32_t(cap);
+        a.max_ng = int32_t(max_ng);
+        P.lds[pass] = (size_t(pass + 1) * cap + 2 * size_t(max_ng)) * sizeof(double2) +
+                      (pass == 1 ? size_t(max_ng) * sizeof(double) : 0);
+        int bpc = 0;
+        if (pq_prepare(pass + 1, P.pmax, P.lds[pass], &bpc) != 0)
+            return fail(VQE_EDEVICE, "persistent pass: kernel does not fit " + std::to_string(P.lds[pass]) +
+                                         " bytes of LDS");
+        P.grid[pass] = bpc * cus;
+    }
+    P.on = true;
+    return VQE_OK;
+}
+
+// Enqueue fn(class, stream) for every class: with fork, on the side streams
+// (heaviest class first, each on the stream with the least work so far)
+// between a fork from b->st and a join back into it; else in order on st.
+template <class F>
+int for_classes(vqe_batch* b, bool fork, hipStream_t st, int fork_id, F fn) {
+    if (!fork) {
+        for (auto& c : b->classes) fn(c, st);
+        return VQE_OK;
+    }
+    const size_t C = b->classes.size();
+    const size_t ns = b->side.size();
+    hipEvent_t* ev = b->events.data() + size_t(fork_id) * (ns + 1);
+    HIPCHK(hipEventRecord(ev[0], st));
+    for (size_t i = 0; i < ns; ++i) HIPCHK(hipStreamWaitEvent(b->side[i], ev[0], 0));
+    std::vector<size_t> ord(C);
+    std::vector<double> w(C), load(ns, 0.0);
+    for (size_t i = 0; i < C; ++i) {
+        ord[i] = i;
+        w[i] = double(b->classes[i].count) * (b->classes[i].ep.fwd_bytes + b->classes[i].ep.adj_bytes);
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t c) { return w[a] > w[c]; });
+    for (size_t i : ord) {
+        const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += w[i];
+        fn(b->classes[i], b->side[k]);
+    }
+    for (size_t i = 0; i < ns; ++i) {
+        HIPCHK(hipEventRecord(ev[1 + i], b->side[i]));
+        HIPCHK(hipStreamWaitEvent(st, ev[1 + i], 0));
+    }
+    return VQE_OK;
+}
+
+// One phase of an evaluation with the persistent gate passes.  Forward: the
+// angles and |HF> of every class, then one launch of all forward runs;
+// H-apply per class; reverse: one launch of all reverse runs; reduction per
+// class.  The counters of both passes are cleared at the start (a fill
+// kernel, not a memset node).
+int enqueue_pq_phase(vqe_batch* b, int ph, bool fork, hipStream_t st) {
+    auto& P = b->pq;
+    if (ph == kPhaseFwd) {
+        launch_pq_reset(P.cnt + 1, P.ncnt - 1, st);
+        if (int rc = for_classes(b, fork, st, 0, [&](vqe_batch::Class& c, hipStream_t s) {
+                launch_angles(b->sd_dev + c.k0, c.count, c.ep.M, s);
+                launch_packed_hf(b->sd_dev + c.k0, c.count, c.ep.lay->size, s);
+            }))
+            return rc;
+        launch_pq(1, P.pmax, P.args[0], P.grid[0], P.lds[0], st);
+    } else if (ph == kPhaseHx) {
+        if (int rc = for_classes(b, fork, st, 1, [&](vqe_batch::Class& c, hipStream_t s) {
+                enqueue_phase(c.ep, b->sd_dev + c.k0, c.count, kPhaseHx, true, s);
+            }))
+            return rc;
+    } else if (ph == kPhaseAdj) {
+        launch_pq(2, P.pmax, P.args[1], P.grid[1], P.lds[1], st);
+    } else {
+        if (int rc = for_classes(b, fork, st, 2, [&](vqe_batch::Class& c, hipStream_t s) {
+                enqueue_phase(c.ep, b->sd_dev + c.k0, c.count, kPhaseReduce, true, s);
+            }))
+            return rc;
+    }
+    HIPCHK(hipGetLastError());
+    return VQE_OK;
+}
+
+// After a synchronised evaluation: did a dependency wait of a persistent
+// pass give up?
+int check_persist(vqe_batch* b) {
+    if (!b->pq.on) return VQE_OK;
+    for (int i = 0; i < 2 * b->pq.nq; ++i)
+        if (b->pq.err_h[i] != 0)
+            return fail(VQE_EDEVICE, std::string("persistent ") + (i < b->pq.nq ? "forward" : "reverse") +
+                                         " pass: a dependency wait gave up (queue " +
+                                         std::to_string(i % b->pq.nq) + ")");
+    return VQE_OK;
+}
+
+int enqueue_err_copy(vqe_batch* b) {
+    if (b->pq.on)
+        HIPCHK(hipMemcpyAsync(b->pq.err_h, b->pq.args[0].err, sizeof(int32_t) * 2 * b->pq.nq,
+                              hipMemcpyDeviceToHost, b->st));
+    return VQE_OK;
+}
+
 // One full evaluation of every class; classes run on forked streams, the
 // heaviest first, each on the stream with the least work so far (work: the
 // class's run traffic, which scales with its state size, gate count and
 // states), so that the largest class does not queue behind others.
 int enqueue_batch(vqe_batch* b) {
+    if (b->pq.on) {
+        for (int ph = kPhaseFwd; ph <= kPhaseReduce; ++ph)
+            if (int rc = enqueue_pq_phase(b, ph, true, b->st)) return rc;
+        return VQE_OK;
+    }
     const size_t C = b->classes.size();
     const size_t ns = b->side.size();
     HIPCHK(hipEventRecord(b->events[0], b->st));
@@ -2850,6 +3155,26 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     b->classes.resize(rep.size());
     for (size_t c = 0; c < rep.size(); ++c)
         if (int rc = make_eval_plan(A[rep[c]], ne[rep[c]], true, &b->classes[c].ep)) return rc;
+    // persistent gate passes: every class on the packed layout with one common
+    // block-bit count (planned again with it), on a device whose XCDs the
+    // probe identified
+    XccMap* xm = nullptr;
+    bool persist = g_persist_mode.load() == 1;
+    const int Lp = g_persist_L.load();
+    for (size_t c = 0; c < rep.size() && persist; ++c) {
+        const EvalPlan& ep = b->classes[c].ep;
+        persist = ep.packed && ep.n >= Lp && packed_min_L(A[rep[c]], ne[rep[c]]) <= Lp;
+    }
+    if (persist) {
+        if (int rc = xcc_map(&xm)) return rc;
+        persist = xm->nq > 0;
+    }
+    if (persist)
+        for (size_t c = 0; c < rep.size(); ++c) {
+            b->classes[c].ep = EvalPlan{};
+            if (int rc = make_eval_plan(A[rep[c]], ne[rep[c]], true, &b->classes[c].ep, Lp)) return rc;
+            persist = persist && b->classes[c].ep.packed && b->classes[c].ep.hx.L == Lp;
+        }
     size_t need = 0;
     for (int i = 0; i < S; ++i)
         need += (b->classes[cls[i]].ep.ci ? 3 : 2) * sizeof(double2) * size_t(b->classes[cls[i]].ep.elems);
@@ -2959,13 +3284,17 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     if (int rc = dalloc(b, &b->sd_dev, S)) return rc;
     HIPCHK(hipMemcpy(b->sd_dev, sds.data(), sizeof(StateDesc) * S, hipMemcpyHostToDevice));
     HIPCHK(hipStreamSynchronize(b->st));
+    if (persist) {
+        if (int rc = build_persist(b, *xm)) return rc;
+        b->work[4] = b->work[6] = 1.0;   // one launch per pass
+    }
     const int nside = int(std::min<size_t>(b->classes.size(), 4));
     for (int i = 0; i < nside; ++i) {
         hipStream_t s;
         HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         b->side.push_back(s);
     }
-    for (int i = 0; i < nside + 1; ++i) {
+    for (int i = 0; i < 3 * (nside + 1); ++i) {   // up to three fork/join points
         hipEvent_t e;
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->events.push_back(e);
@@ -3015,7 +3344,9 @@ extern "C" int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, doub
     if (g_all)
         HIPCHK(hipMemcpyAsync(b->g_h, b->g_dev, sizeof(double) * b->goff[b->S],
                               hipMemcpyDeviceToHost, b->st));
+    if (int rc = enqueue_err_copy(b)) return rc;
     HIPCHK(hipStreamSynchronize(b->st));
+    if (int rc = check_persist(b)) return rc;
     std::memcpy(e_all, b->e_h, sizeof(double) * b->S);
     bool ok = finite_all(e_all, b->S);
     if (g_all) {
@@ -3038,15 +3369,23 @@ extern "C" int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps
     for (int r = 0; r < reps && rc == VQE_OK; ++r) {
         (void)hipEventRecord(ev[0], b->st);
         for (int ph = kPhaseFwd; ph <= kPhaseReduce; ++ph) {
-            for (auto& c : b->classes) enqueue_phase(c.ep, b->sd_dev + c.k0, c.count, ph, true, b->st);
+            if (b->pq.on) {
+                if ((rc = enqueue_pq_phase(b, ph, false, b->st)) != VQE_OK) break;
+            } else {
+                for (auto& c : b->classes) enqueue_phase(c.ep, b->sd_dev + c.k0, c.count, ph, true, b->st);
+            }
             (void)hipEventRecord(ev[ph + 1], b->st);
         }
+        if (rc == VQE_OK) rc = enqueue_err_copy(b);
+        if (rc != VQE_OK) break;
         hipError_t e = hipEventSynchronize(ev[4]);
         if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) {
             rc = fail(VQE_EDEVICE, std::string("profile: ") + hipGetErrorString(e));
             break;
         }
+        (void)hipStreamSynchronize(b->st);
+        if ((rc = check_persist(b)) != VQE_OK) break;
         for (int ph = 0; ph < 4; ++ph) {
             float t = 0.f;
             (void)hipEventElapsedTime(&t, ev[ph], ev[ph + 1]);
@@ -3097,6 +3436,52 @@ extern "C" int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, i
     if (!ok(fwd_threads) || !ok(adj_threads))
         return fail(VQE_ERANGE, "run threads must be 64, 256, 512 or 1024");
     g_threads[key] = {fwd_threads, adj_threads};
+    return VQE_OK;
+}
+
+extern "C" int vqe_set_persistent(int mode, int block_bits) {
+    if (mode < 0 || mode > 1) return fail(VQE_ERANGE, "persistent mode must be 0 or 1");
+    if (block_bits != 0 && (block_bits < 8 || block_bits > kHxMaxL))
+        return fail(VQE_ERANGE, "block_bits must be 0 or in [8, 14]");
+    g_persist_mode.store(mode);
+    g_persist_L.store(block_bits == 0 ? 12 : block_bits);
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_persistent(const vqe_batch* b, int* info) {
+    if (!b || !info) return fail(VQE_EINVAL, "null pointer argument");
+    const auto& P = b->pq;
+    info[0] = P.on ? 1 : 0;
+    info[1] = P.nq;
+    info[2] = P.grid[0];
+    info[3] = P.grid[1];
+    info[4] = int(std::min<size_t>(P.items[0].size(), size_t(INT32_MAX)));
+    info[5] = P.pmax;
+    info[6] = int(P.lds[0]);
+    info[7] = int(P.lds[1]);
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_test_wait(vqe_batch* b, int spin_limit, int poison) {
+    if (!b) return fail(VQE_EINVAL, "null batch");
+    if (spin_limit < 0) return fail(VQE_ERANGE, "spin_limit must be >= 0");
+    auto& P = b->pq;
+    if (!P.on) return fail(VQE_EINVAL, "the batch does not use the persistent passes");
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != b->dev) return fail(VQE_EINVAL, "batch belongs to another device");
+    HIPCHK(hipStreamSynchronize(b->st));
+    const int32_t spin = spin_limit == 0 ? g_persist_spin.load() : spin_limit;
+    HIPCHK(hipMemcpy(P.cnt, &spin, sizeof(int32_t), hipMemcpyHostToDevice));
+    // the first forward item with a dependency: its count out of reach, or restored
+    for (size_t i = 0; i < P.items[0].size(); ++i) {
+        if (P.items[0][i].need <= 0) continue;
+        PqItem it = P.items[0][i];
+        if (poison) it.need = INT32_MAX;
+        HIPCHK(hipMemcpy(const_cast<PqItem*>(P.args[0].items) + i, &it, sizeof(PqItem),
+                         hipMemcpyHostToDevice));
+        break;
+    }
     return VQE_OK;
 }
 
