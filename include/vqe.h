@@ -246,6 +246,23 @@ int vqe_expectation(const vqe_state* s, const vqe_hamiltonian* H, double* energy
 int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
                     const double* theta, double* energy, double* grad, void* hip_stream);
 
+/* vqe_energy_grad without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and kernels as
+ * vqe_energy_grad; calls no hipMalloc, hipFree or allocating library routine.
+ * Preconditions: vqe_energy_grad has run once with the same H, A and
+ * n_electrons on the current device (it builds the plans this call reuses;
+ * else EINVAL).  Workspace: a static device array of 64 MiB per device
+ * (held from module load until the process ends) holding phi, lambda, the
+ * H-apply's lambda planes, the angles, partials and outputs; evaluations
+ * that need more (on the packed layout, beyond about 22 qubits) return
+ * ERANGE before any device work.  Every call on a device shares that
+ * device's array: calls that overlap on one device (from several host
+ * threads or streams) race.  Synchronises hip_stream.  Errors: EINVAL,
+ * ERANGE, EDEVICE, ENUMERIC. */
+int vqe_energy_grad_noalloc(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electrons,
+                            const double* theta, double* energy, double* grad, void* hip_stream);
+
 /* ADAPT-VQE pool gradient (Sec. 2.1, "ADAPT-VQE algorithm"): with
  * psi = U_A(theta)|HF>, *energy = <psi|H|psi> and, for every parameter k of
  * `pool`, pool_grad[k] = d/dt <psi_t|H|psi_t> at t = 0, where psi_t applies

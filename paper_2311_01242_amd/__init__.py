@@ -21,7 +21,7 @@ from ._lib import Options, Result, lib
 VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -2, -3, -4, -5
 
 __all__ = [
-    "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "EnergyGrad",
+    "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "energy_grad_noalloc", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
     "set_packed", "set_run_threads", "copy_ceiling", "set_persistent",
 ]
@@ -348,6 +348,20 @@ def energy_grad(ham: Hamiltonian, ansatz: Ansatz, n_electrons: int, theta, grad:
     _check(lib().vqe_energy_grad(ham._h, ansatz._h, int(n_electrons), _dptr(theta), C.byref(e),
                                  _dptr(g) if grad else None,
                                  stream if stream is not None else current_stream()))
+    return e.value, (g[:theta.size] if grad else None)
+
+
+def energy_grad_noalloc(ham: Hamiltonian, ansatz: Ansatz, n_electrons: int, theta, grad: bool = True,
+                        stream=None):
+    """energy_grad through the library's allocation-free entry point (its
+    workspace is a static device array; energy_grad must have run once with
+    the same ham, ansatz and n_electrons on this device)."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    e = C.c_double()
+    g = np.empty(max(theta.size, 1), np.float64) if grad else None
+    _check(lib().vqe_energy_grad_noalloc(ham._h, ansatz._h, int(n_electrons), _dptr(theta), C.byref(e),
+                                         _dptr(g) if grad else None,
+                                         stream if stream is not None else current_stream()))
     return e.value, (g[:theta.size] if grad else None)
 
 

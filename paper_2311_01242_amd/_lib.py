@@ -68,6 +68,7 @@ SIGNATURES = {
     "vqe_apply_ansatz": (c_int, [vp, vp, P(c_double)]),
     "vqe_expectation": (c_int, [vp, vp, P(c_double)]),
     "vqe_energy_grad": (c_int, [vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
+    "vqe_energy_grad_noalloc": (c_int, [vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
     "vqe_pool_gradient": (c_int, [vp, vp, vp, c_int, P(c_double), P(c_double), P(c_double), vp]),
     "vqe_pool_gradient_profile": (c_int, [vp, vp, vp, c_int, P(c_double), c_int, P(c_double),
                                           P(c_double), vp]),

@@ -2085,6 +2085,60 @@ static int64_t sector_key(int n, int ne) { return (int64_t(n) << 16) | ne; }
 
 }  // namespace vqe
 
+namespace vqe {
+
+// ------------------------------------------------ allocation-free evaluation
+//
+// vqe_energy_grad_noalloc keeps its device workspace (phi, lambda, the
+// string-product lambda planes, angles, partials, outputs and the state
+// descriptor) in this array of the code object's static device memory (each
+// device holds its own copy from module load to process end) and its plans
+// in the records vqe_energy_grad leaves; it allocates nothing.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+// Host-side device address of `scratch` per device ordinal, looked up once
+// per device with that device current (the array's name in host code is a
+// stand-in, not a device address).
+constexpr int kNoAllocDevices = 64;
+static char* g_scratch_ptr[kNoAllocDevices] = {};
+static std::mutex g_scratch_mu;
+
+static int scratch_address(int dev, char** out) {
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(VQE_ERANGE, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VQE_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return VQE_OK;
+}
+
+// What the allocation-free call reuses from the last vqe_energy_grad of the
+// same (device, Hamiltonian, ansatz, n_electrons): the evaluation plan and
+// the state descriptor's plan pointers.
+struct NoAllocRec {
+    EvalPlan ep;
+    StateDesc sd;
+};
+static std::mutex g_noalloc_mu;
+static std::map<std::tuple<int, const void*, const void*, int>, NoAllocRec> g_noalloc;
+
+static void noalloc_forget(const void* handle) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    for (auto it = g_noalloc.begin(); it != g_noalloc.end();)
+        if (std::get<1>(it->first) == handle || std::get<2>(it->first) == handle)
+            it = g_noalloc.erase(it);
+        else
+            ++it;
+}
+
+}  // namespace vqe
+
 using namespace vqe;
 
 // ===================================================================== C ABI
@@ -2098,6 +2152,7 @@ struct vqe_state {
 };
 
 vqe_hamiltonian::~vqe_hamiltonian() {
+    noalloc_forget(this);
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto& kv : dev) {
@@ -2156,6 +2211,7 @@ vqe_hamiltonian::~vqe_hamiltonian() {
 }
 
 vqe_ansatz::~vqe_ansatz() {
+    noalloc_forget(this);
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto& kv : dev) {
@@ -2512,6 +2568,13 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     const int64_t M = int64_t(A->gates.size()), P = A->n_params;
     SingleEval e;
     if (int rc = setup_single(H, A, ne, theta, st, ScratchSize{}, &e)) return rc;
+    {   // the plans the allocation-free call reuses
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        g_noalloc[std::make_tuple(dev, static_cast<const void*>(H), static_cast<const void*>(A), ne)] =
+            NoAllocRec{e.ep, e.sd};
+    }
     if (int rc = enqueue_eval(e.ep, e.sd_dev, 1, grad != nullptr, st)) return rc;
     std::vector<double> raw(std::max<int64_t>(M, 1));
     HIPCHK(hipMemcpyAsync(energy, e.sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2521,6 +2584,87 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     bool ok = std::isfinite(*energy);
     if (grad) {
         accumulate_grad(A, raw.data(), grad);
+        ok = ok && finite_all(grad, P);
+    }
+    if (!ok) return fail(VQE_ENUMERIC, "non-finite energy or gradient");
+    return VQE_OK;
+}
+
+extern "C" int vqe_energy_grad_noalloc(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne,
+                                       const double* theta, double* energy, double* grad, void* stream) {
+    if (int rc = check_pair(H, A, ne)) return rc;
+    if (!energy) return fail(VQE_EINVAL, "null energy pointer");
+    if (A->n_params > 0 && !theta) return fail(VQE_EINVAL, "null theta");
+    if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t M = int64_t(A->gates.size()), P = A->n_params;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    NoAllocRec rec;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        auto it = g_noalloc.find(std::make_tuple(dev, static_cast<const void*>(H), static_cast<const void*>(A), ne));
+        if (it == g_noalloc.end())
+            return fail(VQE_EINVAL, "no plan for this Hamiltonian, ansatz and n_electrons on this device: "
+                                    "call vqe_energy_grad with them once first");
+        rec = it->second;
+    }
+    const EvalPlan& ep = rec.ep;
+    // the workspace the regular call carves, in the scratch array
+    const size_t elems = size_t(ep.elems);
+    const size_t planes = ep.ci ? size_t(ep.ciargs.nsplit) : 1;
+    ScratchSize sz;
+    sz.add<double2>(elems);
+    sz.add<double2>(elems);
+    sz.add<double2>(elems * planes);
+    sz.add<double>(size_t(P));
+    sz.add<double2>(size_t(M));
+    sz.add<double>(size_t(ep.nblk_e));
+    sz.add<double>(size_t(std::max<int64_t>(M, 1)) * size_t(ep.gstride));
+    sz.add<double>(1);
+    sz.add<double>(size_t(M));
+    sz.add<StateDesc>(1);
+    if (sz.s > kNoAllocBytes)
+        return fail(VQE_ERANGE, "the allocation-free evaluation needs " + std::to_string(sz.s) +
+                                    " bytes of scratch; it has " + std::to_string(kNoAllocBytes));
+    char* base = nullptr;
+    if (int rc = scratch_address(dev, &base)) return rc;
+    Carver cv{base};
+    StateDesc sd = rec.sd;
+    sd.phi = cv.take<double2>(elems);
+    sd.lam = cv.take<double2>(elems);
+    sd.aux = cv.take<double2>(elems * planes);
+    sd.theta = cv.take<double>(size_t(P));
+    sd.cs = cv.take<double2>(size_t(M));
+    sd.part_e = cv.take<double>(size_t(ep.nblk_e));
+    sd.part_g = cv.take<double>(size_t(std::max<int64_t>(M, 1)) * size_t(ep.gstride));
+    sd.out_e = cv.take<double>(1);
+    sd.out_g = cv.take<double>(size_t(M));
+    StateDesc* sd_dev = cv.take<StateDesc>(1);
+    // the array keeps the last call's contents: the full-layout sector
+    // H-apply writes only in-sector entries, so lambda starts at zero
+    if (ep.sector && !ep.packed) launch_fill_zero(sd.lam, elems, st);
+    if (P > 0)
+        HIPCHK(hipMemcpyAsync(const_cast<double*>(sd.theta), theta, sizeof(double) * P,
+                              hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sd_dev, &sd, sizeof(StateDesc), hipMemcpyHostToDevice, st));
+    if (int rc = enqueue_eval(ep, sd_dev, 1, grad != nullptr, st)) return rc;
+    HIPCHK(hipMemcpyAsync(energy, sd.out_e, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool ok = std::isfinite(*energy);
+    if (grad) {   // per-gate sums in fixed-size pieces, added in gate order
+        std::fill(grad, grad + P, 0.0);
+        constexpr int64_t kPiece = 2048;
+        double raw[kPiece];
+        for (int64_t j0 = 0; j0 < M; j0 += kPiece) {
+            const int64_t cnt = std::min(kPiece, M - j0);
+            HIPCHK(hipMemcpyAsync(raw, sd.out_g + j0, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t k = 0; k < cnt; ++k) {
+                const GateDesc& g = A->gates[size_t(j0 + k)];
+                grad[g.param] += (g.type == kExcitation ? 2.0 : 1.0) * g.scale * raw[k];
+            }
+        }
         ok = ok && finite_all(grad, P);
     }
     if (!ok) return fail(VQE_ENUMERIC, "non-finite energy or gradient");
