@@ -108,7 +108,8 @@ def test_warm_start_beats_hf_start_on_a_small_scan():
     """8-qubit analogue of the learned warm start: 40 scan points of
     h, g = A + B e^-lam + C e^-2lam, 32 train / 8 held out.  The warm start
     must reach the plain-VQE energy (within 1 mHa) at every held-out point,
-    and in fewer BFGS iterations on average."""
+    and in fewer BFGS iterations on average (iterations to within 1 mHa of
+    the lower of the two final energies; every run converged)."""
     from paper_2311_01242_amd import warmstart as W
     from vqe_inputs import warmstart_integrals
     n, ne = 8, 4
@@ -121,6 +122,7 @@ def test_warm_start_beats_hf_start_on_a_small_scan():
     rows = W.evaluate(scan, held, net, norm, A, n, ne, fam)
     s = W.summarize(rows)
     print(s)
-    assert s["within_1mHa"] == len(held)
+    assert s["plain_converged"] == len(held) and s["warm_converged"] == len(held)
+    assert s["warm_within_1mHa_of_plain"] == len(held)
     assert s["warm_iters_to_1mHa"]["missing"] == 0
     assert s["warm_iters_to_1mHa"]["mean"] < s["plain_iters_to_1mHa"]["mean"]
