@@ -354,6 +354,16 @@ int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_thre
  * Errors: ERANGE for other modes. */
 int vqe_set_packed(int mode);
 
+/* Tile size of the packed runs for n_qubits (batched or single-state
+ * launches; applies to plans made after the call).  A run is a stretch of
+ * consecutive gates whose high orbitals (above the block bits) fit a window
+ * of at most 4 bits, applied tile by tile, a tile being the blocks that agree
+ * outside the window; entries (16..8192) bounds the largest tile, so that
+ * fewer block bits with more window bits mean fewer runs (fewer passes over
+ * the state) at the same tile size.  0 restores the default, two of the
+ * layout's largest blocks.  Errors: ERANGE. */
+int vqe_set_tile_cap(int n_qubits, int batched, int entries);
+
 /* Persistent batch passes (process-wide, applies to batches created after
  * the call).  mode 1: when every state of a batch runs on the
  * packed sector layout and the device's XCDs can be identified (a probe

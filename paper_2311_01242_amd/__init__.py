@@ -23,7 +23,7 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "energy_grad_noalloc", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
-    "set_packed", "set_run_threads", "copy_ceiling", "set_persistent",
+    "set_packed", "set_run_threads", "copy_ceiling", "set_persistent", "set_tile_cap",
 ]
 
 
@@ -47,6 +47,13 @@ def set_packed(mode=True):
     full 2^n vectors."""
     m = 2 if mode is True else (0 if mode is False else int(mode))
     _check(lib().vqe_set_packed(m))
+
+
+def set_tile_cap(n_qubits: int, batched: bool, entries: int = 0):
+    """Largest packed run tile (entries per vector) for n_qubits; 0 = the
+    default (two of the layout's largest blocks).  Applies to plans made
+    afterwards."""
+    _check(lib().vqe_set_tile_cap(int(n_qubits), int(bool(batched)), int(entries)))
 
 
 def set_persistent(mode: bool = True, block_bits: int = 0):

@@ -6,13 +6,14 @@ candidate parameters and keeps the fastest:
 
 * forward run tile budget (LDS bytes per workgroup),
 * reverse run tile budget (phi + lambda tiles),
-* low-bit tile L of the sector H-apply.
+* low-bit tile L of the sector H-apply,
+* on the packed layout, the largest run tile (window grouping of the runs).
 
 The three phases are timed separately, so the search is per phase rather
 than over the product of the candidate sets.  On the packed sector layout
 (UCCSD programs, the default) L is also the layout's block size and the run
-budgets play no part, so only L is searched, by the time of the whole
-evaluation.  Only tiling changes: the gate order, and therefore the result
+budgets play no part: (L, largest run tile) pairs are searched by the time of
+the whole evaluation, with the run threads of each pass chosen per pair.  Only tiling changes: the gate order, and therefore the result
 up to summation order, never does.  Results are cached in a JSON file keyed
 by (device name, layout, qubits, electrons, states).
 """
@@ -23,9 +24,11 @@ import os
 
 import numpy as np
 
-from . import Batch, set_run_threads, set_tuning
+from . import Batch, VQEError, set_run_threads, set_tile_cap, set_tuning
 
 RUN_THREADS = (64, 256, 512, 1024)
+# largest packed run tile (entries per vector); 0 = two of the layout's largest blocks
+TILE_CAPS = (0, 1200, 1600, 2400)
 
 FWD_CANDIDATES = (16 << 10, 32 << 10, 64 << 10, 128 << 10)
 ADJ_CANDIDATES = (32 << 10, 64 << 10, 128 << 10)
@@ -56,24 +59,33 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None, packed=True):
         b.close()
         return ms
     if packed:
-        # every (L, threads) pair: the run threads of each pass are chosen per L,
-        # then L by the time of the whole evaluation
+        # every (L, tile cap, threads): the run threads of each pass are chosen
+        # per (L, cap), then (L, cap) by the time of the whole evaluation
         best, best_t, best_ms = None, None, None
-        for L in sorted({min(n, max(L, ne)) for L in (8, 9, 10, 11, 12, 13, 14)}):
-            rec = {}
-            for th in RUN_THREADS[:3]:
-                set_run_threads(n, True, th, th)
-                rec[th] = measure(64 << 10, 64 << 10, L)
-            tf = min(rec, key=lambda t: rec[t][0])
-            ta = min(rec, key=lambda t: rec[t][2])
-            m = [rec[tf][0], min(r[1] for r in rec.values()), rec[ta][2]]
-            t = sum(m)
-            if log:
-                log(f"n={n} packed L={L}: fwd {m[0]:.3f} ({tf}) + H {m[1]:.3f} + adj {m[2]:.3f} ({ta}) ms")
-            if best_t is None or t < best_t:
-                best, best_t, best_ms = (64 << 10, 64 << 10, L, tf, ta), t, m
+        for L in sorted({min(n, max(L, ne)) for L in (10, 11, 12, 13, 14)}):
+            for cap in TILE_CAPS:
+                set_tile_cap(n, True, cap)
+                rec = {}
+                for th in RUN_THREADS[1:3]:
+                    set_run_threads(n, True, th, th)
+                    try:
+                        rec[th] = measure(64 << 10, 64 << 10, L)
+                    except VQEError:   # a tile too large for the pair lists or the LDS
+                        pass
+                if not rec:
+                    continue
+                tf = min(rec, key=lambda t: rec[t][0])
+                ta = min(rec, key=lambda t: rec[t][2])
+                m = [rec[tf][0], min(r[1] for r in rec.values()), rec[ta][2]]
+                t = sum(m)
+                if log:
+                    log(f"n={n} packed L={L} cap={cap}: fwd {m[0]:.3f} ({tf}) + H {m[1]:.3f} + "
+                        f"adj {m[2]:.3f} ({ta}) ms")
+                if best_t is None or t < best_t:
+                    best, best_t, best_ms = (64 << 10, 64 << 10, L, tf, ta, cap), t, m
         set_tuning(n, True, *best[:3])
-        set_run_threads(n, True, *best[3:])
+        set_run_threads(n, True, *best[3:5])
+        set_tile_cap(n, True, best[5])
         return best, best_ms
     base = (64 << 10, 64 << 10, min(n, 14))
     best = list(base)
@@ -123,14 +135,16 @@ def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, 
         classes.setdefault((n, ne), []).append(i)
     out = {}
     for (n, ne), idx in sorted(classes.items()):
-        key = f"{dev}|{'packed' if packed else 'full'}|n={n}|ne={ne}|states={len(idx)}"
+        key = f"{dev}|{'packed-win' if packed else 'full'}|n={n}|ne={ne}|states={len(idx)}"
         if tag:
             key += f"|{tag}"
         if key in cache_data:
             vals = tuple(cache_data[key])
             set_tuning(n, True, *vals[:3])
-            if len(vals) == 5:
-                set_run_threads(n, True, *vals[3:])
+            if len(vals) >= 5:
+                set_run_threads(n, True, *vals[3:5])
+            if len(vals) >= 6:
+                set_tile_cap(n, True, vals[5])
             out[n] = vals
             continue
         sub = idx[:max_per_class]

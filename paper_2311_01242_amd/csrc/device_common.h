@@ -279,27 +279,101 @@ struct HxChunk {
 // Padding of a gate's pair list up to its class's stride.
 constexpr uint32_t kPairNone = 0xffffffffu;
 
+constexpr int kMaxTileBlocks = 16;   // blocks of one packed tile (window of at most 4 high bits)
+
+// A run of consecutive gates on the packed layout.  Its window W (high-part
+// bits, i.e. qubits L + bit) holds every high orbital its gates annihilate or
+// create; a tile is the set of blocks whose high parts agree outside W: tile
+// o has base high part pdep(o, free_hi) (free_hi = the high bits outside W),
+// and its blocks are base | blk[b] for the nblk patterns blk[b] within W that
+// some gate of the run pairs (blocks of other patterns stay unchanged).  A
+// tile's blocks are staged one after the other (empty blocks take no
+// entries); a gate's pairs come from the run's precomputed list for the
+// tile's class (the alpha and beta electron counts of the base).
 struct PackedRun {
     int32_t g0, g1;
-    uint32_t khi, dhi, free_hi;   // high parts of the created and annihilated orbitals; free bits
+    uint32_t W;                   // window (high-part bits)
+    uint32_t free_hi;             // high-part bits outside the window
     int32_t ntiles, L, na, nb;
-    int32_t shape, shape_adj;   // launch shapes of the forward and reverse passes
-    int32_t max_entries;
-    int32_t ncls;
-    const int2* info;        // per first-block class: {offset, stride} of the padded lists
+    int32_t shape, shape_adj;     // launch shapes of the forward and reverse passes
+    int32_t max_entries;          // largest tile (entries per vector)
+    int32_t ncls, cls_b;          // classes: a * cls_b + b, a/b the base's alpha/beta electrons
+    int32_t nblk;                 // blocks per tile
+    uint32_t blk[kMaxTileBlocks]; // their patterns within W
+    const int2* info;        // per class: {offset, stride} of the padded lists
     const uint32_t* ent;     // gate g of class c: ent[info[c].x + g * info[c].y + i]
     // the tiles that can hold a nonzero amplitude (starting from the
-    // reference, a tile stays zero until a run pairs it with a nonzero block);
-    // null when that is every tile.  Both passes launch these only.  The
-    // reverse sweep may skip a tile that is not live: both its blocks are zero
-    // in phi before the run, so they are zero whenever an earlier gate is
-    // reached, and lambda on them is never paired with a nonzero phi (a tile
-    // that pairs a zero block with a nonzero one is live, and makes both
-    // nonzero); its gradient partials are zero.  Partials are stored by
-    // position in this list (by tile without a list).
+    // reference, a tile stays zero until a run pairs one of its blocks with a
+    // nonzero block); null when that is every tile.  Both passes launch these
+    // only.  The reverse sweep may skip a tile that is not live: its blocks
+    // are zero in phi before the run, so they are zero whenever an earlier
+    // gate is reached, and lambda on them is never paired with a nonzero phi
+    // (a tile that pairs a zero block with a nonzero one is live, and all its
+    // blocks count as nonzero afterwards); its gradient partials are zero.
+    // Partials are stored by position in this list (by tile without a list).
     const int32_t* live;
     int32_t nlive;
 };
+
+// Pair-list entry: D's index in the tile (bits 0-12), E's (bits 13-25), the
+// parity of D's chain bits in the low part and in the window (bit 26).
+constexpr int kEntBits = 13;
+constexpr uint32_t kEntMask = (1u << kEntBits) - 1u;
+constexpr int kEntParity = 2 * kEntBits;
+constexpr int kMaxTileEntries = 1 << kEntBits;
+
+// The blocks of packed tile o of a run: base high part, the global offset and
+// tile offset of each block, total entries and class.  Uniform over a
+// workgroup; T is the layout's block tables (in LDS), base the block offsets.
+struct TileBlocks {
+    uint32_t hbase;               // high part of the tile's base (no window bits)
+    int nE;                       // entries of the tile
+    int cls;                      // the pair lists' class
+    int off[kMaxTileBlocks];      // tile offset of each block (prefix sums)
+    int64_t gb[kMaxTileBlocks];   // global offset of each block
+};
+
+__device__ __forceinline__ void tile_blocks(const HxTables& T, const PackedRun& run, int o,
+                                            const int32_t* __restrict__ base, TileBlocks& tb) {
+    uint32_t hb = 0, bits = run.free_hi, v = uint32_t(o);
+    while (bits) {   // pdep(o, free_hi)
+        const uint32_t low = bits & (~bits + 1u);
+        if (v & 1u) hb |= low;
+        v >>= 1;
+        bits &= bits - 1;
+    }
+    tb.hbase = hb;
+    const uint32_t hbg = hb << run.L;
+    const int ca = __popc(hbg & 0x55555555u), cb = __popc(hbg & 0xAAAAAAAAu);
+    tb.cls = ca * run.cls_b + cb;
+    int acc = 0;
+#pragma unroll
+    for (int b = 0; b < kMaxTileBlocks; ++b) {
+        tb.off[b] = acc;
+        tb.gb[b] = 0;
+        if (b < run.nblk) {
+            const uint32_t sg = run.blk[b] << run.L;
+            const int kA = run.na - ca - __popc(sg & 0x55555555u);
+            const int kB = run.nb - cb - __popc(sg & 0xAAAAAAAAu);
+            if (kA >= 0 && kA <= T.La && kB >= 0 && kB <= T.Lb) {
+                acc += (T.offA[kA + 1] - T.offA[kA]) * (T.offB[kB + 1] - T.offB[kB]);
+                tb.gb[b] = base[hb | run.blk[b]];
+            }
+        }
+    }
+    // a tile larger than the run's planned largest cannot occur; should it,
+    // it is treated as empty rather than overrun the LDS tile
+    tb.nE = acc <= run.max_entries ? acc : 0;
+}
+
+// Global offset of tile entry k (0 <= k < nE).
+__device__ __forceinline__ int64_t tile_global(const TileBlocks& tb, int nblk, int k) {
+    int64_t g = tb.gb[0] + k;
+#pragma unroll
+    for (int b = 1; b < kMaxTileBlocks; ++b)
+        if (b < nblk && k >= tb.off[b]) g = tb.gb[b] + (k - tb.off[b]);
+    return g;
+}
 
 // One excitation of a packed run: annihilated orbitals pd and created
 // orbitals klo in the low bits, chain parity split into low (chlo) and high
@@ -530,10 +604,6 @@ int blocks_for(uint64_t work);
 // One launch applies every run of every packed state of a batch (k_persist.hip).
 
 constexpr int kPqMaxXcc = 256;   // raw XCC ids the queue map covers
-
-struct BlockShape2 {
-    int kA, kB, cnt;
-};
 
 // A run of a class with what its tiles need besides the run descriptor.
 struct PqRun {

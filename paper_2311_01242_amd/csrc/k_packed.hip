@@ -12,36 +12,17 @@
 //
 // L is at least the number of electrons, so the reference lies in block 0.
 // A gate pairs D (annihilated orbitals occupied, created ones empty) with
-// E = D ^ x.  With dhi and khi the high parts of the annihilated and the
-// created orbitals, D lies in a block h that holds dhi and none of khi, and E
-// in block (h & ~dhi) | khi (for UCCSD on the reference dhi = 0: occupied
-// orbitals are low; generalised excitations may annihilate high orbitals).
-// Consecutive gates with the same (dhi, khi) form a run, applied tile by
-// tile: a tile is that block pair (one block when both are 0), staged in
-// LDS, all the run's gates applied, written back.
+// E = D ^ x.  Consecutive gates whose high orbitals (the annihilated and
+// created ones above the block bits) fit a window of at most 4 high bits form
+// a run, applied tile by tile: a tile is the set of blocks whose high parts
+// agree outside the window (those the run's gates pair), staged in LDS one
+// after the other, all the run's gates applied, written back.  For UCCSD on
+// the reference the occupied orbitals are low, so D and E differ in the
+// high bits of the created orbitals only; generalised excitations may also
+// annihilate high orbitals.
 #include "device_common.h"
 
 namespace vqe {
-
-struct BlockShape {
-    int kA, kB, cB, cnt;
-};
-
-// Alpha/beta electrons left to the low bits of block h, and its size (0 when
-// the high part alone has too many or too few electrons).
-__device__ __forceinline__ BlockShape block_shape(const HxTables& T, uint32_t hb, int na, int nb) {
-    BlockShape b;
-    b.kA = na - __popc(hb & 0x55555555u);
-    b.kB = nb - __popc(hb & 0xAAAAAAAAu);
-    if (b.kA < 0 || b.kA > T.La || b.kB < 0 || b.kB > T.Lb) {
-        b.cB = 1;
-        b.cnt = 0;
-        return b;
-    }
-    b.cB = T.offB[b.kB + 1] - T.offB[b.kB];
-    b.cnt = (T.offA[b.kA + 1] - T.offA[b.kA]) * b.cB;
-    return b;
-}
 
 __global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
     const StateDesc& s = sd[blockIdx.y];
@@ -52,10 +33,9 @@ __global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
 
 // VEC = 1: forward pass on phi.  VEC = 2: reverse sweep on phi and lambda
 // with per-gate, per-tile partials of Re <lambda|A_j phi> (A_j = T_j - T_j^dag).
-// Tile entry k (k < c0: block h, else block h | khi) is staged by thread
-// k % BS (EPT * BS covers the largest block of the run); a gate's pairs come
-// from the run's precomputed list for the tile's electron class, one pair
-// per thread per pass.
+// Tile entry k (blocks one after the other) is staged by thread k % BS
+// (2 EPT BS covers the largest tile of the run); a gate's pairs come from the
+// run's precomputed list for the tile's class, one pair per thread per pass.
 template <int VEC, int BS, int EPT>
 __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, PackedRun run,
                                              const PackedGate* __restrict__ pg,
@@ -77,26 +57,21 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const int o = run.live ? ldc(run.live + blockIdx.x) : int(blockIdx.x);
     const int po = int(blockIdx.x);
     const int tid = threadIdx.x;
-    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi) | run.dhi;
-    const uint32_t h1 = (h0 & ~run.dhi) | run.khi;
-    const uint32_t hb0 = h0 << run.L;
-    const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
-    const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
-    if (B0.cnt == 0 || B1.cnt == 0) {   // an empty tile: zero gradient partials
+    TileBlocks tb;
+    tile_blocks(T, run, o, base, tb);
+    if (tb.nE == 0) {   // an empty tile: zero gradient partials
         if (VEC == 2)
             for (int jl = tid; jl < run.g1 - run.g0; jl += BS)
                 s.part_g[size_t(run.g0 + jl) * s.gstride + po] = 0.0;
         return;
     }
-    const int c0 = B0.cnt;
-    const int c1 = (run.khi | run.dhi) ? B1.cnt : 0;
-    const int nE = c0 + c1;
-    const int64_t g0 = base[h0], g1 = base[h1];
+    const int nE = tb.nE;
+    const uint32_t hb0 = tb.hbase << run.L;
     double2* shp = sh;
     double2* shl = sh + nE;
     const bool fwd = (VEC == 1);
     const int ng = run.g1 - run.g0;
-    const int cls = B0.kA * (T.Lb + 1) + B0.kB;
+    const int cls = tb.cls;
     // the tile class's pair lists: gate j's list at lbase + j * stride, padded
     // with kPairNone; the first entry of each thread is loaded one gate ahead
     // (issued before the tile loads, so that it has arrived when the gate loop
@@ -107,7 +82,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     uint32_t ecur = (tid < stride) ? ldg32(lbase + size_t(fwd ? 0 : ng - 1) * stride + tid) : kPairNone;
     // per-gate parameters of this tile after the tile (2 double2 per gate):
     // (cos, sgn sin) and (sgn, 0), sgn the gate's pair sign from the tile's
-    // high bits; staged once, read by broadcast in the gate loop
+    // high bits outside the window (the window's part is in each entry);
+    // staged once, read by broadcast in the gate loop
     double2* gpar = sh + size_t(VEC) * run.max_entries;
     for (int j = tid; j < ng; j += BS) {
         const PackedGate g = pg[j];
@@ -121,7 +97,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
             const int k = min(tid + BS * u, nE - 1);
-            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            const int64_t gi = tile_global(tb, run.nblk, k);
             vp[u] = ldg2(s.phi + gi);
             if (VEC == 2) vl[u] = ldg2(s.lam + gi);
         }
@@ -139,6 +115,9 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         const int jl = fwd ? t : ng - 1 - t;
         const int jn = fwd ? jl + 1 : jl - 1;
         const bool more = t + 1 < ng;
+        // a gate's list is packed from its start: a wave whose lanes have no
+        // first entry has no pair in this gate (its partial is exactly 0)
+        const bool wave_busy = VEC == 2 && __builtin_amdgcn_ballot_w64(ecur != kPairNone) != 0;
         const uint32_t enext = (more && tid < stride) ? ldg32(lbase + size_t(jn) * stride + tid) : kPairNone;
         const double2 cs = gpar[2 * jl];                // (cos, sgn sin)
         const double sgn_hi = gpar[2 * jl + 1].x;      // the tile's part of the sign
@@ -147,8 +126,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         for (int i = tid; i < stride; i += BS) {
             const uint32_t e = (i == tid) ? ecur : ldg32(lbase + size_t(jl) * stride + i);
             if (e == kPairNone) break;   // the padding: the rest of the list is padding too
-            const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
-            const double ss = ((e >> 23) & 1u) ? -ssin : ssin;
+            const int k = int(e & kEntMask), ie = int((e >> kEntBits) & kEntMask);
+            const double ss = ((e >> kEntParity) & 1u) ? -ssin : ssin;
             if (fwd) {
                 double2 d = shp[k], f = shp[ie];
                 givens(d, f, cs.x, ss);
@@ -157,7 +136,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             } else {
                 double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
                 // <lam| A phi> with A|D> = s|E>, A|E> = -s|D> (s = ss / sin)
-                const double sg_t = ((e >> 23) & 1u) ? -sgn_hi : sgn_hi;
+                const double sg_t = ((e >> kEntParity) & 1u) ? -sgn_hi : sgn_hi;
                 acc += sg_t * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
                 givens(fD, fE, cs.x, -ss);   // U^dag: rotation by -theta
                 givens(lD, lE, cs.x, -ss);
@@ -168,7 +147,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             }
         }
         if (!fwd) {
-            acc = wave_total(acc);
+            acc = wave_busy ? wave_total(acc) : 0.0;
             if ((tid & 63) == 0) red[t & 1][tid >> 6] = acc;
             if (tid == 0 && t > 0) {   // previous gate's wave totals, fixed order
                 double v = 0.0;
@@ -194,7 +173,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     for (int u = 0; u < 2 * EPT; ++u) {
         const int k = tid + BS * u;
         if (k < nE) {
-            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            const int64_t gi = tile_global(tb, run.nblk, k);
             stg2(s.phi + gi, shp[k]);
             if (VEC == 2) stg2(s.lam + gi, shl[k]);
         }
@@ -231,19 +210,14 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ng = run.g1 - run.g0;
-    const uint32_t h0 = pdep32(uint32_t(o), run.free_hi) | run.dhi;
-    const uint32_t h1 = (h0 & ~run.dhi) | run.khi;
-    const uint32_t hb0 = h0 << run.L;
-    const BlockShape B0 = block_shape(T, hb0, run.na, run.nb);
-    const BlockShape B1 = block_shape(T, h1 << run.L, run.na, run.nb);
-    if (B0.cnt == 0 || B1.cnt == 0) {
+    TileBlocks tb;
+    tile_blocks(T, run, o, base, tb);
+    if (tb.nE == 0) {
         for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + o] = 0.0;
         return;
     }
-    const int c0 = B0.cnt;
-    const int c1 = (run.khi | run.dhi) ? B1.cnt : 0;
-    const int nE = c0 + c1;
-    const int64_t g0 = base[h0], g1 = base[h1];
+    const int nE = tb.nE;
+    const uint32_t hb0 = tb.hbase << run.L;
     double2* shp = sh;
     double2* shl = sh + nE;
     {
@@ -251,7 +225,7 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
             const int k = min(tid + BS * u, nE - 1);
-            const int64_t gi = (k < c0) ? g0 + k : g1 + (k - c0);
+            const int64_t gi = tile_global(tb, run.nblk, k);
             vp[u] = ldg2(s.phi + gi);
             vl[u] = ldg2(s.lam + gi);
         }
@@ -263,7 +237,7 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
         }
     }
     __syncthreads();
-    const int cls = B0.kA * (T.Lb + 1) + B0.kB;
+    const int cls = tb.cls;
     const PackedGate* pg = pg_all + run.g0;
     const int2 lc = ldc(run.info + cls);
     for (int jl = w; jl < ng; jl += BS / 64) {
@@ -274,8 +248,8 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
         for (int i = lane; i < lc.y; i += 64) {
             const uint32_t e = ldg32(lst + i);
             if (e == kPairNone) break;
-            const int k = int(e & 0x7ffu), ie = int((e >> 11) & 0xfffu);
-            const double sg_t = ((e >> 23) & 1u) ? -sgn_hi : sgn_hi;
+            const int k = int(e & kEntMask), ie = int((e >> kEntBits) & kEntMask);
+            const double sg_t = ((e >> kEntParity) & 1u) ? -sgn_hi : sgn_hi;
             const double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
             acc += sg_t * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
         }

@@ -61,18 +61,6 @@ __device__ __forceinline__ uint32_t xcc_id() {
     return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (15 << 11));
 }
 
-__device__ __forceinline__ BlockShape2 block_shape2(const HxTables& T, uint32_t hb, int na, int nb) {
-    BlockShape2 b;
-    b.kA = na - __popc(hb & 0x55555555u);
-    b.kB = nb - __popc(hb & 0xAAAAAAAAu);
-    if (b.kA < 0 || b.kA > T.La || b.kB < 0 || b.kB > T.Lb) {
-        b.cnt = 0;
-        return b;
-    }
-    b.cnt = (T.offA[b.kA + 1] - T.offA[b.kA]) * (T.offB[b.kB + 1] - T.offB[b.kB]);
-    return b;
-}
-
 // Copy of c consecutive amplitudes (both vectors of the reverse sweep) from
 // global memory into LDS, 8 per lane in flight per pass: buffer loads that
 // miss L1 and read 0 past the block's end (no branch around the loads).
@@ -112,9 +100,7 @@ struct PqTile {
     const double2* cs;       // the state's (cos, sin) per gate
     double* part_g;
     int32_t gstride;
-    int64_t g0, g1;
-    int c0, c1;              // entries of the two blocks (c1 = 0: one block)
-    uint32_t hb0;
+    TileBlocks tb;
     const uint32_t* lbase;   // the tile class's pair lists
     int stride;
     bool empty;
@@ -133,18 +119,9 @@ __device__ __forceinline__ void load_tile(const PqArgs& a, const HxTables& T, in
     d.part_g = s.part_g;
     d.gstride = s.gstride;
     const int o = d.run.live ? ldc(d.run.live + d.item.tile) : d.item.tile;
-    const uint32_t h0 = pdep32(uint32_t(o), d.run.free_hi) | d.run.dhi;
-    const uint32_t h1 = (h0 & ~d.run.dhi) | d.run.khi;
-    d.hb0 = h0 << d.run.L;
-    const BlockShape2 B0 = block_shape2(T, d.hb0, d.run.na, d.run.nb);
-    const BlockShape2 B1 = block_shape2(T, h1 << d.run.L, d.run.na, d.run.nb);
-    d.empty = (B0.cnt == 0 || B1.cnt == 0);
-    d.c0 = B0.cnt;
-    d.c1 = (d.run.khi | d.run.dhi) ? B1.cnt : 0;
-    d.g0 = ldc(base + h0);
-    d.g1 = ldc(base + h1);
-    const int cls = B0.kA * (T.Lb + 1) + B0.kB;
-    const int2 lc = d.empty ? make_int2(0, 0) : ldc(d.run.info + cls);
+    tile_blocks(T, d.run, o, base, d.tb);
+    d.empty = d.tb.nE == 0;
+    const int2 lc = d.empty ? make_int2(0, 0) : ldc(d.run.info + d.tb.cls);
     d.lbase = d.run.ent + lc.x;
     d.stride = lc.y;
 }
@@ -171,13 +148,19 @@ __device__ __forceinline__ void publish(const PqArgs& a, int state, int lane) {
 // per-gate parameters of the tile.
 template <int VEC>
 __device__ __forceinline__ void stage(const PqTile& d, double2* shp, double2* shl, double2* gpar, int lane) {
-    stage_block<VEC>(d.phi + d.g0, d.lam + d.g0, d.c0, shp, shl, lane);
-    if (d.c1 > 0) stage_block<VEC>(d.phi + d.g1, d.lam + d.g1, d.c1, shp + d.c0, shl + d.c0, lane);
+#pragma unroll
+    for (int b = 0; b < kMaxTileBlocks; ++b) {
+        if (b >= d.run.nblk) break;
+        const int c = (b + 1 < d.run.nblk ? d.tb.off[b + 1] : d.tb.nE) - d.tb.off[b];
+        if (c > 0)
+            stage_block<VEC>(d.phi + d.tb.gb[b], d.lam + d.tb.gb[b], c, shp + d.tb.off[b], shl + d.tb.off[b],
+                             lane);
+    }
     const int ng = d.run.g1 - d.run.g0;
     for (int j = lane; j < ng; j += 64) {
         const PackedGate g = d.pg[j];
         const double2 cs = d.cs[d.run.g0 + j];
-        const double sgn = g.csign * parity_sign(d.hb0 & g.chhi);
+        const double sgn = g.csign * parity_sign((d.tb.hbase << d.run.L) & g.chhi);
         gpar[2 * j] = make_double2(cs.x, sgn * cs.y);
         gpar[2 * j + 1] = make_double2(sgn, 0.0);
     }
@@ -226,7 +209,7 @@ __device__ __forceinline__ void apply_gate(const PqTile& d, int jl, const uint32
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         if (on[p]) {
-            const int k = int(e[p] & 0x7ffu), ie = int((e[p] >> 11) & 0xfffu);
+            const int k = int(e[p] & kEntMask), ie = int((e[p] >> kEntBits) & kEntMask);
             fD[p] = shp[k];
             fE[p] = shp[ie];
             if (VEC == 2) {
@@ -238,8 +221,8 @@ __device__ __forceinline__ void apply_gate(const PqTile& d, int jl, const uint32
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         if (on[p]) {
-            const int k = int(e[p] & 0x7ffu), ie = int((e[p] >> 11) & 0xfffu);
-            const bool neg = (e[p] >> 23) & 1u;
+            const int k = int(e[p] & kEntMask), ie = int((e[p] >> kEntBits) & kEntMask);
+            const bool neg = (e[p] >> kEntParity) & 1u;
             const double ss = neg ? -cs.y : cs.y;
             if (fwd) {
                 givens(fD[p], fE[p], cs.x, ss);
@@ -258,8 +241,8 @@ __device__ __forceinline__ void apply_gate(const PqTile& d, int jl, const uint32
     for (int i = lane + 64 * PMAX; OVF && i < d.stride; i += 64) {
         const uint32_t x = ldg32(d.lbase + size_t(jl) * d.stride + i);
         if (x == kPairNone) break;
-        const int k = int(x & 0x7ffu), ie = int((x >> 11) & 0xfffu);
-        const bool neg = (x >> 23) & 1u;
+        const int k = int(x & kEntMask), ie = int((x >> kEntBits) & kEntMask);
+        const bool neg = (x >> kEntParity) & 1u;
         const double ss = neg ? -cs.y : cs.y;
         double2 dd = shp[k], ff = shp[ie];
         if (fwd) {
@@ -366,9 +349,9 @@ __global__ void __launch_bounds__(64) k_pq(PqArgs a) {
         wave_lds_fence();
         if (!d.empty) {
             run_gates<VEC, PMAX, OVF>(d, shp, shl, gpar, gsum, lane);
-            const int nE = d.c0 + d.c1;
+            const int nE = d.tb.nE;
             for (int k = lane; k < nE; k += 64) {
-                const int64_t gi = (k < d.c0) ? d.g0 + k : d.g1 + (k - d.c0);
+                const int64_t gi = tile_global(d.tb, d.run.nblk, k);
                 stg2(d.phi + gi, shp[k]);
                 if (VEC == 2) stg2(d.lam + gi, shl[k]);
             }

@@ -45,11 +45,13 @@ struct Tuning {
     int L;                // low-bit tile of the sector H-apply
     int fwd_threads = 64; // packed layout: least threads per forward run tile
     int adj_threads = 64; // packed layout: least threads per reverse run tile
+    int tile_cap = 0;     // packed layout: entries per run tile (0: two of the largest blocks)
 };
 
 static std::mutex g_tune_mu;
 static std::map<std::pair<int, int>, Tuning> g_tune;   // (n, batched) -> override
 static std::map<std::pair<int, int>, std::pair<int, int>> g_threads;   // -> run threads
+static std::map<std::pair<int, int>, int> g_tile_cap;   // -> entries per run tile
 
 static Tuning default_tuning(int n, bool batched) {
     Tuning t;
@@ -82,6 +84,8 @@ static Tuning tuning_for(int n, bool batched) {
         t.fwd_threads = th->second.first;
         t.adj_threads = th->second.second;
     }
+    auto tc = g_tile_cap.find({n, batched ? 1 : 0});
+    if (tc != g_tile_cap.end()) t.tile_cap = tc->second;
     return t;
 }
 
@@ -225,7 +229,7 @@ struct PackedPlan {
 struct DevAnsatz {
     GateDesc* gates = nullptr;
     std::map<std::pair<int64_t, int64_t>, AnsatzPlan*> plans;
-    std::map<std::tuple<int, int, int>, PackedPlan*> packed;   // by (L, fwd, adj threads)
+    std::map<std::tuple<int, int, int, int>, PackedPlan*> packed;   // by (L, fwd, adj threads, tile cap)
 };
 
 static int current_device(int* dev) {
@@ -1351,7 +1355,7 @@ static int packed_min_L(const vqe_ansatz* A, int ne) {
 static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& lay,
                        const Tuning& tn, PackedPlan** out) {
     std::lock_guard<std::mutex> lk(A->mu);
-    const auto pkey = std::make_tuple(lay.L, tn.fwd_threads, tn.adj_threads);
+    const auto pkey = std::make_tuple(lay.L, tn.fwd_threads, tn.adj_threads, tn.tile_cap);
     auto it = da->packed.find(pkey);
     if (it != da->packed.end()) {
         *out = it->second;
@@ -1361,7 +1365,6 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     const uint32_t hmask = (1u << (n - L)) - 1u, lowmask = (1u << L) - 1u;
     const int64_t M = int64_t(A->gates.size());
     const HxTables& T = *host_tables(L);
-    const int ncls = (T.La + 1) * (T.Lb + 1);
     auto* p = new PackedPlan();
     p->L = L;
     p->gcnt.assign(size_t(M), 1);
@@ -1381,100 +1384,187 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     std::vector<int32_t> live_all;
     std::vector<std::pair<size_t, size_t>> live_of;   // per run: {offset, count}
     constexpr size_t kNoList = ~size_t(0);
+    // tile-size limit of a run (entries per vector): the tuning's, else two of
+    // the layout's largest blocks (a tile of one block pair)
+    int32_t maxblk = 1;
+    for (int32_t b : lay.bsize) maxblk = std::max(maxblk, b);
+    const int64_t cap = std::min<int64_t>(tn.tile_cap > 0 ? tn.tile_cap : 2 * int64_t(maxblk), kMaxTileEntries);
+    // block patterns (within window W) that the gates [j0, j1) pair: D blocks
+    // hold the gate's high annihilated bits and none of its high created ones,
+    // E blocks the reverse, with any combination of the window's other bits
+    auto used_patterns = [&](int64_t j0, int64_t j1, uint32_t W) {
+        uint32_t mask = 0;   // bit i: pattern pdep(i, W)
+        const int nw = __builtin_popcount(W);
+        for (int i = 0; i < (1 << nw); ++i) {
+            uint32_t s_ = 0, bits = W, v = uint32_t(i);
+            while (bits) {
+                const uint32_t low = bits & (~bits + 1u);
+                if (v & 1u) s_ |= low;
+                v >>= 1;
+                bits &= bits - 1;
+            }
+            for (int64_t k = j0; k < j1; ++k) {
+                const GateDesc& h = A->gates[size_t(k)];
+                const uint32_t dg = (h.pd >> L) & hmask, kg = ((h.x & ~h.pd) >> L) & hmask;
+                const uint32_t part = s_ & (dg | kg);
+                if (part == dg || part == kg) {
+                    mask |= 1u << i;
+                    break;
+                }
+            }
+        }
+        return mask;
+    };
+    auto pattern = [&](uint32_t W, int i) {
+        uint32_t s_ = 0, bits = W, v = uint32_t(i);
+        while (bits) {
+            const uint32_t low = bits & (~bits + 1u);
+            if (v & 1u) s_ |= low;
+            v >>= 1;
+            bits &= bits - 1;
+        }
+        return s_;
+    };
+    std::map<std::pair<uint32_t, uint32_t>, int64_t> tile_memo;   // (W, used mask) -> largest tile
+    auto largest_tile = [&](uint32_t W, uint32_t umask) {
+        auto key = std::make_pair(W, umask);
+        auto it2 = tile_memo.find(key);
+        if (it2 != tile_memo.end()) return it2->second;
+        const uint32_t free_ = hmask & ~W;
+        const int nf = __builtin_popcount(free_), nw = __builtin_popcount(W);
+        int64_t best = 0;
+        for (uint32_t o = 0; o < (1u << nf); ++o) {
+            const uint32_t base = pattern(free_, int(o));
+            int64_t sum = 0;
+            for (int i = 0; i < (1 << nw); ++i)
+                if (umask >> i & 1u) sum += lay.bsize[base | pattern(W, i)];
+            best = std::max(best, sum);
+        }
+        tile_memo[key] = best;
+        return best;
+    };
+    const int nAhi = __builtin_popcount((hmask << L) & 0x55555555u);   // alpha high qubits
+    const int nBhi = __builtin_popcount((hmask << L) & 0xAAAAAAAAu);
     int64_t j = 0;
     while (j < M) {
-        const GateDesc& g = A->gates[j];
-        const uint32_t khi = (g.x & ~g.pd) >> L, dhi = g.pd >> L;
-        int64_t j2 = j + 1;
-        while (j2 < M && j2 - j < kMaxRunGates &&
-               ((A->gates[j2].x & ~A->gates[j2].pd) >> L) == khi && (A->gates[j2].pd >> L) == dhi)
+        // grow the run: gate j2 joins while the window stays within 4 bits, the
+        // largest tile within cap entries and the run within kMaxRunGates gates
+        uint32_t W = 0, umask = 0;
+        int64_t j2 = j;
+        while (j2 < M && j2 - j < kMaxRunGates) {
+            const GateDesc& h = A->gates[size_t(j2)];
+            const uint32_t W2 = W | ((h.pd >> L) & hmask) | (((h.x & ~h.pd) >> L) & hmask);
+            if (__builtin_popcount(W2) > 4) break;
+            const uint32_t u2 = used_patterns(j, j2 + 1, W2);
+            if (j2 > j && largest_tile(W2, u2) > cap) break;
+            W = W2;
+            umask = u2;
             ++j2;
+        }
         PackedRun r{};
         r.g0 = int32_t(j);
         r.g1 = int32_t(j2);
-        r.khi = khi;
-        r.dhi = dhi;
-        r.free_hi = hmask & ~(khi | dhi);
+        r.W = W;
+        r.free_hi = hmask & ~W;
         r.ntiles = int32_t(1u << __builtin_popcount(r.free_hi));
         r.L = L;
         r.na = lay.na;
         r.nb = lay.nb;
-        int maxb = 1, maxe = 1;
+        r.nblk = 0;
+        for (int i = 0; i < (1 << __builtin_popcount(W)); ++i)
+            if (umask >> i & 1u) r.blk[r.nblk++] = pattern(W, i);
+        const int nAf = __builtin_popcount((r.free_hi << L) & 0x55555555u);
+        const int nBf = __builtin_popcount((r.free_hi << L) & 0xAAAAAAAAu);
+        (void)nAhi;
+        (void)nBhi;
+        r.cls_b = nBf + 1;
+        r.ncls = (nAf + 1) * (nBf + 1);
+        int maxe = 1;
         int64_t moved = 0, moved_live = 0;
         const size_t live0 = live_all.size();
-        std::vector<char> used(size_t(ncls), 0);   // first-block classes of live tiles
+        std::vector<char> used(size_t(r.ncls), 0);   // classes of nonempty tiles
         for (int32_t o = 0; o < r.ntiles; ++o) {
-            uint32_t h0 = dhi, bits = r.free_hi, v = uint32_t(o);
-            while (bits) {
-                const uint32_t low = bits & (~bits + 1u);
-                if (v & 1u) h0 |= low;
-                v >>= 1;
-                bits &= bits - 1;
+            const uint32_t base = pattern(r.free_hi, o);
+            int nE = 0;
+            bool any_nz = false;
+            for (int b = 0; b < r.nblk; ++b) {
+                const int c = lay.bsize[base | r.blk[b]];
+                nE += c;
+                if (c > 0 && nz[base | r.blk[b]]) any_nz = true;
             }
-            const bool two = (khi | dhi) != 0;   // D and E in different blocks
-            const int c0 = lay.bsize[h0], c1 = two ? lay.bsize[(h0 & ~dhi) | khi] : 0;
-            if (c0 == 0 || (two && c1 == 0)) continue;
-            maxb = std::max(maxb, std::max(c0, c1));
-            maxe = std::max(maxe, c0 + c1);
-            moved += c0 + c1;
-            {   // the run's gates leave a tile of zero blocks zero
-                const uint32_t h1 = two ? (h0 & ~dhi) | khi : h0;
-                if (nz[h0] || nz[h1]) {
-                    live_all.push_back(o);
-                    moved_live += c0 + c1;
-                    nz[h0] = nz[h1] = 1;
-                }
+            if (nE == 0) continue;
+            maxe = std::max(maxe, nE);
+            moved += nE;
+            if (any_nz) {   // the run's gates leave a tile of zero blocks zero
+                live_all.push_back(o);
+                moved_live += nE;
+                for (int b = 0; b < r.nblk; ++b)
+                    if (lay.bsize[base | r.blk[b]] > 0) nz[base | r.blk[b]] = 1;
             }
-            const uint32_t hb = h0 << L;
-            const int kA = lay.na - __builtin_popcount(hb & 0x55555555u);
-            const int kB = lay.nb - __builtin_popcount(hb & 0xAAAAAAAAu);
-            used[size_t(kA * (T.Lb + 1) + kB)] = 1;
+            const uint32_t hb = base << L;
+            used[size_t(__builtin_popcount(hb & 0x55555555u) * r.cls_b +
+                        __builtin_popcount(hb & 0xAAAAAAAAu))] = 1;
         }
-        r.ncls = ncls;
+        if (maxe > kMaxTileEntries) {
+            delete p;
+            return fail(VQE_EINVAL, "packed layout: tile too large for the pair lists");
+        }
         info0.push_back(info.size());
-        // beta electrons the high parts move from block h to block h ^ x_hi
-        // (the alpha ranks come from the per-popcount table)
-        const uint32_t khb = khi << L, dhb = dhi << L;
-        const int dB = __builtin_popcount(khb & 0xAAAAAAAAu) - __builtin_popcount(dhb & 0xAAAAAAAAu);
-        // pair lists per (gate, first-block class); laid out per class with every
-        // gate's list padded to the class's longest (kPairNone), so that gate g's
-        // list starts at offset + g * stride and needs no per-gate descriptor
+        // pair lists per (gate, class); laid out per class with every gate's
+        // list padded to the class's longest (kPairNone), so that gate g's list
+        // starts at offset + g * stride and needs no per-gate descriptor
         const int64_t ng = j2 - j;
-        std::vector<std::vector<uint32_t>> lists(size_t(ng) * size_t(ncls));
-        for (int64_t k = j; k < j2; ++k) {
-            const GateDesc& h = A->gates[k];
-            const uint32_t pd = h.pd & lowmask, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
-            for (int cls = 0; cls < ncls; ++cls) {
-                if (!used[size_t(cls)]) continue;
-                std::vector<uint32_t>& lst = lists[size_t(k - j) * ncls + cls];
-                const int kA0 = cls / (T.Lb + 1), kB0 = cls % (T.Lb + 1);
-                const int kB1 = kB0 - dB;
-                const int cB0 = T.offB[kB0 + 1] - T.offB[kB0];
-                const int c0 = (T.offA[kA0 + 1] - T.offA[kA0]) * cB0;
-                const int cB1 = T.offB[kB1 + 1] - T.offB[kB1];
-                const int eoff = (khi | dhi) ? c0 : 0;
-                for (int e = 0; e < c0; ++e) {   // D entries of the first block, rank order
-                    const uint32_t rd = uint32_t(T.unA[T.offA[kA0] + e / cB0] | T.unB[T.offB[kB0] + e % cB0]);
-                    if ((rd & (pd | klo)) != pd) continue;
-                    const uint32_t re = rd ^ pd ^ klo;
-                    const int ie = eoff + int(T.rankA[compact_even_host(re)]) * cB1 +
-                                   int(T.rankB[compact_even_host(re >> 1)]);
-                    const uint32_t par = uint32_t(__builtin_popcount(rd & chlo) & 1);
-                    if (e >= 2048 || ie >= 4096) {
-                        delete p;
-                        return fail(VQE_EINVAL, "packed layout: tile too large for the pair lists");
+        const int ncl = r.ncls;
+        std::vector<std::vector<uint32_t>> lists(size_t(ng) * size_t(ncl));
+        for (int cls = 0; cls < ncl; ++cls) {
+            if (!used[size_t(cls)]) continue;
+            const int ca = cls / r.cls_b, cb = cls % r.cls_b;
+            // the class's block shapes: (alpha, beta) electrons left to the low bits
+            int kA[kMaxTileBlocks], kB[kMaxTileBlocks], cnt[kMaxTileBlocks], off[kMaxTileBlocks];
+            int acc = 0;
+            for (int b = 0; b < r.nblk; ++b) {
+                const uint32_t sb = r.blk[b] << L;
+                kA[b] = lay.na - ca - __builtin_popcount(sb & 0x55555555u);
+                kB[b] = lay.nb - cb - __builtin_popcount(sb & 0xAAAAAAAAu);
+                const bool ok = kA[b] >= 0 && kA[b] <= T.La && kB[b] >= 0 && kB[b] <= T.Lb;
+                cnt[b] = ok ? (T.offA[kA[b] + 1] - T.offA[kA[b]]) * (T.offB[kB[b] + 1] - T.offB[kB[b]]) : 0;
+                off[b] = acc;
+                acc += cnt[b];
+            }
+            for (int64_t k = j; k < j2; ++k) {
+                const GateDesc& h = A->gates[size_t(k)];
+                const uint32_t pd = h.pd & lowmask, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
+                const uint32_t dg = (h.pd >> L) & hmask, kg = ((h.x & ~h.pd) >> L) & hmask;
+                std::vector<uint32_t>& lst = lists[size_t(k - j) * ncl + cls];
+                for (int b = 0; b < r.nblk; ++b) {
+                    if ((r.blk[b] & (dg | kg)) != dg || cnt[b] == 0) continue;   // D blocks
+                    const uint32_t se = r.blk[b] ^ dg ^ kg;
+                    int be = -1;
+                    for (int b2 = 0; b2 < r.nblk; ++b2)
+                        if (r.blk[b2] == se) be = b2;
+                    if (be < 0 || cnt[be] == 0) continue;
+                    const uint32_t par_hi = uint32_t(__builtin_popcount((r.blk[b] << L) & h.chain & ~lowmask) & 1);
+                    const int cB0 = T.offB[kB[b] + 1] - T.offB[kB[b]];
+                    const int cB1 = T.offB[kB[be] + 1] - T.offB[kB[be]];
+                    for (int e = 0; e < cnt[b]; ++e) {   // D entries of the block, rank order
+                        const uint32_t rd = uint32_t(T.unA[T.offA[kA[b]] + e / cB0] | T.unB[T.offB[kB[b]] + e % cB0]);
+                        if ((rd & (pd | klo)) != pd) continue;
+                        const uint32_t re = rd ^ pd ^ klo;
+                        const int ie = off[be] + int(T.rankA[compact_even_host(re)]) * cB1 +
+                                       int(T.rankB[compact_even_host(re >> 1)]);
+                        const uint32_t par = (uint32_t(__builtin_popcount(rd & chlo)) + par_hi) & 1u;
+                        lst.push_back(uint32_t(off[b] + e) | (uint32_t(ie) << kEntBits) | (par << kEntParity));
                     }
-                    lst.push_back(uint32_t(e) | (uint32_t(ie) << 11) | (par << 23));
                 }
             }
         }
-        for (int cls = 0; cls < ncls; ++cls) {
+        for (int cls = 0; cls < ncl; ++cls) {
             int2 rec = make_int2(int(ent.size()), 0);
             if (used[size_t(cls)]) {
                 size_t stride = 0;
-                for (int64_t g = 0; g < ng; ++g) stride = std::max(stride, lists[size_t(g) * ncls + cls].size());
+                for (int64_t g = 0; g < ng; ++g) stride = std::max(stride, lists[size_t(g) * ncl + cls].size());
                 for (int64_t g = 0; g < ng; ++g) {
-                    const std::vector<uint32_t>& lst = lists[size_t(g) * ncls + cls];
+                    const std::vector<uint32_t>& lst = lists[size_t(g) * ncl + cls];
                     ent.insert(ent.end(), lst.begin(), lst.end());
                     ent.insert(ent.end(), stride - lst.size(), kPairNone);
                 }
@@ -1487,16 +1577,16 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             delete p;
             return fail(VQE_ERANGE, "packed layout: pair lists too large");
         }
-        r.shape = packed_shape(maxb, tn.fwd_threads);
-        r.shape_adj = packed_shape(maxb, tn.adj_threads);
+        r.shape = packed_shape((maxe + 1) / 2, tn.fwd_threads);
+        r.shape_adj = packed_shape((maxe + 1) / 2, tn.adj_threads);
         r.max_entries = maxe;
         if (r.shape < 0 || r.shape_adj < 0) {
             delete p;
-            return fail(VQE_EINVAL, "packed layout: block too large for the run kernels");
+            return fail(VQE_EINVAL, "packed layout: tile too large for the run kernels");
         }
         p->off.push_back(int(pg.size()));
         for (int64_t k = j; k < j2; ++k) {
-            const GateDesc& h = A->gates[k];
+            const GateDesc& h = A->gates[size_t(k)];
             PackedGate q{};
             q.pd = h.pd;
             q.klo = (h.x & ~h.pd) & lowmask;
@@ -1504,7 +1594,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             q.chhi = h.chain & ~lowmask;
             q.csign = h.csign;
             pg.push_back(q);
-            p->gcnt[k] = r.ntiles;
+            p->gcnt[size_t(k)] = r.ntiles;
         }
         p->gstride = std::max(p->gstride, r.ntiles);
         p->max_lds = std::max(p->max_lds, (size_t(maxe) * 2 + 2 * size_t(ng)) * sizeof(double2));
@@ -2689,7 +2779,7 @@ static int pool_sweep(const vqe_ansatz* pool, PackedPlan* p, const PoolSweep** o
     const int nblk = int(blk.size());
     blk.insert(blk.end(), first.begin(), first.end());
     PoolSweep ps{};
-    ps.shape = packed_shape(maxe, 256);
+    ps.shape = packed_shape((maxe + 1) / 2, 256);
     if (ps.shape < 0) return fail(VQE_EINVAL, "pool sweep: block too large for the run kernels");
     PackedRun* d_runs = nullptr;
     int32_t* d_blk = nullptr;
@@ -3580,6 +3670,18 @@ extern "C" int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, i
     if (!ok(fwd_threads) || !ok(adj_threads))
         return fail(VQE_ERANGE, "run threads must be 64, 256, 512 or 1024");
     g_threads[key] = {fwd_threads, adj_threads};
+    return VQE_OK;
+}
+
+extern "C" int vqe_set_tile_cap(int n_qubits, int batched, int entries) {
+    if (n_qubits < 1 || n_qubits > 32) return fail(VQE_ERANGE, "n_qubits must be in [1, 32]");
+    if (entries != 0 && (entries < 16 || entries > kMaxTileEntries))
+        return fail(VQE_ERANGE, "entries must be 0 or in [16, 8192]");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (entries == 0)
+        g_tile_cap.erase({n_qubits, batched ? 1 : 0});
+    else
+        g_tile_cap[{n_qubits, batched ? 1 : 0}] = entries;
     return VQE_OK;
 }
 
