@@ -23,7 +23,7 @@ ARCH = os.environ.get("VQE_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX_HOST", shutil.which("g++") or "g++")
 
-DEVICE_SOURCES = ["k_gates.hip", "k_hamiltonian.hip", "k_packed.hip", "k_hx_ci.hip", "k_mlp.hip", "k_measure.hip", "k_persist.hip", "vqe_device.hip"]
+DEVICE_SOURCES = ["k_gates.hip", "k_hamiltonian.hip", "k_packed.hip", "k_hx_ci.hip", "k_mlp.hip", "k_measure.hip", "k_persist.hip", "k_small.hip", "vqe_device.hip"]
 HOST_SOURCES = ["vqe_host.cpp"]
 DEVICE_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -67,6 +67,7 @@ struct StateDesc {
     // the pair) ^ (its class's wbc without the pair's two orbitals); the list
     // entry carries the first part's parity for its column (bit 31)
     int32_t ci_psplit;
+    int32_t nsub, ntab;      // subgroup descriptors and table entries of the Hamiltonian
 };
 
 // String-product ("CI") order of the sector: the amplitude of alpha string a
@@ -598,6 +599,31 @@ int packed_shape_threads(int shape);
 int packed_enable_lds(size_t bytes);  // 0 on success
 
 int blocks_for(uint64_t work);
+
+// ------------------------------------------------------ small sectors
+//
+// Number-conserving programs whose sector (strings of k set qubits among n)
+// fits one workgroup: whole-state kernels (k_small.hip).
+constexpr int kSmallMaxN = 13;          // rank table of 2^n int16 entries in LDS
+constexpr int kSmallMaxSector = 2048;   // amplitudes per state
+
+constexpr int kSmallMaxGates = 1024;
+constexpr int kSmallHamLds = 96 << 10;  // largest Hamiltonian staged in LDS (bytes)
+
+struct SmallSpace {
+    const uint32_t* str;     // [nsec] the sector's strings, increasing
+    const int16_t* rank;     // [2^n] rank of a string in the sector, -1 outside
+    int32_t n, nsec, ref_rank, M;
+    int32_t ham_lds;         // LDS bytes for the largest Hamiltonian of the launch; 0: read from memory
+};
+
+// Bytes of a Hamiltonian's groups, subgroups and tables.
+__host__ __device__ inline size_t small_ham_bytes(int G, int nsub, int ntab) {
+    return 16 * size_t(G) + 8 * size_t(nsub) + 8 * size_t(ntab);
+}
+size_t small_lds(const SmallSpace& sp, int phase);
+int small_prepare(const SmallSpace& sp);   // 0 when the kernels can launch
+void launch_small(int phase, const StateDesc* sd, int count, const SmallSpace& sp, hipStream_t st);
 
 // ------------------------------------------------------- persistent passes
 //

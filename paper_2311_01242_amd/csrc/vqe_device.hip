@@ -2000,7 +2000,71 @@ struct EvalPlan {
     const CiSpace* cspace = nullptr;
     CiArgs ciargs{};
     const int32_t* perm = nullptr;
+    bool small = false;      // whole-state kernels on a small number-conserving sector
+    SmallSpace sspace{};
 };
+
+// The strings of k set qubits among n (increasing) and their rank table, per
+// (device, n, k).
+struct SmallTables {
+    uint32_t* str = nullptr;
+    int16_t* rank = nullptr;
+    int nsec = 0;
+    std::vector<int16_t> rank_h;
+};
+static std::mutex g_small_mu;
+static std::map<std::tuple<int, int, int>, SmallTables*> g_small;
+
+static int small_tables(int n, int k, SmallTables** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_small_mu);
+    SmallTables*& t = g_small[std::make_tuple(dev, n, k)];
+    if (t) {
+        *out = t;
+        return VQE_OK;
+    }
+    auto* x = new SmallTables();
+    std::vector<uint32_t> str;
+    x->rank_h.assign(size_t(1) << n, int16_t(-1));
+    for (uint32_t b = 0; b < (1u << n); ++b)
+        if (__builtin_popcount(b) == k) {
+            x->rank_h[b] = int16_t(str.size());
+            str.push_back(b);
+        }
+    x->nsec = int(str.size());
+    int rc = upload(&x->str, str.data(), str.size());
+    if (!rc) rc = upload(&x->rank, x->rank_h.data(), x->rank_h.size());
+    if (rc) {
+        (void)hipFree(x->str);
+        (void)hipFree(x->rank);
+        delete x;
+        return rc;
+    }
+    t = x;
+    *out = t;
+    return VQE_OK;
+}
+
+// Every gate an excitation whose created qubits are as many as its
+// annihilated ones: the number of set qubits is conserved.
+static bool number_conserving(const vqe_ansatz* A) {
+    for (const GateDesc& g : A->gates)
+        if (g.type != kExcitation || __builtin_popcount(g.pd) != __builtin_popcount(g.x & ~g.pd))
+            return false;
+    return true;
+}
+
+// Let the small-sector H-apply stage Hamiltonian H in LDS when it fits (the
+// launch then reserves room for the largest of its states' Hamiltonians).
+static void small_fit_ham(EvalPlan* ep, const vqe_hamiltonian* H) {
+    if (!ep->small) return;
+    const size_t bytes = small_ham_bytes(int(H->groups.size()), int(H->subs.size()), int(H->tabs.size()));
+    if (bytes > size_t(kSmallHamLds) || bytes <= size_t(ep->sspace.ham_lds)) return;
+    SmallSpace t = ep->sspace;
+    t.ham_lds = int32_t((bytes + 7) & ~size_t(7));
+    if (small_prepare(t) == 0) ep->sspace = t;
+}
 
 static bool sector_path(const vqe_ansatz* A, int ne) {
     return A->sector_conserving && A->n_electrons == ne;
@@ -2066,6 +2130,30 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
         }
     } else {
         ep->nblk_e = blocks_for(uint64_t(1) << n);
+        // number-conserving programs on a small sector: whole-state kernels
+        const uint32_t ref = A->ref_bits >= 0 ? uint32_t(A->ref_bits) : uint32_t((uint64_t(1) << ne) - 1);
+        if (g_packed_enabled.load() >= 1 && n <= kSmallMaxN && number_conserving(A) &&
+            binom(n, __builtin_popcount(ref)) <= kSmallMaxSector && A->gates.size() <= size_t(kSmallMaxGates)) {
+            SmallTables* st;
+            if (int rc = small_tables(n, __builtin_popcount(ref), &st)) return rc;
+            ep->small = true;
+            ep->sspace.str = st->str;
+            ep->sspace.rank = st->rank;
+            ep->sspace.n = n;
+            ep->sspace.nsec = st->nsec;
+            ep->sspace.ref_rank = st->rank_h[ref];
+            ep->sspace.M = int32_t(A->gates.size());
+            ep->sspace.ham_lds = 0;
+            ep->elems = st->nsec;
+            ep->nblk_e = 1;
+            ep->gstride = 1;
+            ep->d_gcnt = nullptr;
+            ep->fwd_bytes = double(sizeof(double2)) * double(st->nsec);        // phi written
+            ep->adj_bytes = 2.0 * double(sizeof(double2)) * double(st->nsec);  // phi, lambda read
+            ep->fwd_steps = ep->adj_steps = 1;
+            if (small_prepare(ep->sspace) != 0)
+                return fail(VQE_EDEVICE, "could not enable the small-sector kernels' LDS size");
+        }
     }
     return VQE_OK;
 }
@@ -2103,6 +2191,17 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
 
 static void enqueue_phase(const EvalPlan& ep, const StateDesc* sd, int count, int phase, bool grad,
                           hipStream_t st) {
+    if (ep.small) {
+        if (phase == kPhaseFwd) {
+            launch_small(0, sd, count, ep.sspace, st);
+        } else if (phase == kPhaseHx) {
+            launch_small(1, sd, count, ep.sspace, st);
+        } else if (phase == kPhaseAdj) {
+            if (grad) launch_small(2, sd, count, ep.sspace, st);
+        }
+        // the H-apply writes the energy, the reverse sweep the per-gate sums
+        return;
+    }
     if (ep.packed) {
         enqueue_packed(ep, sd, count, phase, grad, st);
         return;
@@ -2512,6 +2611,8 @@ extern "C" int vqe_expectation(const vqe_state* s, const vqe_hamiltonian* H, dou
     c.sd.subs = dh->subs;
     c.sd.tabs = dh->tabs;
     c.sd.G = int32_t(H->groups.size());
+    c.sd.nsub = int32_t(H->subs.size());
+    c.sd.ntab = int32_t(H->tabs.size());
     HIPCHK(hipMemcpyAsync(c.sd_dev, &c.sd, sizeof(StateDesc), hipMemcpyHostToDevice, s->st));
     launch_hx_dense(c.sd_dev, 1, N, nblk, 0, s->st);
     launch_reduce_e(c.sd_dev, 1, nblk, s->st);
@@ -2541,6 +2642,7 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
     const int64_t M = int64_t(A->gates.size()), P = A->n_params;
     if (int rc = dev_ham(H, &e->dh)) return rc;
     if (int rc = make_eval_plan(A, ne, false, &e->ep)) return rc;
+    small_fit_ham(&e->ep, H);
     if (int rc = dev_ansatz(A, &e->da)) return rc;
     const EvalPlan& ep = e->ep;
     HxWork* hw = nullptr;
@@ -2635,6 +2737,8 @@ int setup_single(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne, const do
     sd.out_g = cv.take<double>(M);
     sd.n = n;
     sd.G = int32_t(H->groups.size());
+    sd.nsub = int32_t(H->subs.size());
+    sd.ntab = int32_t(H->tabs.size());
     sd.M = int32_t(M);
     sd.ne = ne;
     sd.ref = reference_index(A, ne);
@@ -3425,6 +3529,7 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         auto& cl = b->classes[cls[i]];
         if (cl.count == 0) cl.k0 = k;
         ++cl.count;
+        small_fit_ham(&cl.ep, H[i]);
         const EvalPlan& ep = cl.ep;
         const int n = H[i]->n;
         const int64_t M = int64_t(A[i]->gates.size());
@@ -3501,6 +3606,8 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         sd.out_g = b->g_dev + b->goff[i];
         sd.n = n;
         sd.G = int32_t(H[i]->groups.size());
+        sd.nsub = int32_t(H[i]->subs.size());
+        sd.ntab = int32_t(H[i]->tabs.size());
         sd.M = int32_t(M);
         sd.ne = ne[i];
         sd.ref = reference_index(A[i], ne[i]);
