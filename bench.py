@@ -312,6 +312,45 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
     return out
 
 
+def time_batch(b, theta, args):
+    """Time `args.steps` evaluations of batch b after `args.warmup` untimed
+    ones.  The timed loop calls the device-resident entry (theta, E and g in
+    HBM, nothing crosses PCIe); the host-buffer entry (theta upload, E/g
+    download, host gradient accumulation and checks) is timed after it over
+    the same number of steps and reported beside the value, never as it.
+    Returns (seconds device entry, seconds host entry, E, g) with E, g copied
+    back once after the timed region."""
+    import torch
+    P = int(b.offsets[-1])
+    th = torch.tensor(np.asarray(theta, np.float64), device="cuda")
+    e = torch.empty(b.S, dtype=torch.float64, device="cuda")
+    g = torch.empty(P, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        b.energy_grad_device(th, e, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.energy_grad_device(th, e, g)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e_h, g_h = e.cpu().numpy(), g.cpu().numpy()
+    assert np.all(np.isfinite(e_h)) and np.all(np.isfinite(g_h))
+    b.energy_grad(theta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.energy_grad(theta)
+    torch.cuda.synchronize()
+    dt_host = time.perf_counter() - t0
+    return dt, dt_host, e_h, g_h
+
+
+def host_entry(states, steps, dt_host):
+    return {"value": round(states * steps / dt_host, 2), "ms_per_step": round(1e3 * dt_host / steps, 3),
+            "what": "host-buffer entry: theta upload, E/g download and host-side gradient accumulation "
+                    "included (PCIe-inclusive rate; not the value)"}
+
+
 def run_batch(args):
     import torch
     import paper_2311_01242_amd as vq
@@ -332,16 +371,8 @@ def run_batch(args):
         phase_ms = b.profile(theta, reps=args.profile_reps)
         return {"profile_only": True, "phase_ms": [round(x, 3) for x in phase_ms],
                 "work": b.work().tolist()}
-    for _ in range(args.warmup):
-        b.energy_grad(theta)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e, g = b.energy_grad(theta)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt, dt_host, e, g = time_batch(b, theta, args)
     ms_step = 1e3 * dt / args.steps
-    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
     key = TRAFFIC_WORKLOAD if (args.states, args.ansatz) == (512, "uccsd") else None
     roof = roofline(b, theta, args.profile_reps, Hs, nes, traffic_key=key)
     ceilings = copy_ceilings()
@@ -360,6 +391,7 @@ def run_batch(args):
                    "parallelism": "single GPU"},
         "roofline": roof,
         "ceilings": ceilings,
+        "host_entry": host_entry(args.states, args.steps, dt_host),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(spec, ansatz=args.ansatz)
@@ -408,15 +440,7 @@ def run_puccd11(args):
     A = vq.Ansatz.puccd(n_orb, n_pairs)
     b = vq.Batch(Hs, [A] * S, [n_pairs] * S)
     th = np.concatenate([uniform_theta(50000 + i, A.n_params) for i in range(S)])
-    for _ in range(args.warmup):
-        b.energy_grad(th)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e, g = b.energy_grad(th)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert np.all(np.isfinite(e)) and np.all(np.isfinite(g))
+    dt, dt_host, e, g = time_batch(b, th, args)
     from math import comb
     nsec = comb(n_orb, n_pairs)
     # (output, x-group) pairs the sector H-apply evaluates: every in-sector
@@ -432,6 +456,7 @@ def run_puccd11(args):
                                "per step, one HIP-graph launch (330-string pair-number sector)",
                    "states": S},
         "roofline": roof,
+        "host_entry": host_entry(S, args.steps, dt_host),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_puccd(fam, lams, th, n_orb, n_pairs)
@@ -509,14 +534,7 @@ def run_scan12(args):
         autotune.autotune_batch(Hs, [A] * len(Hs), [6] * len(Hs), th, offs, cache=TUNE_CACHE,
                                 packed=(args.mapping == "jw"), tag="scan-" + args.mapping)
     b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
-    for _ in range(args.warmup):
-        b.energy_grad(th)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.energy_grad(th)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt, dt_host, _, _ = time_batch(b, th, args)
     if args.mapping == "bk":
         roof = roofline(b, th, args.profile_reps, Hs, [6] * len(Hs), kernels=ROTATION_KERNELS,
                         pairs=float(sum((1 << 12) * H.info()[1] for H in Hs)))
@@ -533,6 +551,7 @@ def run_scan12(args):
                                   "bk": "Bravyi-Kitaev (full-vector Pauli-rotation kernels)"}[args.mapping],
                    "mapping": args.mapping},
         "roofline": roof,
+        "host_entry": host_entry(len(Hs), args.steps, dt_host),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_scan(fam, SCAN12_LAMBDAS, th[:A.n_params])

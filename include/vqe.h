@@ -308,6 +308,21 @@ int vqe_batch_offsets(const vqe_batch* b, int64_t* offsets);
 int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, double* e_all,
                           double* g_all);
 
+/* The same evaluation with every buffer in device memory of the batch's
+ * device: theta_all (total params doubles) is read, e_all[n_states] and
+ * g_all[total params] (nullable) are written, with the gradient in the same
+ * bits as vqe_batch_energy_grad's.  Asynchronous: ordered after the work
+ * already enqueued on the hip_stream given to vqe_batch_create, and that
+ * stream waits for the results, so the caller synchronises it (or orders
+ * later work on it) before reading them.  No host copy and no host-side
+ * check: non-finite values are not reported (the caller tests them), and the
+ * call returns EINVAL on a batch with persistent passes, whose wait checks
+ * need the host.  The first call with g_all builds the batch's parameter map
+ * (device allocation, synchronous); later calls allocate nothing.  The
+ * buffers must stay valid until the stream has passed the call. */
+int vqe_batch_energy_grad_device(vqe_batch* b, const double* theta_all, double* e_all,
+                                 double* g_all);
+
 void vqe_batch_free(vqe_batch* b);
 
 /* Phase timing of one evaluation, measured with HIP events on the batch

@@ -461,6 +461,25 @@ class Batch:
                                            _dptr(g) if grad else None))
         return e, (g[:theta_all.size] if grad else None)
 
+    def energy_grad_device(self, theta_all, e_all, g_all=None):
+        """The evaluation on device buffers (float64 tensors on the batch's
+        device: theta_all [total params], e_all [S], g_all [total params] or
+        None), ordered on the stream the batch was created with; nothing is
+        copied to the host and nothing is checked there."""
+        import torch
+        P = int(self.offsets[-1])
+        for name, t, size in (("theta_all", theta_all, P), ("e_all", e_all, self.S),
+                              ("g_all", g_all, P)):
+            if t is None:
+                if name != "g_all":
+                    raise ValueError(f"{name} is required")
+                continue
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == size):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of {size} entries")
+        _check(lib().vqe_batch_energy_grad_device(self._h, C.c_void_p(theta_all.data_ptr()),
+                                                  C.c_void_p(e_all.data_ptr()),
+                                                  C.c_void_p(g_all.data_ptr()) if g_all is not None else None))
+
     def profile(self, theta_all, reps: int = 3):
         """Per-phase milliseconds of one evaluation (forward, H-apply, adjoint,
         reductions), timed with HIP events on the batch stream."""

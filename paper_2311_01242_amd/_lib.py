@@ -75,6 +75,7 @@ SIGNATURES = {
     "vqe_batch_create": (c_int, [c_int, P(vp), P(vp), P(c_int), vp, P(vp)]),
     "vqe_batch_offsets": (c_int, [vp, P(c_int64)]),
     "vqe_batch_energy_grad": (c_int, [vp, P(c_double), P(c_double), P(c_double)]),
+    "vqe_batch_energy_grad_device": (c_int, [vp, vp, vp, vp]),
     "vqe_batch_free": (None, [vp]),
     "vqe_batch_profile": (c_int, [vp, P(c_double), c_int, P(c_double)]),
     "vqe_batch_work": (c_int, [vp, P(c_double)]),

@@ -554,6 +554,8 @@ void launch_adj_pauli(const StateDesc* sd, int count, int j, uint64_t N, int nbl
 void launch_hx_dense(const StateDesc* sd, int count, uint64_t N, int nblk, int write_lam,
                      hipStream_t st);
 void launch_reduce_e(const StateDesc* sd, int count, int nblk, hipStream_t st);
+void launch_param_grad(const int64_t* start, const int64_t* gate, const double* coef, const double* raw,
+                       double* g, int64_t P, hipStream_t st);
 void launch_reduce_g(const StateDesc* sd, int count, int M, const int32_t* cnt, int cnt_uniform,
                      hipStream_t st);
 void launch_run_fwd(const StateDesc* sd, int count, const RunDesc& run, const TileGate* tg,
@@ -617,9 +619,11 @@ struct SmallSpace {
     int32_t ham_lds;         // LDS bytes for the largest Hamiltonian of the launch; 0: read from memory
 };
 
-// Bytes of a Hamiltonian's groups, subgroups and tables.
+// LDS bytes of a Hamiltonian staged for the small-sector H-apply: groups,
+// tables, subgroups and the subgroup -> group map, each 16-byte aligned.
 __host__ __device__ inline size_t small_ham_bytes(int G, int nsub, int ntab) {
-    return 16 * size_t(G) + 8 * size_t(nsub) + 8 * size_t(ntab);
+    auto r16 = [](size_t v) { return (v + 15) & ~size_t(15); };
+    return 16 * size_t(G) + r16(8 * size_t(ntab)) + r16(8 * size_t(nsub)) + r16(4 * size_t(nsub));
 }
 size_t small_lds(const SmallSpace& sp, int phase);
 int small_prepare(const SmallSpace& sp);   // 0 when the kernels can launch

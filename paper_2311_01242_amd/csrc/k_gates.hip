@@ -214,6 +214,20 @@ __global__ void __launch_bounds__(kBlock) k_reduce_g(const StateDesc* __restrict
     if (threadIdx.x == 0) s.out_g[j] = r;
 }
 
+// Per-parameter gradient from the raw per-gate sums: parameter q takes, in
+// gate order, coef[k] * raw[gate[k]] for k in [start[q], start[q + 1]), each
+// product rounded before its addition (the host accumulation's arithmetic, so
+// both give the same bits).
+__global__ void k_param_grad(const int64_t* __restrict__ start, const int64_t* __restrict__ gate,
+                             const double* __restrict__ coef, const double* __restrict__ raw,
+                             double* __restrict__ g, int64_t P) {
+    const int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (q >= P) return;
+    double acc = 0.0;
+    for (int64_t k = start[q]; k < start[q + 1]; ++k) acc = __dadd_rn(acc, __dmul_rn(coef[k], raw[gate[k]]));
+    g[q] = acc;
+}
+
 // ------------------------------------------------------------ fused runs
 
 __device__ __forceinline__ uint32_t tile_index(const RunDesc& run, uint32_t o_dep, uint32_t e,
@@ -560,6 +574,13 @@ void launch_adj_exc(const StateDesc* sd, int count, int j, uint64_t npairs, int 
 void launch_adj_pauli(const StateDesc* sd, int count, int j, uint64_t N, int nblk,
                       hipStream_t st) {
     hipLaunchKernelGGL(k_adj_pauli, dim3(nblk, count), dim3(kBlock), 0, st, sd, j, N);
+}
+
+void launch_param_grad(const int64_t* start, const int64_t* gate, const double* coef, const double* raw,
+                       double* g, int64_t P, hipStream_t st) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_param_grad, dim3(unsigned((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, start, gate,
+                       coef, raw, g, P);
 }
 
 void launch_reduce_e(const StateDesc* sd, int count, int nblk, hipStream_t st) {

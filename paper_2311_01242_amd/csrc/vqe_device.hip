@@ -3135,6 +3135,7 @@ struct vqe_batch {
     hipStream_t user = nullptr;     // caller's stream: evaluations are ordered after its work
     hipStream_t st = nullptr;       // the batch's own stream (graph capture and launches)
     hipEvent_t user_ev = nullptr;
+    hipEvent_t done_ev = nullptr;   // end of a device-resident evaluation (the caller's stream waits)
     std::vector<const vqe_ansatz*> A;
     std::vector<int64_t> poff;      // parameter offsets [S+1]
     std::vector<int64_t> goff;      // gate offsets [S+1]
@@ -3150,6 +3151,11 @@ struct vqe_batch {
     double* theta_dev = nullptr;
     double* e_dev = nullptr;
     double* g_dev = nullptr;        // raw per-gate sums, concatenated
+    // parameter -> (gate, coefficient) lists of the whole batch, gate order
+    // within a parameter (device-resident gradients; built at first use)
+    int64_t* pg_start = nullptr;
+    int64_t* pg_gate = nullptr;
+    double* pg_coef = nullptr;
     double* theta_h = nullptr;      // pinned staging
     double* e_h = nullptr;
     double* g_h = nullptr;
@@ -3178,6 +3184,7 @@ struct vqe_batch {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (hipStream_t s : side) (void)hipStreamDestroy(s);
         if (user_ev) (void)hipEventDestroy(user_ev);
+        if (done_ev) (void)hipEventDestroy(done_ev);
         if (st) (void)hipStreamDestroy(st);
         for (char* p : allocs) (void)hipFree(p);
         (void)hipHostFree(theta_h);
@@ -3466,6 +3473,7 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     HIPCHK(hipGetDevice(&b->dev));
     HIPCHK(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->user_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(b->user));
     b->A.assign(A, A + S);
     b->poff.assign(S + 1, 0);
@@ -3696,6 +3704,66 @@ extern "C" int vqe_batch_energy_grad(vqe_batch* b, const double* theta_all, doub
         ok = ok && finite_all(g_all, b->poff[b->S]);
     }
     if (!ok) return fail(VQE_ENUMERIC, "non-finite energy or gradient");
+    return VQE_OK;
+}
+
+// The parameter -> gate lists of the batch (accumulate_grad's sums, in its
+// order), uploaded once.
+static int batch_param_map(vqe_batch* b) {
+    if (b->pg_start) return VQE_OK;
+    const int64_t P = b->poff[b->S];
+    std::vector<int64_t> start(size_t(P) + 1, 0), gate(size_t(std::max<int64_t>(b->goff[b->S], 1)));
+    std::vector<double> coef(gate.size());
+    for (int i = 0; i < b->S; ++i)
+        for (const GateDesc& g : b->A[i]->gates) ++start[size_t(b->poff[i] + g.param) + 1];
+    for (int64_t q = 0; q < P; ++q) start[size_t(q) + 1] += start[size_t(q)];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int i = 0; i < b->S; ++i) {
+        const auto& gates = b->A[i]->gates;
+        for (size_t j = 0; j < gates.size(); ++j) {
+            const GateDesc& g = gates[j];
+            const int64_t k = fill[size_t(b->poff[i] + g.param)]++;
+            gate[size_t(k)] = b->goff[i] + int64_t(j);
+            coef[size_t(k)] = (g.type == kExcitation ? 2.0 : 1.0) * g.scale;
+        }
+    }
+    int64_t *ds, *dg;
+    double* dc;
+    if (int rc = dalloc(b, &ds, start.size())) return rc;
+    if (int rc = dalloc(b, &dg, gate.size())) return rc;
+    if (int rc = dalloc(b, &dc, coef.size())) return rc;
+    HIPCHK(hipMemcpy(ds, start.data(), sizeof(int64_t) * start.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dg, gate.data(), sizeof(int64_t) * gate.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dc, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice));
+    b->pg_start = ds;
+    b->pg_gate = dg;
+    b->pg_coef = dc;
+    return VQE_OK;
+}
+
+extern "C" int vqe_batch_energy_grad_device(vqe_batch* b, const double* theta_all, double* e_all,
+                                            double* g_all) {
+    if (!b || !e_all) return fail(VQE_EINVAL, "null pointer argument");
+    const int64_t P = b->poff[b->S];
+    if (P > 0 && !theta_all) return fail(VQE_EINVAL, "null theta_all");
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != b->dev) return fail(VQE_EINVAL, "batch belongs to another device");
+    if (b->pq.on)
+        return fail(VQE_EINVAL, "the device-resident evaluation is not available with persistent passes "
+                                "(their wait checks need the host)");
+    if (g_all)
+        if (int rc = batch_param_map(b)) return rc;
+    HIPCHK(hipEventRecord(b->user_ev, b->user));
+    HIPCHK(hipStreamWaitEvent(b->st, b->user_ev, 0));
+    if (P > 0)
+        HIPCHK(hipMemcpyAsync(b->theta_dev, theta_all, sizeof(double) * P, hipMemcpyDeviceToDevice, b->st));
+    HIPCHK(hipGraphLaunch(b->exec, b->st));
+    HIPCHK(hipMemcpyAsync(e_all, b->e_dev, sizeof(double) * b->S, hipMemcpyDeviceToDevice, b->st));
+    if (g_all) launch_param_grad(b->pg_start, b->pg_gate, b->pg_coef, b->g_dev, g_all, P, b->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(b->done_ev, b->st));
+    HIPCHK(hipStreamWaitEvent(b->user, b->done_ev, 0));
     return VQE_OK;
 }
 
