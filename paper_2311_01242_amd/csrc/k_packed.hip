@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                                              const int32_t* __restrict__ base) {
     extern __shared__ double2 sh[];
     __shared__ HxTables T;
-    __shared__ double red[2][BS / 64];                      // wave totals of the last two gates
+    constexpr int kRedGates = 8;                            // gates per batch of wave totals
+    __shared__ double red[2][VEC == 2 ? kRedGates : 1][BS / 64];   // wave totals of the last two batches
     __shared__ double gsum[VEC == 2 ? kMaxRunGates : 1];   // per-gate tile totals
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
@@ -111,13 +112,13 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         }
     }
     __syncthreads();
-    for (int t = 0; t < ng; ++t) {
+    // one gate: its pairs (one per thread per pass), returning the thread's
+    // part of the reverse sweep's Re <lambda|A_j phi>; the next gate's first
+    // entry is loaded meanwhile
+    auto gate_step = [&](int t) -> double {
         const int jl = fwd ? t : ng - 1 - t;
         const int jn = fwd ? jl + 1 : jl - 1;
         const bool more = t + 1 < ng;
-        // a gate's list is packed from its start: a wave whose lanes have no
-        // first entry has no pair in this gate (its partial is exactly 0)
-        const bool wave_busy = VEC == 2 && __builtin_amdgcn_ballot_w64(ecur != kPairNone) != 0;
         const uint32_t enext = (more && tid < stride) ? ldg32(lbase + size_t(jn) * stride + tid) : kPairNone;
         const double2 cs = gpar[2 * jl];                // (cos, sgn sin)
         const double sgn_hi = gpar[2 * jl + 1].x;      // the tile's part of the sign
@@ -146,25 +147,53 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                 shl[ie] = lE;
             }
         }
-        if (!fwd) {
-            acc = wave_busy ? wave_total(acc) : 0.0;
-            if ((tid & 63) == 0) red[t & 1][tid >> 6] = acc;
-            if (tid == 0 && t > 0) {   // previous gate's wave totals, fixed order
-                double v = 0.0;
+        __syncthreads();
+        ecur = enext;
+        return acc;
+    };
+    if (fwd) {
+        for (int t = 0; t < ng; ++t) (void)gate_step(t);
+    } else {
+        // the wave totals of kRedGates consecutive gates are taken together
+        // after them (independent chains, off the per-gate barrier path);
+        // thread u < kRedGates adds the waves of gate u of the previous batch
+        // once a barrier has passed since they were written
+        for (int t0 = 0; t0 < ng; t0 += kRedGates) {
+            double acc[kRedGates];
+            uint32_t busy = 0;
 #pragma unroll
-                for (int w = 0; w < BS / 64; ++w) v += red[(t - 1) & 1][w];
-                gsum[jl + 1] = v;
+            for (int u = 0; u < kRedGates; ++u) {
+                acc[u] = 0.0;
+                if (t0 + u < ng) {
+                    // a gate's list is packed from its start: a wave whose lanes
+                    // have no first entry has no pair in this gate (partial 0)
+                    if (__builtin_amdgcn_ballot_w64(ecur != kPairNone) != 0) busy |= 1u << u;
+                    acc[u] = gate_step(t0 + u);
+                    if (u == 0 && t0 > 0 && tid < kRedGates) {
+                        const int tp = t0 - kRedGates + tid;
+                        double v = 0.0;
+#pragma unroll
+                        for (int w = 0; w < BS / 64; ++w) v += red[(t0 / kRedGates - 1) & 1][tid][w];
+                        gsum[ng - 1 - tp] = v;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRedGates; ++u) acc[u] = ((busy >> u) & 1u) ? wave_total(acc[u]) : 0.0;
+            if ((tid & 63) == 0) {
+#pragma unroll
+                for (int u = 0; u < kRedGates; ++u) red[(t0 / kRedGates) & 1][u][tid >> 6] = acc[u];
             }
         }
         __syncthreads();
-        ecur = enext;
-    }
-    if (!fwd) {
-        if (tid == 0) {
-            double v = 0.0;
+        {
+            const int t0 = (ng - 1) / kRedGates * kRedGates;   // the last batch
+            if (tid < kRedGates && t0 + tid < ng) {
+                double v = 0.0;
 #pragma unroll
-            for (int w = 0; w < BS / 64; ++w) v += red[(ng - 1) & 1][w];
-            gsum[0] = v;
+                for (int w = 0; w < BS / 64; ++w) v += red[(t0 / kRedGates) & 1][tid][w];
+                gsum[ng - 1 - (t0 + tid)] = v;
+            }
         }
         __syncthreads();
         for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + po] = gsum[jl];
