@@ -158,10 +158,22 @@ CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_PAIR = 4   # sign parity (AND + BCNT) and a real-by-complex multiply-add (2 FMA)
 # published FP64 vector peak, and the floating-point work of one nonzero matrix
-# element applied to a complex amplitude (real element x complex value,
-# accumulated: two FMA)
+# element applied to an amplitude: real element x complex value, accumulated
+# (two FMA); with real amplitudes (the packed string-product path's default),
+# one FMA
 FP64_PEAK_TFLOPS = 78.6
 FLOPS_PER_ELEMENT = 4
+FLOPS_PER_ELEMENT_REAL = 2
+
+
+def batch_real(b):
+    """True when every state of batch b is evaluated with real amplitudes."""
+    return int(b.work()[7]) == b.S
+
+
+def amp_dtype(real):
+    return "float64" if real else "complex128"
+
 
 # phase -> (kernel, source file, bound)
 PHASE_KERNELS = {
@@ -266,7 +278,8 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
     sector = pairs is None
     if sector:
         elements = sum(sector_elements(H, H.info()[0], ne) for H, ne in zip(Hs, nes))
-        h_work = FLOPS_PER_ELEMENT * elements
+        fpe = FLOPS_PER_ELEMENT_REAL if batch_real(b) else FLOPS_PER_ELEMENT
+        h_work = fpe * elements
     else:
         h_work = OPS_PER_PAIR * pairs
     traffic = {}
@@ -307,6 +320,7 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
                        "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}
     if sector:
         out["in_sector_matrix_elements_per_eval"] = elements
+        out["flops_per_element"] = fpe
     else:
         out["term_pairs_per_eval"] = pairs
     return out
@@ -384,7 +398,7 @@ def run_batch(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "complex128", "data": "synthetic",
+        "dtype": amp_dtype(batch_real(b)), "data": "synthetic",
         "config": {"workload": f"batched {BATCH_NAMES[args.ansatz]} energy+adjoint gradient, {args.states} states, "
                                "n~U{12..20}, n_e=n/2, seeded integrals, one HIP-graph launch",
                    "states": args.states, "qubits": "12-20", "global_batch": args.states,
@@ -512,7 +526,7 @@ def run_single24(args):
     return {
         "metric": "energy+adjoint-grad evals/s", "value": round(args.steps / dt, 3), "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "complex128",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": amp_dtype(batch_real(b)),
         "data": "synthetic",
         "config": {"workload": "single 24-qubit UCCSD energy+adjoint gradient (12 e-, 1818 params)"},
         "roofline": roof,
@@ -545,7 +559,7 @@ def run_scan12(args):
         "metric": "energy+adjoint-grad evals/s", "value": round(len(Hs) * args.steps / dt, 2),
         "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
+        "vs_baseline": None, "dtype": amp_dtype(batch_real(b)), "data": "synthetic",
         "config": {"workload": "12-qubit bond-stretch scan, 20 geometries per step, "
                                + {"jw": "Jordan-Wigner (packed sector kernels)",
                                   "bk": "Bravyi-Kitaev (full-vector Pauli-rotation kernels)"}[args.mapping],
@@ -677,10 +691,12 @@ def run_adapt20(args):
     assert np.isfinite(e) and np.all(np.isfinite(gp))
     ms, w = vq.pool_gradient_profile(H, A, pool, ne, th, reps=args.profile_reps)
     elements = sector_elements(H, n, ne)
+    real = batch_real(vq.Batch([H], [A], [ne]))   # the plan the single-state call makes too
+    fpe = FLOPS_PER_ELEMENT_REAL if real else FLOPS_PER_ELEMENT
     recs = {}
     for i, (phase, work, bound, kernel) in enumerate([
             ("forward", w[0], "hbm", PHASE_KERNELS["forward"][0]),
-            ("h_apply", FLOPS_PER_ELEMENT * elements, "alu", PHASE_KERNELS["h_apply"][0]),
+            ("h_apply", fpe * elements, "alu", PHASE_KERNELS["h_apply"][0]),
             ("pool_sweep", w[2], "hbm", "k_ppool<*,*> (one read-only launch: the pool at angle 0)")]):
         t_s = ms[i] * 1e-3
         if bound == "hbm":
@@ -702,7 +718,7 @@ def run_adapt20(args):
         "metric": "ADAPT pool-gradient evals/s", "value": round(args.steps / dt, 3),
         "unit": "pool-gradient evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": amp_dtype(real), "data": "synthetic",
         "config": {"workload": f"ADAPT-VQE, 20 qubits, 10 e-, UCCSD pool of {pool.n_params} "
                                f"operators, ansatz of {len(sel)} selected operators",
                    "pool": pool.n_params, "ansatz_operators": len(sel)},

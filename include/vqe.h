@@ -336,7 +336,8 @@ int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps, double* m
  * once, plus the |HF> write), w[1] 0, w[2] reverse-sweep bytes (phi and
  * lambda tiles read and written once), w[3] bytes of all phi + lambda,
  * w[4] gate-step launches of the forward sweep, w[5] H-apply launches,
- * w[6] gate-step launches of the reverse sweep, w[7] 0. */
+ * w[6] gate-step launches of the reverse sweep, w[7] states evaluated with
+ * real amplitudes (vqe_set_real). */
 int vqe_batch_work(const vqe_batch* b, double* w);
 
 /* Launch-parameter override for states of n_qubits (batched = 1 for batch
@@ -368,6 +369,17 @@ int vqe_set_run_threads(int n_qubits, int batched, int fwd_threads, int adj_thre
  * vectors.  Results agree to rounding; applies to plans made after the call.
  * Errors: ERANGE for other modes. */
 int vqe_set_packed(int mode);
+
+/* Real-amplitude switch for the string-product path of mode 2 (process-wide,
+ * default on).  Excitation gates are real rotations (Sec. 2.1.2) and the
+ * Hamiltonian is a real matrix here (every Pauli term's i^#Y phase is folded
+ * into its real coefficient, Eq. 2), so from the real reference phi = U|HF>
+ * and lambda = H phi are real: with the switch on, that path stores and
+ * moves one double per amplitude instead of two.  Off keeps complex
+ * amplitudes.  Results agree to rounding; applies to plans made after the
+ * call (a batch's persistent passes always use complex amplitudes).
+ * Never fails. */
+int vqe_set_real(int on);
 
 /* Tile size of the packed runs for n_qubits (batched or single-state
  * launches; applies to plans made after the call).  A run is a stretch of

@@ -23,7 +23,7 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "energy_grad_noalloc", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
-    "set_packed", "set_run_threads", "copy_ceiling", "set_persistent", "set_tile_cap",
+    "set_packed", "set_real", "set_run_threads", "copy_ceiling", "set_persistent", "set_tile_cap",
 ]
 
 
@@ -47,6 +47,14 @@ def set_packed(mode=True):
     full 2^n vectors."""
     m = 2 if mode is True else (0 if mode is False else int(mode))
     _check(lib().vqe_set_packed(m))
+
+
+def set_real(on=True):
+    """Real amplitudes on the string-product path (the default; applies to
+    plans made afterwards): phi and lambda of excitation programs are real, so
+    one double per amplitude is stored instead of two.  False keeps complex
+    amplitudes there."""
+    _check(lib().vqe_set_real(int(bool(on))))
 
 
 def set_tile_cap(n_qubits: int, batched: bool, entries: int = 0):

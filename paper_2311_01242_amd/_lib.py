@@ -81,6 +81,7 @@ SIGNATURES = {
     "vqe_batch_work": (c_int, [vp, P(c_double)]),
     "vqe_set_tuning": (c_int, [c_int, c_int, c_int64, c_int64, c_int]),
     "vqe_set_packed": (c_int, [c_int]),
+    "vqe_set_real": (c_int, [c_int]),
     "vqe_set_tile_cap": (c_int, [c_int, c_int, c_int]),
     "vqe_set_persistent": (c_int, [c_int, c_int]),
     "vqe_batch_persistent": (c_int, [vp, P(c_int)]),

@@ -515,6 +515,48 @@ __device__ __forceinline__ void givens(double2& d, double2& e, double c, double 
     e = make_double2(c * pe.x + ss * pd.x, c * pe.y + ss * pd.y);
 }
 
+// Amplitudes of the packed path come in two value types: double2 (complex)
+// and double.  Excitation gates are real rotations and the Hamiltonian's
+// matrix is real in this library's representation (the i^#Y phase of every
+// Pauli term is folded into a real coefficient), so a state prepared from a
+// basis state by excitations, and H applied to it, are real: the packed path
+// then stores and moves real parts only.  These overloads let one kernel
+// source serve both types.
+__device__ __forceinline__ double ldgv(const double* p) { return ldg64(p); }
+__device__ __forceinline__ double2 ldgv(const double2* p) { return ldg2(p); }
+__device__ __forceinline__ void stgv(double* p, double v) {
+    *reinterpret_cast<__attribute__((address_space(1))) double*>(reinterpret_cast<uintptr_t>(p)) = v;
+}
+__device__ __forceinline__ void stgv(double2* p, double2 v) { stg2(p, v); }
+__device__ __forceinline__ void nt_store(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void givens(double& d, double& e, double c, double ss) {
+    const double pd = d, pe = e;
+    d = c * pd - ss * pe;
+    e = c * pe + ss * pd;
+}
+// Re(conj(a) b)
+__device__ __forceinline__ double redot(double a, double b) { return a * b; }
+__device__ __forceinline__ double redot(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }
+// acc += c p (c real)
+__device__ __forceinline__ void axpy(double& acc, double c, double p) { acc += c * p; }
+__device__ __forceinline__ void axpy(double2& acc, double c, double2 p) {
+    acc.x += c * p.x;
+    acc.y += c * p.y;
+}
+template <typename V>
+__device__ __forceinline__ V vzero();
+template <>
+__device__ __forceinline__ double vzero<double>() { return 0.0; }
+template <>
+__device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double vunit(double) { return 1.0; }
+__device__ __forceinline__ double2 vunit(double2) { return make_double2(1.0, 0.0); }
+__device__ __forceinline__ void vadd(double& a, double b) { a += b; }
+__device__ __forceinline__ void vadd(double2& a, double2 b) {
+    a.x += b.x;
+    a.y += b.y;
+}
+
 __device__ __forceinline__ double parity_sign(uint32_t v) {
     return (__popc(v) & 1) ? -1.0 : 1.0;
 }
@@ -568,18 +610,18 @@ void launch_hx_packed(const StateDesc* sd, int count, const HxPlan& plan, const 
                       const int32_t* base, hipStream_t st);
 void launch_fill_zero(double2* p, uint64_t n, hipStream_t st);
 // Packed block order <-> string-product order: lam[perm[k]] = phi[k], and
-// lam[k] = aux[perm[k]].
-void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
+// lam[k] = aux[perm[k]].  real: the vectors hold doubles (real states).
+void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size, bool real,
                        hipStream_t st);
 void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
-                      int nsplit, hipStream_t st);
+                      int nsplit, bool real, hipStream_t st);
 int ci_choose_splits(const CiArgs& ci);
 // lambda (aux) = H phi (lam) in string-product order, energy partial per row.
-void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st);
+void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, bool real, hipStream_t st);
 int ci_prepare(const CiArgs& ci);   // 0 when the kernel can launch for these sizes
-void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st);
+void launch_packed_hf(const StateDesc* sd, int count, int64_t size, bool real, hipStream_t st);
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st);
+                       const HxTables* tabs, const int32_t* base, bool adjoint, bool real, hipStream_t st);
 // Launch shape covering blocks of max_block entries with at least min_threads
 // threads per tile if there is one (else any), or -1.
 // Single-launch zero-angle sweep of a pool's packed runs (pool gradients):
@@ -595,7 +637,7 @@ struct PoolSweep {
     size_t lds;
 };
 void launch_pool_sweep(const StateDesc* sd, int count, const PoolSweep& ps, const HxTables* tabs,
-                       const int32_t* base, hipStream_t st);
+                       const int32_t* base, bool real, hipStream_t st);
 int packed_shape(int max_block, int min_threads);
 int packed_shape_threads(int shape);
 int packed_enable_lds(size_t bytes);  // 0 on success

@@ -34,32 +34,33 @@ __device__ __forceinline__ uint32_t pext_mask(uint32_t v, uint32_t mask) {
     return out;
 }
 
-// Words of a wave's LDS slice: its staged row, then the beta-pair
-// coefficient records of the current pair class, then 16 doubles for the
-// row's part of the diagonal's alpha-beta terms.
-__host__ __device__ inline int ci_wave_words(int nb, int npairs) {
-    return nb + npairs + (npairs * 4 + 15) / 16 + 8;   // in double2 (16-byte) units
+// Words of a wave's LDS slice: its staged row (nb amplitudes of vbytes
+// each), then the beta-pair coefficient records of the current pair class,
+// then 16 doubles for the row's part of the diagonal's alpha-beta terms.
+__host__ __device__ inline int ci_row_words(int nb, int vbytes) { return (nb * vbytes + 15) / 16; }
+__host__ __device__ inline int ci_wave_words(int nb, int npairs, int vbytes) {
+    return ci_row_words(nb, vbytes) + npairs + (npairs * 4 + 15) / 16 + 8;   // in 16-byte units
 }
 
 // lambda += D_G(b) phi(partner) for one group over the wave's columns.
 // tab: the group's table base (LDS chunk or global); sp: its subgroups.
-template <int COLS, int W, bool GTAB>
+// V: amplitude type (double2, or double for real states).
+template <int COLS, int W, bool GTAB, typename V>
 __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, const double* tab,
                                          uint32_t sA, const uint32_t (&sB)[COLS],
                                          const int (&ibc)[COLS], bool col_only,
-                                         const double2* prow, const double2* row,
-                                         const int16_t* RB, double (&lr)[COLS],
-                                         double (&li)[COLS]) {
+                                         const V* prow, const V* row,
+                                         const int16_t* RB, V (&sig)[COLS]) {
     const uint32_t ta = pext_mask(sA, G.tba);
     const int ka = (G.meta >> 8) & 0xff;
     const uint32_t q0 = G.tbb & 31, q1 = (G.tbb >> 5) & 31, q2 = (G.tbb >> 10) & 31,
                    q3 = (G.tbb >> 15) & 31;
-    double2 p[COLS];
+    V p[COLS];
     bool ok[COLS];
     if (col_only) {
 #pragma unroll
         for (int c = 0; c < COLS; ++c) {
-            p[c] = ldg2(prow + ibc[c]);
+            p[c] = ldgv(prow + ibc[c]);
             ok[c] = true;
         }
     } else {   // all loads first, then the selects
@@ -123,8 +124,7 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const double dd = ok[c] ? d[c] : 0.0;
-        lr[c] += dd * p[c].x;
-        li[c] += dd * p[c].y;
+        axpy(sig[c], dd, p[c]);
     }
 }
 
@@ -143,7 +143,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // 8 q + (b mod 8), q = (b / 8) / nrb: all rows of a state run on one XCD,
 // whose L2 then serves the partner rows every pair class and chunk reads
 // again.  Workgroups past the last state exit at once.
-template <int COLS, int R, int W>
+template <int COLS, int R, int W, typename V>
 __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restrict__ sd, CiArgs ci,
                                                       int xs, int nrb) {
     static_assert(R == 1 || W == 1, "several rows of one wave each, or one row of several waves");
@@ -170,20 +170,21 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     const int ia = rblk * R + rslot;
     const bool row_live = ia < ci.na_str;   // waves past the last row only help with staging
     const int NB = ci.nb_str;
-    double2* row = lds_ci + ((nrank * 2 + 15) >> 4) + size_t(rslot) * ci_wave_words(NB, ci.npairs);
-    double2* wc = row + NB;                                   // pair coefficients (tb = 1, tb = 2)
+    double2* slice = lds_ci + ((nrank * 2 + 15) >> 4) + size_t(rslot) * ci_wave_words(NB, ci.npairs, sizeof(V));
+    V* row = reinterpret_cast<V*>(slice);
+    double2* wc = slice + ci_row_words(NB, sizeof(V));        // pair coefficients (tb = 1, tb = 2)
     uint32_t* ww = reinterpret_cast<uint32_t*>(wc + ci.npairs);   // pair beta sign masks
-    const double2* __restrict__ phi = s.lam;   // phi in string-product order
+    const V* __restrict__ phi = reinterpret_cast<const V*>(s.lam);   // phi in string-product order
     const uint32_t sA = ldc(ci.sa + (row_live ? ia : 0));
     uint32_t sB[COLS];
     int ibc[COLS];
-    double lr[COLS], li[COLS];
+    V sig[COLS];   // this lane's part of lambda
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const int ib = rt + 64 * W * c;
         ibc[c] = ib < NB ? ib : 0;   // a column past the end repeats column 0, unwritten
         sB[c] = ci.sb[ibc[c]];
-        lr[c] = li[c] = 0.0;
+        sig[c] = vzero<V>();
     }
     auto row_sync = [&]() {   // the row's LDS slice is shared by its W waves
         if (W == 1)
@@ -191,10 +192,10 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         else
             __syncthreads();
     };
-    auto stage_row = [&](const double2* prow) {
-        double2 v[COLS];
+    auto stage_row = [&](const V* prow) {
+        V v[COLS];
 #pragma unroll
-        for (int c = 0; c < COLS; ++c) v[c] = ldg2(prow + ibc[c]);
+        for (int c = 0; c < COLS; ++c) v[c] = ldgv(prow + ibc[c]);
         if (W == 1) __builtin_amdgcn_wave_barrier();   // reads of the previous row are done
         else __syncthreads();
 #pragma unroll
@@ -241,14 +242,13 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                 for (int c = 0; c < COLS; ++c) {
                     const uint32_t ent = __builtin_amdgcn_raw_buffer_load_b32(lrs, voff[c], e * NB * 4, 0);
                     const double t = wcd[(ent >> 16) & 0x1ff];   // 2 pair + pattern
-                    const double2 p = row[ent & 0xffff];
+                    const V p = row[ent & 0xffff];
                     // chain parity (bit 31) and the class mask over the column; the
                     // class mask's bit at the pair's occupied orbital, which cfl
                     // counted and the record leaves out, is in the coefficient
                     const uint32_t flip = (ent & 0x80000000u) ^ cfl[c];
                     const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
-                    lr[c] += coef * p.x;
-                    li[c] += coef * p.y;
+                    axpy(sig[c], coef, p);
                 }
             }
         } else {
@@ -258,17 +258,16 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                     const uint32_t ent = ldg32(lst + ibc[c]);
                     const int pid = (ent >> 17) & 0xff;
                     const double t = wcd[(ent >> 16) & 0x1ff];
-                    const double2 p = row[ent & 0xffff];
+                    const V p = row[ent & 0xffff];
                     const uint32_t flip = uint32_t(__popc(sB[c] & ww[pid])) << 31;
                     const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
-                    lr[c] += coef * p.x;
-                    li[c] += coef * p.y;
+                    axpy(sig[c], coef, p);
                 }
             }
         }
         for (int g = P.rest0; g < P.rest1; ++g) {   // the class's other groups
             const CiGroup G = ldc(s.ci_rgroups + g);
-            ci_group<COLS, W, true>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, lr, li);
+            ci_group<COLS, W, true, V>(G, s.ci_rsubs, s.ci_ptabs, sA, sB, ibc, false, nullptr, row, RB, sig);
         }
     }
     // ---- row moves: the row's own list, partners read in place
@@ -280,11 +279,11 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             CiRowMove e[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) e[u] = ldc(s.ci_rm + m + u * nsplit);
-            double2 p[kU][COLS];
+            V p[kU][COLS];
 #pragma unroll
             for (int u = 0; u < kU; ++u)
 #pragma unroll
-                for (int c = 0; c < COLS; ++c) p[u][c] = ldg2(phi + size_t(e[u].partner) * NB + ibc[c]);
+                for (int c = 0; c < COLS; ++c) p[u][c] = ldgv(phi + size_t(e[u].partner) * NB + ibc[c]);
 #pragma unroll
             for (int u = 0; u < kU; ++u)
 #pragma unroll
@@ -292,20 +291,18 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                     const uint32_t flip = uint32_t(__popc(sB[c] & e[u].wb)) << 31;
                     const double cf = __hiloint2double(__double2hiint(e[u].coef) ^ int(flip),
                                                        __double2loint(e[u].coef));
-                    lr[c] += cf * p[u][c].x;
-                    li[c] += cf * p[u][c].y;
+                    axpy(sig[c], cf, p[u][c]);
                 }
         }
         for (; m < m1; m += nsplit) {
             const CiRowMove e = ldc(s.ci_rm + m);
 #pragma unroll
             for (int c = 0; c < COLS; ++c) {
-                const double2 pv = ldg2(phi + size_t(e.partner) * NB + ibc[c]);
+                const V pv = ldgv(phi + size_t(e.partner) * NB + ibc[c]);
                 const uint32_t flip = uint32_t(__popc(sB[c] & e.wb)) << 31;
                 const double cf = __hiloint2double(__double2hiint(e.coef) ^ int(flip),
                                                    __double2loint(e.coef));
-                lr[c] += cf * pv.x;
-                li[c] += cf * pv.y;
+                axpy(sig[c], cf, pv);
             }
         }
     }
@@ -322,15 +319,15 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             CiAlphaHop e[NH];
 #pragma unroll
             for (int u = 0; u < NH; ++u) e[u] = ldc(s.ci_ah + h + u * nsplit);
-            double2 pv[NH][COLS];
+            V pv[NH][COLS];
             double bv[NH][COLS];
 #pragma unroll
             for (int u = 0; u < NH; ++u) {
-                const double2* prow = phi + size_t(e[u].w & 0xffffu) * NB;
+                const V* prow = phi + size_t(e[u].w & 0xffffu) * NB;
                 const double* bp = s.ci_ahb + (size_t((e[u].w >> 16) & 0xffu) * 2 + ((e[u].w >> 24) & 1u)) * NB;
 #pragma unroll
                 for (int c = 0; c < COLS; ++c) {
-                    pv[u][c] = ldg2(prow + ibc[c]);
+                    pv[u][c] = ldgv(prow + ibc[c]);
                     bv[u][c] = ldg64(bp + ibc[c]);
                 }
             }
@@ -342,8 +339,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                     const double v = e[u].coef + (neg ? -bv[u][c] : bv[u][c]);
                     const uint32_t flip = uint32_t(__popc(sB[c] & e[u].wb)) << 31;
                     const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
-                    lr[c] += cf * pv[u][c].x;
-                    li[c] += cf * pv[u][c].y;
+                    axpy(sig[c], cf, pv[u][c]);
                 }
             }
         };
@@ -357,7 +353,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     if (row_live && diag) {
         // E(a, b) = R(a) + C(b) + sum over occupied alpha t, beta u of X[t][u]:
         // the row's sums over t per beta orbital u, then per lane its u
-        double* dv = reinterpret_cast<double*>(row + NB + ci.npairs + (ci.npairs * 4 + 15) / 16);
+        double* dv = reinterpret_cast<double*>(wc + ci.npairs + (ci.npairs * 4 + 15) / 16);
         for (int u = rt; u < ci.ob; u += 64 * W) {
             double v = 0.0;
             for (uint32_t m = sA; m; m &= m - 1) v += ldg64(s.ci_dgx + (__ffs(m) - 1) * 16 + u);
@@ -369,9 +365,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         for (int c = 0; c < COLS; ++c) {
             double d = ra + ldg64(s.ci_dgc + ibc[c]);
             for (uint32_t m = sB[c]; m; m &= m - 1) d += dv[__ffs(m) - 1];
-            const double2 pv = row[ibc[c]];
-            lr[c] += d * pv.x;
-            li[c] += d * pv.y;
+            axpy(sig[c], d, row[ibc[c]]);
         }
     }
     if (row_live && s.ci_nbh > 0) {
@@ -401,9 +395,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
             const double v = q.x + __hiloint2double(hi, __double2loint(a) & keep);
             const uint32_t flip = uint32_t(__popc(sA & uint32_t(ww2 >> 32))) << 31;
             const double cf = __hiloint2double(__double2hiint(v) ^ int(flip), __double2loint(v));
-            const double2 pv = row[w & 0xffffu];
-            lr[c] += cf * pv.x;
-            li[c] += cf * pv.y;
+            axpy(sig[c], cf, row[w & 0xffffu]);
         };
         constexpr int kM = COLS <= 2 ? 4 : 2;
         int e = split;
@@ -426,11 +418,10 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
         const double2* cmv = reinterpret_cast<const double2*>(s.ci_cm);
         auto move = [&](const double2 q, int c) {   // q = {coef, partner | wa << 32}
             const uint64_t pw = uint64_t(__double_as_longlong(q.y));
-            const double2 pv = row[int(uint32_t(pw))];
+            const V pv = row[int(uint32_t(pw))];
             const uint32_t flip = uint32_t(__popc(sA & uint32_t(pw >> 32))) << 31;
             const double cf = __hiloint2double(__double2hiint(q.x) ^ int(flip), __double2loint(q.x));
-            lr[c] += cf * pv.x;
-            li[c] += cf * pv.y;
+            axpy(sig[c], cf, pv);
         };
         // the moves' records (per column, the same for every row) come from L2:
         // kM of them in flight per pass
@@ -473,7 +464,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     __syncthreads();
     uint32_t cur_xa = 0xffffffffu;   // class whose partner row is staged
     bool valid = false, col_only = false;
-    const double2* prow = phi;
+    const V* prow = phi;
     for (int ch = split, it = 0; ch < nch; ch += nsplit, ++it) {
         const int chn = ch + nsplit;
         if (chn < nch) tload(chn);   // in flight during this chunk
@@ -494,7 +485,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                     if (!col_only) stage_row(prow);
                 }
             }
-            if (valid) ci_group<COLS, W, false>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, lr, li);
+            if (valid) ci_group<COLS, W, false, V>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, sig);
             G = Gn;
         }
         if (chn < nch) tstore((it + 1) & 1);   // the buffer read two chunks ago
@@ -502,15 +493,14 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     }
     if (!row_live) return;
     double acc = 0.0;
-    const double2* mine = phi + size_t(ia) * NB;
-    double2* out = s.aux + size_t(split) * size_t(ci.na_str) * NB + size_t(ia) * NB;
+    const V* mine = phi + size_t(ia) * NB;
+    V* out = reinterpret_cast<V*>(s.aux) + size_t(split) * size_t(ci.na_str) * NB + size_t(ia) * NB;
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const int ib = rt + 64 * W * c;
         if (ib < NB) {
-            stg2(out + ib, make_double2(lr[c], li[c]));
-            const double2 q = ldg2(mine + ib);
-            acc += q.x * lr[c] + q.y * li[c];
+            stgv(out + ib, sig[c]);
+            acc += redot(ldgv(mine + ib), sig[c]);
         }
     }
     acc = wave_total(acc);
@@ -528,52 +518,61 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     }
 }
 
+template <typename V>
 __global__ void k_ci_scatter(const StateDesc* __restrict__ sd, const int32_t* __restrict__ perm,
                              int64_t size) {
     const StateDesc& s = sd[blockIdx.y];
+    const V* phi = reinterpret_cast<const V*>(s.phi);
+    V* lam = reinterpret_cast<V*>(s.lam);
     for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
          k += int64_t(gridDim.x) * blockDim.x)
-        s.lam[perm[k]] = s.phi[k];
+        lam[perm[k]] = phi[k];
 }
 
 // lambda in block order: the sum of the split planes, in plane order.
+template <typename V>
 __global__ void k_ci_gather(const StateDesc* __restrict__ sd, const int32_t* __restrict__ perm,
                             int64_t size, int nsplit) {
     const StateDesc& s = sd[blockIdx.y];
+    const V* aux = reinterpret_cast<const V*>(s.aux);
+    V* lam = reinterpret_cast<V*>(s.lam);
     for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
          k += int64_t(gridDim.x) * blockDim.x) {
         const int64_t q = perm[k];
-        double2 v = s.aux[q];
-        for (int z = 1; z < nsplit; ++z) {
-            const double2 w = s.aux[size_t(z) * size + q];
-            v.x += w.x;
-            v.y += w.y;
-        }
-        s.lam[k] = v;
+        V v = aux[q];
+        for (int z = 1; z < nsplit; ++z) vadd(v, aux[size_t(z) * size + q]);
+        lam[k] = v;
     }
 }
 
-void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
+void launch_ci_scatter(const StateDesc* sd, int count, const int32_t* perm, int64_t size, bool real,
                        hipStream_t st) {
-    hipLaunchKernelGGL(k_ci_scatter, dim3(blocks_for(uint64_t(size)), count), dim3(kBlock), 0, st,
-                       sd, perm, size);
+    const dim3 grid(blocks_for(uint64_t(size)), count);
+    if (real)
+        hipLaunchKernelGGL(k_ci_scatter<double>, grid, dim3(kBlock), 0, st, sd, perm, size);
+    else
+        hipLaunchKernelGGL(k_ci_scatter<double2>, grid, dim3(kBlock), 0, st, sd, perm, size);
 }
 
 void launch_ci_gather(const StateDesc* sd, int count, const int32_t* perm, int64_t size,
-                      int nsplit, hipStream_t st) {
-    hipLaunchKernelGGL(k_ci_gather, dim3(blocks_for(uint64_t(size)), count), dim3(kBlock), 0, st,
-                       sd, perm, size, nsplit);
+                      int nsplit, bool real, hipStream_t st) {
+    const dim3 grid(blocks_for(uint64_t(size)), count);
+    if (real)
+        hipLaunchKernelGGL(k_ci_gather<double>, grid, dim3(kBlock), 0, st, sd, perm, size, nsplit);
+    else
+        hipLaunchKernelGGL(k_ci_gather<double2>, grid, dim3(kBlock), 0, st, sd, perm, size, nsplit);
 }
 
 // Launch shape: rows of up to 256 beta strings take one wave each, as many
 // rows per workgroup as fit 64 KiB of slices (at most 4: measured on the
 // 512-state batch, 8 rows per workgroup were 7% slower, 2 rows 16%); longer
-// rows take four waves each, one row per workgroup.
+// rows take four waves each, one row per workgroup.  vbytes: bytes per
+// amplitude (16 complex, 8 real).
 struct CiShape {
     int cols, rows, waves;
 };
 
-static CiShape ci_shape(const CiArgs& ci) {
+static CiShape ci_shape(const CiArgs& ci, int vbytes) {
     CiShape sh;
     if (ci.nb_str > 256) {
         sh.waves = 4;
@@ -583,7 +582,7 @@ static CiShape ci_shape(const CiArgs& ci) {
     }
     sh.waves = 1;
     sh.cols = (ci.nb_str + 63) / 64;
-    const size_t w = size_t(ci_wave_words(ci.nb_str, ci.npairs)) * sizeof(double2);
+    const size_t w = size_t(ci_wave_words(ci.nb_str, ci.npairs, vbytes)) * sizeof(double2);
     sh.rows = 4;
     while (sh.rows > 1 && size_t(sh.rows) * w > (64u << 10)) sh.rows >>= 1;
     return sh;
@@ -592,56 +591,65 @@ static CiShape ci_shape(const CiArgs& ci) {
 // Splits of one state's groups so that a lone state still occupies the
 // chip: about 2048 waves (two per SIMD), at most 8 splits.
 int ci_choose_splits(const CiArgs& ci) {
-    const CiShape sh = ci_shape(ci);
+    const CiShape sh = ci_shape(ci, 16);
     const int waves = ci.na_str * sh.waves;
     return std::max(1, std::min(8, (2048 + waves - 1) / std::max(waves, 1)));
 }
 
-static size_t ci_lds(const CiArgs& ci) {
+static size_t ci_lds(const CiArgs& ci, int vbytes) {
     const size_t rank_bytes = ((size_t(2) << ci.ob) + 15) & ~size_t(15);
-    return rank_bytes + size_t(ci_shape(ci).rows) * ci_wave_words(ci.nb_str, ci.npairs) * sizeof(double2);
+    return rank_bytes +
+           size_t(ci_shape(ci, vbytes).rows) * ci_wave_words(ci.nb_str, ci.npairs, vbytes) * sizeof(double2);
 }
 
-template <int COLS, int R, int W>
+template <int COLS, int R, int W, typename V>
 static void launch_crw(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
     const int nrb = (ci.na_str + R - 1) / R;
+    const size_t lds = ci_lds(ci, int(sizeof(V)));
     if (count >= 8 && ci.nsplit == 1) {   // XCD-grouped batch
         const dim3 grid(unsigned(8 * ((count + 7) / 8) * nrb), 1, 1);
-        hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci,
-                           count, nrb);
+        hipLaunchKernelGGL((k_hx_ci<COLS, R, W, V>), grid, dim3(R * W * 64), lds, st, sd, ci, count, nrb);
         return;
     }
     const dim3 grid(unsigned(nrb), count, ci.nsplit);
-    hipLaunchKernelGGL((k_hx_ci<COLS, R, W>), grid, dim3(R * W * 64), ci_lds(ci), st, sd, ci, 0,
-                       nrb);
+    hipLaunchKernelGGL((k_hx_ci<COLS, R, W, V>), grid, dim3(R * W * 64), lds, st, sd, ci, 0, nrb);
 }
 
-template <int COLS>
+template <int COLS, typename V>
 static void launch_c(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    switch (ci_shape(ci).rows) {
-        case 8: launch_crw<COLS, 8, 1>(sd, count, ci, st); break;
-        case 4: launch_crw<COLS, 4, 1>(sd, count, ci, st); break;
-        case 2: launch_crw<COLS, 2, 1>(sd, count, ci, st); break;
-        default: launch_crw<COLS, 1, 1>(sd, count, ci, st); break;
+    switch (ci_shape(ci, int(sizeof(V))).rows) {
+        case 8: launch_crw<COLS, 8, 1, V>(sd, count, ci, st); break;
+        case 4: launch_crw<COLS, 4, 1, V>(sd, count, ci, st); break;
+        case 2: launch_crw<COLS, 2, 1, V>(sd, count, ci, st); break;
+        default: launch_crw<COLS, 1, 1, V>(sd, count, ci, st); break;
     }
 }
 
-void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
-    const CiShape sh = ci_shape(ci);
+template <typename V>
+static void launch_hx_ci_t(const StateDesc* sd, int count, const CiArgs& ci, hipStream_t st) {
+    const CiShape sh = ci_shape(ci, int(sizeof(V)));
     if (sh.waves > 1) {
-        if (sh.cols <= 1) launch_crw<1, 1, 4>(sd, count, ci, st);
-        else if (sh.cols <= 2) launch_crw<2, 1, 4>(sd, count, ci, st);
-        else if (sh.cols <= 3) launch_crw<3, 1, 4>(sd, count, ci, st);
-        else launch_crw<4, 1, 4>(sd, count, ci, st);
+        if (sh.cols <= 1) launch_crw<1, 1, 4, V>(sd, count, ci, st);
+        else if (sh.cols <= 2) launch_crw<2, 1, 4, V>(sd, count, ci, st);
+        else if (sh.cols <= 3) launch_crw<3, 1, 4, V>(sd, count, ci, st);
+        else launch_crw<4, 1, 4, V>(sd, count, ci, st);
         return;
     }
-    if (sh.cols <= 1) launch_c<1>(sd, count, ci, st);
-    else if (sh.cols <= 2) launch_c<2>(sd, count, ci, st);
-    else launch_c<4>(sd, count, ci, st);
+    if (sh.cols <= 1) launch_c<1, V>(sd, count, ci, st);
+    else if (sh.cols <= 2) launch_c<2, V>(sd, count, ci, st);
+    else launch_c<4, V>(sd, count, ci, st);
 }
 
+void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, bool real, hipStream_t st) {
+    if (real)
+        launch_hx_ci_t<double>(sd, count, ci, st);
+    else
+        launch_hx_ci_t<double2>(sd, count, ci, st);
+}
+
+// The complex layout needs the most LDS; the real one fits wherever it does.
 int ci_prepare(const CiArgs& ci) {
-    const size_t lds = ci_lds(ci);
+    const size_t lds = ci_lds(ci, 16);
     const size_t fixed = sizeof(double) * 2 * kCiChunkTabs + 64;
     if (ci.nb_str > 1024 || lds + fixed > (160u << 10)) return 1;
     if (lds + fixed <= (64u << 10)) return 0;
@@ -650,19 +658,23 @@ int ci_prepare(const CiArgs& ci) {
         const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (r != hipSuccess) e = r;
     };
-#define VQE_CI_SET(C)                                                   \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 8, 1>));              \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 4, 1>));              \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 2, 1>));              \
-    set(reinterpret_cast<const void*>(&k_hx_ci<C, 1, 1>));
-    VQE_CI_SET(1)
-    VQE_CI_SET(2)
-    VQE_CI_SET(4)
+#define VQE_CI_SET(C, V)                                                   \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 8, 1, V>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 4, 1, V>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 2, 1, V>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<C, 1, 1, V>));
+#define VQE_CI_SET_V(V)                                                    \
+    VQE_CI_SET(1, V)                                                       \
+    VQE_CI_SET(2, V)                                                       \
+    VQE_CI_SET(4, V)                                                       \
+    set(reinterpret_cast<const void*>(&k_hx_ci<1, 1, 4, V>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<2, 1, 4, V>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<3, 1, 4, V>));              \
+    set(reinterpret_cast<const void*>(&k_hx_ci<4, 1, 4, V>));
+    VQE_CI_SET_V(double2)
+    VQE_CI_SET_V(double)
+#undef VQE_CI_SET_V
 #undef VQE_CI_SET
-    set(reinterpret_cast<const void*>(&k_hx_ci<1, 1, 4>));
-    set(reinterpret_cast<const void*>(&k_hx_ci<2, 1, 4>));
-    set(reinterpret_cast<const void*>(&k_hx_ci<3, 1, 4>));
-    set(reinterpret_cast<const void*>(&k_hx_ci<4, 1, 4>));
     return e == hipSuccess ? 0 : 1;
 }
 

@@ -24,19 +24,22 @@
 
 namespace vqe {
 
+template <typename V>
 __global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
     const StateDesc& s = sd[blockIdx.y];
+    V* phi = reinterpret_cast<V*>(s.phi);
     for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < size;
          k += int64_t(gridDim.x) * blockDim.x)
-        nt_store(&s.phi[k], make_double2(k == 0 ? 1.0 : 0.0, 0.0));
+        nt_store(phi + k, k == 0 ? vunit(V{}) : vzero<V>());
 }
 
 // VEC = 1: forward pass on phi.  VEC = 2: reverse sweep on phi and lambda
 // with per-gate, per-tile partials of Re <lambda|A_j phi> (A_j = T_j - T_j^dag).
+// V: amplitude type (double2, or double for real states).
 // Tile entry k (blocks one after the other) is staged by thread k % BS
 // (2 EPT BS covers the largest tile of the run); a gate's pairs come from the
 // run's precomputed list for the tile's class, one pair per thread per pass.
-template <int VEC, int BS, int EPT>
+template <int VEC, int BS, int EPT, typename V>
 __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, PackedRun run,
                                              const PackedGate* __restrict__ pg,
                                              const HxTables* __restrict__ tabsrc,
@@ -68,8 +71,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     }
     const int nE = tb.nE;
     const uint32_t hb0 = tb.hbase << run.L;
-    double2* shp = sh;
-    double2* shl = sh + nE;
+    V* shp = reinterpret_cast<V*>(sh);
+    V* shl = shp + nE;
     const bool fwd = (VEC == 1);
     const int ng = run.g1 - run.g0;
     const int cls = tb.cls;
@@ -85,7 +88,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     // (cos, sgn sin) and (sgn, 0), sgn the gate's pair sign from the tile's
     // high bits outside the window (the window's part is in each entry);
     // staged once, read by broadcast in the gate loop
-    double2* gpar = sh + size_t(VEC) * run.max_entries;
+    double2* gpar = sh + (size_t(VEC) * run.max_entries * sizeof(V) + 15) / 16;
     for (int j = tid; j < ng; j += BS) {
         const PackedGate g = pg[j];
         const double2 cs = s.cs[run.g0 + j];
@@ -94,13 +97,13 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         gpar[2 * j + 1] = make_double2(sgn, 0.0);
     }
     {   // all loads first (clamped into the tile), then the LDS stores
-        double2 vp[2 * EPT], vl[2 * EPT];
+        V vp[2 * EPT], vl[2 * EPT];
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
             const int k = min(tid + BS * u, nE - 1);
             const int64_t gi = tile_global(tb, run.nblk, k);
-            vp[u] = ldg2(s.phi + gi);
-            if (VEC == 2) vl[u] = ldg2(s.lam + gi);
+            vp[u] = ldgv(reinterpret_cast<const V*>(s.phi) + gi);
+            if (VEC == 2) vl[u] = ldgv(reinterpret_cast<const V*>(s.lam) + gi);
         }
         // unconditional stores (a clamped slot rewrites the last entry with its
         // own value), so that every load is waited for on every path
@@ -130,15 +133,15 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             const int k = int(e & kEntMask), ie = int((e >> kEntBits) & kEntMask);
             const double ss = ((e >> kEntParity) & 1u) ? -ssin : ssin;
             if (fwd) {
-                double2 d = shp[k], f = shp[ie];
+                V d = shp[k], f = shp[ie];
                 givens(d, f, cs.x, ss);
                 shp[k] = d;
                 shp[ie] = f;
             } else {
-                double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
+                V fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
                 // <lam| A phi> with A|D> = s|E>, A|E> = -s|D> (s = ss / sin)
                 const double sg_t = ((e >> kEntParity) & 1u) ? -sgn_hi : sgn_hi;
-                acc += sg_t * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
+                acc += sg_t * (redot(lE, fD) - redot(lD, fE));
                 givens(fD, fE, cs.x, -ss);   // U^dag: rotation by -theta
                 givens(lD, lE, cs.x, -ss);
                 shp[k] = fD;
@@ -203,8 +206,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         const int k = tid + BS * u;
         if (k < nE) {
             const int64_t gi = tile_global(tb, run.nblk, k);
-            stg2(s.phi + gi, shp[k]);
-            if (VEC == 2) stg2(s.lam + gi, shl[k]);
+            stgv(reinterpret_cast<V*>(s.phi) + gi, shp[k]);
+            if (VEC == 2) stgv(reinterpret_cast<V*>(s.lam) + gi, shl[k]);
         }
     }
 }
@@ -216,7 +219,7 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
 // wave takes whole gates (w, w + BS/64, ...) and its 64 lanes split the
 // gate's pair list, so a gate's tile partial of Re <lambda|A_j phi> is one
 // wave total, stored without a block barrier.
-template <int BS, int EPT>
+template <int BS, int EPT, typename V>
 __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
                                               const PackedRun* __restrict__ runs,
                                               const int32_t* __restrict__ blk_run,
@@ -247,16 +250,16 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
     }
     const int nE = tb.nE;
     const uint32_t hb0 = tb.hbase << run.L;
-    double2* shp = sh;
-    double2* shl = sh + nE;
+    V* shp = reinterpret_cast<V*>(sh);
+    V* shl = shp + nE;
     {
-        double2 vp[2 * EPT], vl[2 * EPT];
+        V vp[2 * EPT], vl[2 * EPT];
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
             const int k = min(tid + BS * u, nE - 1);
             const int64_t gi = tile_global(tb, run.nblk, k);
-            vp[u] = ldg2(s.phi + gi);
-            vl[u] = ldg2(s.lam + gi);
+            vp[u] = ldgv(reinterpret_cast<const V*>(s.phi) + gi);
+            vl[u] = ldgv(reinterpret_cast<const V*>(s.lam) + gi);
         }
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
@@ -279,8 +282,8 @@ __global__ void __launch_bounds__(BS) k_ppool(const StateDesc* __restrict__ sd,
             if (e == kPairNone) break;
             const int k = int(e & kEntMask), ie = int((e >> kEntBits) & kEntMask);
             const double sg_t = ((e >> kEntParity) & 1u) ? -sgn_hi : sgn_hi;
-            const double2 fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
-            acc += sg_t * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
+            const V fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
+            acc += sg_t * (redot(lE, fD) - redot(lD, fE));
         }
         acc = wave_total(acc);
         if (lane == 0) s.part_g[size_t(run.g0 + jl) * s.gstride + o] = acc;
@@ -316,53 +319,67 @@ int packed_shape_threads(int shape) { return kPShapes[shape].bs; }
 using PackedLauncher = void (*)(const StateDesc*, int, const PackedRun&, const PackedGate*,
                                 const HxTables*, const int32_t*, hipStream_t);
 
-template <int VEC, int BS, int EPT>
+template <int VEC, int BS, int EPT, typename V>
 static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
                        const HxTables* tabs, const int32_t* base, hipStream_t st) {
-    const size_t lds = (size_t(run.max_entries) * VEC + 2 * size_t(run.g1 - run.g0)) * sizeof(double2);
+    // the tile's amplitudes (16-byte aligned), then 2 double2 per gate
+    const size_t lds = (size_t(run.max_entries) * VEC * sizeof(V) + 15) / 16 * 16 +
+                       2 * size_t(run.g1 - run.g0) * sizeof(double2);
     const int nx = run.live ? run.nlive : run.ntiles;
     if (nx == 0) return;   // a run with no live tile: nothing to do, no partials
-    hipLaunchKernelGGL((k_prun<VEC, BS, EPT>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg, tabs,
+    hipLaunchKernelGGL((k_prun<VEC, BS, EPT, V>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg, tabs,
                        base);
 }
 
-#define VQE_FWD_ENTRY(B, E) &launch_one<1, B, E>,
-#define VQE_ADJ_ENTRY(B, E) &launch_one<2, B, E>,
+#define VQE_FWD_ENTRY(B, E) &launch_one<1, B, E, double2>,
+#define VQE_ADJ_ENTRY(B, E) &launch_one<2, B, E, double2>,
+#define VQE_FWD_REAL(B, E) &launch_one<1, B, E, double>,
+#define VQE_ADJ_REAL(B, E) &launch_one<2, B, E, double>,
 static const PackedLauncher kFwdLaunch[] = {VQE_PACKED_SHAPES(VQE_FWD_ENTRY)};
 static const PackedLauncher kAdjLaunch[] = {VQE_PACKED_SHAPES(VQE_ADJ_ENTRY)};
+static const PackedLauncher kFwdLaunchR[] = {VQE_PACKED_SHAPES(VQE_FWD_REAL)};
+static const PackedLauncher kAdjLaunchR[] = {VQE_PACKED_SHAPES(VQE_ADJ_REAL)};
 #undef VQE_FWD_ENTRY
 #undef VQE_ADJ_ENTRY
+#undef VQE_FWD_REAL
+#undef VQE_ADJ_REAL
 
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, bool adjoint, hipStream_t st) {
+                       const HxTables* tabs, const int32_t* base, bool adjoint, bool real, hipStream_t st) {
     if (adjoint)
-        kAdjLaunch[run.shape_adj](sd, count, run, pg, tabs, base, st);
+        (real ? kAdjLaunchR : kAdjLaunch)[run.shape_adj](sd, count, run, pg, tabs, base, st);
     else
-        kFwdLaunch[run.shape](sd, count, run, pg, tabs, base, st);
+        (real ? kFwdLaunchR : kFwdLaunch)[run.shape](sd, count, run, pg, tabs, base, st);
 }
 
 using PoolLauncher = void (*)(const StateDesc*, int, const PoolSweep&, const HxTables*,
                               const int32_t*, hipStream_t);
 
-template <int BS, int EPT>
+template <int BS, int EPT, typename V>
 static void launch_pool_one(const StateDesc* sd, int count, const PoolSweep& ps,
                             const HxTables* tabs, const int32_t* base, hipStream_t st) {
-    hipLaunchKernelGGL((k_ppool<BS, EPT>), dim3(ps.nblk, count), dim3(BS), ps.lds, st, sd, ps.runs,
+    hipLaunchKernelGGL((k_ppool<BS, EPT, V>), dim3(ps.nblk, count), dim3(BS), ps.lds, st, sd, ps.runs,
                        ps.blk_run, ps.blk0, ps.gates, tabs, base);
 }
 
-#define VQE_POOL_ENTRY(B, E) &launch_pool_one<B, E>,
+#define VQE_POOL_ENTRY(B, E) &launch_pool_one<B, E, double2>,
+#define VQE_POOL_REAL(B, E) &launch_pool_one<B, E, double>,
 static const PoolLauncher kPoolLaunch[] = {VQE_PACKED_SHAPES(VQE_POOL_ENTRY)};
+static const PoolLauncher kPoolLaunchR[] = {VQE_PACKED_SHAPES(VQE_POOL_REAL)};
 #undef VQE_POOL_ENTRY
+#undef VQE_POOL_REAL
 
 void launch_pool_sweep(const StateDesc* sd, int count, const PoolSweep& ps, const HxTables* tabs,
-                       const int32_t* base, hipStream_t st) {
-    if (ps.nblk > 0) kPoolLaunch[ps.shape](sd, count, ps, tabs, base, st);
+                       const int32_t* base, bool real, hipStream_t st) {
+    if (ps.nblk > 0) (real ? kPoolLaunchR : kPoolLaunch)[ps.shape](sd, count, ps, tabs, base, st);
 }
 
-void launch_packed_hf(const StateDesc* sd, int count, int64_t size, hipStream_t st) {
+void launch_packed_hf(const StateDesc* sd, int count, int64_t size, bool real, hipStream_t st) {
     const int nblk = blocks_for(uint64_t(size));
-    hipLaunchKernelGGL(k_packed_hf, dim3(nblk, count), dim3(kBlock), 0, st, sd, size);
+    if (real)
+        hipLaunchKernelGGL(k_packed_hf<double>, dim3(nblk, count), dim3(kBlock), 0, st, sd, size);
+    else
+        hipLaunchKernelGGL(k_packed_hf<double2>, dim3(nblk, count), dim3(kBlock), 0, st, sd, size);
 }
 
 int packed_enable_lds(size_t bytes) {
@@ -371,10 +388,13 @@ int packed_enable_lds(size_t bytes) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
         if (r != hipSuccess) e = r;
     };
-#define VQE_SET_ENTRY(B, E)                                          \
-    set(reinterpret_cast<const void*>(&k_prun<1, B, E>));            \
-    set(reinterpret_cast<const void*>(&k_prun<2, B, E>));            \
-    set(reinterpret_cast<const void*>(&k_ppool<B, E>));
+#define VQE_SET_ENTRY(B, E)                                                 \
+    set(reinterpret_cast<const void*>(&k_prun<1, B, E, double2>));          \
+    set(reinterpret_cast<const void*>(&k_prun<2, B, E, double2>));          \
+    set(reinterpret_cast<const void*>(&k_ppool<B, E, double2>));            \
+    set(reinterpret_cast<const void*>(&k_prun<1, B, E, double>));           \
+    set(reinterpret_cast<const void*>(&k_prun<2, B, E, double>));           \
+    set(reinterpret_cast<const void*>(&k_ppool<B, E, double>));
     VQE_PACKED_SHAPES(VQE_SET_ENTRY)
 #undef VQE_SET_ENTRY
     return e == hipSuccess ? 0 : 1;

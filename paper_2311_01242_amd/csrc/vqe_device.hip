@@ -1889,6 +1889,9 @@ static int ci_diag(const vqe_hamiltonian* H, CiHam* c, const CiSpace& cs, DiagPa
 // 0: full 2^n vectors; 1: packed layout with the block-order H-apply;
 // 2: packed layout with the string-product H-apply where it applies.
 static std::atomic<int> g_packed_enabled{2};
+// Real amplitudes on the packed string-product path (see k_packed.hip): on by
+// default; off keeps complex amplitudes there (tests compare the two).
+static std::atomic<int> g_real_enabled{1};
 
 // ------------------------------------------------------------- workspaces
 
@@ -2000,6 +2003,7 @@ struct EvalPlan {
     const CiSpace* cspace = nullptr;
     CiArgs ciargs{};
     const int32_t* perm = nullptr;
+    bool real = false;       // packed path with real amplitudes (double, not double2)
     bool small = false;      // whole-state kernels on a small number-conserving sector
     SmallSpace sspace{};
 };
@@ -2118,6 +2122,13 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
                 if (cs->NB <= kCiMaxCols) {
                     if (int rc = layout_perm(ep->lay, *cs, *host_tables(ep->hx.L))) return rc;
                     ep->ci = true;
+                    // excitations are real rotations and H is a real matrix:
+                    // phi and lambda stay real on this path
+                    ep->real = g_real_enabled.load() != 0;
+                    if (ep->real) {   // the plan's bytes count complex amplitudes
+                        ep->fwd_bytes *= 0.5;
+                        ep->adj_bytes *= 0.5;
+                    }
                     ep->cspace = cs;
                     ep->ciargs = cs->args();
                     ep->ciargs.nsplit = batched ? 1 : ci_choose_splits(ep->ciargs);
@@ -2166,15 +2177,15 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
     const PackedPlan& pp = *ep.pp;
     if (phase == kPhaseFwd) {
         launch_angles(sd, count, ep.M, st);
-        launch_packed_hf(sd, count, ep.lay->size, st);
+        launch_packed_hf(sd, count, ep.lay->size, ep.real, st);
         for (size_t r = 0; r < pp.runs.size(); ++r)
             launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
-                              ep.lay->d_base, false, st);
+                              ep.lay->d_base, false, ep.real, st);
     } else if (phase == kPhaseHx) {
         if (ep.ci) {
-            launch_ci_scatter(sd, count, ep.perm, ep.lay->size, st);
-            launch_hx_ci(sd, count, ep.ciargs, st);
-            launch_ci_gather(sd, count, ep.perm, ep.lay->size, ep.ciargs.nsplit, st);
+            launch_ci_scatter(sd, count, ep.perm, ep.lay->size, ep.real, st);
+            launch_hx_ci(sd, count, ep.ciargs, ep.real, st);
+            launch_ci_gather(sd, count, ep.perm, ep.lay->size, ep.ciargs.nsplit, ep.real, st);
         } else {
             launch_hx_packed(sd, count, ep.hx, ep.hxt, ep.lay->d_base, st);
         }
@@ -2182,7 +2193,7 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
         if (!grad) return;
         for (size_t r = pp.runs.size(); r-- > 0;)
             launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
-                              ep.lay->d_base, true, st);
+                              ep.lay->d_base, true, ep.real, st);
     } else {
         launch_reduce_e(sd, count, ep.nblk_e, st);
         if (grad) launch_reduce_g(sd, count, ep.M, pp.d_gcnt_live, 0, st);
@@ -2979,7 +2990,7 @@ int pool_gradient_impl(const vqe_hamiltonian* H, const vqe_ansatz* A, const vqe_
             enqueue_phase(ep, e.sd_dev, 1, kPhaseHx, true, st);
         } else if (ph == 2) {
             if (probe.packed) {
-                launch_pool_sweep(sp_dev, 1, *psw, ep.hxt, ep.lay->d_base, st);
+                launch_pool_sweep(sp_dev, 1, *psw, ep.hxt, ep.lay->d_base, ep.real, st);
             } else {
                 launch_angles(sp_dev, 1, int(Mp), st);
                 const uint64_t N = uint64_t(1) << n;
@@ -3028,7 +3039,7 @@ int pool_gradient_impl(const vqe_hamiltonian* H, const vqe_ansatz* A, const vqe_
         for (int ph = 0; ph < 4; ++ph) ms[ph] = acc[ph] / reps;
         work[0] = ep.fwd_bytes;
         work[1] = 0.0;
-        work[2] = probe.packed ? ppool->sweep_bytes : apool->adj_bytes;
+        work[2] = probe.packed ? ppool->sweep_bytes * (ep.real ? 0.5 : 1.0) : apool->adj_bytes;
         work[3] = double(probe.packed ? 1 : apool->adj_steps.size());
     }
     std::vector<double> raw(static_cast<size_t>(Mp));
@@ -3383,7 +3394,7 @@ int enqueue_pq_phase(vqe_batch* b, int ph, bool fork, hipStream_t st) {
         launch_pq_reset(P.cnt + 1, P.ncnt - 1, st);
         if (int rc = for_classes(b, fork, st, 0, [&](vqe_batch::Class& c, hipStream_t s) {
                 launch_angles(b->sd_dev + c.k0, c.count, c.ep.M, s);
-                launch_packed_hf(b->sd_dev + c.k0, c.count, c.ep.lay->size, s);
+                launch_packed_hf(b->sd_dev + c.k0, c.count, c.ep.lay->size, c.ep.real, s);
             }))
             return rc;
         launch_pq(1, P.pmax, P.args[0], P.grid[0], P.lds[0], st);
@@ -3519,6 +3530,11 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         for (size_t c = 0; c < rep.size(); ++c) {
             b->classes[c].ep = EvalPlan{};
             if (int rc = make_eval_plan(A[rep[c]], ne[rep[c]], true, &b->classes[c].ep, Lp)) return rc;
+            if (b->classes[c].ep.real) {   // the persistent passes move complex amplitudes
+                b->classes[c].ep.real = false;
+                b->classes[c].ep.fwd_bytes *= 2.0;
+                b->classes[c].ep.adj_bytes *= 2.0;
+            }
             persist = persist && b->classes[c].ep.packed && b->classes[c].ep.hx.L == Lp;
         }
     size_t need = 0;
@@ -3622,7 +3638,8 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         sd.gstride = ep.gstride;
         b->work[0] += ep.fwd_bytes;
         b->work[2] += ep.adj_bytes;
-        b->work[3] += 2.0 * double(sizeof(double2)) * double(ep.elems);
+        if (ep.real) b->work[7] += 1.0;
+        b->work[3] += 2.0 * double(ep.real ? sizeof(double) : sizeof(double2)) * double(ep.elems);
     }
     HIPCHK(hipGetLastError());
     for (auto& c : b->classes) {   // launches per evaluation (one per class and step)
@@ -3903,6 +3920,11 @@ extern "C" int vqe_batch_test_wait(vqe_batch* b, int spin_limit, int poison) {
                          hipMemcpyHostToDevice));
         break;
     }
+    return VQE_OK;
+}
+
+extern "C" int vqe_set_real(int on) {
+    g_real_enabled.store(on ? 1 : 0);
     return VQE_OK;
 }
 
