@@ -234,6 +234,14 @@ def copy_ceilings():
                     "working_set_bytes": 2 * half, "passes": passes, "ms": round(ms, 4)}
         del a, b
         torch.cuda.empty_cache()
+    # on-chip: LDS read-modify-write on every CU (bytes read + written)
+    times = []
+    for r in range(7):
+        ms, nbytes = vq.lds_ceiling(4000)
+        if r >= 2:
+            times.append(ms)
+    ms = float(np.median(times))
+    out["lds_rw"] = {"GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1), "bytes": nbytes, "ms": round(ms, 4)}
     return out
 
 
@@ -252,11 +260,19 @@ def cpu_model():
 
 def add_ceiling_fracs(roof, ceilings):
     """Fractions of the HBM-bound phases' achieved GB/s against the measured
-    copy ceilings (the vendor-peak fraction stays in `frac`)."""
+    copy ceilings (the vendor-peak fraction stays in `frac`), and of the
+    packed gate runs' LDS traffic against the measured LDS ceiling."""
     for rec in [roof] + list(roof.get("phases", {}).values()):
         if rec.get("bound") == "hbm" and rec.get("unit") == "GB/s":
             rec["frac_copy_64MB"] = round(rec["achieved"] / ceilings["copy_64MB"]["GB/s"], 4)
             rec["frac_copy_4GB"] = round(rec["achieved"] / ceilings["copy_4GB"]["GB/s"], 4)
+        if "lds_bytes_per_eval" in rec and "lds_rw" in ceilings:
+            t = rec["phase_ms"]
+            if isinstance(t, dict):   # the top-level record: its own phase's time
+                t = t[rec["dominant_phase"]]
+            gbs = rec["lds_bytes_per_eval"] / (t * 1e-3) / 1e9
+            rec["lds_GB/s"] = round(gbs, 1)
+            rec["frac_lds_rw"] = round(gbs / ceilings["lds_rw"]["GB/s"], 4)
 
 
 def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None):
@@ -310,11 +326,19 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
                            round(work / launches, 1),
                        "avg_launch_us": round(1e3 * phase_ms[i] / launches, 2),
                        "launches_per_eval": int(launches), "phase_ms": round(phase_ms[i], 3)}
+    if sector and w[1] > 0:
+        # packed gate runs: each pair update reads and writes back its two
+        # amplitudes (forward: phi; reverse: phi and lambda) in LDS, and each
+        # live tile is staged into LDS and written out once (the HBM bytes)
+        vbytes = 8 if batch_real(b) else 16
+        recs["forward"]["lds_bytes_per_eval"] = 4 * vbytes * w[1] + w[0]
+        recs["adjoint"]["lds_bytes_per_eval"] = 8 * vbytes * w[1] + w[2]
+        recs["forward"]["pair_updates_per_eval"] = recs["adjoint"]["pair_updates_per_eval"] = w[1]
     dom = max(recs, key=lambda k: recs[k]["phase_ms"])
     out = dict(recs[dom])
     out["dominant_phase"] = dom
     out["phases"] = {k: {kk: v[kk] for kk in ("kernel", "bound", "achieved", "unit", "frac", "traffic",
-                                               "phase_ms")}
+                                               "phase_ms", "lds_bytes_per_eval") if kk in v}
                      for k, v in recs.items()}
     out["phase_ms"] = {"forward": round(phase_ms[0], 3), "h_apply": round(phase_ms[1], 3),
                        "adjoint": round(phase_ms[2], 3), "reduce": round(phase_ms[3], 3)}

@@ -333,7 +333,9 @@ int vqe_batch_profile(vqe_batch* b, const double* theta_all, int reps, double* m
 
 /* Algorithmic work of one evaluation of the whole batch, from the launch
  * plan (8 doubles): w[0] forward-sweep bytes (each run tile read and written
- * once, plus the |HF> write), w[1] 0, w[2] reverse-sweep bytes (phi and
+ * once, plus the |HF> write), w[1] pair updates of one pass over the gates
+ * on the packed layout (live tiles; the reverse sweep makes as many), w[2]
+ * reverse-sweep bytes (phi and
  * lambda tiles read and written once), w[3] bytes of all phi + lambda,
  * w[4] gate-step launches of the forward sweep, w[5] H-apply launches,
  * w[6] gate-step launches of the reverse sweep, w[7] states evaluated with
@@ -430,6 +432,18 @@ int vqe_batch_test_wait(vqe_batch* b, int spin_limit, int poison);
  * misaligned), ERANGE (sizes), EDEVICE. */
 int vqe_copy_ceiling(const void* src, void* dst, int64_t bytes, int passes, void* hip_stream,
                      double* ms);
+
+/* Measurement helper, not a step of the method: one launch of two 512-thread
+ * workgroups per compute unit, each reading, changing and writing back its
+ * own 64 KiB LDS array (16-byte accesses, consecutive lanes on consecutive
+ * addresses) `iters` times (1..1000000), timed with HIP events on
+ * hip_stream.  *ms receives the launch time and *bytes the LDS bytes moved
+ * (reads + writes); their ratio is the measured LDS ceiling the gate
+ * kernels' on-chip traffic (each pair's amplitudes read and written back
+ * through LDS) is reported against.  No device memory is allocated.
+ * Synchronises the stream.  Errors: EINVAL (null output), ERANGE (iters),
+ * EDEVICE. */
+int vqe_lds_ceiling(int iters, void* hip_stream, double* ms, double* bytes);
 
 /* ---------------------------------------------------------------------------
  * BFGS and the VQE loop

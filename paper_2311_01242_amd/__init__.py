@@ -23,7 +23,7 @@ VQE_OK, VQE_EINVAL, VQE_ERANGE, VQE_ENOMEM, VQE_EDEVICE, VQE_ENUMERIC = 0, -1, -
 __all__ = [
     "VQEError", "Hamiltonian", "Ansatz", "State", "Batch", "energy_grad", "energy_grad_noalloc", "EnergyGrad",
     "minimize_bfgs", "run_vqe", "Options", "Result", "lib", "current_stream", "set_tuning",
-    "set_packed", "set_real", "set_run_threads", "copy_ceiling", "set_persistent", "set_tile_cap",
+    "set_packed", "set_real", "real_enabled", "set_run_threads", "copy_ceiling", "lds_ceiling", "set_persistent", "set_tile_cap",
 ]
 
 
@@ -49,12 +49,21 @@ def set_packed(mode=True):
     _check(lib().vqe_set_packed(m))
 
 
+_real = [True]
+
+
 def set_real(on=True):
     """Real amplitudes on the string-product path (the default; applies to
     plans made afterwards): phi and lambda of excitation programs are real, so
     one double per amplitude is stored instead of two.  False keeps complex
     amplitudes there."""
     _check(lib().vqe_set_real(int(bool(on))))
+    _real[0] = bool(on)
+
+
+def real_enabled():
+    """Whether plans made now use real amplitudes on the string-product path."""
+    return _real[0]
 
 
 def set_tile_cap(n_qubits: int, batched: bool, entries: int = 0):
@@ -82,6 +91,15 @@ def copy_ceiling(src, dst, passes: int = 1) -> float:
     _check(lib().vqe_copy_ceiling(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
                                   int(nbytes), int(passes), current_stream(), C.byref(ms)))
     return ms.value
+
+
+def lds_ceiling(iters: int = 4000):
+    """(milliseconds, bytes) of one library launch that reads and writes back
+    LDS on every compute unit `iters` times (a measured on-chip ceiling for
+    the gate kernels, not a step of the method)."""
+    ms, nb = C.c_double(), C.c_double()
+    _check(lib().vqe_lds_ceiling(int(iters), current_stream(), C.byref(ms), C.byref(nb)))
+    return ms.value, nb.value
 
 
 _MAPS = {"jw": 0, "bk": 1}
@@ -497,8 +515,9 @@ class Batch:
         return ms
 
     def work(self):
-        """Work of one evaluation: (forward bytes, 0, adjoint bytes, all phi + lambda
-        bytes, forward launches, H-apply launches, adjoint launches, 0)."""
+        """Work of one evaluation: (forward bytes, packed pair updates per pass,
+        adjoint bytes, all phi + lambda bytes, forward launches, H-apply
+        launches, adjoint launches, states with real amplitudes)."""
         w = np.empty(8, np.float64)
         _check(lib().vqe_batch_work(self._h, _dptr(w)))
         return w

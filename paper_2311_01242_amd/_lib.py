@@ -87,6 +87,7 @@ SIGNATURES = {
     "vqe_batch_persistent": (c_int, [vp, P(c_int)]),
     "vqe_batch_test_wait": (c_int, [vp, c_int, c_int]),
     "vqe_copy_ceiling": (c_int, [vp, vp, c_int64, c_int, vp, P(c_double)]),
+    "vqe_lds_ceiling": (c_int, [c_int, vp, P(c_double), P(c_double)]),
     "vqe_set_run_threads": (c_int, [c_int, c_int, c_int, c_int]),
     "vqe_mlp_create": (c_int, [c_int, P(c_int32), vp, P(vp)]),
     "vqe_mlp_n_params": (c_int, [vp, P(c_int64)]),

@@ -24,11 +24,13 @@ import os
 
 import numpy as np
 
-from . import Batch, VQEError, set_run_threads, set_tile_cap, set_tuning
+from . import Batch, VQEError, real_enabled, set_run_threads, set_tile_cap, set_tuning
 
 RUN_THREADS = (64, 256, 512, 1024)
 # largest packed run tile (entries per vector); 0 = two of the layout's largest blocks
 TILE_CAPS = (0, 1200, 1600, 2400)
+# with real amplitudes a tile takes half the LDS: larger tiles are candidates too
+TILE_CAPS_REAL = (0, 1600, 2400, 3200)
 
 FWD_CANDIDATES = (16 << 10, 32 << 10, 64 << 10, 128 << 10)
 ADJ_CANDIDATES = (32 << 10, 64 << 10, 128 << 10)
@@ -62,11 +64,12 @@ def tune_class(hams, ansatz, n, ne, theta, reps=2, log=None, packed=True):
         # every (L, tile cap, threads): the run threads of each pass are chosen
         # per (L, cap), then (L, cap) by the time of the whole evaluation
         best, best_t, best_ms = None, None, None
+        real = real_enabled()
         for L in sorted({min(n, max(L, ne)) for L in (10, 11, 12, 13, 14)}):
-            for cap in TILE_CAPS:
+            for cap in (TILE_CAPS_REAL if real else TILE_CAPS):
                 set_tile_cap(n, True, cap)
                 rec = {}
-                for th in RUN_THREADS[1:3]:
+                for th in (RUN_THREADS[1:] if real else RUN_THREADS[1:3]):
                     set_run_threads(n, True, th, th)
                     try:
                         rec[th] = measure(64 << 10, 64 << 10, L)
@@ -135,7 +138,8 @@ def autotune_batch(hams, ansatzes, n_electrons, theta_all, offsets, cache=None, 
         classes.setdefault((n, ne), []).append(i)
     out = {}
     for (n, ne), idx in sorted(classes.items()):
-        key = f"{dev}|{'packed-win' if packed else 'full'}|n={n}|ne={ne}|states={len(idx)}"
+        layout = ("packed-real" if real_enabled() else "packed-win") if packed else "full"
+        key = f"{dev}|{layout}|n={n}|ne={ne}|states={len(idx)}"
         if tag:
             key += f"|{tag}"
         if key in cache_data:

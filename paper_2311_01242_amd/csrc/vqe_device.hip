@@ -224,6 +224,7 @@ struct PackedPlan {
     int32_t* d_blk = nullptr;    // run of each block, then the first block of each run
     PoolSweep sweep{};
     double sweep_bytes = 0.0;    // phi and lambda entries of every live tile, read once
+    double pairs = 0.0;          // pair updates of one pass over the gates (live tiles)
 };
 
 struct DevAnsatz {
@@ -1483,6 +1484,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         int64_t moved = 0, moved_live = 0;
         const size_t live0 = live_all.size();
         std::vector<char> used(size_t(r.ncls), 0);   // classes of nonempty tiles
+        std::vector<int64_t> live_cls(size_t(r.ncls), 0);   // live tiles per class
         for (int32_t o = 0; o < r.ntiles; ++o) {
             const uint32_t base = pattern(r.free_hi, o);
             int nE = 0;
@@ -1498,6 +1500,9 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             if (any_nz) {   // the run's gates leave a tile of zero blocks zero
                 live_all.push_back(o);
                 moved_live += nE;
+                const uint32_t hl = base << L;
+                ++live_cls[size_t(__builtin_popcount(hl & 0x55555555u) * r.cls_b +
+                                  __builtin_popcount(hl & 0xAAAAAAAAu))];
                 for (int b = 0; b < r.nblk; ++b)
                     if (lay.bsize[base | r.blk[b]] > 0) nz[base | r.blk[b]] = 1;
             }
@@ -1534,6 +1539,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             for (int64_t k = j; k < j2; ++k) {
                 const GateDesc& h = A->gates[size_t(k)];
                 const uint32_t pd = h.pd & lowmask, klo = (h.x & ~h.pd) & lowmask, chlo = h.chain & lowmask;
+                const size_t list_before = lists[size_t(k - j) * ncl + cls].size();
                 const uint32_t dg = (h.pd >> L) & hmask, kg = ((h.x & ~h.pd) >> L) & hmask;
                 std::vector<uint32_t>& lst = lists[size_t(k - j) * ncl + cls];
                 for (int b = 0; b < r.nblk; ++b) {
@@ -1556,6 +1562,8 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
                         lst.push_back(uint32_t(off[b] + e) | (uint32_t(ie) << kEntBits) | (par << kEntParity));
                     }
                 }
+                // pair updates of the gate over the run's live tiles of this class
+                p->pairs += double(lists[size_t(k - j) * ncl + cls].size() - list_before) * double(live_cls[size_t(cls)]);
             }
         }
         for (int cls = 0; cls < ncl; ++cls) {
@@ -2004,6 +2012,7 @@ struct EvalPlan {
     CiArgs ciargs{};
     const int32_t* perm = nullptr;
     bool real = false;       // packed path with real amplitudes (double, not double2)
+    double pairs = 0.0;      // packed path: pair updates of one pass over the gates
     bool small = false;      // whole-state kernels on a small number-conserving sector
     SmallSpace sspace{};
 };
@@ -2115,6 +2124,7 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
             ep->elems = ep->lay->size;
             ep->fwd_bytes = ep->pp->fwd_bytes;
             ep->adj_bytes = ep->pp->adj_bytes;
+            ep->pairs = ep->pp->pairs;
             ep->fwd_steps = ep->adj_steps = ep->pp->runs.size();
             if (g_packed_enabled.load() >= 2 && (n + 1) / 2 <= kCiMaxBits) {
                 CiSpace* cs;
@@ -3639,6 +3649,7 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
         b->work[0] += ep.fwd_bytes;
         b->work[2] += ep.adj_bytes;
         if (ep.real) b->work[7] += 1.0;
+        b->work[1] += ep.pairs;
         b->work[3] += 2.0 * double(ep.real ? sizeof(double) : sizeof(double2)) * double(ep.elems);
     }
     HIPCHK(hipGetLastError());
