@@ -55,7 +55,7 @@ def _parse():
                     help="batch512: the ansatz of every state (UCCSD, UCCSD with 2 Trotter "
                          "steps, or k-UpCCGSD with k = 2)")
     ap.add_argument("--profile-only", action="store_true",
-                    help="batch512: only the eager HIP-event phase profile (for rocprof runs)")
+                    help="batch512, single24: only the eager HIP-event phase profile (for rocprof runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -151,8 +151,9 @@ def cpu_baseline_batch(spec, budget_s=20.0, ansatz="uccsd"):
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2311_01242_amd", "tuning_cache.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "batch512_hbm_traffic.json")
-TRAFFIC_WORKLOAD = "batch512-uccsd"   # the workload the counters were taken on
+# rocprof FETCH/WRITE summaries per workload: (file, the workload key inside)
+TRAFFIC = {"batch512": (os.path.join(ROOT, "profiles", "batch512_hbm_traffic.json"), "batch512-uccsd"),
+           "single24": (os.path.join(ROOT, "profiles", "single24_hbm_traffic.json"), "single24-uccsd")}
 CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
 # lane-operations per second of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -299,10 +300,10 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
     else:
         h_work = OPS_PER_PAIR * pairs
     traffic = {}
-    if traffic_key is not None and os.path.exists(TRAFFIC):
-        with open(TRAFFIC) as f:
+    if traffic_key is not None and os.path.exists(TRAFFIC[traffic_key][0]):
+        with open(TRAFFIC[traffic_key][0]) as f:
             rec = json.load(f)
-        if rec.get("workload") == traffic_key:
+        if rec.get("workload") == TRAFFIC[traffic_key][1]:
             traffic = rec.get("kernels", {})
     recs = {}
     for i, (phase, work, launches) in enumerate(
@@ -411,7 +412,7 @@ def run_batch(args):
                 "work": b.work().tolist()}
     dt, dt_host, e, g = time_batch(b, theta, args)
     ms_step = 1e3 * dt / args.steps
-    key = TRAFFIC_WORKLOAD if (args.states, args.ansatz) == (512, "uccsd") else None
+    key = "batch512" if (args.states, args.ansatz) == (512, "uccsd") else None
     roof = roofline(b, theta, args.profile_reps, Hs, nes, traffic_key=key)
     ceilings = copy_ceilings()
     add_ceiling_fracs(roof, ceilings)
@@ -534,6 +535,10 @@ def run_single24(args):
     H = vq.Hamiltonian.from_integrals(n, h0, h, g)
     A = vq.Ansatz.uccsd(n, ne)
     th = uniform_theta(1, A.n_params)
+    if args.profile_only:   # the roofline's eager evaluations only (as a one-state batch)
+        b = vq.Batch([H], [A], [ne])
+        phase_ms = b.profile(th, reps=args.profile_reps)
+        return {"profile_only": True, "phase_ms": [round(x, 3) for x in phase_ms], "work": b.work().tolist()}
     for _ in range(args.warmup):
         vq.energy_grad(H, A, ne, th)
     torch.cuda.synchronize()
@@ -543,8 +548,7 @@ def run_single24(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     b = vq.Batch([H], [A], [ne])
-    roof = roofline(b, th, args.profile_reps, [H], [ne])
-    roof["traffic"] = None
+    roof = roofline(b, th, args.profile_reps, [H], [ne], traffic_key="single24")
     ceilings = copy_ceilings()
     add_ceiling_fracs(roof, ceilings)
     return {

@@ -17,9 +17,10 @@ Three sub-commands, both reading the CSV files rocprofv3 writes with
             phase, with the sha256 of the kernel source it was measured on)
             and prints a markdown table.
 
-Phase of a kernel: k_prun<1,...> / k_run_fwd forward, k_prun<2,...> /
-k_run_adj adjoint, k_ppool pool sweep, k_hx_ci / k_ci_scatter / k_ci_gather /
-k_hx_packed / k_hx_sector / k_hx_dense H-apply.
+Phase of a kernel: k_prun<1,...> / k_run_fwd / k_small_fwd forward,
+k_prun<2,...> / k_run_adj / k_small_adj adjoint, k_ppool pool sweep, k_hx_ci /
+k_ci_scatter / k_ci_gather / k_hx_packed / k_hx_sector / k_hx_dense /
+k_small_hx H-apply.
 """
 from __future__ import annotations
 
@@ -37,10 +38,12 @@ COPY_BYTES = 2 ** 31
 
 
 def phase_of(name: str):
-    if "k_prun<1" in name or "k_run_fwd" in name:
+    if "k_prun<1" in name or "k_run_fwd" in name or "k_small_fwd" in name:
         return "forward"
-    if "k_prun<2" in name or "k_run_adj" in name:
+    if "k_prun<2" in name or "k_run_adj" in name or "k_small_adj" in name:
         return "adjoint"
+    if "k_small_hx" in name:
+        return "h_apply"
     if "k_ppool" in name:
         return "pool_sweep"
     if any(k in name for k in ("k_hx_ci", "k_ci_scatter", "k_ci_gather", "k_hx_packed",

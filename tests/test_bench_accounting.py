@@ -47,7 +47,8 @@ def test_traffic_reported_only_for_its_workload_and_source(tmp_path, monkeypatch
                "kernels": {"adjoint": {"bytes_per_launch": 123.0, "source_sha256": sha}}}
         f = tmp_path / "traffic.json"
         f.write_text(json.dumps(rec))
-        monkeypatch.setattr(bench, "TRAFFIC", str(f))
+        # key -> (file, the workload the file must name)
+        monkeypatch.setattr(bench, "TRAFFIC", {"w1": (str(f), "w1"), "w2": (str(f), "w2")})
 
     class Batch:   # phase times (ms) and work counters of one evaluation
         def profile(self, theta, reps):
