@@ -51,6 +51,9 @@ def _parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--mapping", default="jw", choices=["jw", "bk"],
                     help="scan12: fermion-to-qubit mapping")
+    ap.add_argument("--bk-rotations", action="store_true",
+                    help="scan12 --mapping bk: the encoded Pauli rotations on full vectors (packed "
+                         "layout off) instead of the occupation-basis packed path")
     ap.add_argument("--ansatz", default="uccsd", choices=list(ANSATZE),
                     help="batch512: the ansatz of every state (UCCSD, UCCSD with 2 Trotter "
                          "steps, or k-UpCCGSD with k = 2)")
@@ -567,17 +570,20 @@ def run_scan12(args):
     import paper_2311_01242_amd as vq
     from vqe_inputs import SCAN12_LAMBDAS, scan_integrals, uniform_theta
     fam = scan_integrals(12, 2)
+    rotations = args.mapping == "bk" and args.bk_rotations
+    if rotations:
+        vq.set_packed(0)   # BK programs as encoded rotations on full vectors
     A = vq.Ansatz.uccsd_map(12, 6, args.mapping)
     Hs = [vq.Hamiltonian.from_integrals_map(12, args.mapping, *fam(l)) for l in SCAN12_LAMBDAS]
     th = np.concatenate([uniform_theta(7, A.n_params)] * len(Hs))
-    if not args.no_autotune:   # tile budgets of this batch (cached per mapping)
+    if not args.no_autotune:   # tile budgets of this batch (cached per mapping and layout)
         from paper_2311_01242_amd import autotune
         offs = np.cumsum([0] + [A.n_params] * len(Hs))
         autotune.autotune_batch(Hs, [A] * len(Hs), [6] * len(Hs), th, offs, cache=TUNE_CACHE,
-                                packed=(args.mapping == "jw"), tag="scan-" + args.mapping)
+                                packed=not rotations, tag="scan-" + args.mapping)
     b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
     dt, dt_host, _, _ = time_batch(b, th, args)
-    if args.mapping == "bk":
+    if rotations:
         roof = roofline(b, th, args.profile_reps, Hs, [6] * len(Hs), kernels=ROTATION_KERNELS,
                         pairs=float(sum((1 << 12) * H.info()[1] for H in Hs)))
     else:
@@ -589,8 +595,9 @@ def run_scan12(args):
         "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": amp_dtype(batch_real(b)), "data": "synthetic",
         "config": {"workload": "12-qubit bond-stretch scan, 20 geometries per step, "
-                               + {"jw": "Jordan-Wigner (packed sector kernels)",
-                                  "bk": "Bravyi-Kitaev (full-vector Pauli-rotation kernels)"}[args.mapping],
+                               + ("Bravyi-Kitaev (encoded Pauli rotations on full vectors)" if rotations else
+                                  {"jw": "Jordan-Wigner (packed sector kernels)",
+                                   "bk": "Bravyi-Kitaev (occupation-basis packed sector kernels)"}[args.mapping]),
                    "mapping": args.mapping},
         "roofline": roof,
         "host_entry": host_entry(len(Hs), args.steps, dt_host),

@@ -142,7 +142,16 @@ int vqe_ansatz_uccsd(int n_qubits, int n_electrons, vqe_ansatz** out, int32_t* n
  * sum_k i d_k P_k (commuting Hermitian strings) and applied as the Pauli
  * rotations exp(-i (-2 d_k theta) / 2 P_k), on full 2^n vectors, from the
  * encoded reference beta (2^n_electrons - 1) (vqe_ansatz_reference).
- * Excitations are reported as for vqe_ansatz_uccsd. */
+ * Excitations are reported as for vqe_ansatz_uccsd.  Energy and gradient
+ * evaluations (vqe_energy_grad, its allocation-free form, vqe_batch_*,
+ * vqe_run) with the packed layout on (vqe_set_packed, default) evaluate
+ * the program in the occupation basis instead: the encoded program and
+ * Hamiltonian are the occupation-basis ones conjugated by the basis
+ * relabelling b = beta n, so the same energy and gradient come from the
+ * decoded reference, the occupation-basis excitations and the Hamiltonian's
+ * terms taken to that basis (X^x Z^z -> X^{beta^-1 x} Z^{beta^T z}, made once
+ * per Hamiltonian and encoding), on the packed sector path.  With the
+ * packed layout off the rotations run on full vectors as given. */
 int vqe_ansatz_uccsd_map(int n_qubits, int n_electrons, int mapping, vqe_ansatz** out,
                          int32_t* n_params);
 

@@ -57,6 +57,9 @@ struct vqe_hamiltonian {
     int32_t diag_group = -1;          // index of the x = 0 group, -1 if none
     mutable std::mutex mu;
     mutable std::map<int, vqe::DevHam*> dev;  // per device ordinal
+    // this Hamiltonian in the occupation basis of an encoding (keyed by the
+    // encoding's rows of beta^-1), made on first use
+    mutable std::map<std::vector<uint32_t>, vqe_hamiltonian*> occ;
     ~vqe_hamiltonian();
 };
 
@@ -93,6 +96,12 @@ struct vqe_ansatz {
     bool sector_conserving = false;   // every gate conserves N and S_z
     std::vector<vqe::GateDesc> gates;
     std::vector<int32_t> exc;         // 4 per gate for UCCSD (i, a, -1, -1) / (i, j, a, b)
+    // UCCSD under a linear encoding b = beta n other than Jordan-Wigner: the
+    // same excitations in the occupation basis (owned; null otherwise), with
+    // the encoding's columns (enc_c[P]: the qubits that flip with n_P) and
+    // the rows of beta^-1 (enc_r[P]: n_P as a parity of qubits)
+    vqe_ansatz* occ = nullptr;
+    uint32_t enc_c[32] = {}, enc_r[32] = {};
     mutable std::mutex mu;
     mutable std::map<int, vqe::DevAnsatz*> dev;
     ~vqe_ansatz();
@@ -101,4 +110,9 @@ struct vqe_ansatz {
 namespace vqe {
 // Host-side helpers used by both translation units.
 bool finite_all(const double* v, int64_t n);
+// H with every term's masks taken to the occupation basis of the encoding
+// (enc_c, enc_r as in vqe_ansatz): X^x Z^z on encoded qubits acts on
+// occupations as X^{beta^-1 x} Z^{beta^T z} with the same coefficient.
+int hamiltonian_to_occupation(const vqe_hamiltonian* H, const uint32_t* enc_c, const uint32_t* enc_r,
+                              vqe_hamiltonian** out);
 }  // namespace vqe

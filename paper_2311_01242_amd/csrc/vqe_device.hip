@@ -2293,6 +2293,35 @@ static int check_pair(const vqe_hamiltonian* H, const vqe_ansatz* A, int ne) {
 
 static int64_t sector_key(int n, int ne) { return (int64_t(n) << 16) | ne; }
 
+// A UCCSD program under a linear encoding other than Jordan-Wigner is the
+// Jordan-Wigner program conjugated by the basis relabelling b = beta n, and
+// so is its Hamiltonian when both come from the same integrals: energy and
+// gradient are those of (H in the occupation basis, the occupation-basis
+// program) from the decoded reference, which the packed sector path
+// evaluates (the decoded occupations define the sector).  With the packed
+// layout off, the encoded rotations run on full vectors as given.
+static int resolve_encoded(const vqe_hamiltonian*& H, const vqe_ansatz*& A) {
+    if (!A->occ || g_packed_enabled.load() == 0) return VQE_OK;
+    const std::vector<uint32_t> key(A->enc_r, A->enc_r + A->n);
+    vqe_hamiltonian* ho = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(H->mu);
+        auto it = H->occ.find(key);
+        if (it != H->occ.end()) ho = it->second;
+    }
+    if (!ho) {
+        vqe_hamiltonian* made = nullptr;
+        if (int rc = hamiltonian_to_occupation(H, A->enc_c, A->enc_r, &made)) return rc;
+        std::lock_guard<std::mutex> lk(H->mu);
+        auto ins = H->occ.emplace(key, made);
+        if (!ins.second) delete made;   // another thread made it first
+        ho = ins.first->second;
+    }
+    H = ho;
+    A = A->occ;
+    return VQE_OK;
+}
+
 }  // namespace vqe
 
 namespace vqe {
@@ -2334,6 +2363,7 @@ static int scratch_address(int dev, char** out) {
 struct NoAllocRec {
     EvalPlan ep;
     StateDesc sd;
+    const vqe_ansatz* prog = nullptr;   // the program the plan runs (an encoded one's occupation form)
 };
 static std::mutex g_noalloc_mu;
 static std::map<std::tuple<int, const void*, const void*, int>, NoAllocRec> g_noalloc;
@@ -2363,6 +2393,7 @@ struct vqe_state {
 
 vqe_hamiltonian::~vqe_hamiltonian() {
     noalloc_forget(this);
+    for (auto& kv : occ) delete kv.second;
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto& kv : dev) {
@@ -2447,6 +2478,7 @@ vqe_ansatz::~vqe_ansatz() {
         delete kv.second;
     }
     (void)hipSetDevice(cur);
+    delete occ;
 }
 
 extern "C" int vqe_state_create(int n, void* stream, vqe_state** out) {
@@ -2779,6 +2811,9 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
     if (!energy) return fail(VQE_EINVAL, "null energy pointer");
     if (A->n_params > 0 && !theta) return fail(VQE_EINVAL, "null theta");
     if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
+    const void* const key_h = H;   // the allocation-free call is keyed by the caller's handles
+    const void* const key_a = A;
+    if (int rc = resolve_encoded(H, A)) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t M = int64_t(A->gates.size()), P = A->n_params;
     SingleEval e;
@@ -2787,8 +2822,7 @@ extern "C" int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, in
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
         std::lock_guard<std::mutex> lk(g_noalloc_mu);
-        g_noalloc[std::make_tuple(dev, static_cast<const void*>(H), static_cast<const void*>(A), ne)] =
-            NoAllocRec{e.ep, e.sd};
+        g_noalloc[std::make_tuple(dev, key_h, key_a, ne)] = NoAllocRec{e.ep, e.sd, A};
     }
     if (int rc = enqueue_eval(e.ep, e.sd_dev, 1, grad != nullptr, st)) return rc;
     std::vector<double> raw(std::max<int64_t>(M, 1));
@@ -2811,19 +2845,22 @@ extern "C" int vqe_energy_grad_noalloc(const vqe_hamiltonian* H, const vqe_ansat
     if (!energy) return fail(VQE_EINVAL, "null energy pointer");
     if (A->n_params > 0 && !theta) return fail(VQE_EINVAL, "null theta");
     if (!finite_all(theta, A->n_params)) return fail(VQE_EINVAL, "theta has a non-finite entry");
+    const void* const key_h = H;
+    const void* const key_a = A;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t M = int64_t(A->gates.size()), P = A->n_params;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     NoAllocRec rec;
     {
         std::lock_guard<std::mutex> lk(g_noalloc_mu);
-        auto it = g_noalloc.find(std::make_tuple(dev, static_cast<const void*>(H), static_cast<const void*>(A), ne));
+        auto it = g_noalloc.find(std::make_tuple(dev, key_h, key_a, ne));
         if (it == g_noalloc.end())
             return fail(VQE_EINVAL, "no plan for this Hamiltonian, ansatz and n_electrons on this device: "
                                     "call vqe_energy_grad with them once first");
         rec = it->second;
     }
+    A = rec.prog;   // the program the recorded plan runs
+    const int64_t M = int64_t(A->gates.size()), P = A->n_params;
     const EvalPlan& ep = rec.ep;
     // the workspace the regular call carves, in the scratch array
     const size_t elems = size_t(ep.elems);
@@ -3487,6 +3524,13 @@ extern "C" int vqe_batch_create(int S, const vqe_hamiltonian* const* H, const vq
     for (int i = 0; i < S; ++i)
         if (int rc = check_pair(H[i], A[i], ne[i]))
             return fail(rc, "state " + std::to_string(i) + ": " + vqe_last_error());
+    // encoded programs evaluate in the occupation basis (resolve_encoded)
+    std::vector<const vqe_hamiltonian*> Hr(H, H + S);
+    std::vector<const vqe_ansatz*> Ar(A, A + S);
+    for (int i = 0; i < S; ++i)
+        if (int rc = resolve_encoded(Hr[i], Ar[i])) return rc;
+    H = Hr.data();
+    A = Ar.data();
     auto* b = new vqe_batch();
     std::unique_ptr<vqe_batch> guard(b);
     b->S = S;

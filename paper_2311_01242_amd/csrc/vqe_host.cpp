@@ -641,6 +641,10 @@ extern "C" int vqe_ansatz_uccsd_map(int n, int ne, int mapping, vqe_ansatz** out
     uint32_t ref = 0;
     for (int P = 0; P < ne; ++P) ref ^= E.c[P];
     A->ref_bits = int64_t(ref);
+    for (int P = 0; P < n; ++P) {
+        A->enc_c[P] = E.c[P];
+        A->enc_r[P] = E.r[P];
+    }
     const size_t M = base->exc.size() / 4;
     for (size_t k = 0; k < M; ++k) {
         const int32_t* o = &base->exc[4 * k];
@@ -680,10 +684,30 @@ extern "C" int vqe_ansatz_uccsd_map(int n, int ne, int mapping, vqe_ansatz** out
             A->gates.push_back(gd);
         }
     }
-    vqe_ansatz_free(base);
+    A->occ = base;   // the same excitations in the occupation basis
     *out = A;
     return VQE_OK;
 }
+
+namespace vqe {
+
+int hamiltonian_to_occupation(const vqe_hamiltonian* H, const uint32_t* enc_c, const uint32_t* enc_r,
+                              vqe_hamiltonian** out) {
+    const size_t T = H->x.size();
+    std::vector<uint32_t> x(T), z(T);
+    for (size_t t = 0; t < T; ++t) {
+        uint32_t xo = 0, zo = 0;
+        for (int P = 0; P < H->n; ++P) {
+            xo |= uint32_t(popc(H->x[t] & enc_r[P]) & 1) << P;   // beta^-1 x
+            zo |= uint32_t(popc(H->z[t] & enc_c[P]) & 1) << P;   // beta^T z
+        }
+        x[t] = xo;
+        z[t] = zo;
+    }
+    return vqe_hamiltonian_from_paulis(H->n, int64_t(T), x.data(), z.data(), H->c.data(), out);
+}
+
+}  // namespace vqe
 
 extern "C" int vqe_ansatz_reference(const vqe_ansatz* A, uint64_t* index) {
     if (!A || !index) return fail(VQE_EINVAL, "null pointer argument");

@@ -25,8 +25,17 @@ def _device():
     yield
 
 
+@pytest.fixture(params=[0, 2], ids=["full-vector-rotations", "packed-occupation-basis"])
+def layout(request):
+    """BK programs as encoded Pauli rotations on full vectors, and (the
+    default) in the occupation basis on the packed sector path."""
+    vq.set_packed(request.param)
+    yield request.param
+    vq.set_packed(True)
+
+
 @pytest.mark.parametrize("n,ne", [(4, 2), (5, 2), (6, 3), (8, 4), (10, 5), (12, 6), (13, 6)])
-def test_bk_energy_and_gradient_vs_oracle(n, ne):
+def test_bk_energy_and_gradient_vs_oracle(n, ne, layout):
     h0, h, g = random_integrals(n, 1000 + n)
     H = vq.Hamiltonian.from_integrals_map(n, "bk", h0, h, g)
     A = vq.Ansatz.uccsd_map(n, ne, "bk")
@@ -37,6 +46,36 @@ def test_bk_energy_and_gradient_vs_oracle(n, ne):
     assert np.abs(gr - prob.grad_shift(theta)).max() < TOL_E
     e0, g0 = vq.energy_grad(H, A, ne, np.zeros(A.n_params))
     assert abs(e0 - F.hf_energy_closed_form(n, ne, h0, h, g)) < TOL_E
+    # the allocation-free call reuses the plan of the call before it
+    e1, g1 = vq.energy_grad_noalloc(H, A, ne, np.zeros(A.n_params))
+    assert e1 == e0 and np.array_equal(g1, g0)
+
+
+def test_bk_layouts_agree_on_a_batch():
+    """A 12-qubit BK stretch batch: occupation-basis packed evaluation against
+    the encoded rotations on full vectors (1e-12), and the Hamiltonian's
+    terms taken to the occupation basis against the Jordan-Wigner ones."""
+    fam = scan_integrals(12, 5)
+    lams = np.linspace(0.8, 2.5, 5)
+    A = vq.Ansatz.uccsd_map(12, 6, "bk")
+    th = np.concatenate([uniform_theta(70 + i, A.n_params, -0.3, 0.3) for i in range(len(lams))])
+    out = []
+    for mode in (0, 2):
+        vq.set_packed(mode)
+        try:
+            Hs = [vq.Hamiltonian.from_integrals_map(12, "bk", *fam(l)) for l in lams]
+            b = vq.Batch(Hs, [A] * len(Hs), [6] * len(Hs))
+            out.append(b.energy_grad(th))
+        finally:
+            vq.set_packed(True)
+    (e0, g0), (e2, g2) = out
+    assert np.abs(e0 - e2).max() < 1e-12 and np.abs(g0 - g2).max() < 1e-12
+    # the same values as the Jordan-Wigner program on the same integrals
+    Aj = vq.Ansatz.uccsd(12, 6)
+    bj = vq.Batch([vq.Hamiltonian.from_integrals(12, *fam(l)) for l in lams], [Aj] * len(lams),
+                  [6] * len(lams))
+    ej, gj = bj.energy_grad(th)
+    assert np.abs(ej - e2).max() < 1e-12 and np.abs(gj - g2).max() < 1e-12
 
 
 def test_bk_statevector_matches_oracle():
