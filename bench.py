@@ -40,7 +40,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch512",
-                    choices=["batch512", "single24", "scan12", "warmstart16", "adapt20", "puccd11"])
+                    choices=["batch512", "single24", "scan12", "warmstart16", "adapt20", "puccd11", "mlp16"])
     ap.add_argument("--scan-points", type=int, default=200)
     ap.add_argument("--mlp-steps", type=int, default=4000)
     ap.add_argument("--states", type=int, default=512)
@@ -654,7 +654,7 @@ def run_warmstart16(args):
     return {
         "metric": "VQE iterations to 1 mHa, warm start vs plain", "value": s["warm_iters_to_1mHa"]["mean"],
         "unit": "BFGS iterations (mean over held-out points)", "higher_is_better": False,
-        "n_gpus": 1, "dtype": "complex128 (VQE) / bf16+fp32 (MLP)", "data": "synthetic",
+        "n_gpus": 1, "dtype": "float64 (VQE, real amplitudes) / bf16+fp32 (MLP)", "data": "synthetic",
         "vs_baseline": None,
         "config": {"workload": f"16-qubit warm-start scan, {len(lams)} points, {len(train)} train / "
                                f"{len(held)} held out", "mlp": [37, 256, 256, 360],
@@ -663,6 +663,77 @@ def run_warmstart16(args):
         "mlp_loss_first_last": [float(loss[0]), float(loss[-1])],
         "per_point": [{k: (round(v, 9) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
     }
+
+
+BF16_PEAK_TFLOPS = 2500.0   # dense MFMA bf16 (no sparsity)
+
+
+def run_mlp16(args):
+    """The warm start's network trained alone, at its 16-qubit shapes: 160
+    samples of 37 features to 360 amplitudes, 37 -> 256 -> 256 -> 360,
+    bf16 products on the matrix cores, fp32 Adam; seeded synthetic inputs
+    and targets.  One step = forward, MSE gradient and Adam update of all
+    168,040 parameters; value = steps/s over args.mlp_steps steps."""
+    import torch
+    from paper_2311_01242_amd.mlp import MLP
+    widths = [37, 256, 256, 360]
+    B = 160
+    rng = np.random.default_rng(16)
+    x = rng.normal(0.0, 1.0, size=(B, widths[0])).astype(np.float32)
+    y = rng.normal(0.0, 0.1, size=(B, widths[-1])).astype(np.float32)
+    net = MLP(widths)
+    parts = []
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / fi), size=fo * fi))
+        parts.append(np.zeros(fo))
+    p0 = np.concatenate(parts).astype(np.float32)
+    net.set_params(p0)
+    net.train(x, y, 50)   # warm-up
+    net.set_params(p0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = net.train(x, y, args.mlp_steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # products per step: forward a W^T, backward dz^T a and dz W per layer
+    # (the first layer's input gradient is not formed), 2 flops per multiply-add
+    flops = 0
+    for li, (fi, fo) in enumerate(zip(widths[:-1], widths[1:])):
+        flops += 2 * B * fi * fo * (3 if li > 0 else 2)
+    achieved = flops * args.mlp_steps / dt / 1e12
+    out = {
+        "metric": "MLP training steps/s", "value": round(args.mlp_steps / dt, 2), "unit": "Adam steps/s",
+        "n_gpus": 1, "steps": args.mlp_steps, "warmup": 50, "ms_per_step": round(1e3 * dt / args.mlp_steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (products) / fp32",
+        "data": "synthetic",
+        "config": {"workload": "warm-start MLP 37-256-256-360 trained on 160 samples (16-qubit shapes)"},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm_bf16 (v_mfma_f32_16x16x32_bf16)",
+                     "achieved": round(achieved, 3), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 6), "traffic": None,
+                     "algorithmic_flops_per_step": flops},
+        "loss_first_last": [float(loss[0]), float(loss[-1])],
+    }
+    if not args.no_cpu_baseline:
+        from oracle import mlp as OM
+        params = p0.astype(np.float64)
+        m = np.zeros_like(params)
+        v = np.zeros_like(params)
+        k, t_cpu = 0, 0.0
+        while t_cpu < 10.0 and k < 200:
+            t1 = time.perf_counter()
+            _, gr = OM.loss_and_grad(params, widths, x, y)
+            params, m, v = OM.adam_step(params, gr, m, v, k + 1)
+            t_cpu += time.perf_counter() - t1
+            k += 1
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        out["cpu_baseline"] = {"value": round(k / t_cpu, 3), "unit": "Adam steps/s", "cores": cores,
+                               "cpu_model": cpu_model(), "kind": "oracle",
+                               "sample": f"{k} oracle steps (NumPy float64 with bf16 rounding emulation)"}
+    return out
 
 
 def cpu_baseline_pool(n, ne, seed, sel, theta, budget_s=20.0):
@@ -792,7 +863,7 @@ def main():
         return
     fn = {"batch512": run_batch, "single24": run_single24, "scan12": run_scan12,
           "warmstart16": run_warmstart16, "adapt20": run_adapt20,
-          "puccd11": run_puccd11}[args.workload]
+          "puccd11": run_puccd11, "mlp16": run_mlp16}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

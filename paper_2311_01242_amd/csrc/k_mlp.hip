@@ -1,5 +1,5 @@
 // Warm-start MLP on gfx950: bfloat16 GEMM operands on the matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation), FP32 bias / GELU / MSE /
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), FP32 bias / GELU / MSE /
 // Adam, FP32 master weights with a bfloat16 copy for the products.
 //
 // A project addition on top of the method: the network maps a bond-stretch
@@ -20,7 +20,8 @@
 
 #include "internal.h"
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace vqe {
@@ -57,9 +58,12 @@ __global__ void k_to_bf16(const float* __restrict__ src, uint16_t* __restrict__ 
 }
 
 // C[i][j] = sum_k A(i,k) B(k,j) (+ bias[j]);  A(i,k) = A[i*sai + k*sak],
-// B(k,j) = B[k*sbk + j*sbj], both bfloat16.  One wave64 per 16x16 tile of C.
-// Operand fragments of v_mfma_f32_16x16x16_bf16: lane l holds A[l%16][4(l/16)+r]
-// and B[4(l/16)+r][l%16], r = 0..3; the result D[4(l/16)+r][l%16].
+// B(k,j) = B[k*sbk + j*sbj], both bfloat16.  One wave64 per 16x16 tile of C,
+// 32 k per matrix instruction.  Operand fragments of
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)+r] and
+// B[8(l/16)+r][l%16], r = 0..7 (A and B split k the same way, so the sum
+// over k does not depend on which k a slot holds); the result
+// D[4(l/16)+r][l%16], r = 0..3.
 // Epilogue: C (fp32, row stride ldc) = acc + bias; if cbf, cbf[i*ldc + j] =
 // bf16(GELU(C)) (act = 1) or bf16(C) (act = 0).
 __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A,
@@ -71,21 +75,23 @@ __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uin
     const int lane = threadIdx.x;
     const int ti = blockIdx.y * 16, tj = blockIdx.x * 16;
     const int i = ti + (lane & 15), j = tj + (lane & 15);
-    const int kq = (lane >> 4) * 4;
+    const int kq = (lane >> 4) * 8;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x4 a, b;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        s16x8 a, b;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 8; ++r) {
             const int k = k0 + kq + r;
             a[r] = (i < M && k < K) ? short(A[i * sai + k * sak]) : short(0);
             b[r] = (j < N && k < K) ? short(B[k * sbk + j * sbj]) : short(0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       acc, 0, 0, 0);
     }
+    const int rq = (lane >> 4) * 4;   // the result rows of this lane
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int ii = ti + kq + r, jj = tj + (lane & 15);
+        const int ii = ti + rq + r, jj = tj + (lane & 15);
         if (ii < M && jj < N) {
             const float c = acc[r] + (bias ? bias[jj] : 0.f);
             C[ii * ldc + jj] = c;
@@ -95,16 +101,19 @@ __global__ void __launch_bounds__(64) k_gemm_bf16(int M, int N, int K, const uin
 }
 
 // dz = 2 (out - y) / (B N) (fp32 and bf16 copies); loss = mean (out - y)^2,
-// summed in a fixed order by one block; loss_trace[*t] = loss when *t < cap.
-__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ out, const float* __restrict__ y,
-                                             int64_t n, float* __restrict__ dz,
-                                             uint16_t* __restrict__ dzbf, float* __restrict__ loss,
-                                             const int* __restrict__ t, float* __restrict__ trace,
-                                             int cap) {
-    __shared__ float red[256];
+// summed in a fixed order by one block of kMseThreads threads (each thread's
+// strided elements, then a tree); loss_trace[*t] = loss when *t < cap.
+constexpr int kMseThreads = 1024;
+
+__global__ void __launch_bounds__(kMseThreads) k_mse(const float* __restrict__ out, const float* __restrict__ y,
+                                                     int64_t n, float* __restrict__ dz,
+                                                     uint16_t* __restrict__ dzbf, float* __restrict__ loss,
+                                                     const int* __restrict__ t, float* __restrict__ trace,
+                                                     int cap) {
+    __shared__ float red[kMseThreads];
     float acc = 0.f;
     const float sc = 2.0f / float(n);
-    for (int64_t k = threadIdx.x; k < n; k += 256) {
+    for (int64_t k = threadIdx.x; k < n; k += kMseThreads) {
         const float d = out[k] - y[k];
         acc += d * d;
         const float g = sc * d;
@@ -113,7 +122,7 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ out, cons
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = kMseThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -124,13 +133,17 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ out, cons
     }
 }
 
-// db[j] = sum_i dz[i][j] (fixed order over i)
-__global__ void k_colsum(const float* __restrict__ dz, int B, int N, float* __restrict__ db) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// db[j] = sum_i dz[i][j]: one wave per column j, lane l adding rows l, l + 64,
+// ... in order, then the 64 lane sums by a fixed butterfly (lane 0's result).
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ dz, int B, int N,
+                                                float* __restrict__ db) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= N) return;   // whole waves
     float s = 0.f;
-    for (int i = 0; i < B; ++i) s += dz[int64_t(i) * N + j];
-    db[j] = s;
+    for (int i = lane; i < B; i += 64) s += dz[int64_t(i) * N + j];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) db[j] = s;
 }
 
 // dz = da * GELU'(z), with a bf16 copy
@@ -279,7 +292,7 @@ void enqueue_forward(vqe_mlp* n, int B) {
 // Loss and gradients (into n->g) for targets n->y; t/trace for the loss record.
 void enqueue_backward(vqe_mlp* n, int B, bool record) {
     const int fo_last = n->w[n->L];
-    hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, n->st, n->z[n->L - 1], n->y,
+    hipLaunchKernelGGL(k_mse, dim3(1), dim3(kMseThreads), 0, n->st, n->z[n->L - 1], n->y,
                        int64_t(B) * fo_last, n->dz, n->dzbf, n->loss, n->t,
                        record ? n->trace : nullptr, n->trace_cap);
     for (int l = n->L - 1; l >= 0; --l) {
@@ -287,7 +300,7 @@ void enqueue_backward(vqe_mlp* n, int B, bool record) {
         // dW[j][k] = sum_i dz[i][j] a[i][k]: A(j,i) = dzbf[i*fo + j], B(i,k) = abf[i*fi + k]
         gemm(n->st, fo, fi, B, n->dzbf, 1, fo, n->abf[l], fi, 1, n->g + n->woff[l], fi, nullptr,
              nullptr, 0);
-        hipLaunchKernelGGL(k_colsum, dim3((fo + 255) / 256), dim3(256), 0, n->st, n->dz, B, fo,
+        hipLaunchKernelGGL(k_colsum, dim3((fo + 3) / 4), dim3(256), 0, n->st, n->dz, B, fo,
                            n->g + n->boff[l]);
         if (l > 0) {
             // da[i][k] = sum_j dz[i][j] W[j][k]: A(i,j) = dzbf[i*fo + j], B(j,k) = W[j*fi + k]
