@@ -51,6 +51,8 @@ def test_traffic_reported_only_for_its_workload_and_source(tmp_path, monkeypatch
         monkeypatch.setattr(bench, "TRAFFIC", {"w1": (str(f), "w1"), "w2": (str(f), "w2")})
 
     class Batch:   # phase times (ms) and work counters of one evaluation
+        S = 1
+
         def profile(self, theta, reps):
             return [1.0, 1.0, 2.0, 0.1]
 
