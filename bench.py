@@ -161,6 +161,7 @@ CSRC = os.path.join(ROOT, "paper_2311_01242_amd", "csrc")
 # lane-operations per second of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_PAIR = 4   # sign parity (AND + BCNT) and a real-by-complex multiply-add (2 FMA)
+OPS_PER_PAIR_REAL = 3   # the same on a real amplitude (1 FMA)
 # published FP64 vector peak, and the floating-point work of one nonzero matrix
 # element applied to an amplitude: real element x complex value, accumulated
 # (two FMA); with real amplitudes (the packed string-product path's default),
@@ -301,7 +302,7 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
         fpe = FLOPS_PER_ELEMENT_REAL if batch_real(b) else FLOPS_PER_ELEMENT
         h_work = fpe * elements
     else:
-        h_work = OPS_PER_PAIR * pairs
+        h_work = (OPS_PER_PAIR_REAL if batch_real(b) else OPS_PER_PAIR) * pairs
     traffic = {}
     if traffic_key is not None and os.path.exists(TRAFFIC[traffic_key][0]):
         with open(TRAFFIC[traffic_key][0]) as f:
@@ -493,7 +494,7 @@ def run_puccd11(args):
         "metric": "energy+adjoint-grad evals/s", "value": round(S * args.steps / dt, 2),
         "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "complex128", "data": "synthetic",
+        "vs_baseline": None, "dtype": amp_dtype(batch_real(b)), "data": "synthetic",
         "config": {"workload": f"pUCCD hard-core bosons, 11 qubits, 7 pairs, 28 params, {S} geometries "
                                "per step, one HIP-graph launch (330-string pair-number sector)",
                    "states": S},

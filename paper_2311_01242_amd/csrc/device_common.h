@@ -659,6 +659,7 @@ struct SmallSpace {
     const int16_t* rank;     // [2^n] rank of a string in the sector, -1 outside
     int32_t n, nsec, ref_rank, M;
     int32_t ham_lds;         // LDS bytes for the largest Hamiltonian of the launch; 0: read from memory
+    int32_t vbytes;          // bytes per amplitude: 8 real, 16 complex
 };
 
 // LDS bytes of a Hamiltonian staged for the small-sector H-apply: groups,

@@ -200,18 +200,20 @@ __global__ void __launch_bounds__(kBlock) k_reduce_e(const StateDesc* __restrict
     if (threadIdx.x == 0) s.out_e[0] = r;
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce_g(const StateDesc* __restrict__ sd,
-                                                     const int32_t* __restrict__ cnt,
-                                                     int cnt_uniform) {
-    __shared__ double red[kBlock / 64];
+// out_g[j] = the sum of gate j's partials: one wave per gate (lane l adds
+// partials l, l + 64, ... in order, then the fixed-order wave total), four
+// gates per workgroup.
+__global__ void __launch_bounds__(256) k_reduce_g(const StateDesc* __restrict__ sd,
+                                                  const int32_t* __restrict__ cnt, int cnt_uniform, int M) {
     const StateDesc& s = sd[blockIdx.y];
-    const int j = blockIdx.x;
+    const int j = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= M) return;   // whole waves
     const int nb = cnt ? cnt[j] : cnt_uniform;
     const double* part = s.part_g + size_t(j) * s.gstride;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) acc += part[b];
-    const double r = block_sum(acc, red);
-    if (threadIdx.x == 0) s.out_g[j] = r;
+    for (int b = lane; b < nb; b += 64) acc += part[b];
+    acc = wave_total(acc);
+    if (lane == 0) s.out_g[j] = acc;
 }
 
 // Per-parameter gradient from the raw per-gate sums: parameter q takes, in
@@ -590,7 +592,7 @@ void launch_reduce_e(const StateDesc* sd, int count, int nblk, hipStream_t st) {
 void launch_reduce_g(const StateDesc* sd, int count, int M, const int32_t* cnt, int cnt_uniform,
                      hipStream_t st) {
     if (M <= 0) return;
-    hipLaunchKernelGGL(k_reduce_g, dim3(M, count), dim3(kBlock), 0, st, sd, cnt, cnt_uniform);
+    hipLaunchKernelGGL(k_reduce_g, dim3((M + 3) / 4, count), dim3(256), 0, st, sd, cnt, cnt_uniform, M);
 }
 
 static size_t run_lds(const RunDesc& run, int vectors) {

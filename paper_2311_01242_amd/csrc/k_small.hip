@@ -22,7 +22,9 @@
 // threads when the workgroup has more threads than the sector has strings,
 // and adds the parts in a fixed order.  The H-apply writes the energy and the
 // reverse sweep the per-gate gradient sums directly (no separate reduction
-// launches).
+// launches).  Amplitudes are real (double) or complex (double2), as the rest
+// of the sector paths: the pair moves are real rotations and H is a real
+// matrix.
 #include <mutex>
 
 #include "device_common.h"
@@ -99,11 +101,11 @@ enum SmallPhase { kSmallFwd = 0, kSmallHx = 1, kSmallAdj = 2 };
 
 __host__ __device__ inline SmallLayout small_layout(const SmallSpace& sp, int phase) {
     SmallLayout l;
-    const size_t vbytes = 16 * size_t(sp.nsec);
+    const size_t vbytes = size_t(sp.vbytes) * size_t(sp.nsec);   // one vector's amplitudes
     l.vec = 0;
-    l.part = l.vec + (phase == kSmallAdj ? 2 : 1) * vbytes;
+    l.part = l.vec + (phase == kSmallAdj ? 2 : 1) * small_r16(vbytes);   // phi [, lambda]
     const int sl = small_slices(sp.nsec);
-    l.gates = l.part + (phase == kSmallHx && sl > 1 ? size_t(sl) * vbytes : 0);
+    l.gates = l.part + (phase == kSmallHx && sl > 1 ? small_r16(size_t(sl) * vbytes) : 0);
     l.ham = l.gates + (phase == kSmallHx ? 0 : sizeof(SmallGate) * size_t(sp.M));
     l.rank = l.ham + (phase == kSmallHx ? small_r16(size_t(sp.ham_lds)) : 0);
     l.str = l.rank + small_r16(2 * (size_t(1) << sp.n));
@@ -119,14 +121,15 @@ __device__ __forceinline__ void small_stage_space(const SmallSpace& sp, uint32_t
 }
 
 // Pair update of gate g on LDS amplitudes: psi <- U psi.
+template <typename V>
 __device__ __forceinline__ void small_gate(const SmallGate& g, const uint32_t* str, const int16_t* rank, int nsec,
-                                           double2* psi) {
+                                           V* psi) {
     for (int t = threadIdx.x; t < nsec; t += kSmallThreads) {
         const uint32_t d = str[t];
         if ((d & g.x) != g.pd) continue;
         const int re = rank[d ^ g.x];
         const double ss = double(g.csign) * parity_sign(d & g.chain) * g.s;
-        double2 a = psi[t], b = psi[re];
+        V a = psi[t], b = psi[re];
         givens(a, b, g.c, ss);
         psi[t] = a;
         psi[re] = b;
@@ -134,17 +137,18 @@ __device__ __forceinline__ void small_gate(const SmallGate& g, const uint32_t* s
 }
 
 // Forward pass: |ref> then U_M ... U_1; phi and the gates' (cos, sin) out.
+template <typename V>
 __global__ void __launch_bounds__(kSmallThreads) k_small_fwd(const StateDesc* __restrict__ sd, SmallSpace sp) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallLayout L = small_layout(sp, kSmallFwd);
     const StateDesc& s = sd[blockIdx.y];
-    double2* psi = reinterpret_cast<double2*>(smem + L.vec);
+    V* psi = reinterpret_cast<V*>(smem + L.vec);
     SmallGate* gs = reinterpret_cast<SmallGate*>(smem + L.gates);
     uint32_t* str = reinterpret_cast<uint32_t*>(smem + L.str);
     int16_t* rank = reinterpret_cast<int16_t*>(smem + L.rank);
     small_stage_space<kSmallThreads>(sp, str, rank);
     for (int t = threadIdx.x; t < sp.nsec; t += kSmallThreads)
-        psi[t] = make_double2(t == sp.ref_rank ? 1.0 : 0.0, 0.0);
+        psi[t] = t == sp.ref_rank ? vunit(V{}) : vzero<V>();
     for (int j = threadIdx.x; j < s.M; j += kSmallThreads) {
         const GateDesc g = s.gates[j];
         double sn, c;
@@ -154,25 +158,28 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_fwd(const StateDesc* __
     }
     __syncthreads();
     for (int j = 0; j < s.M; ++j) {
-        small_gate(gs[j], str, rank, sp.nsec, psi);
+        small_gate<V>(gs[j], str, rank, sp.nsec, psi);
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < sp.nsec; t += kSmallThreads) s.phi[t] = psi[t];
+    V* phi = reinterpret_cast<V*>(s.phi);
+    for (int t = threadIdx.x; t < sp.nsec; t += kSmallThreads) phi[t] = psi[t];
 }
 
 // lambda = H phi on the sector, and E = Re <phi|lambda> into out_e.
+template <typename V>
 __global__ void __launch_bounds__(kSmallHxThreads) k_small_hx(const StateDesc* __restrict__ sd, SmallSpace sp) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kSmallHxThreads / 64];
     const SmallLayout L = small_layout(sp, kSmallHx);
     const StateDesc& s = sd[blockIdx.y];
     const int nsec = sp.nsec;
-    double2* psi = reinterpret_cast<double2*>(smem + L.vec);
-    double2* part = reinterpret_cast<double2*>(smem + L.part);
+    V* psi = reinterpret_cast<V*>(smem + L.vec);
+    V* part = reinterpret_cast<V*>(smem + L.part);
+    V* lam = reinterpret_cast<V*>(s.lam);
     uint32_t* str = reinterpret_cast<uint32_t*>(smem + L.str);
     int16_t* rank = reinterpret_cast<int16_t*>(smem + L.rank);
     small_stage_space<kSmallHxThreads>(sp, str, rank);
-    small_copy<kSmallHxThreads>(psi, s.phi, 16 * size_t(nsec));
+    small_copy<kSmallHxThreads>(psi, s.phi, sizeof(V) * size_t(nsec));
     // the state's own Hamiltonian fits the staged region when the launch has one
     const bool hlds = sp.ham_lds > 0 && small_ham_bytes(s.G, s.nsub, s.ntab) <= size_t(sp.ham_lds);
     double e = 0.0;
@@ -196,7 +203,7 @@ __global__ void __launch_bounds__(kSmallHxThreads) k_small_hx(const StateDesc* _
         for (int i = threadIdx.x; i < sl * nsec; i += kSmallHxThreads) {
             const int r = i % nsec, q = i / nsec;
             const uint32_t b = str[r];
-            double lr = 0.0, li = 0.0;
+            V acc = vzero<V>();
             for (int si = q; si < s.nsub; si += sl) {
                 const GroupDesc gd = groups[sgrp[si]];
                 const uint32_t p = b ^ gd.x;
@@ -206,48 +213,39 @@ __global__ void __launch_bounds__(kSmallHxThreads) k_small_hx(const StateDesc* _
                 const SubDesc sub = subs[si];
                 const double t = tabs[sub.tab + pext_pos(b, gd.pos)];
                 const double d = (__popc(b & sub.w) & 1) ? -t : t;
-                const double2 f = psi[rp];
-                lr += d * f.x;
-                li += d * f.y;
+                axpy(acc, d, psi[rp]);
             }
             if (sl > 1) {
-                part[size_t(q) * nsec + r] = make_double2(lr, li);
+                part[size_t(q) * nsec + r] = acc;
             } else {
-                s.lam[r] = make_double2(lr, li);
-                e += psi[r].x * lr + psi[r].y * li;
+                lam[r] = acc;
+                e += redot(psi[r], acc);
             }
         }
         if (sl > 1) {
             __syncthreads();
             for (int r = threadIdx.x; r < nsec; r += kSmallHxThreads) {
-                double lr = 0.0, li = 0.0;
-                for (int q = 0; q < sl; ++q) {
-                    const double2 v = part[size_t(q) * nsec + r];
-                    lr += v.x;
-                    li += v.y;
-                }
-                s.lam[r] = make_double2(lr, li);
-                e += psi[r].x * lr + psi[r].y * li;
+                V acc = vzero<V>();
+                for (int q = 0; q < sl; ++q) vadd(acc, part[size_t(q) * nsec + r]);
+                lam[r] = acc;
+                e += redot(psi[r], acc);
             }
         }
     } else {
         __syncthreads();
         for (int r = threadIdx.x; r < nsec; r += kSmallHxThreads) {
             const uint32_t b = str[r];
-            double lr = 0.0, li = 0.0;
+            V acc = vzero<V>();
             for (int gi = 0; gi < s.G; ++gi) {
                 const GroupDesc gd = s.groups[gi];
                 const uint32_t p = b ^ gd.x;
                 if (p >= (1u << sp.n)) continue;
                 const int rp = rank[p];
                 if (rp < 0) continue;
-                const double d = group_coeff(gd, s.subs, s.tabs, b);
-                const double2 f = psi[rp];
-                lr += d * f.x;
-                li += d * f.y;
+                axpy(acc, group_coeff(gd, s.subs, s.tabs, b), psi[rp]);
             }
-            s.lam[r] = make_double2(lr, li);
-            e += psi[r].x * lr + psi[r].y * li;
+            lam[r] = acc;
+            e += redot(psi[r], acc);
         }
     }
     const double tot = small_block_total<kSmallHxThreads>(e, red);
@@ -257,20 +255,21 @@ __global__ void __launch_bounds__(kSmallHxThreads) k_small_hx(const StateDesc* _
 // Reverse sweep: per gate (last first) each wave's part of Re <lambda|A_j phi>
 // into LDS, then U_j^dag on phi and lambda in the same pass; the per-gate sums
 // (waves added in fixed order) into out_g at the end.
+template <typename V>
 __global__ void __launch_bounds__(kSmallThreads) k_small_adj(const StateDesc* __restrict__ sd, SmallSpace sp) {
     constexpr int kWaves = kSmallThreads / 64;
     extern __shared__ __align__(16) unsigned char smem[];
     const SmallLayout L = small_layout(sp, kSmallAdj);
     const StateDesc& s = sd[blockIdx.y];
-    double2* psi = reinterpret_cast<double2*>(smem + L.vec);
-    double2* lam = psi + sp.nsec;
+    V* psi = reinterpret_cast<V*>(smem + L.vec);
+    V* lam = reinterpret_cast<V*>(smem + L.vec + small_r16(sizeof(V) * size_t(sp.nsec)));
     SmallGate* gs = reinterpret_cast<SmallGate*>(smem + L.gates);
     uint32_t* str = reinterpret_cast<uint32_t*>(smem + L.str);
     int16_t* rank = reinterpret_cast<int16_t*>(smem + L.rank);
     double* part = reinterpret_cast<double*>(smem + L.total);   // [M][waves] gradient partials
     small_stage_space<kSmallThreads>(sp, str, rank);
-    small_copy<kSmallThreads>(psi, s.phi, 16 * size_t(sp.nsec));
-    small_copy<kSmallThreads>(lam, s.lam, 16 * size_t(sp.nsec));
+    small_copy<kSmallThreads>(psi, s.phi, sizeof(V) * size_t(sp.nsec));
+    small_copy<kSmallThreads>(lam, s.lam, sizeof(V) * size_t(sp.nsec));
     for (int j = threadIdx.x; j < s.M; j += kSmallThreads) {
         const GateDesc g = s.gates[j];
         const double2 cs = s.cs[j];
@@ -286,9 +285,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_adj(const StateDesc* __
             if ((d & g.x) != g.pd) continue;
             const int re = rank[d ^ g.x];
             const double sg = double(g.csign) * parity_sign(d & g.chain);
-            double2 fD = psi[t], fE = psi[re], lD = lam[t], lE = lam[re];
+            V fD = psi[t], fE = psi[re], lD = lam[t], lE = lam[re];
             // A|D> = s|E>, A|E> = -s|D>: <lam|A phi> = s (lam_E^* phi_D - lam_D^* phi_E)
-            acc += sg * ((lE.x * fD.x + lE.y * fD.y) - (lD.x * fE.x + lD.y * fE.y));
+            acc += sg * (redot(lE, fD) - redot(lD, fE));
             const double ss = -sg * g.s;   // U^dag: rotation by -theta
             givens(fD, fE, g.c, ss);
             givens(lD, lE, g.c, ss);
@@ -326,22 +325,34 @@ int small_prepare(const SmallSpace& sp) {
     static std::once_flag once;
     static int rc = 0;
     std::call_once(once, [] {
-        const void* fs[3] = {reinterpret_cast<const void*>(&k_small_fwd), reinterpret_cast<const void*>(&k_small_hx),
-                             reinterpret_cast<const void*>(&k_small_adj)};
+        const void* fs[6] = {reinterpret_cast<const void*>(&k_small_fwd<double2>),
+                             reinterpret_cast<const void*>(&k_small_hx<double2>),
+                             reinterpret_cast<const void*>(&k_small_adj<double2>),
+                             reinterpret_cast<const void*>(&k_small_fwd<double>),
+                             reinterpret_cast<const void*>(&k_small_hx<double>),
+                             reinterpret_cast<const void*>(&k_small_adj<double>)};
         for (const void* f : fs)
             if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(kMax)) != hipSuccess) rc = 1;
     });
     return rc;
 }
 
-void launch_small(int phase, const StateDesc* sd, int count, const SmallSpace& sp, hipStream_t st) {
+template <typename V>
+static void launch_small_t(int phase, const StateDesc* sd, int count, const SmallSpace& sp, hipStream_t st) {
     const size_t lds = small_lds(sp, phase);
     if (phase == kSmallFwd)
-        hipLaunchKernelGGL(k_small_fwd, dim3(1, count), dim3(kSmallThreads), lds, st, sd, sp);
+        hipLaunchKernelGGL(k_small_fwd<V>, dim3(1, count), dim3(kSmallThreads), lds, st, sd, sp);
     else if (phase == kSmallHx)
-        hipLaunchKernelGGL(k_small_hx, dim3(1, count), dim3(kSmallHxThreads), lds, st, sd, sp);
+        hipLaunchKernelGGL(k_small_hx<V>, dim3(1, count), dim3(kSmallHxThreads), lds, st, sd, sp);
     else
-        hipLaunchKernelGGL(k_small_adj, dim3(1, count), dim3(kSmallThreads), lds, st, sd, sp);
+        hipLaunchKernelGGL(k_small_adj<V>, dim3(1, count), dim3(kSmallThreads), lds, st, sd, sp);
+}
+
+void launch_small(int phase, const StateDesc* sd, int count, const SmallSpace& sp, hipStream_t st) {
+    if (sp.vbytes == 8)
+        launch_small_t<double>(phase, sd, count, sp, st);
+    else
+        launch_small_t<double2>(phase, sd, count, sp, st);
 }
 
 }  // namespace vqe

@@ -2165,12 +2165,16 @@ static int make_eval_plan(const vqe_ansatz* A, int ne, bool batched, EvalPlan* e
             ep->sspace.ref_rank = st->rank_h[ref];
             ep->sspace.M = int32_t(A->gates.size());
             ep->sspace.ham_lds = 0;
+            // pair moves are real rotations and H is a real matrix (as on the
+            // string-product path): real amplitudes unless switched off
+            ep->real = g_real_enabled.load() != 0;
+            ep->sspace.vbytes = ep->real ? 8 : 16;
             ep->elems = st->nsec;
             ep->nblk_e = 1;
             ep->gstride = 1;
             ep->d_gcnt = nullptr;
-            ep->fwd_bytes = double(sizeof(double2)) * double(st->nsec);        // phi written
-            ep->adj_bytes = 2.0 * double(sizeof(double2)) * double(st->nsec);  // phi, lambda read
+            ep->fwd_bytes = double(ep->sspace.vbytes) * double(st->nsec);        // phi written
+            ep->adj_bytes = 2.0 * double(ep->sspace.vbytes) * double(st->nsec);  // phi, lambda read
             ep->fwd_steps = ep->adj_steps = 1;
             if (small_prepare(ep->sspace) != 0)
                 return fail(VQE_EDEVICE, "could not enable the small-sector kernels' LDS size");
