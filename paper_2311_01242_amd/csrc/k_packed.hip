@@ -20,9 +20,23 @@
 // the reference the occupied orbitals are low, so D and E differ in the
 // high bits of the created orbitals only; generalised excitations may also
 // annihilate high orbitals.
+#include <type_traits>
+#include <utility>
+
 #include "device_common.h"
 
 namespace vqe {
+
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1 in order (the
+// bodies see i as a constant).
+template <typename F, int... I>
+__device__ __forceinline__ void unroll_each(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void unroll_n(F&& f) {
+    unroll_each(f, std::make_integer_sequence<int, N>{});
+}
 
 template <typename V>
 __global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
@@ -47,6 +61,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     extern __shared__ double2 sh[];
     __shared__ HxTables T;
     constexpr int kRedGates = 8;                            // gates per batch of wave totals
+    constexpr int kListAhead = 4;                           // list prefetch distance (gates)
+    static_assert(kRedGates % kListAhead == 0, "a batch of wave totals starts at slot 0");
     __shared__ double red[2][VEC == 2 ? kRedGates : 1][BS / 64];   // wave totals of the last two batches
     __shared__ double gsum[VEC == 2 ? kMaxRunGates : 1];   // per-gate tile totals
     {
@@ -77,13 +93,29 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const int ng = run.g1 - run.g0;
     const int cls = tb.cls;
     // the tile class's pair lists: gate j's list at lbase + j * stride, padded
-    // with kPairNone; the first entry of each thread is loaded one gate ahead
-    // (issued before the tile loads, so that it has arrived when the gate loop
-    // starts), and needs no per-gate descriptor
+    // with kPairNone.  Each thread's first entry of a gate is loaded kListAhead
+    // gates ahead (the first kListAhead before the tile loads) into slot
+    // t % kListAhead of eq; the gate loops are unrolled so that every slot
+    // index is a constant, so a gate waits only for its own entry's load and
+    // the list reads' latency overlaps kListAhead gate steps
     const int2 lc = ldc(run.info + cls);
     const uint32_t* lbase = run.ent + lc.x;
     const int stride = lc.y;
-    uint32_t ecur = (tid < stride) ? ldg32(lbase + size_t(fwd ? 0 : ng - 1) * stride + tid) : kPairNone;
+    // the loads go through a buffer resource bounded to the class's lists and
+    // are issued unconditionally for a clamped gate (reads past the lists
+    // return 0); a slot is checked only when its gate takes it (a thread past
+    // the list's length has no entry), so the compiler can wait for that
+    // slot's load alone while the later ones stay in flight
+    const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(lbase), 0, int(uint32_t(ng) * uint32_t(stride) * 4u), 0x00020000);
+    const bool has_slot = tid < stride;
+    auto list_first = [&](int j) -> uint32_t {   // raw: the thread's first entry of gate j
+        const int jc = j < 0 ? 0 : (j >= ng ? ng - 1 : j);
+        return __builtin_amdgcn_raw_buffer_load_b32(lrs, uint32_t(jc * stride + tid) * 4u, 0, 0);
+    };
+    uint32_t eq[kListAhead];
+#pragma unroll
+    for (int d = 0; d < kListAhead; ++d) eq[d] = list_first(fwd ? d : ng - 1 - d);
     // per-gate parameters of this tile after the tile (2 double2 per gate):
     // (cos, sgn sin) and (sgn, 0), sgn the gate's pair sign from the tile's
     // high bits outside the window (the window's part is in each entry);
@@ -116,18 +148,22 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     }
     __syncthreads();
     // one gate: its pairs (one per thread per pass), returning the thread's
-    // part of the reverse sweep's Re <lambda|A_j phi>; the next gate's first
-    // entry is loaded meanwhile
-    auto gate_step = [&](int t) -> double {
+    // part of the reverse sweep's Re <lambda|A_j phi>; the slot's entry for
+    // gate t + kListAhead is loaded meanwhile.  LONG (a list longer than the
+    // block): the thread's later entries are read in the gate itself; the
+    // gate loops are built separately for the two cases, so that the common
+    // one has no other list reads than the slots'
+    auto gate_step = [&](int t, auto slot, auto long_tag) -> double {
+        constexpr int q = decltype(slot)::value;   // t % kListAhead
+        constexpr bool LONG = decltype(long_tag)::value;
         const int jl = fwd ? t : ng - 1 - t;
-        const int jn = fwd ? jl + 1 : jl - 1;
-        const bool more = t + 1 < ng;
-        const uint32_t enext = (more && tid < stride) ? ldg32(lbase + size_t(jn) * stride + tid) : kPairNone;
+        const int jn = fwd ? jl + kListAhead : jl - kListAhead;
+        const uint32_t ecur = has_slot ? eq[q] : kPairNone;
         const double2 cs = gpar[2 * jl];                // (cos, sgn sin)
         const double sgn_hi = gpar[2 * jl + 1].x;      // the tile's part of the sign
         const double ssin = cs.y;
         double acc = 0.0;
-        for (int i = tid; i < stride; i += BS) {
+        for (int i = tid; i < (LONG ? stride : tid + 1); i += BS) {
             const uint32_t e = (i == tid) ? ecur : ldg32(lbase + size_t(jl) * stride + i);
             if (e == kPairNone) break;   // the padding: the rest of the list is padding too
             const int k = int(e & kEntMask), ie = int((e >> kEntBits) & kEntMask);
@@ -150,28 +186,45 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                 shl[ie] = lE;
             }
         }
+        // the slot's next entry, issued once this gate's entry is dead (so
+        // that it can take the same register)
+        eq[q] = list_first(jn);
         __syncthreads();
-        ecur = enext;
         return acc;
     };
+    // Whole rounds of slots (and whole batches of wave totals) run without
+    // per-gate bounds, so every one issues the same loads and a gate waits for
+    // its own slot only; the last, partial one checks each gate.
     if (fwd) {
-        for (int t = 0; t < ng; ++t) (void)gate_step(t);
+        auto gates = [&](auto long_tag) {
+            int t0 = 0;
+            for (; t0 + kListAhead <= ng; t0 += kListAhead)
+                unroll_n<kListAhead>([&](auto slot) {
+                    (void)gate_step(t0 + decltype(slot)::value, slot, long_tag);
+                });
+            unroll_n<kListAhead>([&](auto slot) {
+                if (t0 + decltype(slot)::value < ng) (void)gate_step(t0 + decltype(slot)::value, slot, long_tag);
+            });
+        };
+        if (stride > BS) gates(std::true_type{});
+        else gates(std::false_type{});
     } else {
         // the wave totals of kRedGates consecutive gates are taken together
         // after them (independent chains, off the per-gate barrier path);
         // thread u < kRedGates adds the waves of gate u of the previous batch
         // once a barrier has passed since they were written
-        for (int t0 = 0; t0 < ng; t0 += kRedGates) {
+        auto batch = [&](int t0, auto long_tag, auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
             double acc[kRedGates];
             uint32_t busy = 0;
-#pragma unroll
-            for (int u = 0; u < kRedGates; ++u) {
+            unroll_n<kRedGates>([&](auto uu) {
+                constexpr int u = decltype(uu)::value;
                 acc[u] = 0.0;
-                if (t0 + u < ng) {
+                if (FULL || t0 + u < ng) {
                     // a gate's list is packed from its start: a wave whose lanes
                     // have no first entry has no pair in this gate (partial 0)
-                    if (__builtin_amdgcn_ballot_w64(ecur != kPairNone) != 0) busy |= 1u << u;
-                    acc[u] = gate_step(t0 + u);
+                    if (__builtin_amdgcn_ballot_w64(has_slot && eq[u % kListAhead] != kPairNone) != 0) busy |= 1u << u;
+                    acc[u] = gate_step(t0 + u, std::integral_constant<int, u % kListAhead>{}, long_tag);
                     if (u == 0 && t0 > 0 && tid < kRedGates) {
                         const int tp = t0 - kRedGates + tid;
                         double v = 0.0;
@@ -180,14 +233,21 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                         gsum[ng - 1 - tp] = v;
                     }
                 }
-            }
+            });
 #pragma unroll
             for (int u = 0; u < kRedGates; ++u) acc[u] = ((busy >> u) & 1u) ? wave_total(acc[u]) : 0.0;
             if ((tid & 63) == 0) {
 #pragma unroll
                 for (int u = 0; u < kRedGates; ++u) red[(t0 / kRedGates) & 1][u][tid >> 6] = acc[u];
             }
-        }
+        };
+        auto gates = [&](auto long_tag) {
+            int t0 = 0;
+            for (; t0 + kRedGates <= ng; t0 += kRedGates) batch(t0, long_tag, std::true_type{});
+            if (t0 < ng) batch(t0, long_tag, std::false_type{});
+        };
+        if (stride > BS) gates(std::true_type{});
+        else gates(std::false_type{});
         __syncthreads();
         {
             const int t0 = (ng - 1) / kRedGates * kRedGates;   // the last batch
