@@ -282,6 +282,29 @@ constexpr uint32_t kPairNone = 0xffffffffu;
 
 constexpr int kMaxTileBlocks = 16;   // blocks of one packed tile (window of at most 4 high bits)
 
+// A launched tile of a packed run, computed on the host: its entries, pair
+// list class and high part, and where each of its blocks starts in the tile
+// (off) and in the state vector (entry k of block b, off[b] <= k, is at
+// k + delta[b]).  Blocks absent from the sector have the size 0.
+struct TileDesc {
+    int32_t nE;                       // entries (0: an empty tile)
+    int32_t cls;                      // the pair lists' class
+    uint32_t hbase;                   // high part of the tile's base (no window bits)
+    int32_t pad;
+    int32_t off[kMaxTileBlocks];      // tile offset of each block (prefix sums)
+    int32_t delta[kMaxTileBlocks];    // state offset minus tile offset of each block
+};
+static_assert(sizeof(TileDesc) == 144, "TileDesc is read as whole words");
+
+// State-vector index of entry k (0 <= k < nE) of a tile.
+__device__ __forceinline__ int tile_index(const TileDesc& d, int nblk, int k) {
+    int g = k + d.delta[0];
+#pragma unroll
+    for (int b = 1; b < kMaxTileBlocks; ++b)
+        if (b < nblk && k >= d.off[b]) g = k + d.delta[b];
+    return g;
+}
+
 // A run of consecutive gates on the packed layout.  Its window W (high-part
 // bits, i.e. qubits L + bit) holds every high orbital its gates annihilate or
 // create; a tile is the set of blocks whose high parts agree outside W: tile
@@ -314,6 +337,8 @@ struct PackedRun {
     // Partials are stored by position in this list (by tile without a list).
     const int32_t* live;
     int32_t nlive;
+    // the launched tiles in launch order (the live list's, else every tile)
+    const TileDesc* tdesc;
 };
 
 // Pair-list entry: D's index in the tile (bits 0-12), E's (bits 13-25), the

@@ -53,32 +53,24 @@ __global__ void k_packed_hf(const StateDesc* __restrict__ sd, int64_t size) {
 // Tile entry k (blocks one after the other) is staged by thread k % BS
 // (2 EPT BS covers the largest tile of the run); a gate's pairs come from the
 // run's precomputed list for the tile's class, one pair per thread per pass.
+// The tile's geometry is its host-built descriptor (one scalar read), so the
+// tile loads, the gate parameters and the first list entries are all in
+// flight together before the first wait.
 template <int VEC, int BS, int EPT, typename V>
 __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, PackedRun run,
-                                             const PackedGate* __restrict__ pg,
-                                             const HxTables* __restrict__ tabsrc,
-                                             const int32_t* __restrict__ base) {
+                                             const PackedGate* __restrict__ pg) {
     extern __shared__ double2 sh[];
-    __shared__ HxTables T;
     constexpr int kRedGates = 8;                            // gates per batch of wave totals
     constexpr int kListAhead = 4;                           // list prefetch distance (gates)
     static_assert(kRedGates % kListAhead == 0, "a batch of wave totals starts at slot 0");
     __shared__ double red[2][VEC == 2 ? kRedGates : 1][BS / 64];   // wave totals of the last two batches
     __shared__ double gsum[VEC == 2 ? kMaxRunGates : 1];   // per-gate tile totals
-    {
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(tabsrc);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(&T);
-        for (int i = threadIdx.x; i < int(sizeof(HxTables) / 4); i += BS) dst[i] = src[i];
-    }
-    __syncthreads();
     const StateDesc& s = sd[blockIdx.y];
     // both passes cover the run's live tiles only (all of them without a list);
     // gradient partials go to the tile's position in the launch
-    const int o = run.live ? ldc(run.live + blockIdx.x) : int(blockIdx.x);
+    const TileDesc tb = ldc(run.tdesc + blockIdx.x);
     const int po = int(blockIdx.x);
     const int tid = threadIdx.x;
-    TileBlocks tb;
-    tile_blocks(T, run, o, base, tb);
     if (tb.nE == 0) {   // an empty tile: zero gradient partials
         if (VEC == 2)
             for (int jl = tid; jl < run.g1 - run.g0; jl += BS)
@@ -121,21 +113,22 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     // high bits outside the window (the window's part is in each entry);
     // staged once, read by broadcast in the gate loop
     double2* gpar = sh + (size_t(VEC) * run.max_entries * sizeof(V) + 15) / 16;
-    for (int j = tid; j < ng; j += BS) {
-        const PackedGate g = pg[j];
-        const double2 cs = s.cs[run.g0 + j];
-        const double sgn = g.csign * parity_sign(hb0 & g.chhi);
-        gpar[2 * j] = make_double2(cs.x, sgn * cs.y);
-        gpar[2 * j + 1] = make_double2(sgn, 0.0);
-    }
+    // the state index of each staged entry, kept for the write-back
+    int gix[2 * EPT];
     {   // all loads first (clamped into the tile), then the LDS stores
         V vp[2 * EPT], vl[2 * EPT];
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
-            const int k = min(tid + BS * u, nE - 1);
-            const int64_t gi = tile_global(tb, run.nblk, k);
-            vp[u] = ldgv(reinterpret_cast<const V*>(s.phi) + gi);
-            if (VEC == 2) vl[u] = ldgv(reinterpret_cast<const V*>(s.lam) + gi);
+            gix[u] = tile_index(tb, run.nblk, min(tid + BS * u, nE - 1));
+            vp[u] = ldgv(reinterpret_cast<const V*>(s.phi) + gix[u]);
+            if (VEC == 2) vl[u] = ldgv(reinterpret_cast<const V*>(s.lam) + gix[u]);
+        }
+        for (int j = tid; j < ng; j += BS) {
+            const PackedGate g = pg[j];
+            const double2 cs = s.cs[run.g0 + j];
+            const double sgn = g.csign * parity_sign(hb0 & g.chhi);
+            gpar[2 * j] = make_double2(cs.x, sgn * cs.y);
+            gpar[2 * j + 1] = make_double2(sgn, 0.0);
         }
         // unconditional stores (a clamped slot rewrites the last entry with its
         // own value), so that every load is waited for on every path
@@ -265,9 +258,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     for (int u = 0; u < 2 * EPT; ++u) {
         const int k = tid + BS * u;
         if (k < nE) {
-            const int64_t gi = tile_global(tb, run.nblk, k);
-            stgv(reinterpret_cast<V*>(s.phi) + gi, shp[k]);
-            if (VEC == 2) stgv(reinterpret_cast<V*>(s.lam) + gi, shl[k]);
+            stgv(reinterpret_cast<V*>(s.phi) + gix[u], shp[k]);
+            if (VEC == 2) stgv(reinterpret_cast<V*>(s.lam) + gix[u], shl[k]);
         }
     }
 }
@@ -387,8 +379,9 @@ static void launch_one(const StateDesc* sd, int count, const PackedRun& run, con
                        2 * size_t(run.g1 - run.g0) * sizeof(double2);
     const int nx = run.live ? run.nlive : run.ntiles;
     if (nx == 0) return;   // a run with no live tile: nothing to do, no partials
-    hipLaunchKernelGGL((k_prun<VEC, BS, EPT, V>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg, tabs,
-                       base);
+    (void)tabs;
+    (void)base;
+    hipLaunchKernelGGL((k_prun<VEC, BS, EPT, V>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg);
 }
 
 #define VQE_FWD_ENTRY(B, E) &launch_one<1, B, E, double2>,

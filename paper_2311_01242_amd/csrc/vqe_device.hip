@@ -209,6 +209,7 @@ struct PackedPlan {
     int2* d_info = nullptr;           // pair-list index: {offset, stride} per run and class
     uint32_t* d_ent = nullptr;        // pair lists
     int32_t* d_live = nullptr;        // live tiles of the runs that have a list
+    TileDesc* d_tdesc = nullptr;      // launched tiles of each run, in launch order
     std::vector<int32_t> gcnt;        // gradient partials per gate (tiles of its run)
     int32_t* d_gcnt = nullptr;
     int32_t* d_gcnt_live = nullptr;   // the same for the reverse sweep (live tiles of its run)
@@ -631,6 +632,40 @@ struct PackedLayout {
     int32_t* d_base = nullptr;
     int32_t* d_perm = nullptr;           // block order -> string-product order (or null)
 };
+
+// The run kernels' descriptor of tile o of run r (host side of the block
+// geometry the pair lists were built with: block sizes from the popcount
+// tables, block starts from the layout's base offsets).
+static TileDesc host_tile_desc(const HxTables& T, const PackedRun& r, int o, const std::vector<int32_t>& base) {
+    TileDesc d{};
+    uint32_t hb = 0, bits = r.free_hi, v = uint32_t(o);
+    while (bits) {   // pdep(o, free_hi)
+        const uint32_t low = bits & (~bits + 1u);
+        if (v & 1u) hb |= low;
+        v >>= 1;
+        bits &= bits - 1;
+    }
+    d.hbase = hb;
+    const uint32_t hbg = hb << r.L;
+    const int ca = __builtin_popcount(hbg & 0x55555555u), cb = __builtin_popcount(hbg & 0xAAAAAAAAu);
+    d.cls = ca * r.cls_b + cb;
+    int acc = 0;
+    for (int b = 0; b < kMaxTileBlocks; ++b) {
+        d.off[b] = acc;
+        d.delta[b] = -acc;
+        if (b < r.nblk) {
+            const uint32_t sg = r.blk[b] << r.L;
+            const int kA = r.na - ca - __builtin_popcount(sg & 0x55555555u);
+            const int kB = r.nb - cb - __builtin_popcount(sg & 0xAAAAAAAAu);
+            if (kA >= 0 && kA <= T.La && kB >= 0 && kB <= T.Lb) {
+                d.delta[b] = base[hb | r.blk[b]] - acc;
+                acc += (T.offA[kA + 1] - T.offA[kA]) * (T.offB[kB + 1] - T.offB[kB]);
+            }
+        }
+    }
+    d.nE = acc <= r.max_entries ? acc : 0;
+    return d;
+}
 
 static std::mutex g_lay_mu;
 static std::map<std::tuple<int, int, int, int>, PackedLayout*> g_lay;   // (dev, n, ne, L)
@@ -1384,6 +1419,12 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         }
     std::vector<int32_t> live_all;
     std::vector<std::pair<size_t, size_t>> live_of;   // per run: {offset, count}
+    std::vector<TileDesc> tdesc;                      // launched tiles of every run
+    std::vector<size_t> tdesc0;                       // per run: its first descriptor
+    if (lay.size >= (int64_t(1) << 31)) {
+        delete p;
+        return fail(VQE_ERANGE, "packed layout: state too large for 32-bit tile offsets");
+    }
     constexpr size_t kNoList = ~size_t(0);
     // tile-size limit of a run (entries per vector): the tuning's, else two of
     // the layout's largest blocks (a tile of one block pair)
@@ -1615,6 +1656,11 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         } else {
             live_of.emplace_back(live0, live_all.size() - live0);
         }
+        tdesc0.push_back(tdesc.size());
+        if (live_of.back().second == kNoList)
+            for (int32_t o = 0; o < r.ntiles; ++o) tdesc.push_back(host_tile_desc(T, r, o, lay.base));
+        else
+            for (size_t i = live0; i < live_all.size(); ++i) tdesc.push_back(host_tile_desc(T, r, live_all[i], lay.base));
         p->fwd_bytes += 2.0 * double(sizeof(double2)) * double(moved_live);
         p->adj_bytes += 4.0 * double(sizeof(double2)) * double(moved_live);   // live tiles, as the forward
         p->sweep_bytes += 2.0 * double(sizeof(double2)) * double(moved);
@@ -1627,6 +1673,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
     if (!rc) rc = upload(&p->d_info, info.data(), info.size());
     if (!rc) rc = upload(&p->d_ent, ent.data(), ent.size());
     if (!rc) rc = upload(&p->d_live, live_all.data(), live_all.size());
+    if (!rc) rc = upload(&p->d_tdesc, tdesc.data(), tdesc.size());
     std::vector<int32_t> gcnt_live(p->gcnt);
     if (!rc)
         for (size_t r = 0; r < p->runs.size(); ++r) {
@@ -1635,6 +1682,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
             const bool listed = live_of[r].second != kNoList && p->d_live != nullptr;
             p->runs[r].live = listed ? p->d_live + live_of[r].first : nullptr;
             p->runs[r].nlive = listed ? int32_t(live_of[r].second) : p->runs[r].ntiles;
+            p->runs[r].tdesc = p->d_tdesc + tdesc0[r];
             for (int k = p->runs[r].g0; k < p->runs[r].g1; ++k) gcnt_live[size_t(k)] = p->runs[r].nlive;
         }
     if (!rc) rc = upload(&p->d_gcnt_live, gcnt_live.data(), gcnt_live.size());
@@ -1646,6 +1694,7 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         (void)hipFree(p->d_info);
         (void)hipFree(p->d_ent);
         (void)hipFree(p->d_live);
+        (void)hipFree(p->d_tdesc);
         (void)hipFree(p->d_gcnt_live);
         delete p;
         return rc;
@@ -2474,6 +2523,7 @@ vqe_ansatz::~vqe_ansatz() {
             (void)hipFree(pl.second->d_info);
             (void)hipFree(pl.second->d_ent);
             (void)hipFree(pl.second->d_live);
+            (void)hipFree(pl.second->d_tdesc);
             (void)hipFree(pl.second->d_gcnt_live);
             (void)hipFree(pl.second->d_runs);
             (void)hipFree(pl.second->d_blk);
