@@ -445,6 +445,52 @@ __device__ __forceinline__ double wave_total(double v) {
     return (lane(15) + lane(31)) + (lane(47) + lane(63));
 }
 
+// Swaps of whole 16-lane rows between two doubles (gfx950 v_permlane16_swap /
+// v_permlane32_swap on both halves): swap32 exchanges lanes 32-63 of d with
+// lanes 0-31 of s, swap16 rows 1 and 3 of d with rows 0 and 2 of s.
+__device__ __forceinline__ void swap_rows32(double& d, double& s) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(uint32_t(__double2loint(d)), uint32_t(__double2loint(s)), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(uint32_t(__double2hiint(d)), uint32_t(__double2hiint(s)), false, false);
+    d = __hiloint2double(int(hi[0]), int(lo[0]));
+    s = __hiloint2double(int(hi[1]), int(lo[1]));
+}
+__device__ __forceinline__ void swap_rows16(double& d, double& s) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(uint32_t(__double2loint(d)), uint32_t(__double2loint(s)), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(uint32_t(__double2hiint(d)), uint32_t(__double2hiint(s)), false, false);
+    d = __hiloint2double(int(hi[0]), int(lo[0]));
+    s = __hiloint2double(int(hi[1]), int(lo[1]));
+}
+
+// Wave totals of eight values per lane at once: lane l returns the total over
+// the 64 lanes of v[(l >> 3) & 7].  Three halving steps pair lane l with
+// l ^ 32, l ^ 16 and l ^ 8 (row swaps, then a DPP row rotation): each lane
+// keeps the sum for one half of its values.  Then the eight lanes of a group
+// add by DPP mirror and quad permutations.  Every partial sum is formed once
+// in a fixed order, and the last three steps give equal bits on all lanes of a
+// group (a + b == b + a), so the totals are deterministic.  VALU only: no LDS
+// traffic and no wait counters.
+__device__ __forceinline__ double wave_totals8(const double (&v)[8], int lane) {
+    double a[4], b[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {   // lanes < 32 keep v[i], lanes >= 32 v[i + 4]
+        double d = v[i], s = v[i + 4];
+        swap_rows32(d, s);
+        a[i] = d + s;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {   // even rows keep a[i], odd rows a[i + 2]
+        double d = a[i], s = a[i + 2];
+        swap_rows16(d, s);
+        b[i] = d + s;
+    }
+    const bool h8 = lane & 8;   // lanes 8-15 of a row keep b[1]
+    double c = (h8 ? b[1] : b[0]) + dpp_from<0x128>(h8 ? b[0] : b[1]);   // row_ror:8
+    c += dpp_from<0x141>(c);   // row_half_mirror
+    c += dpp_from<0x4e>(c);    // quad_perm [2, 3, 0, 1]
+    c += dpp_from<0xb1>(c);    // quad_perm [1, 0, 3, 2]
+    return c;
+}
+
 // Fixed-order block sum over kBlock threads; result valid in thread 0.
 // Contains __syncthreads(): every thread of the block must call it.
 __device__ __forceinline__ double block_sum(double v, double* sh4) {

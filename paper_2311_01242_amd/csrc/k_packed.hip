@@ -209,20 +209,17 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         else gates(std::false_type{});
     } else {
         // the wave totals of kRedGates consecutive gates are taken together
-        // after them (independent chains, off the per-gate barrier path);
-        // thread u < kRedGates adds the waves of gate u of the previous batch
-        // once a barrier has passed since they were written
+        // after them (wave_totals8: off the per-gate barrier path); thread
+        // u < kRedGates adds the waves of gate u of the previous batch once a
+        // barrier has passed since they were written
+        static_assert(kRedGates == 8, "wave_totals8 takes eight gates");
         auto batch = [&](int t0, auto long_tag, auto full_tag) {
             constexpr bool FULL = decltype(full_tag)::value;
             double acc[kRedGates];
-            uint32_t busy = 0;
             unroll_n<kRedGates>([&](auto uu) {
                 constexpr int u = decltype(uu)::value;
                 acc[u] = 0.0;
                 if (FULL || t0 + u < ng) {
-                    // a gate's list is packed from its start: a wave whose lanes
-                    // have no first entry has no pair in this gate (partial 0)
-                    if (__builtin_amdgcn_ballot_w64(has_slot && eq[u % kListAhead] != kPairNone) != 0) busy |= 1u << u;
                     acc[u] = gate_step(t0 + u, std::integral_constant<int, u % kListAhead>{}, long_tag);
                     if (u == 0 && t0 > 0 && tid < kRedGates) {
                         const int tp = t0 - kRedGates + tid;
@@ -233,12 +230,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                     }
                 }
             });
-#pragma unroll
-            for (int u = 0; u < kRedGates; ++u) acc[u] = ((busy >> u) & 1u) ? wave_total(acc[u]) : 0.0;
-            if ((tid & 63) == 0) {
-#pragma unroll
-                for (int u = 0; u < kRedGates; ++u) red[(t0 / kRedGates) & 1][u][tid >> 6] = acc[u];
-            }
+            const double tot = wave_totals8(acc, tid & 63);
+            if ((tid & 7) == 0) red[(t0 / kRedGates) & 1][(tid & 63) >> 3][tid >> 6] = tot;
         };
         auto gates = [&](auto long_tag) {
             int t0 = 0;
