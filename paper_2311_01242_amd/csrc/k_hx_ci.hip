@@ -10,9 +10,9 @@
 // sorted by (xa, xb): the partner row changes only between classes of equal
 // xa and is staged once per class in the wave's slice of LDS, from which the
 // lanes gather column b ^ xb.  Groups of classes whose members all have
-// xb = 0 read the partner in the same column straight from memory.  The
-// workgroup's rows share the group, subgroup and table data, staged chunk by
-// chunk in LDS with the next chunk's loads in flight during the current one.
+// xb = 0 read the partner in the same column straight from memory.  Group,
+// subgroup and table data are read through the caches (every row of a state
+// reads the same ones).
 #include <type_traits>
 
 #include "device_common.h"
@@ -20,9 +20,8 @@
 namespace vqe {
 
 // Group and subgroup descriptors are the same for every lane: they are read
-// through the scalar data cache (ldc) one group ahead.
-// The tables, gathered per lane, are staged chunk by chunk in LDS with the
-// next chunk's loads in flight during the current one.
+// through the scalar data cache (ldc) one group ahead; the tables, gathered
+// per lane, through the vector caches.
 __device__ __forceinline__ uint32_t pext_mask(uint32_t v, uint32_t mask) {
     uint32_t out = 0;
     int k = 0;
@@ -43,7 +42,7 @@ __host__ __device__ inline int ci_wave_words(int nb, int npairs, int vbytes) {
 }
 
 // lambda += D_G(b) phi(partner) for one group over the wave's columns.
-// tab: the group's table base (LDS chunk or global); sp: its subgroups.
+// tab: the group's table base (LDS or global); sp: its subgroups.
 // V: amplitude type (double2, or double for real states).
 template <int COLS, int W, bool GTAB, typename V>
 __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, const double* tab,
@@ -148,9 +147,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                                                       int xs, int nrb) {
     static_assert(R == 1 || W == 1, "several rows of one wave each, or one row of several waves");
     constexpr int kT = R * W * 64;
-    constexpr int kTPer = (kCiChunkTabs + kT - 1) / kT;
     extern __shared__ double2 lds_ci[];
-    __shared__ double tstage[2][kCiChunkTabs];
     __shared__ double ered[W];
     int rblk = blockIdx.x, sidx = blockIdx.y;
     if (xs > 0) {
@@ -162,6 +159,7 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
     const int nrank = 1 << ci.ob;
     int16_t* RB = reinterpret_cast<int16_t*>(lds_ci);
     for (int i = threadIdx.x; i < nrank; i += kT) RB[i] = ci.rank_b[i];
+    __syncthreads();   // every wave reads the whole table
     const StateDesc& s = sd[sidx];
     const int split = blockIdx.z, nsplit = ci.nsplit;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -442,39 +440,21 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
             for (int c = 0; c < COLS; ++c) move(ldg2(cmv + size_t(e) * NB + ibc[c]), c);
     }
-    // ---- generic groups, chunk by chunk (chunks split, split + nsplit, ...)
+    // ---- generic groups, chunk by chunk (chunks split, split + nsplit, ...);
+    // their tables are read from global memory (every row of the state reads
+    // the same ones, so they stay in L2)
     const int nch = s.ci_nchunks;
-    double treg[kTPer];
-    auto tload = [&](int c) {
-        const CiChunk ck = ldc(s.ci_chunks + c);
-#pragma unroll
-        for (int k = 0; k < kTPer; ++k) {
-            const int i = threadIdx.x + k * kT;
-            treg[k] = (i < ck.t1 - ck.t0) ? ldg64(s.ci_tabs + ck.t0 + i) : 0.0;
-        }
-    };
-    auto tstore = [&](int buf) {
-#pragma unroll
-        for (int k = 0; k < kTPer; ++k) tstage[buf][threadIdx.x + k * kT] = treg[k];
-    };
-    if (split < nch) {
-        tload(split);
-        tstore(0);
-    }
-    __syncthreads();
     uint32_t cur_xa = 0xffffffffu;   // class whose partner row is staged
     bool valid = false, col_only = false;
     const V* prow = phi;
-    for (int ch = split, it = 0; ch < nch; ch += nsplit, ++it) {
-        const int chn = ch + nsplit;
-        if (chn < nch) tload(chn);   // in flight during this chunk
-        const double* tab = tstage[it & 1];
+    for (int ch = split; row_live && ch < nch; ch += nsplit) {
         const CiChunk ck = ldc(s.ci_chunks + ch);
+        const double* tab = s.ci_tabs + ck.t0;
         const CiGroup* gp = s.ci_groups + ck.g0;
         const CiSub* sp = s.ci_subs + ck.s0;
         const int ng = ck.g1 - ck.g0;
         CiGroup G = ldc(gp);
-        for (int g = 0; row_live && g < ng; ++g) {
+        for (int g = 0; g < ng; ++g) {
             const CiGroup Gn = ldc(gp + (g + 1 < ng ? g + 1 : g));   // next group, ahead
             if (G.xa != cur_xa) {   // a new class: its partner row
                 cur_xa = G.xa;
@@ -485,11 +465,9 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
                     if (!col_only) stage_row(prow);
                 }
             }
-            if (valid) ci_group<COLS, W, false, V>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, sig);
+            if (valid) ci_group<COLS, W, true, V>(G, sp, tab, sA, sB, ibc, col_only, prow, row, RB, sig);
             G = Gn;
         }
-        if (chn < nch) tstore((it + 1) & 1);   // the buffer read two chunks ago
-        __syncthreads();
     }
     if (!row_live) return;
     double acc = 0.0;
@@ -650,7 +628,7 @@ void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, bool real, h
 // The complex layout needs the most LDS; the real one fits wherever it does.
 int ci_prepare(const CiArgs& ci) {
     const size_t lds = ci_lds(ci, 16);
-    const size_t fixed = sizeof(double) * 2 * kCiChunkTabs + 64;
+    const size_t fixed = 64;
     if (ci.nb_str > 1024 || lds + fixed > (160u << 10)) return 1;
     if (lds + fixed <= (64u << 10)) return 0;
     hipError_t e = hipSuccess;
