@@ -187,6 +187,28 @@ def cmd_counters(args):
             print(f"| {label} | " + " | ".join(vals) + " |")
 
 
+def cmd_derived(args):
+    """Mean over the dispatches of each selected kernel of every counter in
+    the given pmc CSV files (for rocprofv3's derived metrics, which are per
+    dispatch ratios: VALUBusy, OccupancyPercent, ...), one row per kernel."""
+    vals = {k: collections.defaultdict(list) for k in args.kernel}
+    names = []
+    for path in args.csv:
+        for r in csv.DictReader(open(path)):
+            name = short(r["Kernel_Name"]).replace(" ", "")
+            for k in args.kernel:
+                if name.startswith(k.replace(" ", "")):
+                    c = r["Counter_Name"]
+                    if c not in names:
+                        names.append(c)
+                    vals[k][c].append(float(r["Counter_Value"]))
+    print("| kernel | " + " | ".join(names) + " |")
+    print("|---|" + "---:|" * len(names))
+    for k in args.kernel:
+        row = [f"{sum(vals[k][c]) / len(vals[k][c]):.2f}" if vals[k][c] else "-" for c in names]
+        print(f"| {k} | " + " | ".join(row) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser(prog="python -m paper_2311_01242_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -204,8 +226,12 @@ def main():
     c.add_argument("--kernel", action="append", required=True,
                    help="kernel name prefix as rocprof prints it, e.g. 'k_prun<2, 512, 3>'")
     c.add_argument("csv", nargs="+", help="*_counter_collection.csv files of the pmc passes")
+    d = sub.add_parser("derived")
+    d.add_argument("--kernel", action="append", required=True,
+                   help="kernel name prefix as rocprof prints it, e.g. 'k_prun<2, 512, 3>'")
+    d.add_argument("csv", nargs="+", help="*_counter_collection.csv files of the pmc passes")
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters, "derived": cmd_derived}[a.cmd](a)
 
 
 if __name__ == "__main__":
