@@ -194,8 +194,10 @@ struct CiArgs {
     const uint32_t* sb;      // beta strings [nb_str]
     const int32_t* rank_a;   // [2^oa], -1 for other popcounts
     const int16_t* rank_b;   // [2^ob], -1 for other popcounts
-    // beta-pair lists, entry-major [e1][nb_str]: partner column (bits 0-15),
-    // pair index (bits 16-23), 1 if the pair's higher orbital is the occupied one (bit 24)
+    // beta-pair lists, entry-major [e1][nb_str]: 8 x the partner column (bits
+    // 0-15), 8 x (2 pair index + 1 if the pair's higher orbital is the
+    // occupied one) (bits 16-30), the parity of the occupied orbitals between
+    // the pair's two (bit 31)
     const uint32_t* plist;
     int32_t na_str, nb_str, ob;
     int32_t npairs, e1;      // beta pairs C(ob, 2); list entries per column

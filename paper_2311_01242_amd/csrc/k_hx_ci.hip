@@ -127,6 +127,12 @@ __device__ __forceinline__ void ci_group(const CiGroup& G, const CiSub* sp, cons
     }
 }
 
+// The element of an LDS array at a byte offset.
+template <typename T, typename B>
+__device__ __forceinline__ T lds_at(const B* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -239,8 +245,8 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
                 for (int c = 0; c < COLS; ++c) {
                     const uint32_t ent = __builtin_amdgcn_raw_buffer_load_b32(lrs, voff[c], e * NB * 4, 0);
-                    const double t = wcd[(ent >> 16) & 0x1ff];   // 2 pair + pattern
-                    const V p = row[ent & 0xffff];
+                    const double t = lds_at<double>(wcd, (ent >> 16) & 0x7fffu);   // 2 pair + pattern
+                    const V p = lds_at<V>(row, (ent & 0xffffu) * uint32_t(sizeof(V) / 8));
                     // chain parity (bit 31) and the class mask over the column; the
                     // class mask's bit at the pair's occupied orbital, which cfl
                     // counted and the record leaves out, is in the coefficient
@@ -254,9 +260,9 @@ __global__ void __launch_bounds__(R * W * 64) k_hx_ci(const StateDesc* __restric
 #pragma unroll
                 for (int c = 0; c < COLS; ++c) {
                     const uint32_t ent = ldg32(lst + ibc[c]);
-                    const int pid = (ent >> 17) & 0xff;
-                    const double t = wcd[(ent >> 16) & 0x1ff];
-                    const V p = row[ent & 0xffff];
+                    const int pid = (ent >> 20) & 0x7ff;
+                    const double t = lds_at<double>(wcd, (ent >> 16) & 0x7fffu);
+                    const V p = lds_at<V>(row, (ent & 0xffffu) * uint32_t(sizeof(V) / 8));
                     const uint32_t flip = uint32_t(__popc(sB[c] & ww[pid])) << 31;
                     const double coef = __hiloint2double(__double2hiint(t) ^ int(flip), __double2loint(t));
                     axpy(sig[c], coef, p);

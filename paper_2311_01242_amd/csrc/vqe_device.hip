@@ -807,8 +807,10 @@ static int ci_space(int n, int ne, CiSpace** out) {
                 if (bp == bq) continue;
                 const int16_t r = c->rank_b[b ^ (1u << p) ^ (1u << q)];
                 const uint32_t between = ((1u << q) - 1u) & ~((2u << p) - 1u);   // orbitals p+1 .. q-1
-                plist[size_t(e) * c->NB + ib] = uint32_t(r) |
-                                                (uint32_t(2 * pair_index(p, q, c->ob) + bq) << 16) |
+                // byte offsets (of an 8-byte amplitude, of an 8-byte coefficient)
+                // so that the kernel adds them to its LDS bases as they are
+                plist[size_t(e) * c->NB + ib] = uint32_t(r) * 8u |
+                                                (uint32_t(2 * pair_index(p, q, c->ob) + bq) * 8u << 16) |
                                                 (uint32_t(__builtin_popcount(b & between) & 1) << 31);
                 ++e;
             }
