@@ -264,8 +264,9 @@ int vqe_energy_grad(const vqe_hamiltonian* H, const vqe_ansatz* A, int n_electro
  * else EINVAL).  Workspace: a static device array of 64 MiB per device
  * (held from module load until the process ends) holding phi, lambda, the
  * H-apply's lambda planes, the angles, partials and outputs; evaluations
- * that need more (on the packed layout, beyond about 22 qubits) return
- * ERANGE before any device work.  Every call on a device shares that
+ * that need more (on the packed layout with real amplitudes, beyond 24
+ * qubits; on full 2^n vectors, from 21 qubits on) return ERANGE before any
+ * device work.  Every call on a device shares that
  * device's array: calls that overlap on one device (from several host
  * threads or streams) race.  Synchronises hip_stream.  Errors: EINVAL,
  * ERANGE, EDEVICE, ENUMERIC. */

@@ -1428,11 +1428,16 @@ static int packed_plan(const vqe_ansatz* A, DevAnsatz* da, const PackedLayout& l
         return fail(VQE_ERANGE, "packed layout: state too large for 32-bit tile offsets");
     }
     constexpr size_t kNoList = ~size_t(0);
-    // tile-size limit of a run (entries per vector): the tuning's, else two of
-    // the layout's largest blocks (a tile of one block pair)
+    // tile-size limit of a run (entries per vector): the tuning's, else at
+    // least kDefaultTileCap and two of the layout's largest blocks (a tile of
+    // one block pair).  Measured on a single 24-qubit state with the run
+    // kernels' 256 threads: caps of 2400 and 3200 entries 2.23-2.24 ms per
+    // energy + gradient, 800-1600 entries 2.48-2.52 ms, two largest blocks 2.53
+    constexpr int64_t kDefaultTileCap = 2400;
     int32_t maxblk = 1;
     for (int32_t b : lay.bsize) maxblk = std::max(maxblk, b);
-    const int64_t cap = std::min<int64_t>(tn.tile_cap > 0 ? tn.tile_cap : 2 * int64_t(maxblk), kMaxTileEntries);
+    const int64_t cap = std::min<int64_t>(
+        tn.tile_cap > 0 ? tn.tile_cap : std::max<int64_t>(2 * int64_t(maxblk), kDefaultTileCap), kMaxTileEntries);
     // block patterns (within window W) that the gates [j0, j1) pair: D blocks
     // hold the gate's high annihilated bits and none of its high created ones,
     // E blocks the reverse, with any combination of the window's other bits

@@ -75,12 +75,18 @@ def test_missing_setup_and_oversize_are_rejected():
     with pytest.raises(vq.VQEError) as ex:
         vq.energy_grad_noalloc(H, A, 6, theta)
     assert ex.value.code == vq.VQE_EINVAL
-    H24, A24 = _problem(24, 12, 911)
-    t24 = uniform_theta(912, A24.n_params)
-    vq.energy_grad(H24, A24, 12, t24, grad=False)        # plans exist now
-    with pytest.raises(vq.VQEError) as ex:
-        vq.energy_grad_noalloc(H24, A24, 12, t24)
-    assert ex.value.code == vq.VQE_ERANGE and "scratch" in str(ex.value)
+    # full vectors at 22 qubits: phi and lambda alone (2 x 2^22 complex
+    # amplitudes, 128 MiB) exceed the 64 MiB scratch, whatever the tiling
+    vq.set_packed(0)
+    try:
+        H22, A22 = _problem(22, 11, 911)
+        t22 = uniform_theta(912, A22.n_params)
+        vq.energy_grad(H22, A22, 11, t22, grad=False)        # plans exist now
+        with pytest.raises(vq.VQEError) as ex:
+            vq.energy_grad_noalloc(H22, A22, 11, t22)
+        assert ex.value.code == vq.VQE_ERANGE and "scratch" in str(ex.value)
+    finally:
+        vq.set_packed(True)
 
 
 def test_device_memory_unchanged_across_calls():
