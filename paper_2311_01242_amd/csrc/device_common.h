@@ -694,7 +694,7 @@ void launch_hx_ci(const StateDesc* sd, int count, const CiArgs& ci, bool real, h
 int ci_prepare(const CiArgs& ci);   // 0 when the kernel can launch for these sizes
 void launch_packed_hf(const StateDesc* sd, int count, int64_t size, bool real, hipStream_t st);
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, bool adjoint, bool real, hipStream_t st);
+                       bool adjoint, bool real, hipStream_t st);
 // Launch shape covering blocks of max_block entries with at least min_threads
 // threads per tile if there is one (else any), or -1.
 // Single-launch zero-angle sweep of a pool's packed runs (pool gradients):

@@ -140,17 +140,17 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         }
     }
     __syncthreads();
+    // forward pass: the next gate's (cos, sgn sin) is read at the start of the
+    // current gate, so that only pair data follows the barrier (measured: the
+    // forward runs 4% faster, the reverse sweep, which reads the sign too, 5%
+    // slower, so it reads its parameters after the barrier)
+    double2 cs_ahead = gpar[0];
     // one gate: its pairs (one per thread per pass), returning the thread's
     // part of the reverse sweep's Re <lambda|A_j phi>; the slot's entry for
     // gate t + kListAhead is loaded meanwhile.  LONG (a list longer than the
     // block): the thread's later entries are read in the gate itself; the
     // gate loops are built separately for the two cases, so that the common
     // one has no other list reads than the slots'
-    // forward pass: the next gate's (cos, sgn sin) is read at the start of the
-    // current gate, so that only pair data follows the barrier (measured: the
-    // forward runs 4% faster, the reverse sweep, which reads the sign too, 5%
-    // slower, so it reads its parameters after the barrier)
-    double2 cs_ahead = gpar[0];
     auto gate_step = [&](int t, auto slot, auto long_tag) -> double {
         constexpr int q = decltype(slot)::value;   // t % kListAhead
         constexpr bool LONG = decltype(long_tag)::value;
@@ -367,19 +367,16 @@ int packed_shape(int max_block, int min_threads) {
 
 int packed_shape_threads(int shape) { return kPShapes[shape].bs; }
 
-using PackedLauncher = void (*)(const StateDesc*, int, const PackedRun&, const PackedGate*,
-                                const HxTables*, const int32_t*, hipStream_t);
+using PackedLauncher = void (*)(const StateDesc*, int, const PackedRun&, const PackedGate*, hipStream_t);
 
 template <int VEC, int BS, int EPT, typename V>
 static void launch_one(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, hipStream_t st) {
+                       hipStream_t st) {
     // the tile's amplitudes (16-byte aligned), then 2 double2 per gate
     const size_t lds = (size_t(run.max_entries) * VEC * sizeof(V) + 15) / 16 * 16 +
                        2 * size_t(run.g1 - run.g0) * sizeof(double2);
     const int nx = run.live ? run.nlive : run.ntiles;
     if (nx == 0) return;   // a run with no live tile: nothing to do, no partials
-    (void)tabs;
-    (void)base;
     hipLaunchKernelGGL((k_prun<VEC, BS, EPT, V>), dim3(nx, count), dim3(BS), lds, st, sd, run, pg);
 }
 
@@ -397,11 +394,11 @@ static const PackedLauncher kAdjLaunchR[] = {VQE_PACKED_SHAPES(VQE_ADJ_REAL)};
 #undef VQE_ADJ_REAL
 
 void launch_packed_run(const StateDesc* sd, int count, const PackedRun& run, const PackedGate* pg,
-                       const HxTables* tabs, const int32_t* base, bool adjoint, bool real, hipStream_t st) {
+                       bool adjoint, bool real, hipStream_t st) {
     if (adjoint)
-        (real ? kAdjLaunchR : kAdjLaunch)[run.shape_adj](sd, count, run, pg, tabs, base, st);
+        (real ? kAdjLaunchR : kAdjLaunch)[run.shape_adj](sd, count, run, pg, st);
     else
-        (real ? kFwdLaunchR : kFwdLaunch)[run.shape](sd, count, run, pg, tabs, base, st);
+        (real ? kFwdLaunchR : kFwdLaunch)[run.shape](sd, count, run, pg, st);
 }
 
 using PoolLauncher = void (*)(const StateDesc*, int, const PoolSweep&, const HxTables*,

@@ -2249,8 +2249,7 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
         launch_angles(sd, count, ep.M, st);
         launch_packed_hf(sd, count, ep.lay->size, ep.real, st);
         for (size_t r = 0; r < pp.runs.size(); ++r)
-            launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
-                              ep.lay->d_base, false, ep.real, st);
+            launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], false, ep.real, st);
     } else if (phase == kPhaseHx) {
         if (ep.ci) {
             launch_ci_scatter(sd, count, ep.perm, ep.lay->size, ep.real, st);
@@ -2262,8 +2261,7 @@ static void enqueue_packed(const EvalPlan& ep, const StateDesc* sd, int count, i
     } else if (phase == kPhaseAdj) {
         if (!grad) return;
         for (size_t r = pp.runs.size(); r-- > 0;)
-            launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], ep.hxt,
-                              ep.lay->d_base, true, ep.real, st);
+            launch_packed_run(sd, count, pp.runs[r], pp.d_gates + pp.off[r], true, ep.real, st);
     } else {
         launch_reduce_e(sd, count, ep.nblk_e, st);
         if (grad) launch_reduce_g(sd, count, ep.M, pp.d_gcnt_live, 0, st);
