@@ -200,6 +200,18 @@ def _binom(n, k):
     return comb(n, k, exact=False)
 
 
+def walk_lds_bytes(n, ne, vbytes):
+    """LDS bytes the string-product H-apply's beta-pair walk gathers for one
+    (n, n_e) state: for every row (alpha string), every alpha orbital pair
+    with one orbital occupied in it (a pair class, present for every pair in
+    a molecular Hamiltonian), every column (beta string) and every beta pair
+    with one orbital occupied in the column (a list entry), one 8-byte pair
+    coefficient and one partner amplitude of vbytes."""
+    na, nb = (ne + 1) // 2, ne // 2
+    oa, ob = (n + 1) // 2, n // 2
+    return float((vbytes + 8) * int(_binom(oa, na)) * na * (oa - na) * int(_binom(ob, nb)) * nb * (ob - nb))
+
+
 def sector_elements(H, n, ne):
     """Nonzero matrix elements of H inside the (N, S_z) sector of the
     reference: (output, distinct x-mask) pairs whose partner output ^ x is in
@@ -266,7 +278,8 @@ def cpu_model():
 def add_ceiling_fracs(roof, ceilings):
     """Fractions of the HBM-bound phases' achieved GB/s against the measured
     copy ceilings (the vendor-peak fraction stays in `frac`), and of the
-    packed gate runs' LDS traffic against the measured LDS ceiling."""
+    packed gate runs' LDS traffic and the string-product H-apply's beta-pair
+    gathers against the measured LDS ceiling."""
     for rec in [roof] + list(roof.get("phases", {}).values()):
         if rec.get("bound") == "hbm" and rec.get("unit") == "GB/s":
             rec["frac_copy_64MB"] = round(rec["achieved"] / ceilings["copy_64MB"]["GB/s"], 4)
@@ -339,6 +352,11 @@ def roofline(b, theta, reps, Hs, nes, kernels=None, pairs=None, traffic_key=None
         recs["forward"]["lds_bytes_per_eval"] = 4 * vbytes * w[1] + w[0]
         recs["adjoint"]["lds_bytes_per_eval"] = 8 * vbytes * w[1] + w[2]
         recs["forward"]["pair_updates_per_eval"] = recs["adjoint"]["pair_updates_per_eval"] = w[1]
+        # string-product H-apply (n <= 26, at most 1024 beta strings): the
+        # beta-pair walk's LDS gathers, the bulk of its LDS traffic
+        if all(H.info()[0] <= 26 and _binom(H.info()[0] // 2, ne // 2) <= 1024 for H, ne in zip(Hs, nes)):
+            recs["h_apply"]["lds_bytes_per_eval"] = sum(walk_lds_bytes(H.info()[0], ne, vbytes)
+                                                        for H, ne in zip(Hs, nes))
     dom = max(recs, key=lambda k: recs[k]["phase_ms"])
     out = dict(recs[dom])
     out["dominant_phase"] = dom

@@ -36,6 +36,35 @@ def test_sector_elements_match_enumeration(n, ne, seed):
         assert np.count_nonzero(np.abs(m[np.ix_(sector, sector)]) > 1e-12) == brute
 
 
+@pytest.mark.parametrize("n,ne", [(6, 3), (8, 4), (9, 4), (10, 5)])
+def test_walk_lds_bytes_match_enumeration(n, ne):
+    """The beta-pair walk's gather count: (row, alpha pair with one occupied
+    orbital, column, beta pair with one occupied orbital), each a coefficient
+    and an amplitude; every alpha pair with a beta pair is a group of the
+    molecular Hamiltonian (so every such alpha pair is a class)."""
+    import itertools
+    import bench
+    import paper_2311_01242_amd as vq
+    from vqe_inputs import random_integrals
+    na, nb = (ne + 1) // 2, ne // 2
+    oa, ob = (n + 1) // 2, n // 2
+    rows = [a for a in range(1 << oa) if bin(a).count("1") == na]
+    cols = [b for b in range(1 << ob) if bin(b).count("1") == nb]
+    apairs = list(itertools.combinations(range(oa), 2))
+    bpairs = list(itertools.combinations(range(ob), 2))
+    one = lambda s, p, q: ((s >> p) & 1) != ((s >> q) & 1)
+    count = sum(1 for a in rows for p, q in apairs if one(a, p, q)
+                for b in cols for r, t in bpairs if one(b, r, t))
+    assert bench.walk_lds_bytes(n, ne, 8) == 16 * count
+    assert bench.walk_lds_bytes(n, ne, 16) == 24 * count
+    # every alpha pair appears with a beta pair among the Hamiltonian's x-masks
+    h0, h, g = random_integrals(n, 5)
+    x, _, _ = vq.Hamiltonian.from_integrals(n, h0, h, g).terms()
+    xa = {sum(((int(v) >> (2 * i)) & 1) << i for i in range(oa)) for v in x
+          if bin(sum(((int(v) >> (2 * i + 1)) & 1) << i for i in range(ob))).count("1") == 2}
+    assert all((1 << p) | (1 << q) in xa for p, q in apairs)
+
+
 def test_traffic_reported_only_for_its_workload_and_source(tmp_path, monkeypatch):
     """roofline.traffic comes from the counter file only for the workload it
     was measured on and while the kernel source hash matches."""
