@@ -399,8 +399,8 @@ int vqe_set_real(int on);
  * of at most 4 bits, applied tile by tile, a tile being the blocks that agree
  * outside the window; entries (16..8192) bounds the largest tile, so that
  * fewer block bits with more window bits mean fewer runs (fewer passes over
- * the state) at the same tile size.  0 restores the default, two of the
- * layout's largest blocks.  Errors: ERANGE. */
+ * the state) at the same tile size.  0 restores the default: 2400 entries,
+ * or two of the layout's largest blocks when they hold more.  Errors: ERANGE. */
 int vqe_set_tile_cap(int n_qubits, int batched, int entries);
 
 /* Persistent batch passes (process-wide, applies to batches created after

@@ -68,8 +68,8 @@ def real_enabled():
 
 def set_tile_cap(n_qubits: int, batched: bool, entries: int = 0):
     """Largest packed run tile (entries per vector) for n_qubits; 0 = the
-    default (two of the layout's largest blocks).  Applies to plans made
-    afterwards."""
+    default (2400 entries, or two of the layout's largest blocks when they
+    hold more).  Applies to plans made afterwards."""
     _check(lib().vqe_set_tile_cap(int(n_qubits), int(bool(batched)), int(entries)))
 
 

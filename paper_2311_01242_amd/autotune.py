@@ -27,7 +27,8 @@ import numpy as np
 from . import Batch, VQEError, real_enabled, set_run_threads, set_tile_cap, set_tuning
 
 RUN_THREADS = (64, 256, 512, 1024)
-# largest packed run tile (entries per vector); 0 = two of the layout's largest blocks
+# largest packed run tile (entries per vector); 0 = the default (2400, or two of the
+# layout's largest blocks when they hold more)
 TILE_CAPS = (0, 1200, 1600, 2400)
 # with real amplitudes a tile takes half the LDS: larger tiles are candidates too
 TILE_CAPS_REAL = (0, 1600, 2400, 3200)

@@ -376,6 +376,28 @@ def test_packed_run_thread_counts_agree(threads):
     assert abs(e - e0) < 1e-12 and np.abs(g - g0).max() < 1e-12
 
 
+def test_pair_lists_longer_than_the_block():
+    """Gate runs whose pair lists are longer than the run's thread count (each
+    thread then takes several pairs of a gate, the later ones read in the gate
+    itself): 64-thread tiles of up to 1000 entries, against the oracle and
+    the default launch shape."""
+    n, ne = 16, 8
+    H, A, prob = _pair(n, ne, 1711)
+    theta = uniform_theta(1712, A.n_params)
+    e0, g0 = vq.energy_grad(H, A, ne, theta)
+    try:
+        vq.set_run_threads(n, False, 64, 64)
+        vq.set_tile_cap(n, False, 1000)
+        e, g = vq.energy_grad(H, vq.Ansatz.uccsd(n, ne), ne, theta)
+    finally:
+        vq.set_run_threads(n, False, 0, 0)
+        vq.set_tile_cap(n, False, 0)
+    assert abs(e - prob.energy(theta)) < TOL_E
+    k = [0, 1, A.n_params - 2, A.n_params - 1]
+    assert np.abs(g[k] - prob.grad_shift(theta, k)).max() < TOL_E
+    assert abs(e - e0) < 1e-12 and np.abs(g - g0).max() < 1e-12
+
+
 def test_string_product_long_rows_match_block_order():
     """Beta-string rows longer than 256 take several waves per row in the
     string-product H-apply; against the block-order H-apply (itself pinned to
