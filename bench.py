@@ -862,7 +862,7 @@ def run_adapt20(args):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
                                    "(states and geometries shard across GPUs by design, "
                                    "but no multi-GPU path is implemented)"}))
         sys.exit(2)
