@@ -81,6 +81,11 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     const uint32_t hb0 = tb.hbase << run.L;
     V* shp = reinterpret_cast<V*>(sh);
     V* shl = shp + nE;
+    // the reverse sweep on real amplitudes keeps (phi, lambda) of an entry
+    // side by side, so that a pair's four values take two 16-byte LDS reads
+    // and two writes
+    constexpr bool kPL = VEC == 2 && std::is_same<V, double>::value;
+    double2* shpl = sh;
     const bool fwd = (VEC == 1);
     const int ng = run.g1 - run.g0;
     const int cls = tb.cls;
@@ -111,7 +116,8 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
     // per-gate parameters of this tile after the tile (2 double2 per gate):
     // (cos, sgn sin) and (sgn, 0), sgn the gate's pair sign from the tile's
     // high bits outside the window (the window's part is in each entry);
-    // staged once, read by broadcast in the gate loop
+    // staged once; the first is read by broadcast in the gate loop, the
+    // second (reverse sweep) applied to the gate's tile total at the end
     double2* gpar = sh + (size_t(VEC) * run.max_entries * sizeof(V) + 15) / 16;
     // the state index of each staged entry, kept for the write-back
     int gix[2 * EPT];
@@ -135,8 +141,12 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
 #pragma unroll
         for (int u = 0; u < 2 * EPT; ++u) {
             const int k = min(tid + BS * u, nE - 1);
-            shp[k] = vp[u];
-            if (VEC == 2) shl[k] = vl[u];
+            if constexpr (kPL) {
+                shpl[k] = make_double2(vp[u], vl[u]);
+            } else {
+                shp[k] = vp[u];
+                if (VEC == 2) shl[k] = vl[u];
+            }
         }
     }
     __syncthreads();
@@ -158,7 +168,6 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
         const int jn = fwd ? jl + kListAhead : jl - kListAhead;
         const uint32_t ecur = has_slot ? eq[q] : kPairNone;
         const double2 cs = VEC == 1 ? cs_ahead : gpar[2 * jl];   // (cos, sgn sin)
-        const double sgn_hi = VEC == 1 ? 0.0 : gpar[2 * jl + 1].x;   // the tile's part of the sign
         const double ssin = cs.y;
         if (VEC == 1) cs_ahead = gpar[2 * (jl + 1 < ng ? jl + 1 : jl)];
         double acc = 0.0;
@@ -173,16 +182,35 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
                 shp[k] = d;
                 shp[ie] = f;
             } else {
-                V fD = shp[k], fE = shp[ie], lD = shl[k], lE = shl[ie];
+                V fD, fE, lD, lE;
+                if constexpr (kPL) {
+                    const double2 pD = shpl[k], pE = shpl[ie];
+                    fD = pD.x;
+                    lD = pD.y;
+                    fE = pE.x;
+                    lE = pE.y;
+                } else {
+                    fD = shp[k];
+                    fE = shp[ie];
+                    lD = shl[k];
+                    lE = shl[ie];
+                }
                 // <lam| A phi> with A|D> = s|E>, A|E> = -s|D> (s = ss / sin)
-                const double sg_t = ((e >> kEntParity) & 1u) ? -sgn_hi : sgn_hi;
-                acc += sg_t * (redot(lE, fD) - redot(lD, fE));
+                // the entry's part of the sign here; the tile's (a factor of
+                // +-1 common to the gate) when the tile's total is stored
+                const double dv = redot(lE, fD) - redot(lD, fE);
+                acc += ((e >> kEntParity) & 1u) ? -dv : dv;
                 givens(fD, fE, cs.x, -ss);   // U^dag: rotation by -theta
                 givens(lD, lE, cs.x, -ss);
-                shp[k] = fD;
-                shp[ie] = fE;
-                shl[k] = lD;
-                shl[ie] = lE;
+                if constexpr (kPL) {
+                    shpl[k] = make_double2(fD, lD);
+                    shpl[ie] = make_double2(fE, lE);
+                } else {
+                    shp[k] = fD;
+                    shp[ie] = fE;
+                    shl[k] = lD;
+                    shl[ie] = lE;
+                }
             }
         }
         // the slot's next entry, issued once this gate's entry is dead (so
@@ -251,14 +279,21 @@ __global__ void __launch_bounds__(BS) k_prun(const StateDesc* __restrict__ sd, P
             }
         }
         __syncthreads();
-        for (int jl = tid; jl < ng; jl += BS) s.part_g[size_t(run.g0 + jl) * s.gstride + po] = gsum[jl];
+        for (int jl = tid; jl < ng; jl += BS)
+            s.part_g[size_t(run.g0 + jl) * s.gstride + po] = gsum[jl] * gpar[2 * jl + 1].x;
     }
 #pragma unroll
     for (int u = 0; u < 2 * EPT; ++u) {
         const int k = tid + BS * u;
         if (k < nE) {
-            stgv(reinterpret_cast<V*>(s.phi) + gix[u], shp[k]);
-            if (VEC == 2) stgv(reinterpret_cast<V*>(s.lam) + gix[u], shl[k]);
+            if constexpr (kPL) {
+                const double2 pl = shpl[k];
+                stgv(reinterpret_cast<double*>(s.phi) + gix[u], pl.x);
+                stgv(reinterpret_cast<double*>(s.lam) + gix[u], pl.y);
+            } else {
+                stgv(reinterpret_cast<V*>(s.phi) + gix[u], shp[k]);
+                if (VEC == 2) stgv(reinterpret_cast<V*>(s.lam) + gix[u], shl[k]);
+            }
         }
     }
 }
